@@ -1,0 +1,153 @@
+"""Pins of the oracle's expansions and FMM (no GPU).
+
+* Expansion pieces against the direct 1/r sum: the multipole (eq. 10) and
+  local (eq. 11) series converge, M2M and L2L are exact re-expansions, the
+  local derivatives match finite differences and are harmonic.
+* The FMM converges exponentially in p to the direct sum with the cutoff
+  dropped beyond adjacent leaves (the far-field model of Sec. 3.1), in free
+  space and for periodic image blocks.
+* With no far field (free space, one leaf) the FMM is the direct sum.
+* A quarter turn of the particle set about the box axis maps the tree onto
+  itself; truncation at degree p is rotation invariant, so the FMM output
+  must rotate with it to round-off.  A wrong sign, index or transposed
+  operand in any translation breaks this.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct as D
+from oracle import fmm as F
+from oracle import harmonics as H
+from oracle import tree as T
+
+L = 2 * math.pi
+
+
+def _pot(x, src, q):
+    return np.array([[np.sum(q[:, k] / np.linalg.norm(xx - src, axis=1)) for k in range(q.shape[1])]
+                     for xx in x])
+
+
+def test_multipole_and_local_series_converge():
+    rng = np.random.default_rng(0)
+    src = rng.uniform(-0.5, 0.5, (7, 3))
+    q = rng.standard_normal((7, 2))
+    x = np.array([[2.2, -1.5, 1.9], [0.4, 2.6, -1.7]])
+    exact = _pot(x, src, q)
+    errs = []
+    for p in (4, 8, 12, 16):
+        M = H.p2m(src, q, p)
+        errs.append(np.abs(H.eval_multipole(M, x, p) - exact).max())
+    assert all(b < a / 5 for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-9
+    # M2L: local expansion about a far centre, evaluated near it
+    t = np.array([3.0, 2.0, -2.5])
+    near = t + rng.uniform(-0.4, 0.4, (3, 3))
+    exact = _pot(near, src, q)
+    errs = []
+    for p in (4, 8, 12, 16):
+        M = H.p2m(src, q, p)
+        Lc = (H.m2l_matrix(-t, p) @ M.T).T
+        errs.append(np.abs(H.eval_local(Lc, near - t, p) - exact).max())
+    assert all(b < a / 5 for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-8
+
+
+def test_m2m_and_l2l_are_exact():
+    rng = np.random.default_rng(1)
+    p = 10
+    src = rng.uniform(-0.5, 0.5, (9, 3))
+    q = rng.standard_normal((9, 3))
+    M = H.p2m(src, q, p)
+    c = np.array([0.25, -0.25, 0.25])
+    M2 = (H.m2m_matrix(-c, p) @ M.T).T
+    assert np.abs(M2 - H.p2m(src - c, q, p)).max() < 1e-13 * np.abs(M).max()
+    t = np.array([3.0, -2.0, 2.0])
+    Lc = (H.m2l_matrix(-t, p) @ M.T).T
+    e = np.array([0.2, 0.1, -0.3])
+    L2 = (H.l2l_matrix(-e, p) @ Lc.T).T
+    pts = t + e + rng.uniform(-0.2, 0.2, (5, 3))
+    assert np.abs(H.eval_local(L2, pts - t - e, p) - H.eval_local(Lc, pts - t, p)).max() < 1e-13
+
+
+def test_local_derivatives_match_fd_and_are_harmonic():
+    rng = np.random.default_rng(2)
+    p = 8
+    src = rng.uniform(-0.5, 0.5, (6, 3)) + np.array([3.0, 0.0, 0.0])
+    q = rng.standard_normal((6, 1))
+    M = H.p2m(src - np.array([3.0, 0, 0]), q, p)
+    Lc = (H.m2l_matrix(np.array([3.0, 0, 0]), p) @ M.T).T
+    x = rng.uniform(-0.3, 0.3, (4, 3))
+    g, hs = H.local_derivs(Lc, x, p)
+    h = 1e-4
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        f = lambda s: H.eval_local(Lc, x + s * e, p)
+        fd = (8 * (f(1) - f(-1)) - (f(2) - f(-2))) / (12 * h)
+        assert np.abs(fd - g[:, :, a]).max() < 1e-9 * np.abs(g).max()
+    assert np.abs(np.trace(hs, axis1=2, axis2=3)).max() < 1e-12 * np.abs(hs).max()
+
+
+def _model(x, a, sigma, level, periodic):
+    tr = T.build(x, (0, 0, 0), L, level, periodic)
+    c = tr["coords"]
+    return D.direct(tr["xw"], tr["xw"], a, sigma, L, K=periodic, cells_t=c, cells_s=c, level=level)
+
+
+@pytest.mark.parametrize("periodic", [0, 1, 2])
+def test_fmm_converges_to_far_field_model(periodic):
+    x, a = W.random_particles(300, 21)
+    sigma = 0.2
+    u0, J0 = _model(x, a, sigma, 2, periodic)
+    eu, ej = [], []
+    for p in (3, 6, 9):
+        u, J = F.fmm(x, a, sigma, p, 2, periodic=periodic)
+        eu.append(np.linalg.norm(u - u0) / np.linalg.norm(u0))
+        ej.append(np.linalg.norm(J - J0) / np.linalg.norm(J0))
+    assert eu[1] < eu[0] / 4 and eu[2] < eu[1] / 4
+    assert ej[1] < ej[0] / 4 and ej[2] < ej[1] / 4
+    assert eu[2] < 2e-4 and ej[2] < 2e-4
+
+
+def test_fmm_without_far_field_is_direct_sum():
+    x, a = W.random_particles(200, 22)
+    for level in (0, 1):
+        u, J = F.fmm(x, a, 0.3, 6, level, periodic=0)
+        u0, J0 = D.direct(x, x, a, 0.3)
+        assert np.abs(u - u0).max() < 1e-13 * np.abs(u0).max()
+        assert np.abs(J - J0).max() < 1e-13 * np.abs(J0).max()
+
+
+@pytest.mark.parametrize("periodic", [0, 2])
+def test_fmm_rotates_with_its_input(periodic):
+    x, a = W.random_particles(250, 23)
+    sigma = 0.25
+    p, level = 5, 2
+    Rm = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    xr = np.stack([L - x[:, 1], x[:, 0], x[:, 2]], axis=1)   # quarter turn about the box axis
+    ar = a @ Rm.T
+    u, J = F.fmm(x, a, sigma, p, level, periodic=periodic)
+    ur, Jr = F.fmm(xr, ar, sigma, p, level, periodic=periodic)
+    assert np.abs(ur - u @ Rm.T).max() < 1e-12 * np.abs(u).max()
+    assert np.abs(Jr - np.einsum("ia,nab,jb->nij", Rm, J, Rm)).max() < 1e-12 * np.abs(J).max()
+
+
+def test_level_zero_periodic_is_images_plus_lattice():
+    """One leaf with its 26 images in P2P and the lattice operator beyond:
+    converges to the image block S_2 with the cutoff dropped outside S_1."""
+    x, a = W.random_particles(120, 24)
+    sigma = 0.3
+    tr = T.build(x, (0, 0, 0), L, 0, 1)
+    xw = tr["xw"]
+    u1, J1 = D.direct(xw, xw, a, sigma, L, K=1)
+    # images of S_2 outside S_1, singular kernel (rho >= 16 there, g = 1 to double precision)
+    u2, J2 = _model(x, a, sigma, 0, 2)
+    errs = []
+    for p in (4, 8, 12):
+        u, J = F.fmm(x, a, sigma, p, 0, periodic=2)
+        errs.append(np.linalg.norm(u - u2) / np.linalg.norm(u2 - u1))
+    assert errs[1] < errs[0] / 4 and errs[2] < errs[1] / 4
