@@ -1,0 +1,174 @@
+/*
+ * vmfmm -- fast multipole evaluation of the Gaussian-regularised Biot-Savart
+ * velocity and vortex-stretching term for N vortex particles on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method (Yokota & Barba, "FMM-based vortex method for simulation of
+ * isotropic turbulence on GPUs, compared with a spectral method"):
+ *   - particles carry strength alpha_j (= gamma_j), Gaussian core sigma
+ *     (Sec. 2.2, eqs. 3-4);
+ *   - velocity u_i = 1/(4 pi) sum_j q(r) alpha_j x r, r = x_i - x_j,
+ *     q = g(r/sigma)/r^3, g the cutoff of eq. 6 (eq. 5);
+ *   - gradient J_i[a][b] = d u_b / d x_a; stretching (eq. 8)
+ *     dalpha_i/dt = sum_a alpha_{i,a} J_i[a][:]  ("classic"), or the
+ *     transpose J_i . alpha_i, which conserves sum_i alpha_i;
+ *   - far field by multipole/local expansions of degree 0..p of the three
+ *     Laplace potentials psi = G * omega (eqs. 10-15), u = curl psi, with the
+ *     cutoff dropped there; near field (27 adjacent leaves) exact (Sec. 3.1);
+ *   - periodic cube: the 26 neighbouring images through the tree, further
+ *     images of the cubic block 3^K x 3^K x 3^K by a lattice operator on the
+ *     root multipole (Sec. 3.1 last paragraph; Sec. 4.1 uses K = 3).
+ *
+ * Conventions for every entry point:
+ *   - device pointers are HIP device addresses; particle arrays are SoA
+ *     [3][n] (component-major) doubles, 8-byte aligned, owned by the caller;
+ *   - work is enqueued on the context's stream and the call returns after
+ *     enqueueing (no host synchronisation unless stated);
+ *   - a context is used by one host thread at a time; calls on one context
+ *     run in stream order;
+ *   - argument errors return VM_EINVAL before anything is launched; HIP
+ *     failures return VM_EDEVICE; allocation failures VM_ENOMEM; the text
+ *     of the last error is kept in the context (vm_last_error).
+ */
+#ifndef VMFMM_H
+#define VMFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vm_ctx vm_ctx;
+
+typedef enum {
+    VM_OK = 0,
+    VM_EINVAL = -1,   /* invalid argument (nothing launched) */
+    VM_ENOMEM = -2,   /* device or host allocation failed */
+    VM_EDEVICE = -3,  /* HIP runtime / launch failure */
+    VM_EDOMAIN = -4   /* check_domain: a position was non-finite or outside the box */
+} vm_status;
+
+typedef enum { VM_FP64 = 0, VM_MIXED = 1 } vm_precision;
+typedef enum { VM_CLASSIC = 0, VM_TRANSPOSE = 1 } vm_scheme;
+
+typedef struct {
+    double box_lo[3];  /* lower corner of the root cube */
+    double box_len;    /* edge of the root cube; the period when periodic > 0 */
+    int periodic;      /* 0: free space; K in 1..4: images in the block 3^K per side */
+    int precision;     /* vm_precision */
+    int scheme;        /* vm_scheme (stretching form written to dalpha_dt) */
+    int check_domain;  /* 1: flag non-finite / out-of-box positions (one 4-byte
+                          device-to-host copy and a stream synchronisation) */
+} vm_opts;
+
+/* Limits checked on every call. */
+#define VM_MAX_P 20
+#define VM_MAX_LEVEL 10
+
+/* Creates a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  The context owns its
+ * workspace (grown on demand, reused across calls) and its operator cache. */
+vm_status vm_create(vm_ctx **ctx, int device, void *hip_stream);
+void vm_destroy(vm_ctx *ctx);
+vm_status vm_set_stream(vm_ctx *ctx, void *hip_stream);
+const char *vm_last_error(const vm_ctx *ctx);
+
+/*
+ * FMM evaluation (Sec. 3.1, eqs. 5-15).
+ *   n          number of particles, 1 <= n < 2^31
+ *   x          device [3][n]: positions; periodic runs take them modulo the box
+ *   alpha      device [3][n]: strengths
+ *   sigma      Gaussian core radius (> 0), the same for all particles
+ *   p          expansion degree, 1..VM_MAX_P ((p+1)^2 real coefficients per component)
+ *   level      leaf level of the uniform octree, 0..VM_MAX_LEVEL (8^level leaves);
+ *              free space needs level >= 2 for any far field (below that the
+ *              evaluation is the direct sum)
+ *   u          device [3][n] out: velocity
+ *   dalpha_dt  device [3][n] out or NULL: stretching term, opts->scheme form
+ *   grad       device [9][n] out or NULL: J[a][b] = d u_b / d x_a at index 3a+b
+ * All outputs are in the caller's particle order.  FP64 and mixed forms take
+ * and return double precision; the mixed form computes the near field in
+ * FP32 with compensated velocity sums and the expansions in FP32 (MFMA),
+ * keeping the translation operators' generation and the lattice operator in FP64.
+ */
+vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
+                      double sigma, int p, int level, const vm_opts *opts,
+                      double *u, double *dalpha_dt, double *grad);
+
+/*
+ * Device-time accounting (HIP events on the context's stream around every
+ * launch).  When enabled, vm_get_timing reports, for the last vm_fmm_eval,
+ * the summed milliseconds and the number of launches of each phase; it
+ * synchronises the stream.  Phases, in launch order:
+ */
+enum {
+    VM_PH_TREE = 0,   /* keys, radix sort passes, leaf ranges, permutation */
+    VM_PH_P2M,
+    VM_PH_M2M,
+    VM_PH_LATTICE,
+    VM_PH_L2L,
+    VM_PH_M2L,
+    VM_PH_L2P,
+    VM_PH_P2P,        /* near field + combine + scatter to caller order */
+    VM_NPHASE
+};
+vm_status vm_set_timing(vm_ctx *ctx, int enable);
+vm_status vm_get_timing(vm_ctx *ctx, double *ms, int *launches);
+
+/*
+ * Debug views of the last vm_fmm_eval on this context (stream-ordered
+ * device-to-device copies into caller buffers; any pointer may be NULL):
+ *   keys        device [n] uint32: Morton keys in sorted order
+ *   perm        device [n] int32: caller index of each sorted particle
+ *   leaf_start  device [8^level + 1] int32: first sorted index of each leaf
+ * Keys follow the oracle's definition bit for bit (periodic wrap
+ * s = floor((x - lo) * fl(1/L)), x_w = x - s L; c = floor((x_w - lo) * 2^level fl(1/L))
+ * clamped to [0, 2^level - 1]; bit b of c_x, c_y, c_z -> key bits 3b, 3b+1, 3b+2;
+ * ties kept in caller order).
+ */
+vm_status vm_debug_tree(vm_ctx *ctx, uint32_t *keys, int32_t *perm, int32_t *leaf_start);
+
+/*
+ * Debug views of the expansions of the last vm_fmm_eval (stream-ordered copies):
+ *   which 0: multipoles, 1: locals, at `level`; raw layout [8^level][3][kp] with
+ *   kp = (p+1)^2 rounded up to a multiple of 4, element type double (FP64
+ *   form) or float (mixed form); *bytes receives the size.  `out` is a device
+ *   buffer of at least that size, or NULL to query the size only.
+ * vm_debug_far: far-field velocity and gradient per particle in sorted order,
+ *   device double [12][n] (u_x, u_y, u_z, then J[3a+b]).
+ */
+vm_status vm_debug_expansions(vm_ctx *ctx, int which, int level, void *out, int64_t *bytes);
+vm_status vm_debug_far(vm_ctx *ctx, double *out);
+
+/*
+ * Host-only views of the interaction structure (no device work).
+ * vm_debug_offsets: the 316 distinct M2L offsets d = source - target (cells),
+ *   sorted by (dz, dy, dx); out int8 [316][3]; returns the count in *count.
+ * vm_debug_list: M2L list of one cell `key` at `level` (periodic 0/1): up to
+ *   189 entries of source key (int32 src[]), offset (int8 d[][3]) and image
+ *   shift (int8 img[][3]) in (dz, dy, dx) order of d; *count receives the length.
+ */
+vm_status vm_debug_offsets(int8_t *out, int *count);
+vm_status vm_debug_list(int level, int periodic, int32_t key, int32_t *src, int8_t *d,
+                        int8_t *img, int *count);
+
+/*
+ * Host-only: the translation operators in the library's real basis, FP64,
+ * row-major C x C with C = (p+1)^2 (no device work).
+ *   kind 0: M2L for offset index `index` (0..315, the vm_debug_offsets order)
+ *   kind 1: M2M for child octant `index` (0..7)
+ *   kind 2: L2L for child octant `index` (0..7)
+ *   kind 3: periodic lattice operator for K = `index` (1..4)
+ * The basis: solid harmonics R_n^m = r^n P_n^m(cos t) e^{i m phi} / (n+m)!
+ * (P with the Condon-Shortley phase) scaled by sqrt((n+m)!(n-m)!); a cell of
+ * width w stores M_n^m = sum_j q_j conj(R_n^m((x_j - c)/w)) and locals with
+ * phi(x) = (1/w) sum_n,m L_n^m R_n^m((x - c)/w); real index n^2 holds m = 0,
+ * n^2 + 2m - 1 and n^2 + 2m the real and imaginary parts of m > 0.
+ */
+vm_status vm_debug_operator(int kind, int p, int index, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VMFMM_H */

@@ -1,0 +1,177 @@
+"""MI355X-native FMM for the regularised Biot-Savart velocity and stretching.
+
+Python face of ``libvmfmm.so`` (see ``include/vmfmm.h``): torch supplies the
+device memory and the stream, every step of the evaluation runs in the
+library's HIP kernels.
+
+    ctx = FMM()                         # device 0, torch's current stream
+    u, dadt, J = ctx.eval(x, alpha, sigma, p=10, level=6, periodic=3,
+                          precision="mixed", want_grad=True)
+
+``x`` and ``alpha`` are float64 CUDA tensors of shape (3, n) (SoA, the
+library's layout; (n, 3) inputs are transposed into a copy).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import _lib
+
+PRECISIONS = {"fp64": 0, "mixed": 1}
+SCHEMES = {"classic": 0, "transpose": 1}
+
+
+def _soa(t, torch):
+    if t.dim() != 2 or 3 not in t.shape:
+        raise ValueError("expected a (3, n) or (n, 3) tensor")
+    if t.shape[0] != 3:
+        t = t.t()
+    if t.dtype != torch.float64:
+        raise TypeError("positions and strengths must be float64")
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    return t.contiguous()
+
+
+class FMM:
+    """One library context (workspace + operator cache) on one device/stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self._lib = _lib.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        st = self._lib.vm_create(ctypes.byref(h), device, ctypes.c_void_p(self._stream_ptr(stream)))
+        if st != _lib.VM_OK:
+            raise _lib.VmError(st, "vm_create failed (no HIP device?)")
+        self._h = h
+
+    def _stream_ptr(self, stream):
+        torch = self._torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return int(s.cuda_stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.vm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != _lib.VM_OK:
+            msg = self._lib.vm_last_error(self._h).decode()
+            raise _lib.VmError(st, msg)
+
+    def eval(self, x, alpha, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0),
+             box_len=2 * math.pi, precision="fp64", scheme="classic", want_grad=False,
+             want_dalpha=True, check_domain=False, stream=None, out=None):
+        """Velocity (3, n), stretching (3, n) or None, gradient (9, n) or None."""
+        torch = self._torch
+        x = _soa(x, torch)
+        alpha = _soa(alpha, torch)
+        n = x.shape[1]
+        if alpha.shape[1] != n:
+            raise ValueError("x and alpha differ in length")
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        if out is None:
+            u = torch.empty((3, n), dtype=torch.float64, device=x.device)
+            da = torch.empty((3, n), dtype=torch.float64, device=x.device) if want_dalpha else None
+            J = torch.empty((9, n), dtype=torch.float64, device=x.device) if want_grad else None
+        else:
+            u, da, J = out
+        opts = _lib.VmOpts((ctypes.c_double * 3)(*box_lo), float(box_len), int(periodic),
+                           PRECISIONS[precision], SCHEMES[scheme], int(bool(check_domain)))
+        st = self._lib.vm_fmm_eval(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(level),
+                                   ctypes.byref(opts), ctypes.c_void_p(u.data_ptr()),
+                                   ctypes.c_void_p(da.data_ptr() if da is not None else 0),
+                                   ctypes.c_void_p(J.data_ptr() if J is not None else 0))
+        self._check(st)
+        return u, da, J
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.vm_set_timing(self._h, int(bool(enable))))
+
+    def timing(self):
+        """{phase: (milliseconds, launches)} of the last timed evaluation."""
+        ms = np.zeros(len(_lib.PHASES), np.float64)
+        cnt = np.zeros(len(_lib.PHASES), np.int32)
+        self._check(self._lib.vm_get_timing(self._h, ctypes.c_void_p(ms.ctypes.data),
+                                            ctypes.c_void_p(cnt.ctypes.data)))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(_lib.PHASES)}
+
+    def debug_tree(self, n, level):
+        torch = self._torch
+        keys = torch.empty(n, dtype=torch.int32, device="cuda")
+        perm = torch.empty(n, dtype=torch.int32, device="cuda")
+        start = torch.empty((1 << (3 * level)) + 1, dtype=torch.int32, device="cuda")
+        self._check(self._lib.vm_debug_tree(self._h, ctypes.c_void_p(keys.data_ptr()),
+                                            ctypes.c_void_p(perm.data_ptr()),
+                                            ctypes.c_void_p(start.data_ptr())))
+        torch.cuda.synchronize()
+        return (keys.cpu().numpy().view(np.uint32).astype(np.int64), perm.cpu().numpy().astype(np.int64),
+                start.cpu().numpy().astype(np.int64))
+
+    def debug_expansions(self, which, level, p, mixed=False):
+        """Multipoles (which=0) or locals (1) at `level`: array (8^level, 3, C)."""
+        torch = self._torch
+        nbytes = ctypes.c_int64()
+        self._check(self._lib.vm_debug_expansions(self._h, which, level, None, ctypes.byref(nbytes)))
+        buf = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        self._check(self._lib.vm_debug_expansions(self._h, which, level, ctypes.c_void_p(buf.data_ptr()),
+                                                  ctypes.byref(nbytes)))
+        torch.cuda.synchronize()
+        C = (p + 1) ** 2
+        kp = (C + 3) // 4 * 4
+        arr = buf.cpu().numpy().view(np.float32 if mixed else np.float64).reshape(-1, 3, kp)
+        return arr[:, :, :C].astype(np.float64)
+
+    def debug_far(self, n):
+        torch = self._torch
+        out = torch.empty((12, n), dtype=torch.float64, device="cuda")
+        self._check(self._lib.vm_debug_far(self._h, ctypes.c_void_p(out.data_ptr())))
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+
+def debug_offsets():
+    lib = _lib.load()
+    out = np.zeros((316, 3), np.int8)
+    cnt = ctypes.c_int()
+    st = lib.vm_debug_offsets(out.ctypes.data, ctypes.byref(cnt))
+    if st != _lib.VM_OK:
+        raise _lib.VmError(st, "vm_debug_offsets")
+    return out[:cnt.value]
+
+
+def debug_list(level, periodic, key):
+    lib = _lib.load()
+    src = np.zeros(189, np.int32)
+    d = np.zeros((189, 3), np.int8)
+    img = np.zeros((189, 3), np.int8)
+    cnt = ctypes.c_int()
+    st = lib.vm_debug_list(int(level), int(periodic), int(key), src.ctypes.data, d.ctypes.data,
+                           img.ctypes.data, ctypes.byref(cnt))
+    if st != _lib.VM_OK:
+        raise _lib.VmError(st, "vm_debug_list")
+    c = cnt.value
+    return src[:c].copy(), d[:c].copy(), img[:c].copy()
+
+
+def debug_operator(kind, p, index):
+    lib = _lib.load()
+    C = (p + 1) ** 2
+    out = np.zeros((C, C), np.float64)
+    st = lib.vm_debug_operator(int(kind), int(p), int(index), out.ctypes.data)
+    if st != _lib.VM_OK:
+        raise _lib.VmError(st, "vm_debug_operator")
+    return out

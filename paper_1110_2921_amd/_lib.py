@@ -1,0 +1,77 @@
+"""ctypes binding of ``libvmfmm.so`` (argument marshalling only).
+
+The library is built in-tree by ``paper_1110_2921_amd.build``; if it is
+missing the import of the product path fails loudly, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvmfmm.so")
+
+PHASES = ("tree", "p2m", "m2m", "lattice", "l2l", "m2l", "l2p", "p2p")
+
+VM_OK, VM_EINVAL, VM_ENOMEM, VM_EDEVICE, VM_EDOMAIN = 0, -1, -2, -3, -4
+STATUS_NAMES = {0: "VM_OK", -1: "VM_EINVAL", -2: "VM_ENOMEM", -3: "VM_EDEVICE", -4: "VM_EDOMAIN"}
+
+# every symbol include/vmfmm.h declares
+EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_eval",
+           "vm_set_timing", "vm_get_timing", "vm_debug_tree", "vm_debug_expansions", "vm_debug_far", "vm_debug_offsets", "vm_debug_list",
+           "vm_debug_operator")
+
+
+class VmOpts(ctypes.Structure):
+    _fields_ = [("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double),
+                ("periodic", ctypes.c_int), ("precision", ctypes.c_int), ("scheme", ctypes.c_int),
+                ("check_domain", ctypes.c_int)]
+
+
+class VmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_LIB = None
+
+
+def load():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1110_2921_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
+    lib.vm_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, vp]
+    lib.vm_create.restype = ctypes.c_int
+    lib.vm_destroy.argtypes = [vp]
+    lib.vm_destroy.restype = None
+    lib.vm_set_stream.argtypes = [vp, vp]
+    lib.vm_set_stream.restype = ctypes.c_int
+    lib.vm_last_error.argtypes = [vp]
+    lib.vm_last_error.restype = ctypes.c_char_p
+    lib.vm_fmm_eval.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(VmOpts), dp, dp, dp]
+    lib.vm_fmm_eval.restype = ctypes.c_int
+    lib.vm_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.vm_set_timing.restype = ctypes.c_int
+    lib.vm_get_timing.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
+    lib.vm_get_timing.restype = ctypes.c_int
+    lib.vm_debug_tree.argtypes = [vp, dp, dp, dp]
+    lib.vm_debug_tree.restype = ctypes.c_int
+    lib.vm_debug_expansions.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.vm_debug_expansions.restype = ctypes.c_int
+    lib.vm_debug_far.argtypes = [vp, vp]
+    lib.vm_debug_far.restype = ctypes.c_int
+    lib.vm_debug_offsets.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+    lib.vm_debug_offsets.restype = ctypes.c_int
+    lib.vm_debug_list.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+    lib.vm_debug_list.restype = ctypes.c_int
+    lib.vm_debug_operator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.vm_debug_operator.restype = ctypes.c_int
+    _LIB = lib
+    return lib

@@ -1,0 +1,86 @@
+// Launchers of the gfx950 kernels (defined in the .hip files) and the
+// device-side layouts they share with the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace vmfmm {
+
+// Sorted particle record: position relative to its leaf centre, strength.
+struct __align__(64) Part64 { double dx, dy, dz, ax, ay, az, pad0, pad1; };
+struct __align__(32) Part32 { float dx, dy, dz, ax, ay, az, pad0, pad1; };
+
+struct TreeGeom {
+    double lo[3];
+    double box_len;
+    double inv_len;   // fl(1 / box_len)
+    double inv_w;     // 2^level * inv_len
+    double w;         // box_len * 2^-level (leaf width)
+    int level;
+    int periodic;
+};
+
+// --- tree build (kernels_tree.hip) ----------------------------------------
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kRadixThreads * kRadixItems;
+
+hipError_t launch_keys(hipStream_t s, int n, const double *x, const TreeGeom &g, int check,
+                       uint32_t *keys, int32_t *idx, int *flag);
+hipError_t launch_radix_pass(hipStream_t s, int n, int shift, int bits, const uint32_t *kin,
+                             const int32_t *vin, uint32_t *kout, int32_t *vout, uint32_t *hist);
+hipError_t launch_ranges(hipStream_t s, int n, int nleaf, const uint32_t *keys, int32_t *start);
+hipError_t launch_permute(hipStream_t s, int n, const double *x, const double *alpha,
+                          const int32_t *perm, const uint32_t *keys, const TreeGeom &g,
+                          Part64 *p64, Part32 *p32);
+hipError_t launch_iota(hipStream_t s, int n, int32_t *idx, uint32_t *keys);
+
+// --- expansions (kernels_fmm.hip) -------------------------------------------
+struct DevTables {
+    // recurrence constants for balanced regular harmonics (index n(n+1)/2 + m)
+    const double *c1_64, *c2_64, *diag_64;
+    const float *c1_32, *c2_32, *diag_32;
+    // L2P sparse table: rows (3 nu + 9 ng) x width
+    const int32_t *l2p_idx;
+    const double *l2p_w64;
+    const float *l2p_w32;
+    int l2p_width, nu, ng;
+};
+
+template <typename T>
+hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t *start,
+                      int p, int kp, double inv_w, const DevTables &tab, T *m_out);
+
+template <typename T>
+hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start,
+                      int p, int kp, double inv_w, double w, const DevTables &tab,
+                      const T *l_leaf, double *far);
+
+// Generic translation GEMM on MFMA: mode 0 = M2L, 1 = L2L, 2 = M2M.
+template <typename T>
+hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp,
+                            const T *ops, const int16_t *oct_lists, const int8_t *offsets,
+                            const T *src, T *dst, int accumulate);
+
+template <typename T>
+hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, const T *m0, T *l0);
+
+// --- near field (kernels_p2p.hip) ---------------------------------------------
+struct P2PArgs {
+    int n, nleaf, level, periodic, scheme, have_far;
+    double w, sigma;
+    const int32_t *start;
+    const int32_t *perm;
+    const double *alpha;  // caller order [3][n] (stretching contraction in FP64)
+    const double *far;    // sorted order: u[3][n], then J[9][n]
+    double *u, *dalpha, *grad;   // caller order
+};
+hipError_t launch_p2p64(hipStream_t s, const P2PArgs &a, const Part64 *parts);
+hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts);
+
+// rows of the translation-operator GEMM tile
+inline int pad16(int c) { return (c + 15) / 16 * 16; }
+inline int pad4(int c) { return (c + 3) / 4 * 4; }
+
+}  // namespace vmfmm

@@ -1,0 +1,454 @@
+// Expansion kernels: P2M and L2P (one workgroup per leaf), the translation
+// GEMMs (M2M, M2L, L2L) on the MFMA units, and the periodic lattice operator.
+//
+// Coefficient layout: cell-major, [cell][component][kp] with kp = (p+1)^2
+// rounded up to a multiple of 4 (the MFMA K step); entries C..kp-1 are zero.
+#include "kernels.h"
+
+namespace vmfmm {
+
+namespace {
+
+template <typename T> struct Tab;
+template <> struct Tab<double> {
+    static __device__ const double *c1(const DevTables &t) { return t.c1_64; }
+    static __device__ const double *c2(const DevTables &t) { return t.c2_64; }
+    static __device__ const double *dg(const DevTables &t) { return t.diag_64; }
+    static __device__ const double *w(const DevTables &t) { return t.l2p_w64; }
+};
+template <> struct Tab<float> {
+    static __device__ const float *c1(const DevTables &t) { return t.c1_32; }
+    static __device__ const float *c2(const DevTables &t) { return t.c2_32; }
+    static __device__ const float *dg(const DevTables &t) { return t.diag_32; }
+    static __device__ const float *w(const DevTables &t) { return t.l2p_w32; }
+};
+
+template <typename T> struct PartOf;
+template <> struct PartOf<double> { using type = Part64; };
+template <> struct PartOf<float> { using type = Part32; };
+
+// Visits c(X) = [Rb_n^0, Re Rb_n^m, -Im Rb_n^m] for all n <= deg, m <= n, in
+// the order m outer, n inner: f(n, m, re, negim).
+template <typename T, typename F>
+__device__ __forceinline__ void for_each_harmonic(T X, T Y, T Z, int deg, const T *__restrict__ c1,
+                                                  const T *__restrict__ c2, const T *__restrict__ dg, F &&f) {
+    const T r2 = X * X + Y * Y + Z * Z;
+    T dre = T(1), dim = T(0);
+    for (int m = 0; m <= deg; ++m) {
+        if (m > 0) {
+            // Rb_m^m = -(X + iY) diag[m] Rb_{m-1}^{m-1}
+            const T s = -dg[m];
+            const T nre = s * (X * dre - Y * dim);
+            const T nim = s * (X * dim + Y * dre);
+            dre = nre;
+            dim = nim;
+        }
+        T are = dre, aim = dim, bre = T(0), bim = T(0);
+        f(m, m, are, -aim);
+        for (int n = m + 1; n <= deg; ++n) {
+            const int e = n * (n + 1) / 2 + m;
+            const T k1 = c1[e] * Z, k2 = c2[e] * r2;
+            const T cre = k1 * are - k2 * bre;
+            const T cim = k1 * aim - k2 * bim;
+            bre = are; bim = aim;
+            are = cre; aim = cim;
+            f(n, m, are, -aim);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ int slot_re(int n, int m) { return m == 0 ? n * n : n * n + 2 * m - 1; }
+
+// ---------------------------------------------------------------- P2M ----
+// Mb[leaf][c][s] = sum_j alpha_j[c] c_s((x_j - centre) / w).
+template <typename T>
+__global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__restrict__ parts,
+                                            const int32_t *__restrict__ start, int p, int kp, T inv_w,
+                                            DevTables tab, int chunk, T *__restrict__ mout) {
+    extern __shared__ unsigned char smem_raw[];
+    T *cv = reinterpret_cast<T *>(smem_raw);          // [chunk][C]
+    T *al = cv + size_t(chunk) * (p + 1) * (p + 1);    // [chunk][3]
+    const int C = (p + 1) * (p + 1);
+    const int leaf = blockIdx.x, lane = threadIdx.x;
+    const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
+    constexpr int MAXS = 7;   // ceil(441 / 64)
+    T acc[3][MAXS];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int t = 0; t < MAXS; ++t) acc[c][t] = T(0);
+    const T *c1 = Tab<T>::c1(tab), *c2 = Tab<T>::c2(tab), *dg = Tab<T>::dg(tab);
+    for (int base = 0; base < cnt; base += chunk) {
+        const int nj = min(chunk, cnt - base);
+        if (lane < nj) {
+            const auto q = parts[s0 + base + lane];
+            T *row = cv + size_t(lane) * C;
+            for_each_harmonic<T>(T(q.dx) * inv_w, T(q.dy) * inv_w, T(q.dz) * inv_w, p, c1, c2, dg,
+                                 [&](int n, int m, T re, T nim) {
+                                     if (m == 0) {
+                                         row[n * n] = re;
+                                     } else {
+                                         row[n * n + 2 * m - 1] = re;
+                                         row[n * n + 2 * m] = nim;
+                                     }
+                                 });
+            al[lane * 3 + 0] = q.ax;
+            al[lane * 3 + 1] = q.ay;
+            al[lane * 3 + 2] = q.az;
+        }
+        __syncthreads();
+        for (int j = 0; j < nj; ++j) {
+            const T a0 = al[j * 3 + 0], a1 = al[j * 3 + 1], a2 = al[j * 3 + 2];
+            const T *row = cv + size_t(j) * C;
+#pragma unroll
+            for (int t = 0; t < MAXS; ++t) {
+                const int s = lane + 64 * t;
+                if (s < C) {
+                    const T v = row[s];
+                    acc[0][t] += a0 * v;
+                    acc[1][t] += a1 * v;
+                    acc[2][t] += a2 * v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    T *dst = mout + size_t(leaf) * 3 * kp;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int t = 0; t < MAXS; ++t) {
+            const int s = lane + 64 * t;
+            if (s < kp) dst[c * kp + s] = s < C ? acc[c][t] : T(0);
+        }
+}
+
+// ---------------------------------------------------------------- L2P ----
+// Per leaf: velocity / gradient expansions from the sparse table, then per
+// particle u_b = sU sum U_b c(X), J_ab = sJ sum G_ab c(X), written in sorted
+// order as far[0..2][n] (u) and far[3..11][n] (J, index 3a+b).
+template <typename T>
+__global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__restrict__ parts,
+                                            const int32_t *__restrict__ start, int n, int p, int kp,
+                                            T inv_w, double su, double sj, DevTables tab,
+                                            const T *__restrict__ lleaf, double *__restrict__ far) {
+    extern __shared__ unsigned char smem_raw[];
+    const int C = (p + 1) * (p + 1);
+    const int nu = tab.nu, ng = tab.ng, width = tab.l2p_width;
+    T *lam = reinterpret_cast<T *>(smem_raw);   // [3 C]
+    T *coef = lam + 3 * C;                      // [nu][12]: U_x U_y U_z G_00 .. G_22
+    const int leaf = blockIdx.x, lane = threadIdx.x;
+    const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
+    if (cnt == 0) return;
+    const T *src = lleaf + size_t(leaf) * 3 * kp;
+    for (int i = lane; i < 3 * C; i += 64) lam[i] = src[(i / C) * kp + (i % C)];
+    __syncthreads();
+    const T *tw = Tab<T>::w(tab);
+    const int rows = 3 * nu + 9 * ng;
+    for (int r = lane; r < 12 * nu; r += 64) coef[r] = T(0);
+    __syncthreads();
+    for (int r = lane; r < rows; r += 64) {
+        T s = T(0);
+        for (int e = 0; e < width; ++e) s += tw[size_t(r) * width + e] * lam[tab.l2p_idx[size_t(r) * width + e]];
+        int slot, comp;
+        if (r < 3 * nu) {
+            comp = r / nu;
+            slot = r % nu;
+        } else {
+            comp = 3 + (r - 3 * nu) / ng;
+            slot = (r - 3 * nu) % ng;
+        }
+        coef[slot * 12 + comp] = s;
+    }
+    __syncthreads();
+    const T *c1 = Tab<T>::c1(tab), *c2 = Tab<T>::c2(tab), *dg = Tab<T>::dg(tab);
+    for (int base = 0; base < cnt; base += 64) {
+        const int i = base + lane;
+        if (i >= cnt) break;
+        const auto q = parts[s0 + i];
+        T u[3] = {T(0), T(0), T(0)};
+        T J[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) J[k] = T(0);
+        for_each_harmonic<T>(T(q.dx) * inv_w, T(q.dy) * inv_w, T(q.dz) * inv_w, p - 1, c1, c2, dg,
+                             [&](int nn, int m, T re, T nim) {
+                                 const int sr = m == 0 ? nn * nn : nn * nn + 2 * m - 1;
+                                 const T *cr = coef + sr * 12;
+#pragma unroll
+                                 for (int b = 0; b < 3; ++b) u[b] += cr[b] * re;
+#pragma unroll
+                                 for (int k = 0; k < 9; ++k) J[k] += cr[3 + k] * re;
+                                 if (m > 0) {
+                                     const T *ci = cr + 12;
+#pragma unroll
+                                     for (int b = 0; b < 3; ++b) u[b] += ci[b] * nim;
+#pragma unroll
+                                     for (int k = 0; k < 9; ++k) J[k] += ci[3 + k] * nim;
+                                 }
+                             });
+        const size_t gi = size_t(s0) + i;
+        for (int b = 0; b < 3; ++b) far[size_t(b) * n + gi] = double(u[b]) * su;
+        for (int kk = 0; kk < 9; ++kk) far[size_t(3 + kk) * n + gi] = double(J[kk]) * sj;
+    }
+}
+
+// ----------------------------------------------------------- translate ----
+// One workgroup (4 waves) owns TT target cells that share one pair list.
+// For each pair (operator op, sources of the TT targets) the sources'
+// coefficients are staged in LDS and every wave multiplies its row blocks
+// of the operator (pre-swizzled into MFMA A fragments) against them:
+//   out[tile] (Cp x 3TT) += Op (Cp x kp) * Src (kp x 3TT).
+// MFMA 16x16x4: A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16);
+// accumulator register r of lane l holds column l%16 and row (l/16) + 4r for
+// FP64, 4(l/16) + r for FP32 (both checked on gfx950).
+constexpr int TT = 16;
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+__device__ __forceinline__ uint32_t morton3(int cx, int cy, int cz, int level) {
+    uint32_t k = 0;
+    for (int b = 0; b < level; ++b) {
+        k |= uint32_t((cx >> b) & 1) << (3 * b);
+        k |= uint32_t((cy >> b) & 1) << (3 * b + 1);
+        k |= uint32_t((cz >> b) & 1) << (3 * b + 2);
+    }
+    return k;
+}
+
+__device__ __forceinline__ int demorton1(uint32_t k, int d, int level) {
+    int c = 0;
+    for (int b = 0; b < level; ++b) c |= int((k >> (3 * b + d)) & 1u) << b;
+    return c;
+}
+
+template <typename T, int NRBW, int mode>
+__global__ void __launch_bounds__(256) k_translate(int level, int periodic, int C, int kp,
+                                                   int nrb, const T *__restrict__ ops,
+                                                   const int16_t *__restrict__ oct_lists,
+                                                   const int8_t *__restrict__ offsets,
+                                                   const T *__restrict__ src, T *__restrict__ dst,
+                                                   int accumulate) {
+    using V = typename Mfma<T>::v4;
+    extern __shared__ unsigned char smem_raw[];
+    const int ks_stride = kp + 1;                       // odd row stride: conflict-free B reads
+    T *bs = reinterpret_cast<T *>(smem_raw);             // [TT * 3][ks_stride]
+    __shared__ int32_t tkey[TT];
+    __shared__ int32_t skey[TT];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nks = kp / 4;
+
+    // target cells of this tile
+    int octant = 0, tile = blockIdx.x, npair = 1;
+    int64_t ncell_t;
+    if (mode == 2) {                  // M2M: targets are the parents at `level`
+        ncell_t = int64_t(1) << (3 * level);
+        npair = 8;
+    } else {                          // M2L / L2L: targets at `level`, grouped by octant
+        octant = blockIdx.x & 7;
+        tile = blockIdx.x >> 3;
+        ncell_t = int64_t(1) << (3 * (level - 1));   // parents at level - 1
+        npair = mode == 0 ? 189 : 1;
+    }
+    if (tid < TT) {
+        const int64_t slot = int64_t(tile) * TT + tid;
+        int32_t k = -1;
+        if (slot < ncell_t) k = mode == 2 ? int32_t(slot) : int32_t((slot << 3) | octant);
+        tkey[tid] = k;
+    }
+    V acc[NRBW][3];
+#pragma unroll
+    for (int i = 0; i < NRBW; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[i][c] = V{T(0), T(0), T(0), T(0)};
+    __syncthreads();
+
+    const int side = 1 << level;
+    for (int pr = 0; pr < npair; ++pr) {
+        int op;
+        if (mode == 0) op = oct_lists[octant * 189 + pr];
+        else if (mode == 1) op = octant;
+        else op = pr;
+        if (tid < TT) {
+            const int32_t t = tkey[tid];
+            int32_t sk = -1;
+            if (t >= 0) {
+                if (mode == 0) {
+                    int c[3];
+                    bool ok = true;
+                    for (int d = 0; d < 3; ++d) {
+                        c[d] = demorton1(uint32_t(t), d, level) + offsets[op * 3 + d];
+                        if (periodic) c[d] = (c[d] % side + side) % side;
+                        else if (c[d] < 0 || c[d] >= side) ok = false;
+                    }
+                    if (ok) sk = int32_t(morton3(c[0], c[1], c[2], level));
+                } else if (mode == 1) {
+                    sk = t >> 3;
+                } else {
+                    sk = (t << 3) | pr;
+                }
+            }
+            skey[tid] = sk;
+        }
+        __syncthreads();
+        // stage the sources: TT cells x 3 components x kp, each cell contiguous
+        const int per_cell = 3 * kp;
+        for (int e = tid; e < TT * per_cell; e += 256) {
+            const int t = e / per_cell, r = e - t * per_cell;
+            const int c = r / kp, k = r - c * kp;
+            const int32_t sk = skey[t];
+            bs[(t * 3 + c) * ks_stride + k] = sk >= 0 ? src[size_t(sk) * per_cell + r] : T(0);
+        }
+        __syncthreads();
+        const T *opb = ops + size_t(op) * nrb * nks * 64;
+        for (int ks = 0; ks < nks; ++ks) {
+            T bfrag[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bfrag[c] = bs[((lane & 15) * 3 + c) * ks_stride + ks * 4 + (lane >> 4)];
+#pragma unroll
+            for (int i = 0; i < NRBW; ++i) {
+                const int rb = wave + 4 * i;
+                if (rb < nrb) {
+                    const T a = opb[(size_t(rb) * nks + ks) * 64 + lane];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[i][c] = Mfma<T>::op(a, bfrag[c], acc[i][c]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // write back: lane holds rows rb*16 + Mfma::row(lane, r) of target column lane%16
+    const int32_t t = tkey[lane & 15];
+    if (t < 0) return;
+    T *out = dst + size_t(t) * 3 * kp;
+#pragma unroll
+    for (int i = 0; i < NRBW; ++i) {
+        const int rb = wave + 4 * i;
+        if (rb >= nrb) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rb * 16 + Mfma<T>::row(lane, r);
+                if (row < C) {
+                    const T v = acc[i][c][r];
+                    T *o = out + c * kp + row;
+                    *o = accumulate ? *o + v : v;
+                }
+            }
+    }
+}
+
+// ------------------------------------------------------------- lattice ----
+template <typename T>
+__global__ void __launch_bounds__(256) k_lattice(int C, int kp, const double *__restrict__ tlat,
+                                                 const T *__restrict__ m0, T *__restrict__ l0) {
+    __shared__ double m[3 * 441];
+    for (int i = threadIdx.x; i < 3 * C; i += 256) m[i] = double(m0[(i / C) * kp + (i % C)]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * C; i += 256) {
+        const int c = i / C, row = i % C;
+        double s = 0.0;
+        for (int k = 0; k < C; ++k) s += tlat[size_t(row) * C + k] * m[c * C + k];
+        l0[c * kp + row] = T(s);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t *start, int p, int kp,
+                      double inv_w, const DevTables &tab, T *m_out) {
+    const int C = (p + 1) * (p + 1);
+    int chunk = int(49152 / (sizeof(T) * (C + 3)));
+    if (chunk > 64) chunk = 64;
+    if (chunk < 1) chunk = 1;
+    const size_t smem = sizeof(T) * size_t(chunk) * (C + 3);
+    hipLaunchKernelGGL(k_p2m<T>, dim3(nleaf), dim3(64), smem, s,
+                       (const typename PartOf<T>::type *)parts, start, p, kp, T(inv_w), tab, chunk, m_out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start, int p,
+                      int kp, double inv_w, double w, const DevTables &tab, const T *l_leaf, double *far) {
+    const int C = (p + 1) * (p + 1);
+    const size_t smem = sizeof(T) * (3 * size_t(C) + 12 * size_t(tab.nu) + 12);
+    const double four_pi = 12.566370614359172953850573533118;
+    hipLaunchKernelGGL(k_l2p<T>, dim3(nleaf), dim3(64), smem, s, (const typename PartOf<T>::type *)parts,
+                       start, n, p, kp, T(inv_w), 1.0 / (four_pi * w * w), 1.0 / (four_pi * w * w * w), tab,
+                       l_leaf, far);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp, const T *ops,
+                            const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
+                            int accumulate) {
+    const int C = (p + 1) * (p + 1);
+    const int nrb = pad16(C) / 16;
+    const int nrbw = (nrb + 3) / 4;
+    int64_t ncell;
+    int grid;
+    if (mode == 2) {
+        ncell = int64_t(1) << (3 * level);
+        grid = int((ncell + TT - 1) / TT);
+    } else {
+        ncell = int64_t(1) << (3 * (level - 1));
+        grid = int((ncell + TT - 1) / TT) * 8;
+    }
+    const size_t smem = sizeof(T) * size_t(TT) * 3 * (kp + 1);
+#define VM_TR(NR)                                                                                          \
+    case NR:                                                                                               \
+        if (mode == 0)                                                                                     \
+            hipLaunchKernelGGL((k_translate<T, NR, 0>), dim3(grid), dim3(256), smem, s, level, periodic, C, \
+                               kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);                    \
+        else if (mode == 1)                                                                                \
+            hipLaunchKernelGGL((k_translate<T, NR, 1>), dim3(grid), dim3(256), smem, s, level, periodic, C, \
+                               kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);                    \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_translate<T, NR, 2>), dim3(grid), dim3(256), smem, s, level, periodic, C, \
+                               kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);                    \
+        break;
+    switch (nrbw) {
+        VM_TR(1) VM_TR(2) VM_TR(3) VM_TR(4) VM_TR(5) VM_TR(6) VM_TR(7)
+        default: return hipErrorInvalidValue;
+    }
+#undef VM_TR
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, const T *m0, T *l0) {
+    const int C = (p + 1) * (p + 1);
+    hipLaunchKernelGGL(k_lattice<T>, dim3(1), dim3(256), 0, s, C, kp, tlat, m0, l0);
+    return hipGetLastError();
+}
+
+#define VM_INST(T)                                                                                          \
+    template hipError_t launch_p2m<T>(hipStream_t, int, const void *, const int32_t *, int, int, double,    \
+                                      const DevTables &, T *);                                              \
+    template hipError_t launch_l2p<T>(hipStream_t, int, int, const void *, const int32_t *, int, int,       \
+                                      double, double, const DevTables &, const T *, double *);              \
+    template hipError_t launch_translate<T>(hipStream_t, int, int, int, int, int, const T *,                \
+                                            const int16_t *, const int8_t *, const T *, T *, int);          \
+    template hipError_t launch_lattice<T>(hipStream_t, int, int, const double *, const T *, T *);
+VM_INST(double)
+VM_INST(float)
+#undef VM_INST
+
+}  // namespace vmfmm

@@ -1,0 +1,287 @@
+// Near field (P2P): exact regularised Biot-Savart velocity and gradient over
+// the 27 adjacent leaves (paper Sec. 3.1, last paragraph; kernel eqs. 5-8).
+//
+// One wave per target leaf, one target particle per lane.  Source particles
+// are read at wave-uniform addresses, so they arrive through scalar loads and
+// sit in SGPRs: every lane of the wave works on the same source at the same
+// time with no LDS traffic.  The pair kernel, with r = x_i - x_j and rho = r/sigma:
+//   q      = g(rho) / r^3,  g = erf(rho/sqrt2) - sqrt(2/pi) rho exp(-rho^2/2)
+//   q'/r   = (sqrt(2/pi) sigma^-3 exp(-rho^2/2) - 3 q) / r^2
+//   u     += q alpha_j x r
+//   J[a][b] += (q'/r) r_a (alpha_j x r)_b + q eps_abc alpha_j,c
+// For small rho both q and q'/r are even power series in rho (g is the
+// integral of the Gaussian mass, g' = sqrt(2/pi) rho^2 exp(-rho^2/2)).
+// The epilogue adds the far field computed by L2P, contracts the gradient
+// into the stretching term and scatters to the caller's particle order.
+#include "kernels.h"
+
+namespace vmfmm {
+
+namespace {
+
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+constexpr double kSqrt2OverPi = 0.79788456080286535587989211986876373;
+
+// a_n = (-1/2)^n / (n! (2n+3)): g / rho^3 = sqrt(2/pi) sum a_n rho^{2n}
+template <typename T>
+__device__ __forceinline__ void small_rho(T t, T &h0, T &h1) {
+    // Horner in t = rho^2; h1 = d(h0)/dt * 2 = sum 2 n a_n t^{n-1}
+    constexpr double a[14] = {
+        1.0 / 3.0,
+        -0.5 / 5.0,
+        0.25 / (2.0 * 7.0),
+        -0.125 / (6.0 * 9.0),
+        0.0625 / (24.0 * 11.0),
+        -0.03125 / (120.0 * 13.0),
+        0.015625 / (720.0 * 15.0),
+        -0.0078125 / (5040.0 * 17.0),
+        0.00390625 / (40320.0 * 19.0),
+        -0.001953125 / (362880.0 * 21.0),
+        0.0009765625 / (3628800.0 * 23.0),
+        -0.00048828125 / (39916800.0 * 25.0),
+        0.000244140625 / (479001600.0 * 27.0),
+        -0.0001220703125 / (6227020800.0 * 29.0),
+    };
+    T s0 = T(a[13]), s1 = T(2.0 * 13.0 * a[13]);
+#pragma unroll
+    for (int k = 12; k >= 1; --k) {
+        s0 = s0 * t + T(a[k]);
+        s1 = s1 * t + T(2.0 * k * a[k]);
+    }
+    h0 = s0 * t + T(a[0]);
+    h1 = s1;
+}
+
+struct Consts64 {
+    double inv_sigma, inv_s2, is3, is5, thr2;
+};
+
+__device__ __forceinline__ void pair64(double r2, const Consts64 &k, double &q, double &dq) {
+    if (r2 >= k.thr2) {
+        const double rinv = 1.0 / sqrt(r2);
+        const double r = r2 * rinv;
+        const double rho = r * k.inv_sigma;
+        const double e = exp(-0.5 * rho * rho);
+        const double g = erf(rho * 0.70710678118654752440084436210484903) - kSqrt2OverPi * rho * e;
+        const double ir2 = rinv * rinv;
+        q = g * ir2 * rinv;
+        dq = (kSqrt2OverPi * k.is3 * e - 3.0 * q) * ir2;
+    } else {
+        double h0, h1;
+        small_rho<double>(r2 * k.inv_s2, h0, h1);
+        q = kSqrt2OverPi * k.is3 * h0;
+        dq = kSqrt2OverPi * k.is5 * h1;
+    }
+}
+
+struct Consts32 {
+    float inv_sigma, inv_s2, is3, is5, thr2, w;
+};
+
+// FP32 pair kernel.  For rho < 2 the series (13 terms) is used; beyond, the
+// erf of Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7), whose exp(-s^2)
+// factor is shared with the Gaussian term:
+//   1 - g = exp(-rho^2/2) (P(t) + sqrt(2/pi) rho),  t = 1 / (1 + p rho/sqrt2).
+__device__ __forceinline__ void pair32(float r2, const Consts32 &k, float &q, float &dq) {
+    if (r2 >= k.thr2) {
+        const float rinv = __frsqrt_rn(r2);
+        const float r = r2 * rinv;
+        const float rho = r * k.inv_sigma;
+        const float e = __expf(-0.5f * rho * rho);
+        const float t = __frcp_rn(1.0f + 0.3275911f * 0.70710678f * rho);
+        const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+        const float g = 1.0f - e * (poly + float(kSqrt2OverPi) * rho);
+        const float ir2 = rinv * rinv;
+        q = g * ir2 * rinv;
+        dq = (float(kSqrt2OverPi) * k.is3 * e - 3.0f * q) * ir2;
+    } else {
+        float h0, h1;
+        small_rho<float>(r2 * k.inv_s2, h0, h1);
+        q = float(kSqrt2OverPi) * k.is3 * h0;
+        dq = float(kSqrt2OverPi) * k.is5 * h1;
+    }
+}
+
+__device__ __forceinline__ int demorton(int k, int d, int level) {
+    int c = 0;
+    for (int b = 0; b < level; ++b) c |= ((k >> (3 * b + d)) & 1) << b;
+    return c;
+}
+
+__device__ __forceinline__ int morton(int cx, int cy, int cz, int level) {
+    int k = 0;
+    for (int b = 0; b < level; ++b)
+        k |= (((cx >> b) & 1) << (3 * b)) | (((cy >> b) & 1) << (3 * b + 1)) | (((cz >> b) & 1) << (3 * b + 2));
+    return k;
+}
+
+// Writes u, dalpha/dt and J for sorted particle gi (caller index oi).
+__device__ __forceinline__ void epilogue(const P2PArgs &a, int gi, const double un[3], const double Jr[9],
+                                         const double S[3]) {
+    const int n = a.n;
+    const int oi = a.perm[gi];
+    double u[3], J[9];
+    // near gradient = rank-one part + antisymmetric part eps_abc S_c
+    J[0] = Jr[0];          J[1] = Jr[1] + S[2];   J[2] = Jr[2] - S[1];
+    J[3] = Jr[3] - S[2];   J[4] = Jr[4];          J[5] = Jr[5] + S[0];
+    J[6] = Jr[6] + S[1];   J[7] = Jr[7] - S[0];   J[8] = Jr[8];
+    for (int b = 0; b < 3; ++b) u[b] = un[b] * kInv4Pi;
+    for (int k = 0; k < 9; ++k) J[k] *= kInv4Pi;
+    if (a.have_far) {
+        for (int b = 0; b < 3; ++b) u[b] += a.far[size_t(b) * n + gi];
+        for (int k = 0; k < 9; ++k) J[k] += a.far[size_t(3 + k) * n + gi];
+    }
+    for (int b = 0; b < 3; ++b) a.u[size_t(b) * n + oi] = u[b];
+    if (a.grad)
+        for (int k = 0; k < 9; ++k) a.grad[size_t(k) * n + oi] = J[k];
+    if (a.dalpha) {
+        const double al[3] = {a.alpha[oi], a.alpha[size_t(n) + oi], a.alpha[2 * size_t(n) + oi]};
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            if (a.scheme == 0)
+                for (int c = 0; c < 3; ++c) s += al[c] * J[3 * c + b];
+            else
+                for (int c = 0; c < 3; ++c) s += J[3 * b + c] * al[c];
+            a.dalpha[size_t(b) * n + oi] = s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) k_p2p64(P2PArgs a, const Part64 *__restrict__ parts) {
+    const int leaf = blockIdx.x, lane = threadIdx.x;
+    const int s0 = a.start[leaf], cnt = a.start[leaf + 1] - s0;
+    if (cnt == 0) return;
+    const int side = 1 << a.level;
+    const int cx = demorton(leaf, 0, a.level), cy = demorton(leaf, 1, a.level), cz = demorton(leaf, 2, a.level);
+    Consts64 k;
+    k.inv_sigma = 1.0 / a.sigma;
+    k.inv_s2 = k.inv_sigma * k.inv_sigma;
+    k.is3 = k.inv_s2 * k.inv_sigma;
+    k.is5 = k.is3 * k.inv_s2;
+    k.thr2 = 0.0625 * a.sigma * a.sigma;
+    for (int base = 0; base < cnt; base += 64) {
+        const int i = base + lane;
+        const bool valid = i < cnt;
+        const Part64 me = parts[s0 + (valid ? i : cnt - 1)];
+        double u[3] = {0, 0, 0}, Jr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
+        for (int nb = 0; nb < 27; ++nb) {
+            const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
+            int nx = cx + dx, ny = cy + dy, nz = cz + dz;
+            if (a.periodic) {
+                nx = (nx + side) % side;
+                ny = (ny + side) % side;
+                nz = (nz + side) % side;
+            } else if (nx < 0 || ny < 0 || nz < 0 || nx >= side || ny >= side || nz >= side) {
+                continue;
+            }
+            const int nk = morton(nx, ny, nz, a.level);
+            const int js = a.start[nk], je = a.start[nk + 1];
+            // x_i - x_j = (delta_i - d w) - delta_j, d = source - target cell offset
+            const double tx = me.dx - dx * a.w, ty = me.dy - dy * a.w, tz = me.dz - dz * a.w;
+            for (int j = js; j < je; ++j) {
+                const Part64 s = parts[j];
+                const double rx = tx - s.dx, ry = ty - s.dy, rz = tz - s.dz;
+                const double r2 = rx * rx + ry * ry + rz * rz;
+                double q, dq;
+                pair64(r2, k, q, dq);
+                const double c0 = s.ay * rz - s.az * ry;
+                const double c1 = s.az * rx - s.ax * rz;
+                const double c2 = s.ax * ry - s.ay * rx;
+                u[0] += q * c0;
+                u[1] += q * c1;
+                u[2] += q * c2;
+                S[0] += q * s.ax;
+                S[1] += q * s.ay;
+                S[2] += q * s.az;
+                const double t0 = dq * c0, t1 = dq * c1, t2 = dq * c2;
+                Jr[0] += rx * t0; Jr[1] += rx * t1; Jr[2] += rx * t2;
+                Jr[3] += ry * t0; Jr[4] += ry * t1; Jr[5] += ry * t2;
+                Jr[6] += rz * t0; Jr[7] += rz * t1; Jr[8] += rz * t2;
+            }
+        }
+        if (valid) epilogue(a, s0 + i, u, Jr, S);
+    }
+}
+
+// Mixed precision: FP32 pair arithmetic, Kahan-compensated velocity sums.
+__global__ void __launch_bounds__(64) k_p2p32(P2PArgs a, const Part32 *__restrict__ parts) {
+    const int leaf = blockIdx.x, lane = threadIdx.x;
+    const int s0 = a.start[leaf], cnt = a.start[leaf + 1] - s0;
+    if (cnt == 0) return;
+    const int side = 1 << a.level;
+    const int cx = demorton(leaf, 0, a.level), cy = demorton(leaf, 1, a.level), cz = demorton(leaf, 2, a.level);
+    Consts32 k;
+    const double inv_sigma = 1.0 / a.sigma;
+    k.inv_sigma = float(inv_sigma);
+    k.inv_s2 = float(inv_sigma * inv_sigma);
+    k.is3 = float(inv_sigma * inv_sigma * inv_sigma);
+    k.is5 = float(inv_sigma * inv_sigma * inv_sigma * inv_sigma * inv_sigma);
+    k.thr2 = float(4.0 * a.sigma * a.sigma);
+    const float w = float(a.w);
+    for (int base = 0; base < cnt; base += 64) {
+        const int i = base + lane;
+        const bool valid = i < cnt;
+        const Part32 me = parts[s0 + (valid ? i : cnt - 1)];
+        float us[3] = {0, 0, 0}, uc[3] = {0, 0, 0};
+        float Jr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
+        for (int nb = 0; nb < 27; ++nb) {
+            const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
+            int nx = cx + dx, ny = cy + dy, nz = cz + dz;
+            if (a.periodic) {
+                nx = (nx + side) % side;
+                ny = (ny + side) % side;
+                nz = (nz + side) % side;
+            } else if (nx < 0 || ny < 0 || nz < 0 || nx >= side || ny >= side || nz >= side) {
+                continue;
+            }
+            const int nk = morton(nx, ny, nz, a.level);
+            const int js = a.start[nk], je = a.start[nk + 1];
+            const float tx = me.dx - float(dx) * w, ty = me.dy - float(dy) * w, tz = me.dz - float(dz) * w;
+            for (int j = js; j < je; ++j) {
+                const Part32 s = parts[j];
+                const float rx = tx - s.dx, ry = ty - s.dy, rz = tz - s.dz;
+                const float r2 = rx * rx + ry * ry + rz * rz;
+                float q, dq;
+                pair32(r2, k, q, dq);
+                const float c[3] = {s.ay * rz - s.az * ry, s.az * rx - s.ax * rz, s.ax * ry - s.ay * rx};
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const float y = q * c[b] - uc[b];
+                    const float t = us[b] + y;
+                    uc[b] = (t - us[b]) - y;
+                    us[b] = t;
+                }
+                S[0] += q * s.ax;
+                S[1] += q * s.ay;
+                S[2] += q * s.az;
+                const float t0 = dq * c[0], t1 = dq * c[1], t2 = dq * c[2];
+                Jr[0] += rx * t0; Jr[1] += rx * t1; Jr[2] += rx * t2;
+                Jr[3] += ry * t0; Jr[4] += ry * t1; Jr[5] += ry * t2;
+                Jr[6] += rz * t0; Jr[7] += rz * t1; Jr[8] += rz * t2;
+            }
+        }
+        if (valid) {
+            double ud[3], Jd[9], Sd[3];
+            for (int b = 0; b < 3; ++b) {
+                ud[b] = double(us[b]) - double(uc[b]);
+                Sd[b] = double(S[b]);
+            }
+            for (int kk = 0; kk < 9; ++kk) Jd[kk] = double(Jr[kk]);
+            epilogue(a, s0 + i, ud, Jd, Sd);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_p2p64(hipStream_t s, const P2PArgs &a, const Part64 *parts) {
+    hipLaunchKernelGGL(k_p2p64, dim3(a.nleaf), dim3(64), 0, s, a, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts) {
+    hipLaunchKernelGGL(k_p2p32, dim3(a.nleaf), dim3(64), 0, s, a, parts);
+    return hipGetLastError();
+}
+
+}  // namespace vmfmm

@@ -1,0 +1,609 @@
+// Host driver of the C ABI declared in include/vmfmm.h: argument checks,
+// workspace and operator caches, and the launch sequence of one evaluation
+// (tree -> P2M -> M2M -> lattice -> L2L/M2L per level -> L2P -> P2P).
+#include "../../include/vmfmm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kernels.h"
+#include "operators.h"
+
+using namespace vmfmm;
+
+namespace {
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    // grows (never shrinks); new memory is zero-filled when `zero`
+    hipError_t reserve(size_t want, bool zero = false) {
+        if (want <= bytes && ptr) return hipSuccess;
+        release();
+        if (want == 0) want = 256;
+        hipError_t e = hipMalloc(&ptr, want);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            return e;
+        }
+        bytes = want;
+        if (zero) e = hipMemset(ptr, 0, want);
+        return e;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+template <typename T>
+hipError_t upload(DevBuf &b, const std::vector<T> &v) {
+    hipError_t e = b.reserve(v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Operator matrices swizzled into MFMA A fragments: [op][rb][ks][64],
+// element (rb*16 + l%16, ks*4 + l/16) of the zero-padded Cp x kp matrix.
+template <typename T>
+void swizzle(const std::vector<double> &m, int C, std::vector<T> &out, size_t base) {
+    const int cp = pad16(C), kp = pad4(C), nrb = cp / 16, nks = kp / 4;
+    for (int rb = 0; rb < nrb; ++rb)
+        for (int ks = 0; ks < nks; ++ks)
+            for (int l = 0; l < 64; ++l) {
+                const int row = rb * 16 + (l & 15), col = ks * 4 + (l >> 4);
+                const double v = (row < C && col < C) ? m[size_t(row) * C + col] : 0.0;
+                out[base + (size_t(rb) * nks + ks) * 64 + l] = T(v);
+            }
+}
+
+struct OpSet {
+    int p = -1;
+    DevBuf m2l64, m2l32, m2m64, m2m32, l2l64, l2l32;
+    DevBuf c1_64, c2_64, dg_64, c1_32, c2_32, dg_32;
+    DevBuf l2p_idx, l2p_w64, l2p_w32;
+    int width = 0, nu = 0, ng = 0;
+};
+
+}  // namespace
+
+struct vm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // workspace
+    DevBuf keys_a, keys_b, vals_a, vals_b, hist, start, p64, p32, far, flag, mbuf, lbuf;
+    int layout_p = -1, layout_prec = -1;   // layout of mbuf/lbuf
+    // results of the last evaluation, for the debug views
+    uint32_t *last_keys = nullptr;
+    int32_t *last_perm = nullptr;
+    int64_t last_n = 0;
+    int last_level = -1;
+    int last_p = -1, last_mixed = 0, last_far = 0;
+
+    // device-time accounting
+    bool timing = false;
+    std::vector<hipEvent_t> events;              // pool, two per timed launch
+    std::vector<std::pair<int, int>> timed;      // (phase, first event index)
+
+    // operator caches
+    std::map<int, std::unique_ptr<OpSet>> ops;
+    std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice;
+    DevBuf offsets, octlists;
+    bool tables_ready = false;
+};
+
+namespace {
+
+vm_status fail(vm_ctx *c, vm_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+vm_status hip_fail(vm_ctx *c, hipError_t e, const char *what) {
+    const vm_status s = (e == hipErrorOutOfMemory) ? VM_ENOMEM : VM_EDEVICE;
+    return fail(c, s, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define VM_HIP(call, what)                              \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+// Brackets one launch with a pair of events when timing is enabled.
+struct Timed {
+    vm_ctx *ctx;
+    int ev = -1;
+    Timed(vm_ctx *c, int phase) : ctx(c) {
+        if (!ctx->timing) return;
+        const size_t need = 2 * (ctx->timed.size() + 1);
+        while (ctx->events.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            ctx->events.push_back(e);
+        }
+        ev = int(2 * ctx->timed.size());
+        ctx->timed.push_back({phase, ev});
+        (void)hipEventRecord(ctx->events[ev], ctx->stream);
+    }
+    ~Timed() {
+        if (ev >= 0) (void)hipEventRecord(ctx->events[ev + 1], ctx->stream);
+    }
+};
+
+vm_status ensure_tables(vm_ctx *ctx) {
+    if (ctx->tables_ready) return VM_OK;
+    const OffsetTable &t = offset_table();
+    std::vector<int8_t> offs(316 * 3);
+    std::memcpy(offs.data(), t.d, sizeof(t.d));
+    std::vector<int16_t> lists(8 * 189);
+    std::memcpy(lists.data(), t.list, sizeof(t.list));
+    VM_HIP(upload(ctx->offsets, offs), "upload offsets");
+    VM_HIP(upload(ctx->octlists, lists), "upload octant lists");
+    ctx->tables_ready = true;
+    return VM_OK;
+}
+
+vm_status ensure_ops(vm_ctx *ctx, int p, OpSet **out) {
+    auto it = ctx->ops.find(p);
+    if (it != ctx->ops.end()) {
+        *out = it->second.get();
+        return VM_OK;
+    }
+    auto set = std::make_unique<OpSet>();
+    set->p = p;
+    const int C = ncoef(p), cp = pad16(C), kp = pad4(C);
+    const size_t frag = size_t(cp) * kp;
+    const OffsetTable &t = offset_table();
+    std::vector<double> m(size_t(C) * C);
+    {
+        std::vector<double> o64(316 * frag);
+        std::vector<float> o32(316 * frag);
+        for (int i = 0; i < 316; ++i) {
+            const double D[3] = {-double(t.d[i][0]), -double(t.d[i][1]), -double(t.d[i][2])};
+            m2l_matrix(p, D, 1.0, 1.0, m.data());
+            swizzle(m, C, o64, i * frag);
+            swizzle(m, C, o32, i * frag);
+        }
+        VM_HIP(upload(set->m2l64, o64), "upload M2L");
+        VM_HIP(upload(set->m2l32, o32), "upload M2L");
+    }
+    {
+        std::vector<double> a64(8 * frag), b64(8 * frag);
+        std::vector<float> a32(8 * frag), b32(8 * frag);
+        for (int o = 0; o < 8; ++o) {
+            const double d[3] = {((o & 1) - 0.5) * 0.5, (((o >> 1) & 1) - 0.5) * 0.5, (((o >> 2) & 1) - 0.5) * 0.5};
+            m2m_matrix(p, d, 0.5, 1.0, m.data());
+            swizzle(m, C, a64, o * frag);
+            swizzle(m, C, a32, o * frag);
+            l2l_matrix(p, d, 1.0, 0.5, m.data());
+            swizzle(m, C, b64, o * frag);
+            swizzle(m, C, b32, o * frag);
+        }
+        VM_HIP(upload(set->m2m64, a64), "upload M2M");
+        VM_HIP(upload(set->m2m32, a32), "upload M2M");
+        VM_HIP(upload(set->l2l64, b64), "upload L2L");
+        VM_HIP(upload(set->l2l32, b32), "upload L2L");
+    }
+    {
+        const RecTable r = rec_table(p);
+        std::vector<float> f1(r.c1.begin(), r.c1.end()), f2(r.c2.begin(), r.c2.end()), fd(r.diag.begin(), r.diag.end());
+        VM_HIP(upload(set->c1_64, r.c1), "upload rec");
+        VM_HIP(upload(set->c2_64, r.c2), "upload rec");
+        VM_HIP(upload(set->dg_64, r.diag), "upload rec");
+        VM_HIP(upload(set->c1_32, f1), "upload rec");
+        VM_HIP(upload(set->c2_32, f2), "upload rec");
+        VM_HIP(upload(set->dg_32, fd), "upload rec");
+    }
+    {
+        const L2PTable l = l2p_table(p);
+        std::vector<float> w32(l.w.begin(), l.w.end());
+        VM_HIP(upload(set->l2p_idx, l.idx), "upload L2P table");
+        VM_HIP(upload(set->l2p_w64, l.w), "upload L2P table");
+        VM_HIP(upload(set->l2p_w32, w32), "upload L2P table");
+        set->width = l.width;
+        set->nu = l.nu;
+        set->ng = l.ng;
+    }
+    *out = set.get();
+    ctx->ops[p] = std::move(set);
+    return VM_OK;
+}
+
+vm_status ensure_lattice(vm_ctx *ctx, int p, int K, const double **out) {
+    const auto key = std::make_pair(p, K);
+    auto it = ctx->lattice.find(key);
+    if (it == ctx->lattice.end()) {
+        const int C = ncoef(p);
+        std::vector<double> m(size_t(C) * C);
+        lattice_matrix(p, K, m.data());
+        auto b = std::make_unique<DevBuf>();
+        VM_HIP(upload(*b, m), "upload lattice operator");
+        it = ctx->lattice.emplace(key, std::move(b)).first;
+    }
+    *out = it->second->as<double>();
+    return VM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vm_status vm_create(vm_ctx **out, int device, void *hip_stream) {
+    if (!out) return VM_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return VM_EDEVICE;
+    auto *c = new (std::nothrow) vm_ctx();
+    if (!c) return VM_ENOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return VM_OK;
+}
+
+void vm_destroy(vm_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+vm_status vm_set_stream(vm_ctx *ctx, void *hip_stream) {
+    if (!ctx) return VM_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return VM_OK;
+}
+
+const char *vm_last_error(const vm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                      int level, const vm_opts *opts, double *u, double *dalpha_dt, double *grad) {
+    if (!ctx) return VM_EINVAL;
+    if (!opts) return fail(ctx, VM_EINVAL, "opts is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
+    if (!x || !alpha || !u) return fail(ctx, VM_EINVAL, "x, alpha and u must be non-NULL");
+    auto misaligned = [](const void *q) { return q && (reinterpret_cast<uintptr_t>(q) & 7u); };
+    if (misaligned(x) || misaligned(alpha) || misaligned(u) || misaligned(dalpha_dt) || misaligned(grad))
+        return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(ctx, VM_EINVAL, "sigma must be positive");
+    if (p < 1 || p > VM_MAX_P) return fail(ctx, VM_EINVAL, "p out of range [1, 20]");
+    if (level < 0 || level > VM_MAX_LEVEL) return fail(ctx, VM_EINVAL, "level out of range [0, 10]");
+    if (!(opts->box_len > 0.0) || !std::isfinite(opts->box_len))
+        return fail(ctx, VM_EINVAL, "box_len must be positive");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(opts->box_lo[d])) return fail(ctx, VM_EINVAL, "box_lo must be finite");
+    if (opts->periodic < 0 || opts->periodic > 4) return fail(ctx, VM_EINVAL, "periodic out of range [0, 4]");
+    if (opts->precision != VM_FP64 && opts->precision != VM_MIXED)
+        return fail(ctx, VM_EINVAL, "unknown precision");
+    if (opts->scheme != VM_CLASSIC && opts->scheme != VM_TRANSPOSE) return fail(ctx, VM_EINVAL, "unknown scheme");
+
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    const int mixed = opts->precision == VM_MIXED;
+    const int K = opts->periodic;
+    const int periodic = K > 0;
+    const int ni = int(n);
+    const int64_t nleaf = int64_t(1) << (3 * level);
+
+    if (vm_status st = ensure_tables(ctx); st != VM_OK) return st;
+    OpSet *ops = nullptr;
+    if (vm_status st = ensure_ops(ctx, p, &ops); st != VM_OK) return st;
+    const double *tlat = nullptr;
+    if (K >= 2)
+        if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
+
+    // workspace
+    const int C = ncoef(p), kp = pad4(C);
+    const size_t esz = mixed ? sizeof(float) : sizeof(double);
+    const int64_t ncells = ((int64_t(1) << (3 * (level + 1))) - 1) / 7;
+    const int nblk = (ni + kRadixTile - 1) / kRadixTile;
+    VM_HIP(ctx->keys_a.reserve(sizeof(uint32_t) * n), "alloc keys");
+    VM_HIP(ctx->keys_b.reserve(sizeof(uint32_t) * n), "alloc keys");
+    VM_HIP(ctx->vals_a.reserve(sizeof(int32_t) * n), "alloc perm");
+    VM_HIP(ctx->vals_b.reserve(sizeof(int32_t) * n), "alloc perm");
+    VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * size_t(nblk) * 256), "alloc histogram");
+    VM_HIP(ctx->start.reserve(sizeof(int32_t) * size_t(nleaf + 1)), "alloc leaf ranges");
+    if (mixed) VM_HIP(ctx->p32.reserve(sizeof(Part32) * n), "alloc particles");
+    else VM_HIP(ctx->p64.reserve(sizeof(Part64) * n), "alloc particles");
+    VM_HIP(ctx->far.reserve(sizeof(double) * 12 * n), "alloc far field");
+    VM_HIP(ctx->flag.reserve(sizeof(int)), "alloc flag");
+    const size_t cbytes = size_t(ncells) * 3 * kp * esz;
+    const bool relayout = ctx->layout_p != p || ctx->layout_prec != mixed;
+    if (relayout || ctx->mbuf.bytes < cbytes) {
+        // coefficient padding (rows C..kp-1) must stay zero: clear on any change of layout
+        ctx->mbuf.release();
+        ctx->lbuf.release();
+        VM_HIP(ctx->mbuf.reserve(cbytes, true), "alloc multipoles");
+        VM_HIP(ctx->lbuf.reserve(cbytes, true), "alloc locals");
+        ctx->layout_p = p;
+        ctx->layout_prec = mixed;
+    }
+
+    TreeGeom g;
+    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
+    g.box_len = opts->box_len;
+    g.inv_len = 1.0 / opts->box_len;
+    g.inv_w = std::ldexp(g.inv_len, level);
+    g.w = std::ldexp(opts->box_len, -level);
+    g.level = level;
+    g.periodic = periodic;
+
+    // --- tree ------------------------------------------------------------
+    ctx->timed.clear();
+    int32_t *start = ctx->start.as<int32_t>();
+    if (opts->check_domain) VM_HIP(hipMemsetAsync(ctx->flag.ptr, 0, sizeof(int), s), "clear flag");
+    uint32_t *kin = ctx->keys_a.as<uint32_t>(), *kout = ctx->keys_b.as<uint32_t>();
+    int32_t *vin = ctx->vals_a.as<int32_t>(), *vout = ctx->vals_b.as<int32_t>();
+    {
+    Timed tm(ctx, VM_PH_TREE);
+    VM_HIP(launch_keys(s, ni, x, g, opts->check_domain, kin, vin, ctx->flag.as<int>()), "keys");
+    const int total_bits = 3 * level;
+    if (total_bits > 0) {
+        const int npass = (total_bits + 7) / 8;
+        const int bits = (total_bits + npass - 1) / npass;
+        for (int shift = 0; shift < total_bits; shift += bits) {
+            const int b = std::min(bits, total_bits - shift);
+            VM_HIP(launch_radix_pass(s, ni, shift, b, kin, vin, kout, vout, ctx->hist.as<uint32_t>()), "radix sort");
+            std::swap(kin, kout);
+            std::swap(vin, vout);
+        }
+    }
+    VM_HIP(launch_ranges(s, ni, int(nleaf), kin, start), "leaf ranges");
+    VM_HIP(launch_permute(s, ni, x, alpha, vin, kin, g, mixed ? nullptr : ctx->p64.as<Part64>(),
+                          mixed ? ctx->p32.as<Part32>() : nullptr), "permute");
+    }
+    ctx->last_keys = kin;
+    ctx->last_perm = vin;
+    ctx->last_n = n;
+    ctx->last_level = level;
+    ctx->last_p = p;
+    ctx->last_mixed = mixed;
+    const void *parts = mixed ? (const void *)ctx->p32.ptr : (const void *)ctx->p64.ptr;
+
+    // --- far field --------------------------------------------------------
+    const int lmin = periodic ? 0 : 2;
+    const bool far = level >= lmin && !(periodic && K < 2 && level == 0);
+    ctx->last_far = far;
+    if (far) {
+        DevTables tab;
+        tab.c1_64 = ops->c1_64.as<double>(); tab.c2_64 = ops->c2_64.as<double>(); tab.diag_64 = ops->dg_64.as<double>();
+        tab.c1_32 = ops->c1_32.as<float>(); tab.c2_32 = ops->c2_32.as<float>(); tab.diag_32 = ops->dg_32.as<float>();
+        tab.l2p_idx = ops->l2p_idx.as<int32_t>();
+        tab.l2p_w64 = ops->l2p_w64.as<double>();
+        tab.l2p_w32 = ops->l2p_w32.as<float>();
+        tab.l2p_width = ops->width;
+        tab.nu = ops->nu;
+        tab.ng = ops->ng;
+        auto run = [&](auto tag) -> vm_status {
+            using T = decltype(tag);
+            const bool f32 = sizeof(T) == 4;
+            T *M = ctx->mbuf.as<T>(), *L = ctx->lbuf.as<T>();
+            auto lev = [&](T *b, int l) { return b + size_t(((int64_t(1) << (3 * l)) - 1) / 7) * 3 * kp; };
+            const T *m2l = f32 ? (const T *)ops->m2l32.ptr : (const T *)ops->m2l64.ptr;
+            const T *m2m = f32 ? (const T *)ops->m2m32.ptr : (const T *)ops->m2m64.ptr;
+            const T *l2l = f32 ? (const T *)ops->l2l32.ptr : (const T *)ops->l2l64.ptr;
+            const int16_t *lists = ctx->octlists.as<int16_t>();
+            const int8_t *offs = ctx->offsets.as<int8_t>();
+            {
+                Timed tm(ctx, VM_PH_P2M);
+                VM_HIP(launch_p2m<T>(s, int(nleaf), parts, start, p, kp, g.inv_w, tab, lev(M, level)), "P2M");
+            }
+            for (int l = level - 1; l >= lmin; --l) {
+                Timed tm(ctx, VM_PH_M2M);
+                VM_HIP(launch_translate<T>(s, 2, l, periodic, p, kp, m2m, lists, offs, lev(M, l + 1), lev(M, l), 0),
+                       "M2M");
+            }
+            bool have_parent = false;   // L at level l-1 holds something
+            if (periodic && K >= 2) {
+                Timed tm(ctx, VM_PH_LATTICE);
+                VM_HIP(launch_lattice<T>(s, p, kp, tlat, lev(M, 0), lev(L, 0)), "lattice");
+                have_parent = true;
+            }
+            for (int l = periodic ? 1 : 2; l <= level; ++l) {
+                if (have_parent) {
+                    Timed tm(ctx, VM_PH_L2L);
+                    VM_HIP(launch_translate<T>(s, 1, l, periodic, p, kp, l2l, lists, offs, lev(L, l - 1), lev(L, l), 0),
+                           "L2L");
+                }
+                Timed tm(ctx, VM_PH_M2L);
+                VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
+                                           have_parent ? 1 : 0),
+                       "M2L");
+                have_parent = true;
+            }
+            Timed tm(ctx, VM_PH_L2P);
+            VM_HIP(launch_l2p<T>(s, int(nleaf), ni, parts, start, p, kp, g.inv_w, g.w, tab, lev(L, level),
+                                 ctx->far.as<double>()),
+                   "L2P");
+            return VM_OK;
+        };
+        vm_status st = mixed ? run(float()) : run(double());
+        if (st != VM_OK) return st;
+    }
+
+    // --- near field + combine -----------------------------------------------
+    P2PArgs a;
+    a.n = ni;
+    a.nleaf = int(nleaf);
+    a.level = level;
+    a.periodic = periodic;
+    a.scheme = opts->scheme;
+    a.have_far = far ? 1 : 0;
+    a.w = g.w;
+    a.sigma = sigma;
+    a.start = start;
+    a.perm = vin;
+    a.alpha = alpha;
+    a.far = ctx->far.as<double>();
+    a.u = u;
+    a.dalpha = dalpha_dt;
+    a.grad = grad;
+    {
+        Timed tm(ctx, VM_PH_P2P);
+        if (mixed) VM_HIP(launch_p2p32(s, a, ctx->p32.as<Part32>()), "P2P");
+        else VM_HIP(launch_p2p64(s, a, ctx->p64.as<Part64>()), "P2P");
+    }
+
+    if (opts->check_domain) {
+        int flag = 0;
+        VM_HIP(hipMemcpyAsync(&flag, ctx->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s), "read flag");
+        VM_HIP(hipStreamSynchronize(s), "synchronize");
+        if (flag) return fail(ctx, VM_EDOMAIN, "non-finite or out-of-box position");
+    }
+    return VM_OK;
+}
+
+vm_status vm_set_timing(vm_ctx *ctx, int enable) {
+    if (!ctx) return VM_EINVAL;
+    ctx->timing = enable != 0;
+    ctx->timed.clear();
+    return VM_OK;
+}
+
+vm_status vm_get_timing(vm_ctx *ctx, double *ms, int *launches) {
+    if (!ctx || !ms || !launches) return VM_EINVAL;
+    for (int i = 0; i < VM_NPHASE; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    VM_HIP(hipStreamSynchronize(ctx->stream), "synchronize");
+    for (const auto &t : ctx->timed) {
+        float e = 0.0f;
+        VM_HIP(hipEventElapsedTime(&e, ctx->events[t.second], ctx->events[t.second + 1]), "event time");
+        ms[t.first] += double(e);
+        launches[t.first] += 1;
+    }
+    return VM_OK;
+}
+
+vm_status vm_debug_tree(vm_ctx *ctx, uint32_t *keys, int32_t *perm, int32_t *leaf_start) {
+    if (!ctx) return VM_EINVAL;
+    if (ctx->last_level < 0) return fail(ctx, VM_EINVAL, "no evaluation yet");
+    hipStream_t s = ctx->stream;
+    const size_t n = size_t(ctx->last_n);
+    const size_t nleaf = size_t(1) << (3 * ctx->last_level);
+    if (keys) VM_HIP(hipMemcpyAsync(keys, ctx->last_keys, n * 4, hipMemcpyDeviceToDevice, s), "copy keys");
+    if (perm) VM_HIP(hipMemcpyAsync(perm, ctx->last_perm, n * 4, hipMemcpyDeviceToDevice, s), "copy perm");
+    if (leaf_start)
+        VM_HIP(hipMemcpyAsync(leaf_start, ctx->start.ptr, (nleaf + 1) * 4, hipMemcpyDeviceToDevice, s), "copy ranges");
+    return VM_OK;
+}
+
+vm_status vm_debug_expansions(vm_ctx *ctx, int which, int level, void *out, int64_t *bytes) {
+    if (!ctx || !bytes || (which != 0 && which != 1)) return VM_EINVAL;
+    if (ctx->last_level < 0 || level < 0 || level > ctx->last_level)
+        return fail(ctx, VM_EINVAL, "level not in the last evaluation");
+    const int kp = pad4(ncoef(ctx->last_p));
+    const size_t esz = ctx->last_mixed ? 4 : 8;
+    const size_t row = size_t(3) * kp * esz;
+    const size_t before = size_t(((int64_t(1) << (3 * level)) - 1) / 7);
+    const size_t cnt = size_t(1) << (3 * level);
+    *bytes = int64_t(cnt * row);
+    if (!out) return VM_OK;
+    const DevBuf &b = which == 0 ? ctx->mbuf : ctx->lbuf;
+    VM_HIP(hipMemcpyAsync(out, static_cast<const char *>(b.ptr) + before * row, cnt * row,
+                          hipMemcpyDeviceToDevice, ctx->stream), "copy expansions");
+    return VM_OK;
+}
+
+vm_status vm_debug_far(vm_ctx *ctx, double *out) {
+    if (!ctx || !out) return VM_EINVAL;
+    if (ctx->last_level < 0 || !ctx->last_far) return fail(ctx, VM_EINVAL, "no far field in the last evaluation");
+    VM_HIP(hipMemcpyAsync(out, ctx->far.ptr, sizeof(double) * 12 * size_t(ctx->last_n), hipMemcpyDeviceToDevice,
+                          ctx->stream), "copy far field");
+    return VM_OK;
+}
+
+vm_status vm_debug_offsets(int8_t *out, int *count) {
+    if (!out || !count) return VM_EINVAL;
+    const OffsetTable &t = offset_table();
+    std::memcpy(out, t.d, sizeof(t.d));
+    *count = 316;
+    return VM_OK;
+}
+
+vm_status vm_debug_list(int level, int periodic, int32_t key, int32_t *src, int8_t *d, int8_t *img, int *count) {
+    if (!src || !d || !img || !count) return VM_EINVAL;
+    if (level < 1 || level > VM_MAX_LEVEL || (!periodic && level < 2)) return VM_EINVAL;
+    if (key < 0 || int64_t(key) >= (int64_t(1) << (3 * level))) return VM_EINVAL;
+    const OffsetTable &t = offset_table();
+    const int side = 1 << level;
+    int c[3] = {0, 0, 0};
+    for (int b = 0; b < level; ++b)
+        for (int k = 0; k < 3; ++k) c[k] |= ((key >> (3 * b + k)) & 1) << b;
+    const int oct = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
+    int cnt = 0;
+    for (int i = 0; i < 189; ++i) {
+        const int8_t *o = t.d[t.list[oct][i]];
+        int sc[3], im[3];
+        bool ok = true;
+        for (int k = 0; k < 3; ++k) {
+            const int v = c[k] + o[k];
+            if (periodic) {
+                im[k] = v < 0 ? -1 : (v >= side ? 1 : 0);
+                sc[k] = v - im[k] * side;
+            } else {
+                im[k] = 0;
+                sc[k] = v;
+                if (v < 0 || v >= side) ok = false;
+            }
+        }
+        if (!ok) continue;
+        int sk = 0;
+        for (int b = 0; b < level; ++b)
+            for (int k = 0; k < 3; ++k) sk |= ((sc[k] >> b) & 1) << (3 * b + k);
+        src[cnt] = sk;
+        for (int k = 0; k < 3; ++k) {
+            d[3 * cnt + k] = o[k];
+            img[3 * cnt + k] = int8_t(im[k]);
+        }
+        ++cnt;
+    }
+    *count = cnt;
+    return VM_OK;
+}
+
+vm_status vm_debug_operator(int kind, int p, int index, double *out) {
+    if (!out || p < 1 || p > VM_MAX_P) return VM_EINVAL;
+    const OffsetTable &t = offset_table();
+    if (kind == 0) {
+        if (index < 0 || index >= 316) return VM_EINVAL;
+        const double D[3] = {-double(t.d[index][0]), -double(t.d[index][1]), -double(t.d[index][2])};
+        m2l_matrix(p, D, 1.0, 1.0, out);
+        return VM_OK;
+    }
+    if (kind == 1 || kind == 2) {
+        if (index < 0 || index >= 8) return VM_EINVAL;
+        const double d[3] = {((index & 1) - 0.5) * 0.5, (((index >> 1) & 1) - 0.5) * 0.5,
+                             (((index >> 2) & 1) - 0.5) * 0.5};
+        if (kind == 1) m2m_matrix(p, d, 0.5, 1.0, out);
+        else l2l_matrix(p, d, 1.0, 0.5, out);
+        return VM_OK;
+    }
+    if (kind == 3) {
+        if (index < 1 || index > 4) return VM_EINVAL;
+        lattice_matrix(p, index, out);
+        return VM_OK;
+    }
+    return VM_EINVAL;
+}
+
+}  // extern "C"

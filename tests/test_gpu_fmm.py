@@ -1,0 +1,156 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (relative L2 over all particles unless stated):
+* tree arrays (keys, sorted order, leaf ranges): bit-exact;
+* FP64 FMM vs the oracle FMM of the same definition: 1e-10 (both are
+  round-off apart: same tree, lists, truncation and lattice construction);
+* no far field (one leaf, free space): FP64 vs the direct sum 1e-13;
+* mixed (FP32 near field + FP32 MFMA expansions) vs FP64: 1e-5 for u,
+  1e-4 for dalpha/dt and J.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct as D
+from oracle import fmm as OF
+from oracle import tree as T
+
+pytestmark = pytest.mark.gpu
+
+L = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1110_2921_amd as vm
+    return vm.FMM(0)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64).T)).cuda()
+
+
+def _run(ctx, x, a, sigma, p, level, periodic, precision="fp64", scheme="classic", lo=(0, 0, 0)):
+    import torch
+    u, da, J = ctx.eval(_dev(x), _dev(a), sigma, p, level, periodic=periodic, box_lo=lo,
+                        precision=precision, scheme=scheme, want_grad=True)
+    torch.cuda.synchronize()
+    return u.cpu().numpy().T, da.cpu().numpy().T, J.cpu().numpy().T.reshape(-1, 3, 3)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("periodic", [0, 1])
+@pytest.mark.parametrize("level", [1, 2, 3, 5])
+def test_tree_is_bit_exact(ctx, periodic, level):
+    x, a = W.random_particles(5000, 100 + level)
+    if periodic:
+        x[:50] += np.array([L, -L, 3 * L])          # outside the box: wrapped
+        x[50] = [0.0, L, np.nextafter(0.0, -1.0)]    # faces
+    else:
+        x[50] = [0.0, np.nextafter(L, 0), L]
+    lat = W.lattice(16)                              # particles on cell-centre planes
+    x = np.concatenate([x, lat])
+    a = np.concatenate([a, np.ones_like(lat)])
+    _run(ctx, x, a, 0.1, 2, level, periodic)
+    keys, perm, start = ctx.debug_tree(len(x), level)
+    ref = T.build(x, (0, 0, 0), L, level, periodic)
+    assert np.array_equal(perm, ref["perm"])
+    assert np.array_equal(keys, ref["keys"][ref["perm"]])
+    assert np.array_equal(start, np.append(ref["start"], len(x)))
+
+
+def test_level0_free_space_is_direct_sum(ctx):
+    x, a = W.random_particles(2048, 7)
+    sigma = 0.2
+    u, da, J = _run(ctx, x, a, sigma, 4, 0, 0)
+    u0, J0 = D.direct(x, x, a, sigma)
+    assert rel(u, u0) < 1e-13
+    assert rel(J, J0) < 1e-13
+    assert rel(da, D.stretching(J0, a)) < 1e-13
+
+
+def test_taylor_green_free_space_matches_oracle(ctx):
+    w = W.WORKLOADS["tg16_free"]
+    x, a = W.make(w)
+    u, da, J = _run(ctx, x, a, w.sigma, w.p, w.level, 0)
+    uo, Jo = OF.fmm(x, a, w.sigma, w.p, w.level, periodic=0)
+    assert rel(u, uo) < 1e-10
+    assert rel(J, Jo) < 1e-10
+    assert rel(da, D.stretching(Jo, a)) < 1e-10
+    # and it is close to the exact direct sum (p = 6 truncation)
+    ud, Jd = D.direct(x, x, a, w.sigma)
+    assert rel(u, ud) < 1e-3
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_periodic_fp64_matches_oracle(ctx, K):
+    x, a = W.random_field(16, 4.0, 17)
+    h = L / 16
+    u, da, J = _run(ctx, x, a, h, 8, 2, K)
+    uo, Jo = OF.fmm(x, a, h, 8, 2, periodic=K)
+    assert rel(u, uo) < 1e-10
+    assert rel(J, Jo) < 1e-10
+
+
+def test_rand32_periodic_matches_oracle(ctx):
+    w = W.WORKLOADS["rand32_periodic"]
+    x, a = W.make(w)
+    u, da, J = _run(ctx, x, a, w.sigma, w.p, w.level, w.periodic)
+    uo, Jo = OF.fmm(x, a, w.sigma, w.p, w.level, periodic=w.periodic)
+    assert rel(u, uo) < 1e-10
+    assert rel(J, Jo) < 1e-10
+    assert rel(da, D.stretching(Jo, a)) < 1e-10
+    um, dam, Jm = _run(ctx, x, a, w.sigma, w.p, w.level, w.periodic, precision="mixed")
+    assert rel(um, u) < 1e-5
+    assert rel(dam, da) < 1e-4
+    assert rel(Jm, J) < 1e-4
+
+
+def test_transpose_scheme_conserves_vorticity(ctx):
+    x, a = W.random_field(16, 4.0, 23)
+    h = L / 16
+    _, da, _ = _run(ctx, x, a, h, 10, 2, 3, scheme="transpose")
+    _, dc, J = _run(ctx, x, a, h, 10, 2, 3, scheme="classic")
+    tot = np.abs(da.sum(axis=0)).max() / np.abs(da).sum()
+    assert tot < 1e-6
+    assert np.abs(dc.sum(axis=0)).max() / np.abs(dc).sum() > 10 * tot
+    assert rel(da, D.stretching(J, a, "transpose")) < 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_runs_are_bitwise_reproducible(ctx, precision):
+    x, a = W.random_field(16, 4.0, 29)
+    h = L / 16
+    r1 = _run(ctx, x, a, h, 6, 2, 3, precision=precision)
+    r2 = _run(ctx, x, a, h, 6, 2, 3, precision=precision)
+    for p, q in zip(r1, r2):
+        assert np.array_equal(p, q)
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    import paper_1110_2921_amd as vm
+    x, a = W.random_particles(64, 3)
+    for kw in (dict(p=0), dict(p=21), dict(level=11), dict(periodic=5)):
+        args = dict(p=4, level=1, periodic=0)
+        args.update(kw)
+        with pytest.raises(vm._lib.VmError) as e:
+            ctx.eval(_dev(x), _dev(a), 0.1, args["p"], args["level"], periodic=args["periodic"])
+        assert e.value.status == vm._lib.VM_EINVAL
+    with pytest.raises(vm._lib.VmError) as e:
+        ctx.eval(_dev(x), _dev(a), -1.0, 4, 1)
+    assert e.value.status == vm._lib.VM_EINVAL
+    xb = x.copy()
+    xb[3, 0] = 2 * L
+    with pytest.raises(vm._lib.VmError) as e:
+        ctx.eval(_dev(xb), _dev(a), 0.1, 4, 2, check_domain=True)
+    assert e.value.status == vm._lib.VM_EDOMAIN

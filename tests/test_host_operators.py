@@ -1,0 +1,147 @@
+"""The library's host-generated operators against the oracle's (no GPU).
+
+The library and the oracle use different spherical-harmonic conventions
+(the library: Condon-Shortley phase, balanced norms, cell-scaled real
+packing; the oracle: the Cheng et al. notation, complex), so the operators
+are compared through what they mean: potentials of point charges.  The test
+evaluates the library's documented basis with scipy's associated Legendre
+functions.  Both sides truncate at degree p in the same way, so they must
+agree to round-off, not merely to the truncation error.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import lpmv
+
+from oracle import fmm as OF
+from oracle import harmonics as H
+from oracle import tree as T
+
+lib = pytest.importorskip("paper_1110_2921_amd")
+
+
+def _sph(x):
+    x = np.atleast_2d(x)
+    r = np.linalg.norm(x, axis=1)
+    ct = np.where(r > 0, x[:, 2] / np.where(r > 0, r, 1), 1.0)
+    ph = np.arctan2(x[:, 1], x[:, 0])
+    return r, ct, ph
+
+
+def lib_regular(x, p):
+    """Balanced regular harmonics (m >= 0) of the library's documented basis."""
+    r, ct, ph = _sph(x)
+    out = {}
+    for n in range(p + 1):
+        for m in range(n + 1):
+            nrm = math.sqrt(math.factorial(n + m) * math.factorial(n - m)) / math.factorial(n + m)
+            out[(n, m)] = nrm * r ** n * lpmv(m, n, ct) * np.exp(1j * m * ph)
+    return out
+
+
+def lib_irregular(x, p):
+    r, ct, ph = _sph(x)
+    out = {}
+    for n in range(p + 1):
+        for m in range(n + 1):
+            nrm = math.factorial(n - m) / math.sqrt(math.factorial(n + m) * math.factorial(n - m))
+            out[(n, m)] = nrm * lpmv(m, n, ct) * np.exp(1j * m * ph) / r ** (n + 1)
+    return out
+
+
+def lib_p2m(y, q, p):
+    R = lib_regular(y, p)
+    f = np.zeros((p + 1) ** 2)
+    for (n, m), v in R.items():
+        if m == 0:
+            f[n * n] = np.sum(q * v.real)
+        else:
+            f[n * n + 2 * m - 1] = np.sum(q * v.real)
+            f[n * n + 2 * m] = -np.sum(q * v.imag)
+    return f
+
+
+def _eval(f, basis, p):
+    s = 0.0
+    for (n, m), v in basis.items():
+        if m == 0:
+            s = s + f[n * n] * v.real
+        else:
+            s = s + 2.0 * (f[n * n + 2 * m - 1] * v.real - f[n * n + 2 * m] * v.imag)
+    return s
+
+
+def lib_eval_local(f, x, p, w=1.0):
+    return _eval(f, lib_regular(np.atleast_2d(x) / w, p), p) / w
+
+
+def lib_eval_multipole(f, x, p, w=1.0):
+    return _eval(f, lib_irregular(np.atleast_2d(x) / w, p), p) / w
+
+
+@pytest.mark.parametrize("p", [4, 8])
+def test_m2l_operators_match_oracle(p):
+    rng = np.random.default_rng(p)
+    offs = lib.debug_offsets()
+    assert [tuple(map(int, d)) for d in offs] == T.all_offsets()
+    for idx in rng.choice(316, 6, replace=False):
+        d = offs[idx].astype(np.float64)
+        y = rng.uniform(-0.5, 0.5, (5, 3))           # sources in the unit source cell at d
+        q = rng.standard_normal(5)
+        x = rng.uniform(-0.5, 0.5, (4, 3))           # targets in the unit cell at 0
+        Tm = lib.debug_operator(0, p, int(idx))
+        lam = Tm @ lib_p2m(y, q, p)
+        phi_lib = lib_eval_local(lam, x, p)
+        Mo = H.p2m(y, q[:, None], p)
+        Lo = (H.m2l_matrix(d, p) @ Mo.T).T
+        phi_or = H.eval_local(Lo, x, p)[:, 0]
+        assert np.abs(phi_lib - phi_or).max() < 1e-12 * np.abs(phi_or).max()
+
+
+@pytest.mark.parametrize("p", [5, 10])
+def test_m2m_and_l2l_operators_match_oracle(p):
+    rng = np.random.default_rng(10 + p)
+    for o in range(8):
+        ob = np.array([(o >> k) & 1 for k in range(3)], np.float64)
+        cc = (ob - 0.5) * 0.5                        # child centre in parent units
+        y = cc + rng.uniform(-0.25, 0.25, (6, 3))    # sources in the child
+        q = rng.standard_normal(6)
+        fm = lib.debug_operator(1, p, o) @ lib_p2m((y - cc) / 0.5, q, p)
+        far = rng.normal(size=(3, 3))
+        far = 3.0 * far / np.linalg.norm(far, axis=1, keepdims=True)
+        Mo = (H.m2m_matrix(cc, p) @ H.p2m(y - cc, q[:, None], p).T).T
+        a = lib_eval_multipole(fm, far, p)
+        b = H.eval_multipole(Mo, far, p)[:, 0]
+        assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
+        # L2L: a local expansion about the parent re-expanded about the child
+        lam = rng.standard_normal((p + 1) ** 2)
+        xs = cc + rng.uniform(-0.25, 0.25, (4, 3))
+        lam_c = lib.debug_operator(2, p, o) @ lam
+        a = lib_eval_local(lam_c, xs - cc, p, w=0.5)
+        b = lib_eval_local(lam, xs, p, w=1.0)
+        assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_lattice_operator_matches_oracle(K):
+    p = 6
+    rng = np.random.default_rng(K)
+    y = rng.uniform(-0.5, 0.5, (8, 3))
+    q = rng.standard_normal(8)
+    q -= q.mean()
+    x = rng.uniform(-0.5, 0.5, (5, 3))
+    lam = lib.debug_operator(3, p, K) @ lib_p2m(y, q, p)
+    a = lib_eval_local(lam, x, p)
+    Lo = OF.lattice_local(H.p2m(y, q[:, None], p).T.T, p, 1.0, K)
+    b = H.eval_local(Lo, x, p)[:, 0]
+    assert np.abs(a - b).max() < 1e-11 * np.abs(b).max()
+
+
+def test_lists_match_oracle():
+    for periodic, level in ((1, 1), (1, 2), (0, 2), (0, 3)):
+        for key in range(0, 8 ** level, 7):
+            src, d, img = lib.debug_list(level, periodic, key)
+            ref = T.interaction_list(key, level, periodic)
+            got = [(int(s), tuple(map(int, dd)), tuple(map(int, ii))) for s, dd, ii in zip(src, d, img)]
+            assert got == ref
