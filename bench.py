@@ -1,0 +1,258 @@
+"""Throughput of the FMM evaluation on one MI355X.
+
+A step is one full evaluation of the regularised Biot-Savart velocity and the
+stretching term (tree build, P2M, M2M, lattice, L2L/M2L, L2P, P2P, combine)
+over N = 256^3 vortex particles of a seeded random isotropic field (p = 10,
+leaf level 6, 27^3 periodic images), inputs resident in HBM.  Prints one JSON
+line (see the design doc for the field definitions).
+
+    python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published peaks
+    "hbm_gbs": 8000.0,
+    "mfma_f32_tflops": 157.3,
+    "mfma_f64_tflops": 78.6,
+    "valu_f32_tflops": 157.3,
+    "valu_f64_tflops": 78.6,
+}
+# Algorithmic work per unit (derived in the design doc):
+P2P_FLOP_PER_PAIR = {"mixed": 89.0, "fp64": 80.0}   # counted from the pair kernels, FMA = 2
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def m2l_translations(level, periodic):
+    """Number of M2L translations over all levels of a uniform tree."""
+    from itertools import product
+    total = 0
+    lstart = 1 if periodic else 2
+    for l in range(lstart, level + 1):
+        side = 1 << l
+        if periodic:
+            total += 189 * 8 ** l
+            continue
+        c = np.arange(side)
+        for par in product((0, 1), repeat=3):
+            # cells with coordinate parities `par`, offsets d_i in [-2-par_i, 3-par_i]
+            per_dim = []
+            for dd in range(3):
+                cc = c[(c & 1) == par[dd]]
+                per_dim.append((cc, np.arange(-2 - par[dd], 4 - par[dd])))
+            cnt = 0
+            for dx in per_dim[0][1]:
+                for dy in per_dim[1][1]:
+                    for dz in per_dim[2][1]:
+                        if max(abs(dx), abs(dy), abs(dz)) < 2:
+                            continue
+                        nx = np.sum((per_dim[0][0] + dx >= 0) & (per_dim[0][0] + dx < side))
+                        ny = np.sum((per_dim[1][0] + dy >= 0) & (per_dim[1][0] + dy < side))
+                        nz = np.sum((per_dim[2][0] + dz >= 0) & (per_dim[2][0] + dz < side))
+                        cnt += int(nx) * int(ny) * int(nz)
+            total += cnt
+    return total
+
+
+def _morton_tables(level):
+    side = 1 << level
+    c = np.arange(side)
+    spread = np.zeros(side, np.int64)
+    for b in range(level):
+        spread |= ((c >> b) & 1) << (3 * b)
+    return spread
+
+
+def near_pairs(start, level, periodic):
+    counts = np.diff(start).astype(np.int64)
+    side = 1 << level
+    spread = _morton_tables(level)
+    ix, iy, iz = np.meshgrid(np.arange(side), np.arange(side), np.arange(side), indexing="ij")
+    key = spread[ix] | (spread[iy] << 1) | (spread[iz] << 2)
+    cnt = counts[key]
+    total = 0
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                if periodic:
+                    nb = np.roll(cnt, shift=(-dx, -dy, -dz), axis=(0, 1, 2))
+                    total += int(np.sum(cnt * nb))
+                else:
+                    sl_t = [slice(max(0, -d), side - max(0, d)) for d in (dx, dy, dz)]
+                    sl_s = [slice(max(0, d), side - max(0, -d)) for d in (dx, dy, dz)]
+                    total += int(np.sum(cnt[tuple(sl_t)] * cnt[tuple(sl_s)]))
+    return total
+
+
+def cpu_baseline(w, budget_s=30.0):
+    """The oracle FMM timed on the host on a 16^3 sample of the same recipe."""
+    import workloads as W
+    from oracle import fmm as oracle_fmm
+    ng = 16
+    x, a = W.random_field(ng, 4.0, seed=w.seed)
+    h = 2 * math.pi / ng
+    level = 2                     # 64 particles per leaf, as in the full workload
+    t0 = time.perf_counter()
+    oracle_fmm.fmm(x, a, h, w.p, level, periodic=w.periodic)
+    t = time.perf_counter() - t0
+    n_sample = ng ** 3
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": (n_sample / w.n) / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle CPU FMM (NumPy + C/OpenMP, FP64) on N={ng}^3 particles of the same recipe "
+                      f"(k0=4, 64/leaf, p={w.p}, {3 ** w.periodic}^3 images) in {t:.1f} s, scaled by "
+                      f"{n_sample}/{w.n} (cost linear in N at fixed particles per leaf)",
+            "seconds": t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rand256_periodic")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-check", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1110_2921_amd as vm
+    import workloads as W
+
+    w = W.WORKLOADS[args.workload]
+    log(f"[bench] generating {w.name}: N={w.n}")
+    t0 = time.perf_counter()
+    x_np, a_np = W.make(w)
+    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(np.ascontiguousarray(x_np.T)).to(dev)
+    a = torch.from_numpy(np.ascontiguousarray(a_np.T)).to(dev)
+    del x_np
+    n = w.n
+    u = torch.empty((3, n), dtype=torch.float64, device=dev)
+    da = torch.empty((3, n), dtype=torch.float64, device=dev)
+    ctx = vm.FMM(0)
+    kw = dict(periodic=w.periodic, box_len=w.box_len, scheme="classic")
+
+    def step(prec, out):
+        ctx.eval(x, a, w.sigma, w.p, w.level, precision=prec, out=(out[0], out[1], None), **kw)
+
+    for i in range(args.warmup):
+        step(args.precision, (u, da))
+        log(f"[bench] warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+
+    ctx.set_timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for i in range(args.steps):
+        step(args.precision, (u, da))
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = ctx.timing()
+    ctx.set_timing(False)
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1000.0 * wall / args.steps
+    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step (events {gpu_ms / args.steps:.2f} ms)")
+    for k, (ms, cnt) in phases.items():
+        log(f"[bench]   {k:8s} {ms / args.steps:9.3f} ms/step  launches {cnt / args.steps:.0f}")
+
+    # work counts
+    _, _, start = ctx.debug_tree(n, w.level)
+    pairs = near_pairs(start, w.level, w.periodic > 0)
+    ntr = m2l_translations(w.level, w.periodic > 0)
+    C = (w.p + 1) ** 2
+    m2l_flop = 6.0 * C * C * ntr
+    p2p_ms = phases["p2p"][0] / args.steps
+    m2l_ms = phases["m2l"][0] / args.steps
+    m2l_launch = phases["m2l"][1] / args.steps
+    p2p_flop = P2P_FLOP_PER_PAIR[args.precision] * pairs
+    f32 = args.precision == "mixed"
+    roof_m2l = {"bound": "mfma", "kernel": "k_translate<M2L>",
+                "achieved": m2l_flop / m2l_launch / (m2l_ms / m2l_launch * 1e-3) / 1e12,
+                "peak": PEAKS["mfma_f32_tflops" if f32 else "mfma_f64_tflops"], "unit": "TFLOP/s",
+                "traffic": None}
+    roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
+    roof_p2p = {"bound": "alu", "kernel": "k_p2p32" if f32 else "k_p2p64",
+                "achieved": p2p_flop / (p2p_ms * 1e-3) / 1e12,
+                "peak": PEAKS["valu_f32_tflops" if f32 else "valu_f64_tflops"], "unit": "TFLOP/s",
+                "traffic": None}
+    roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
+    dominant = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
+
+    result = {
+        "metric": "FMM evals/sec and P2P Ginteractions/s at N=256^3, p=10, rel-L2 err vs FP64",
+        "value": args.steps / wall,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if f32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: N={w.ng}^3 cell-centred lattice in [0,2pi)^3, random-phase "
+                               f"solenoidal field E(k)~k^4 exp(-2k^2/k0^2), k0={w.k0:g}, sigma=h, "
+                               f"p={w.p}, leaf level {w.level} (64/leaf), {3 ** w.periodic}^3 periodic images, "
+                               f"{args.precision} precision, classic stretching",
+                   "n": n, "p": w.p, "level": w.level, "periodic_K": w.periodic,
+                   "precision": args.precision, "parallelism": "single GPU"},
+        "p2p_gpairs_per_s": pairs / (p2p_ms * 1e-3) / 1e9,
+        "p2p_pairs": pairs,
+        "m2l_translations": ntr,
+        "phase_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
+        "roofline": dominant,
+        "roofline_kernels": {"m2l": roof_m2l, "p2p": roof_p2p},
+    }
+
+    if not args.no_fp64_check and args.precision == "mixed":
+        u64 = torch.empty_like(u)
+        da64 = torch.empty_like(da)
+        step("fp64", (u64, da64))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nf = 2
+        for _ in range(nf):
+            step("fp64", (u64, da64))
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - t0) / nf
+        eu = float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))
+        ed = float(torch.linalg.norm(da - da64) / torch.linalg.norm(da64))
+        result["rel_l2_u_vs_fp64"] = eu
+        result["rel_l2_dalpha_vs_fp64"] = ed
+        result["fp64_evals_per_s"] = 1.0 / t64
+        result["mixed_speedup_vs_fp64"] = (args.steps / wall) * t64
+        log(f"[bench] fp64 {t64 * 1e3:.1f} ms/eval; mixed vs fp64 rel-L2 u {eu:.2e} dalpha {ed:.2e}")
+
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -98,9 +98,10 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
 
 /*
  * Device-time accounting (HIP events on the context's stream around every
- * launch).  When enabled, vm_get_timing reports, for the last vm_fmm_eval,
- * the summed milliseconds and the number of launches of each phase; it
- * synchronises the stream.  Phases, in launch order:
+ * launch).  vm_set_timing(ctx, 1) starts a fresh account (and 0 stops it);
+ * vm_get_timing reports, summed over every vm_fmm_eval since then, the
+ * milliseconds and the number of launches of each phase (at most 32768
+ * launches are recorded); it synchronises the stream.  Phases, in launch order:
  */
 enum {
     VM_PH_TREE = 0,   /* keys, radix sort passes, leaf ranges, permutation */

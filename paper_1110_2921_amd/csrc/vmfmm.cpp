@@ -131,7 +131,7 @@ struct Timed {
     vm_ctx *ctx;
     int ev = -1;
     Timed(vm_ctx *c, int phase) : ctx(c) {
-        if (!ctx->timing) return;
+        if (!ctx->timing || ctx->timed.size() >= 65536) return;
         const size_t need = 2 * (ctx->timed.size() + 1);
         while (ctx->events.size() < need) {
             hipEvent_t e;
@@ -347,7 +347,6 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     g.periodic = periodic;
 
     // --- tree ------------------------------------------------------------
-    ctx->timed.clear();
     int32_t *start = ctx->start.as<int32_t>();
     if (opts->check_domain) VM_HIP(hipMemsetAsync(ctx->flag.ptr, 0, sizeof(int), s), "clear flag");
     uint32_t *kin = ctx->keys_a.as<uint32_t>(), *kout = ctx->keys_b.as<uint32_t>();
