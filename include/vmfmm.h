@@ -97,6 +97,50 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
                       double *u, double *dalpha_dt, double *grad);
 
 /*
+ * Discrete adjoint of vm_fmm_eval's velocity (the transposed FMM): for a
+ * cotangent u_bar of u it returns
+ *   alpha_bar = (du/dalpha)^T u_bar,   x_bar = (du/dx)^T u_bar
+ * of exactly the map vm_fmm_eval computes (same tree, lists, truncation and
+ * lattice operator; the tree is held fixed, since the keys are piecewise
+ * constant in x).  Pipeline: L2P^T, L2L^T, M2L^T (MFMA with transposed
+ * operators), lattice^T, M2M^T, P2M^T with its source-position derivative,
+ * P2P with u_bar as strengths (the pair kernel satisfies K(r)^T = K(-r)),
+ * plus the target terms J u_bar.  The forward state (tree, expansions and
+ * gradient) is recomputed inside the call rather than stored between calls.
+ * x, alpha, u_bar: device [3][n]; x_bar, alpha_bar: device [3][n] out (either
+ * may be NULL).  Same precision forms as vm_fmm_eval; the context keeps
+ * 30 FP64 words per particle of scratch.
+ */
+vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                         int level, const vm_opts *opts, const double *u_bar, double *x_bar, double *alpha_bar);
+
+/*
+ * One step of Heun's method (explicit trapezoidal RK2) for the convection and
+ * stretching ODEs (eqs. 7-8; the paper integrates them with forward Euler,
+ * Sec. 4.1).  With (u, s) = vm_fmm_eval(x, alpha) (s the opts->scheme form):
+ *   x* = x + dt u(x, a),  a* = a + dt s(x, a),
+ *   x <- x + dt/2 (u(x, a) + u(x*, a*)),  a <- a + dt/2 (s(x, a) + s(x*, a*)),
+ * then, periodic, x wrapped into the box as the keys do.  x and alpha (device
+ * [3][n]) are updated in place; sigma stays fixed (no core spreading).
+ * u0, grad0: device [3][n] / [9][n] or NULL: the velocity and gradient at the
+ * initial state (for diagnostics).  The context keeps four [3][n] FP64
+ * scratch arrays (grown on demand).
+ */
+vm_status vm_rk2_step(vm_ctx *ctx, int64_t n, double *x, double *alpha, double sigma, int p, int level,
+                      const vm_opts *opts, double dt, double *u0, double *grad0);
+
+/*
+ * Energy and enstrophy in FP64 with a fixed reduction order (deterministic):
+ *   out[0] = E     = h3/2 sum_i |u_i|^2
+ *   out[1] = Omega = h3/2 sum_i |curl u_i|^2, curl u from grad (0 if grad is NULL)
+ *   out[2] = Omega_p = 1/(2 h3) sum_i |alpha_i|^2 (0 if alpha is NULL)
+ * u [3][n], grad [9][n], alpha [3][n] and out [3] are device pointers; h3 is
+ * the particle volume (h^3).
+ */
+vm_status vm_diagnostics(vm_ctx *ctx, int64_t n, const double *u, const double *grad, const double *alpha,
+                         double h3, double *out);
+
+/*
  * Device-time accounting (HIP events on the context's stream around every
  * launch).  vm_set_timing(ctx, 1) starts a fresh account (and 0 stops it);
  * vm_get_timing reports, summed over every vm_fmm_eval since then, the

@@ -57,14 +57,17 @@ def lattice_local(m0, p, box_len, K):
             s_small = 3.0 ** (k - 3) * box_len
             msup = sum(H.m2m_matrix(e * s_small, p) @ msup.T for e in block).T
         s = 3.0 ** (k - 2) * box_len
-        for d in ring:
-            out = out + (H.m2l_matrix(d * s, p) @ msup.T).T
+        mats = H.m2l_matrices(ring * s, p)
+        for T_d in mats:
+            out = out + (T_d @ msup.T).T
     return out
 
 
 def _m2l_matrices(level, p, box_len):
     w = box_len / (1 << level)
-    return {d: H.m2l_matrix(np.array(d, np.float64) * w, p) for d in T.all_offsets()}
+    offs = T.all_offsets()
+    mats = H.m2l_matrices(np.array(offs, np.float64) * w, p)
+    return dict(zip(offs, mats))
 
 
 def fmm(x, alpha, sigma, p, level, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, periodic=0):

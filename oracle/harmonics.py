@@ -179,10 +179,15 @@ def _m2l_index(p):
 
 def m2l_matrix(d, p):
     """T with L = T @ M for a multipole at (target centre + d)."""
+    return m2l_matrices(np.asarray(d, np.float64)[None], p)[0]
+
+
+def m2l_matrices(ds, p):
+    """M2L matrices for several source-centre offsets ds (K, 3) at once."""
     rows, cols, src, fac = _m2l_index(p)
-    S = irregular(np.asarray(d, np.float64)[None], 2 * p)[0]
-    T = np.zeros((ncoef(p), ncoef(p)), np.complex128)
-    T[rows, cols] = fac * S[src]
+    S = irregular(np.asarray(ds, np.float64), 2 * p)
+    T = np.zeros((len(ds), ncoef(p), ncoef(p)), np.complex128)
+    T[:, rows, cols] = fac[None, :] * S[:, src]
     return T
 
 

@@ -98,6 +98,65 @@ class FMM:
         self._check(st)
         return u, da, J
 
+    def adjoint(self, x, alpha, u_bar, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0),
+                box_len=2 * math.pi, precision="fp64", want_x=True, want_alpha=True, stream=None):
+        """(x_bar, alpha_bar), each (3, n) or None: the transposed FMM applied to u_bar."""
+        torch = self._torch
+        x = _soa(x, torch)
+        alpha = _soa(alpha, torch)
+        u_bar = _soa(u_bar, torch)
+        n = x.shape[1]
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        xb = torch.empty((3, n), dtype=torch.float64, device=x.device) if want_x else None
+        ab = torch.empty((3, n), dtype=torch.float64, device=x.device) if want_alpha else None
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", False)
+        self._check(self._lib.vm_fmm_adjoint(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(level),
+                                             ctypes.byref(opts), ctypes.c_void_p(u_bar.data_ptr()),
+                                             ctypes.c_void_p(xb.data_ptr() if xb is not None else 0),
+                                             ctypes.c_void_p(ab.data_ptr() if ab is not None else 0)))
+        return xb, ab
+
+    def _opts(self, periodic, box_lo, box_len, precision, scheme, check_domain):
+        return _lib.VmOpts((ctypes.c_double * 3)(*box_lo), float(box_len), int(periodic),
+                           PRECISIONS[precision], SCHEMES[scheme], int(bool(check_domain)))
+
+    def rk2_step(self, x, alpha, sigma, p, level, dt, periodic=0, box_lo=(0.0, 0.0, 0.0),
+                 box_len=2 * math.pi, precision="fp64", scheme="classic", want_initial=False,
+                 stream=None):
+        """Heun step, in place on x and alpha ((3, n) contiguous float64 CUDA tensors).
+
+        Returns (u0, J0) at the initial state when ``want_initial``, else None."""
+        torch = self._torch
+        for t in (x, alpha):
+            if t.dim() != 2 or t.shape[0] != 3 or not t.is_contiguous() or t.dtype != torch.float64:
+                raise ValueError("rk2_step updates (3, n) contiguous float64 tensors in place")
+        n = x.shape[1]
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        u0 = J0 = None
+        if want_initial:
+            u0 = torch.empty((3, n), dtype=torch.float64, device=x.device)
+            J0 = torch.empty((9, n), dtype=torch.float64, device=x.device)
+        opts = self._opts(periodic, box_lo, box_len, precision, scheme, False)
+        self._check(self._lib.vm_rk2_step(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(level),
+                                          ctypes.byref(opts), float(dt),
+                                          ctypes.c_void_p(u0.data_ptr() if u0 is not None else 0),
+                                          ctypes.c_void_p(J0.data_ptr() if J0 is not None else 0)))
+        return (u0, J0) if want_initial else None
+
+    def diagnostics(self, u, grad, alpha, h3, stream=None):
+        """(E, Omega, Omega_p) as a float64 CUDA tensor of 3 (FP64 reductions)."""
+        torch = self._torch
+        n = u.shape[1]
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        out = torch.empty(3, dtype=torch.float64, device=u.device)
+        self._check(self._lib.vm_diagnostics(self._h, n, ctypes.c_void_p(u.data_ptr()),
+                                             ctypes.c_void_p(grad.data_ptr() if grad is not None else 0),
+                                             ctypes.c_void_p(alpha.data_ptr() if alpha is not None else 0),
+                                             float(h3), ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def set_timing(self, enable=True):
         self._check(self._lib.vm_set_timing(self._h, int(bool(enable))))
 
@@ -141,6 +200,47 @@ class FMM:
         self._check(self._lib.vm_debug_far(self._h, ctypes.c_void_p(out.data_ptr())))
         torch.cuda.synchronize()
         return out.cpu().numpy()
+
+
+def _velocity_function():
+    import torch
+
+    class VortexFMM(torch.autograd.Function):
+        """u = FMM(x, alpha); backward runs the library's transposed FMM."""
+
+        @staticmethod
+        def forward(ctx, x, alpha, fmm, kw):
+            u, _, _ = fmm.eval(x, alpha, want_dalpha=False, **kw)
+            ctx.save_for_backward(x, alpha)
+            ctx.fmm = fmm
+            ctx.kw = kw
+            return u
+
+        @staticmethod
+        def backward(ctx, u_bar):
+            x, alpha = ctx.saved_tensors
+            kw = dict(ctx.kw)
+            kw.pop("scheme", None)
+            xb, ab = ctx.fmm.adjoint(x, alpha, u_bar.contiguous(), want_x=ctx.needs_input_grad[0],
+                                     want_alpha=ctx.needs_input_grad[1], **kw)
+            return xb, ab, None, None
+
+    return VortexFMM
+
+
+_VORTEX_FMM = None
+
+
+def velocity(x, alpha, fmm, sigma, p, level, **kw):
+    """Differentiable velocity (3, n) of particles x, alpha ((3, n) float64 CUDA tensors).
+
+    Gradients with respect to x and alpha come from the discrete adjoint of the
+    same FMM (``vm_fmm_adjoint``); keyword arguments are those of ``FMM.eval``."""
+    global _VORTEX_FMM
+    if _VORTEX_FMM is None:
+        _VORTEX_FMM = _velocity_function()
+    kw = dict(kw, sigma=sigma, p=p, level=level)
+    return _VORTEX_FMM.apply(x, alpha, fmm, kw)
 
 
 def debug_offsets():

@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "VM_OK", -1: "VM_EINVAL", -2: "VM_ENOMEM", -3: "VM_EDEVICE", 
 
 # every symbol include/vmfmm.h declares
 EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_eval",
+           "vm_fmm_adjoint", "vm_rk2_step", "vm_diagnostics",
            "vm_set_timing", "vm_get_timing", "vm_debug_tree", "vm_debug_expansions", "vm_debug_far", "vm_debug_offsets", "vm_debug_list",
            "vm_debug_operator")
 
@@ -56,6 +57,14 @@ def load():
     lib.vm_fmm_eval.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(VmOpts), dp, dp, dp]
     lib.vm_fmm_eval.restype = ctypes.c_int
+    lib.vm_fmm_adjoint.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(VmOpts), dp, dp, dp]
+    lib.vm_fmm_adjoint.restype = ctypes.c_int
+    lib.vm_rk2_step.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(VmOpts), ctypes.c_double, dp, dp]
+    lib.vm_rk2_step.restype = ctypes.c_int
+    lib.vm_diagnostics.argtypes = [vp, i64, dp, dp, dp, ctypes.c_double, dp]
+    lib.vm_diagnostics.restype = ctypes.c_int
     lib.vm_set_timing.argtypes = [vp, ctypes.c_int]
     lib.vm_set_timing.restype = ctypes.c_int
     lib.vm_get_timing.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]

@@ -20,7 +20,9 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = ["kernels_tree.hip", "kernels_fmm.hip", "kernels_p2p.hip", "operators.cpp", "vmfmm.cpp"]
+SOURCES = ["kernels_tree.hip", "kernels_fmm.hip", "kernels_p2p.hip", "kernels_step.hip", "kernels_adjoint.hip",
+           "operators.cpp",
+           "vmfmm.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -79,6 +79,32 @@ struct P2PArgs {
 hipError_t launch_p2p64(hipStream_t s, const P2PArgs &a, const Part64 *parts);
 hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts);
 
+// --- adjoint (kernels_adjoint.hip) ------------------------------------------------
+template <typename T>
+hipError_t launch_l2p_adj(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start,
+                          const int32_t *perm, const double *ubar, int p, int kp, double inv_w, double w,
+                          const DevTables &tab, const int32_t *t_idx, const T *t_w, int width, T *lbar);
+template <typename T>
+hipError_t launch_p2m_adj(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start, int p, int kp,
+                          double inv_w, const DevTables &tab, const int32_t *g_idx, const T *g_w, int width,
+                          const T *mbar, double *adj);
+hipError_t launch_parts_with64(hipStream_t s, int n, const Part64 *in, const int32_t *perm, const double *ubar,
+                               Part64 *out);
+hipError_t launch_parts_with32(hipStream_t s, int n, const Part32 *in, const int32_t *perm, const double *ubar,
+                               Part32 *out);
+hipError_t launch_adj_combine(hipStream_t s, int n, const int32_t *perm, const double *ubar, const double *alpha,
+                              const double *J, const double *v, const double *Jv, const double *adj, double *xbar,
+                              double *abar);
+
+// --- time stepping and diagnostics (kernels_step.hip) --------------------------
+hipError_t launch_rk_stage1(hipStream_t s, int n, double *x, double *a, const double *u, const double *sv,
+                            double dt, double *xs, double *as);
+hipError_t launch_rk_stage2(hipStream_t s, int n, double *x, double *a, const double *u, const double *sv,
+                            double dt, const TreeGeom &g);
+int diag_blocks(int n);
+hipError_t launch_diagnostics(hipStream_t s, int n, const double *u, const double *J, const double *a,
+                              double h3, double *part, double *out);
+
 // rows of the translation-operator GEMM tile
 inline int pad16(int c) { return (c + 15) / 16 * 16; }
 inline int pad4(int c) { return (c + 3) / 4 * 4; }

@@ -329,6 +329,74 @@ L2PTable l2p_table(int p) {
     return t;
 }
 
+namespace {
+
+// Compresses the rows of a dense matrix into fixed-width (index, weight) lists.
+void compress(const std::vector<double> &dense, int rows, int cols, int &width, std::vector<int32_t> &idx,
+              std::vector<double> &w) {
+    width = 1;
+    for (int r = 0; r < rows; ++r) {
+        int k = 0;
+        for (int c = 0; c < cols; ++c) k += dense[size_t(r) * cols + c] != 0.0;
+        width = std::max(width, k);
+    }
+    idx.assign(size_t(rows) * width, 0);
+    w.assign(size_t(rows) * width, 0.0);
+    for (int r = 0; r < rows; ++r) {
+        int k = 0;
+        for (int c = 0; c < cols; ++c) {
+            const double v = dense[size_t(r) * cols + c];
+            if (v == 0.0) continue;
+            idx[size_t(r) * width + k] = c;
+            w[size_t(r) * width + k] = v;
+            ++k;
+        }
+    }
+}
+
+double eval_weight(int s) {
+    const int n = int(std::sqrt(double(s) + 0.5));
+    return s == n * n ? 1.0 : 2.0;
+}
+
+}  // namespace
+
+AdjTables adj_tables(int p) {
+    AdjTables t;
+    t.p = p;
+    const int C = ncoef(p), nu = p * p;
+    t.nu = nu;
+    // velocity rows of the forward evaluation, U_eval (3 nu x 3C), then transposed
+    std::vector<double> D1[3];
+    for (int a = 0; a < 3; ++a) {
+        D1[a].resize(size_t(nu) * C);
+        deriv_matrix(p, a, D1[a].data());
+    }
+    const int eps[3][3][3] = {{{0, 0, 0}, {0, 0, 1}, {0, -1, 0}},
+                              {{0, 0, -1}, {0, 0, 0}, {1, 0, 0}},
+                              {{0, 1, 0}, {-1, 0, 0}, {0, 0, 0}}};
+    std::vector<double> UT(size_t(3) * C * 3 * nu, 0.0);   // (3C) x (3 nu)
+    for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) {
+                if (!eps[b][c][d]) continue;
+                for (int i = 0; i < nu; ++i)
+                    for (int j = 0; j < C; ++j) {
+                        const double v = eps[b][c][d] * D1[c][size_t(i) * C + j] * eval_weight(i);
+                        UT[size_t(d * C + j) * 3 * nu + b * nu + i] += v;
+                    }
+            }
+    compress(UT, 3 * C, 3 * nu, t.width_t, t.t_idx, t.t_w);
+    // gradient of F = sum_t f_t c_t: with lam = f / w_t, dF/dY_a = sum_s (D_a lam)_s w_s c_s
+    std::vector<double> G(size_t(3) * nu * C, 0.0);
+    for (int a = 0; a < 3; ++a)
+        for (int s2 = 0; s2 < nu; ++s2)
+            for (int j = 0; j < C; ++j)
+                G[size_t(a * nu + s2) * C + j] = D1[a][size_t(s2) * C + j] * eval_weight(s2) / eval_weight(j);
+    compress(G, 3 * nu, C, t.width_g, t.g_idx, t.g_w);
+    return t;
+}
+
 RecTable rec_table(int p) {
     RecTable t;
     const int n_ent = (p + 1) * (p + 2) / 2;

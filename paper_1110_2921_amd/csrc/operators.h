@@ -55,6 +55,21 @@ struct L2PTable {
 };
 L2PTable l2p_table(int p);
 
+// Sparse tables of the adjoint (transposed) far field, from the same FP64
+// derivative operators:
+//   L2P^T: lam_bar[j] = 1/(4 pi w^2) sum_e w * V[idx]  for each of the 3C local
+//          coefficients j, V[b*nu + s] = sum_i ubar_{i,b} c_s(X_i) (degree < p);
+//   P2M gradient: for F(Y) = sum_t f_t c_t(Y) (degree p),
+//          dF/dY_a = sum_s G[a*nu + s] c_s(Y),  G[a*nu + s] = sum_e w * f[idx].
+struct AdjTables {
+    int p = 0, nu = 0, width_t = 0, width_g = 0;
+    std::vector<int32_t> t_idx;   // (3C) x width_t, indices into [0, 3 nu)
+    std::vector<double> t_w;
+    std::vector<int32_t> g_idx;   // (3 nu) x width_g, indices into [0, C)
+    std::vector<double> g_w;
+};
+AdjTables adj_tables(int p);
+
 // Recurrence constants for the balanced regular harmonics, index n(n+1)/2 + m:
 //   Rb_m^m   = -(X + iY) diag[m] Rb_{m-1}^{m-1},  diag[m] = sqrt((2m-1)/(2m))
 //   Rb_n^m   = c1 Z Rb_{n-1}^m - c2 r^2 Rb_{n-2}^m  (n > m)

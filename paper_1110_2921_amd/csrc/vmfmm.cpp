@@ -77,6 +77,11 @@ struct OpSet {
     DevBuf c1_64, c2_64, dg_64, c1_32, c2_32, dg_32;
     DevBuf l2p_idx, l2p_w64, l2p_w32;
     int width = 0, nu = 0, ng = 0;
+    // adjoint: transposed operators and tables (built on first use)
+    bool adj_ready = false;
+    DevBuf m2lT64, m2lT32, m2mT64, m2mT32, l2lT64, l2lT32;
+    DevBuf t_idx, t_w64, t_w32, g_idx, g_w64, g_w32;
+    int width_t = 0, width_g = 0;
 };
 
 }  // namespace
@@ -88,6 +93,9 @@ struct vm_ctx {
 
     // workspace
     DevBuf keys_a, keys_b, vals_a, vals_b, hist, start, p64, p32, far, flag, mbuf, lbuf;
+    DevBuf rk_u, rk_s, rk_x, rk_a, diag;
+    DevBuf adj_u, adj_J, adj_v, adj_Jv, adj_far, adj_p64, adj_p32;
+    std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice_t;
     int layout_p = -1, layout_prec = -1;   // layout of mbuf/lbuf
     // results of the last evaluation, for the debug views
     uint32_t *last_keys = nullptr;
@@ -236,6 +244,83 @@ vm_status ensure_lattice(vm_ctx *ctx, int p, int K, const double **out) {
         auto b = std::make_unique<DevBuf>();
         VM_HIP(upload(*b, m), "upload lattice operator");
         it = ctx->lattice.emplace(key, std::move(b)).first;
+    }
+    *out = it->second->as<double>();
+    return VM_OK;
+}
+
+vm_status ensure_adj_ops(vm_ctx *ctx, OpSet *set) {
+    if (set->adj_ready) return VM_OK;
+    const int p = set->p;
+    const int C = ncoef(p), cp = pad16(C), kp = pad4(C);
+    const size_t frag = size_t(cp) * kp;
+    const OffsetTable &t = offset_table();
+    std::vector<double> m(size_t(C) * C), mt(size_t(C) * C);
+    auto transpose = [&]() {
+        for (int i = 0; i < C; ++i)
+            for (int j = 0; j < C; ++j) mt[size_t(j) * C + i] = m[size_t(i) * C + j];
+    };
+    {
+        // operator for offset d applied in the adjoint gather is T_{-d}^T
+        std::vector<double> o64(316 * frag);
+        std::vector<float> o32(316 * frag);
+        for (int i = 0; i < 316; ++i) {
+            const double D[3] = {double(t.d[i][0]), double(t.d[i][1]), double(t.d[i][2])};   // target - source of -d
+            m2l_matrix(p, D, 1.0, 1.0, m.data());
+            transpose();
+            swizzle(mt, C, o64, i * frag);
+            swizzle(mt, C, o32, i * frag);
+        }
+        VM_HIP(upload(set->m2lT64, o64), "upload M2L^T");
+        VM_HIP(upload(set->m2lT32, o32), "upload M2L^T");
+    }
+    {
+        std::vector<double> a64(8 * frag), b64(8 * frag);
+        std::vector<float> a32(8 * frag), b32(8 * frag);
+        for (int o = 0; o < 8; ++o) {
+            const double d[3] = {((o & 1) - 0.5) * 0.5, (((o >> 1) & 1) - 0.5) * 0.5, (((o >> 2) & 1) - 0.5) * 0.5};
+            m2m_matrix(p, d, 0.5, 1.0, m.data());
+            transpose();
+            swizzle(mt, C, a64, o * frag);
+            swizzle(mt, C, a32, o * frag);
+            l2l_matrix(p, d, 1.0, 0.5, m.data());
+            transpose();
+            swizzle(mt, C, b64, o * frag);
+            swizzle(mt, C, b32, o * frag);
+        }
+        VM_HIP(upload(set->m2mT64, a64), "upload M2M^T");
+        VM_HIP(upload(set->m2mT32, a32), "upload M2M^T");
+        VM_HIP(upload(set->l2lT64, b64), "upload L2L^T");
+        VM_HIP(upload(set->l2lT32, b32), "upload L2L^T");
+    }
+    {
+        const AdjTables a = adj_tables(p);
+        std::vector<float> tw(a.t_w.begin(), a.t_w.end()), gw(a.g_w.begin(), a.g_w.end());
+        VM_HIP(upload(set->t_idx, a.t_idx), "upload adjoint tables");
+        VM_HIP(upload(set->t_w64, a.t_w), "upload adjoint tables");
+        VM_HIP(upload(set->t_w32, tw), "upload adjoint tables");
+        VM_HIP(upload(set->g_idx, a.g_idx), "upload adjoint tables");
+        VM_HIP(upload(set->g_w64, a.g_w), "upload adjoint tables");
+        VM_HIP(upload(set->g_w32, gw), "upload adjoint tables");
+        set->width_t = a.width_t;
+        set->width_g = a.width_g;
+    }
+    set->adj_ready = true;
+    return VM_OK;
+}
+
+vm_status ensure_lattice_t(vm_ctx *ctx, int p, int K, const double **out) {
+    const auto key = std::make_pair(p, K);
+    auto it = ctx->lattice_t.find(key);
+    if (it == ctx->lattice_t.end()) {
+        const int C = ncoef(p);
+        std::vector<double> m(size_t(C) * C), mt(size_t(C) * C);
+        lattice_matrix(p, K, m.data());
+        for (int i = 0; i < C; ++i)
+            for (int j = 0; j < C; ++j) mt[size_t(j) * C + i] = m[size_t(i) * C + j];
+        auto b = std::make_unique<DevBuf>();
+        VM_HIP(upload(*b, mt), "upload lattice operator");
+        it = ctx->lattice_t.emplace(key, std::move(b)).first;
     }
     *out = it->second->as<double>();
     return VM_OK;
@@ -467,6 +552,175 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
         VM_HIP(hipStreamSynchronize(s), "synchronize");
         if (flag) return fail(ctx, VM_EDOMAIN, "non-finite or out-of-box position");
     }
+    return VM_OK;
+}
+
+vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                         int level, const vm_opts *opts, const double *u_bar, double *x_bar, double *alpha_bar) {
+    if (!ctx) return VM_EINVAL;
+    if (!u_bar) return fail(ctx, VM_EINVAL, "u_bar must be non-NULL");
+    if (reinterpret_cast<uintptr_t>(u_bar) & 7u) return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    if ((x_bar && (reinterpret_cast<uintptr_t>(x_bar) & 7u)) || (alpha_bar && (reinterpret_cast<uintptr_t>(alpha_bar) & 7u)))
+        return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t v3 = sizeof(double) * 3 * size_t(n), v9 = sizeof(double) * 9 * size_t(n);
+    VM_HIP(ctx->adj_u.reserve(v3), "alloc adjoint");
+    VM_HIP(ctx->adj_J.reserve(v9), "alloc adjoint");
+    // 1. forward state: tree, expansions, far field and the total gradient J
+    vm_status st = vm_fmm_eval(ctx, n, x, alpha, sigma, p, level, opts, ctx->adj_u.as<double>(), nullptr,
+                               ctx->adj_J.as<double>());
+    if (st != VM_OK) return st;
+    hipStream_t s = ctx->stream;
+    const int mixed = opts->precision == VM_MIXED;
+    const int K = opts->periodic, periodic = K > 0;
+    const int ni = int(n);
+    const int64_t nleaf = int64_t(1) << (3 * level);
+    const int C = ncoef(p), kp = pad4(C);
+    OpSet *ops = ctx->ops[p].get();
+    if (vm_status e = ensure_adj_ops(ctx, ops); e != VM_OK) return e;
+    const double *tlat_t = nullptr;
+    if (K >= 2)
+        if (vm_status e = ensure_lattice_t(ctx, p, K, &tlat_t); e != VM_OK) return e;
+    VM_HIP(ctx->adj_v.reserve(v3), "alloc adjoint");
+    VM_HIP(ctx->adj_Jv.reserve(v9), "alloc adjoint");
+    VM_HIP(ctx->adj_far.reserve(2 * v3), "alloc adjoint");
+    if (mixed) VM_HIP(ctx->adj_p32.reserve(sizeof(Part32) * n), "alloc adjoint");
+    else VM_HIP(ctx->adj_p64.reserve(sizeof(Part64) * n), "alloc adjoint");
+    const int32_t *start = ctx->start.as<int32_t>();
+    const int32_t *perm = ctx->last_perm;
+    const double w = std::ldexp(opts->box_len, -level), inv_w = std::ldexp(1.0 / opts->box_len, level);
+    const void *parts = mixed ? (const void *)ctx->p32.ptr : (const void *)ctx->p64.ptr;
+
+    // 2. far field, transposed: L2P^T -> L2L^T (up) -> lattice^T -> M2M^T + M2L^T (down) -> P2M^T
+    const int lmin = periodic ? 0 : 2;
+    const bool far = ctx->last_far;
+    if (far) {
+        DevTables tab;
+        tab.c1_64 = ops->c1_64.as<double>(); tab.c2_64 = ops->c2_64.as<double>(); tab.diag_64 = ops->dg_64.as<double>();
+        tab.c1_32 = ops->c1_32.as<float>(); tab.c2_32 = ops->c2_32.as<float>(); tab.diag_32 = ops->dg_32.as<float>();
+        tab.l2p_idx = nullptr; tab.l2p_w64 = nullptr; tab.l2p_w32 = nullptr;
+        tab.l2p_width = 0; tab.nu = p * p; tab.ng = (p - 1) * (p - 1);
+        auto run = [&](auto tag) -> vm_status {
+            using T = decltype(tag);
+            const bool f32 = sizeof(T) == 4;
+            T *Mb = ctx->mbuf.as<T>(), *Lb = ctx->lbuf.as<T>();   // adjoints overwrite the forward state
+            auto lev = [&](T *b, int l) { return b + size_t(((int64_t(1) << (3 * l)) - 1) / 7) * 3 * kp; };
+            const T *m2lT = f32 ? (const T *)ops->m2lT32.ptr : (const T *)ops->m2lT64.ptr;
+            const T *m2mT = f32 ? (const T *)ops->m2mT32.ptr : (const T *)ops->m2mT64.ptr;
+            const T *l2lT = f32 ? (const T *)ops->l2lT32.ptr : (const T *)ops->l2lT64.ptr;
+            const T *tw = f32 ? (const T *)ops->t_w32.ptr : (const T *)ops->t_w64.ptr;
+            const T *gw = f32 ? (const T *)ops->g_w32.ptr : (const T *)ops->g_w64.ptr;
+            const int16_t *lists = ctx->octlists.as<int16_t>();
+            const int8_t *offs = ctx->offsets.as<int8_t>();
+            VM_HIP(launch_l2p_adj<T>(s, int(nleaf), ni, parts, start, perm, u_bar, p, kp, inv_w, w, tab,
+                                     ops->t_idx.as<int32_t>(), tw, ops->width_t, lev(Lb, level)),
+                   "L2P^T");
+            const int lstart = periodic ? 1 : 2;
+            auto had_l2l = [&](int l) { return l > lstart || (periodic && K >= 2 && l == 1); };
+            for (int l = level; l >= lstart; --l)
+                if (had_l2l(l))
+                    VM_HIP(launch_translate<T>(s, 2, l - 1, periodic, p, kp, l2lT, lists, offs, lev(Lb, l),
+                                               lev(Lb, l - 1), 0),
+                           "L2L^T");
+            bool parent = false;
+            if (periodic && K >= 2) {
+                VM_HIP(launch_lattice<T>(s, p, kp, tlat_t, lev(Lb, 0), lev(Mb, 0)), "lattice^T");
+                parent = true;
+            }
+            for (int l = periodic ? 1 : lmin; l <= level; ++l) {
+                if (parent)
+                    VM_HIP(launch_translate<T>(s, 1, l, periodic, p, kp, m2mT, lists, offs, lev(Mb, l - 1),
+                                               lev(Mb, l), 0),
+                           "M2M^T");
+                VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2lT, lists, offs, lev(Lb, l), lev(Mb, l),
+                                           parent ? 1 : 0),
+                       "M2L^T");
+                parent = true;
+            }
+            VM_HIP(launch_p2m_adj<T>(s, int(nleaf), ni, parts, start, p, kp, inv_w, tab, ops->g_idx.as<int32_t>(), gw,
+                                     ops->width_g, lev(Mb, level), ctx->adj_far.as<double>()),
+                   "P2M^T");
+            return VM_OK;
+        };
+        st = mixed ? run(float()) : run(double());
+        if (st != VM_OK) return st;
+    }
+
+    // 3. near field with u_bar as strengths: v and its gradient Jv (caller order)
+    P2PArgs a;
+    a.n = ni;
+    a.nleaf = int(nleaf);
+    a.level = level;
+    a.periodic = periodic;
+    a.scheme = 0;
+    a.have_far = 0;
+    a.w = w;
+    a.sigma = sigma;
+    a.start = start;
+    a.perm = perm;
+    a.alpha = nullptr;
+    a.far = nullptr;
+    a.u = ctx->adj_v.as<double>();
+    a.dalpha = nullptr;
+    a.grad = ctx->adj_Jv.as<double>();
+    if (mixed) {
+        VM_HIP(launch_parts_with32(s, ni, ctx->p32.as<Part32>(), perm, u_bar, ctx->adj_p32.as<Part32>()), "adjoint");
+        VM_HIP(launch_p2p32(s, a, ctx->adj_p32.as<Part32>()), "P2P^T");
+    } else {
+        VM_HIP(launch_parts_with64(s, ni, ctx->p64.as<Part64>(), perm, u_bar, ctx->adj_p64.as<Part64>()), "adjoint");
+        VM_HIP(launch_p2p64(s, a, ctx->adj_p64.as<Part64>()), "P2P^T");
+    }
+    // 4. combine
+    VM_HIP(launch_adj_combine(s, ni, perm, u_bar, alpha, ctx->adj_J.as<double>(), ctx->adj_v.as<double>(),
+                              ctx->adj_Jv.as<double>(), far ? ctx->adj_far.as<double>() : nullptr, x_bar, alpha_bar),
+           "adjoint combine");
+    return VM_OK;
+}
+
+vm_status vm_rk2_step(vm_ctx *ctx, int64_t n, double *x, double *alpha, double sigma, int p, int level,
+                      const vm_opts *opts, double dt, double *u0, double *grad0) {
+    if (!ctx) return VM_EINVAL;
+    if (!opts || !x || !alpha) return fail(ctx, VM_EINVAL, "opts, x and alpha must be non-NULL");
+    if (!std::isfinite(dt)) return fail(ctx, VM_EINVAL, "dt must be finite");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t bytes = sizeof(double) * 3 * size_t(n);
+    VM_HIP(ctx->rk_u.reserve(bytes), "alloc rk");
+    VM_HIP(ctx->rk_s.reserve(bytes), "alloc rk");
+    VM_HIP(ctx->rk_x.reserve(bytes), "alloc rk");
+    VM_HIP(ctx->rk_a.reserve(bytes), "alloc rk");
+    double *u = u0 ? u0 : ctx->rk_u.as<double>();
+    double *sv = ctx->rk_s.as<double>();
+    vm_status st = vm_fmm_eval(ctx, n, x, alpha, sigma, p, level, opts, u, sv, grad0);
+    if (st != VM_OK) return st;
+    const int ni = int(n);
+    VM_HIP(launch_rk_stage1(ctx->stream, ni, x, alpha, u, sv, dt, ctx->rk_x.as<double>(), ctx->rk_a.as<double>()),
+           "rk stage 1");
+    u = ctx->rk_u.as<double>();
+    st = vm_fmm_eval(ctx, n, ctx->rk_x.as<double>(), ctx->rk_a.as<double>(), sigma, p, level, opts, u, sv, nullptr);
+    if (st != VM_OK) return st;
+    TreeGeom g;
+    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
+    g.box_len = opts->box_len;
+    g.inv_len = 1.0 / opts->box_len;
+    g.inv_w = 0.0;
+    g.w = 0.0;
+    g.level = level;
+    g.periodic = opts->periodic > 0;
+    VM_HIP(launch_rk_stage2(ctx->stream, ni, x, alpha, u, sv, dt, g), "rk stage 2");
+    return VM_OK;
+}
+
+vm_status vm_diagnostics(vm_ctx *ctx, int64_t n, const double *u, const double *grad, const double *alpha,
+                         double h3, double *out) {
+    if (!ctx) return VM_EINVAL;
+    if (!u || !out) return fail(ctx, VM_EINVAL, "u and out must be non-NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
+    if (!(h3 > 0.0)) return fail(ctx, VM_EINVAL, "h3 must be positive");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    VM_HIP(ctx->diag.reserve(sizeof(double) * 3 * 1024), "alloc diagnostics");
+    VM_HIP(launch_diagnostics(ctx->stream, int(n), u, grad, alpha, h3, ctx->diag.as<double>(), out), "diagnostics");
     return VM_OK;
 }
 

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     text = open(os.path.join(ROOT, "include", "vmfmm.h")).read()
-    decl = r"^(?:vm_status|void|const char \*)\s*(vm_[a-z_]+)\s*\("
+    decl = r"^(?:vm_status|void|const char \*)\s*(vm_[a-z0-9_]+)\s*\("
     return sorted(set(re.findall(decl, text, flags=re.M)))
 
 

@@ -1,0 +1,188 @@
+"""GPU checks of the adjoint FMM, the Heun step and the diagnostics.
+
+Tolerances:
+* dot-product test <u_bar, B alpha> = <B^T u_bar, alpha> (u is linear in alpha): 1e-12 relative;
+* central finite differences (FP64, eps = 1e-6, 32 particles, random directions) of
+  L = h^3/2 sum |u|^2: 1e-6 relative per directional derivative (FD truncation ~eps^2);
+* direct-sum reference gradient (exact kernel, images S_1) at N = 4096:
+    dL/dalpha_k = h^3 v_k,  dL/dx_k = h^3 (J_k u_k + J^v_k alpha_k)
+  with v, J^v the field and gradient of strengths u: 1e-4 (FMM truncation at p = 10);
+* FP32 adjoint vs FP64 adjoint: 1e-4;
+* Heun step against the same step built from the oracle FMM: 1e-10.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct as D
+from oracle import fmm as OF
+from oracle import tree as T
+
+pytestmark = pytest.mark.gpu
+
+L = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1110_2921_amd as vm
+    return vm.FMM(0)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64).T)).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy().T
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+CASE = dict(ng=16, k0=4.0, seed=31, p=8, level=2, K=3)
+
+
+def _case():
+    x, a = W.random_field(CASE["ng"], CASE["k0"], CASE["seed"])
+    h = L / CASE["ng"]
+    return x, a, h
+
+
+def _loss(ctx, x, a, h, precision="fp64", K=None):
+    import torch
+    u, _, _ = ctx.eval(_dev(x), _dev(a), h, CASE["p"], CASE["level"], periodic=CASE["K"] if K is None else K,
+                       precision=precision, want_dalpha=False)
+    torch.cuda.synchronize()
+    u = _host(u)
+    return 0.5 * h ** 3 * np.sum(u * u), u
+
+
+def test_dot_product_identity(ctx):
+    x, a, h = _case()
+    rng = np.random.default_rng(1)
+    ubar = rng.standard_normal(x.shape)
+    _, u = _loss(ctx, x, a, h)
+    _, ab = ctx.adjoint(_dev(x), _dev(a), _dev(ubar), h, CASE["p"], CASE["level"], periodic=CASE["K"],
+                        want_x=False)
+    lhs = np.sum(ubar * u)
+    rhs = np.sum(_host(ab) * a)
+    assert abs(lhs - rhs) < 1e-12 * np.sum(np.abs(ubar * u))
+
+
+def _fd(ctx, x, a, h, xp, xm, ap, am, eps):
+    """Central difference of L = h^3/2 sum |u|^2, formed as h^3/2 sum (u+ - u-).(u+ + u-)
+    (the same number as L+ - L-, without cancelling the ~10^2-sized L)."""
+    _, up = _loss(ctx, xp, ap, h)
+    _, um = _loss(ctx, xm, am, h)
+    return 0.5 * h ** 3 * np.sum((up - um) * (up + um)) / (2 * eps)
+
+
+def test_finite_differences(ctx):
+    x, a, h = _case()
+    _, u = _loss(ctx, x, a, h)
+    xb, ab = ctx.adjoint(_dev(x), _dev(a), _dev(h ** 3 * u), h, CASE["p"], CASE["level"], periodic=CASE["K"])
+    xb, ab = _host(xb), _host(ab)
+    rng = np.random.default_rng(2)
+    eps = 1e-6
+    for k in rng.choice(len(x), 32, replace=False):
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        xp, xm = x.copy(), x.copy()
+        xp[k] += eps * e
+        xm[k] -= eps * e
+        fd = _fd(ctx, x, a, h, xp, xm, a, a, eps)
+        an = float(xb[k] @ e)
+        assert abs(fd - an) < 1e-6 * max(abs(an), 1e-3 * np.abs(xb).max()), (k, fd, an)
+    for k in rng.choice(len(x), 8, replace=False):
+        e = rng.standard_normal(3)
+        ap, am = a.copy(), a.copy()
+        ap[k] += eps * e
+        am[k] -= eps * e
+        fd = _fd(ctx, x, a, h, x, x, ap, am, eps)
+        an = float(ab[k] @ e)
+        assert abs(fd - an) < 1e-6 * max(abs(an), 1e-3 * np.abs(ab).max()), (k, fd, an)
+
+
+def test_direct_sum_reference_gradient(ctx):
+    x, a = W.random_field(16, 4.0, 37)
+    h = L / 16
+    K, p, level = 1, 10, 2
+    tr = T.build(x, (0, 0, 0), L, level, 1)
+    xw = tr["xw"]
+    u, J = D.direct(xw, xw, a, h, L, K=K)
+    v, Jv = D.direct(xw, xw, h ** 3 * u, h, L, K=K)
+    ab_ref = v
+    xb_ref = h ** 3 * (np.einsum("iab,ib->ia", J, u) + np.einsum("iab,ib->ia", Jv / h ** 3, a))
+    import torch
+    ug, _, _ = ctx.eval(_dev(x), _dev(a), h, p, level, periodic=K, want_dalpha=False)
+    torch.cuda.synchronize()
+    xb, ab = ctx.adjoint(_dev(x), _dev(a), h ** 3 * ug, h, p, level, periodic=K)
+    assert rel(_host(ab), ab_ref) < 1e-4
+    assert rel(_host(xb), xb_ref) < 1e-4
+
+
+def test_mixed_adjoint_matches_fp64(ctx):
+    x, a, h = _case()
+    _, u = _loss(ctx, x, a, h)
+    ub = _dev(h ** 3 * u)
+    args = (h, CASE["p"], CASE["level"])
+    xb, ab = ctx.adjoint(_dev(x), _dev(a), ub, *args, periodic=CASE["K"])
+    xm, am = ctx.adjoint(_dev(x), _dev(a), ub, *args, periodic=CASE["K"], precision="mixed")
+    assert rel(_host(am), _host(ab)) < 1e-4
+    assert rel(_host(xm), _host(xb)) < 1e-4
+
+
+def test_autograd_function(ctx):
+    import torch
+    import paper_1110_2921_amd as vm
+    x, a, h = _case()
+    xt = _dev(x).requires_grad_(True)
+    at = _dev(a).requires_grad_(True)
+    u = vm.velocity(xt, at, ctx, h, CASE["p"], CASE["level"], periodic=CASE["K"])
+    loss = 0.5 * h ** 3 * (u * u).sum()
+    gx, ga = torch.autograd.grad(loss, (xt, at))
+    xb, ab = ctx.adjoint(_dev(x), _dev(a), (h ** 3 * u).detach(), h, CASE["p"], CASE["level"],
+                         periodic=CASE["K"])
+    assert torch.equal(gx, xb) and torch.equal(ga, ab)
+
+
+def test_heun_step_matches_oracle(ctx):
+    import torch
+    x, a = W.random_field(8, 2.0, 41)
+    h = L / 8
+    p, level, K, dt = 6, 1, 3, 0.05
+    xt, at = _dev(x), _dev(a)
+    ctx.rk2_step(xt, at, h, p, level, dt, periodic=K)
+    torch.cuda.synchronize()
+
+    def rates(xx, aa):
+        u, J = OF.fmm(xx, aa, h, p, level, periodic=K)
+        return u, D.stretching(J, aa)
+
+    u1, s1 = rates(x, a)
+    u2, s2 = rates(x + dt * u1, a + dt * s1)
+    x1 = T.wrap(x + 0.5 * dt * u1 + 0.5 * dt * u2, (0, 0, 0), L)
+    a1 = a + 0.5 * dt * s1 + 0.5 * dt * s2
+    assert rel(_host(xt), x1) < 1e-10
+    assert rel(_host(at), a1) < 1e-10
+
+
+def test_diagnostics(ctx):
+    import torch
+    x, a, h = _case()
+    u, _, J = ctx.eval(_dev(x), _dev(a), h, 6, 2, periodic=3, want_grad=True)
+    d = ctx.diagnostics(u, J, _dev(a), h ** 3).cpu().numpy()
+    un, Jn = _host(u), _host(J).reshape(-1, 3, 3)
+    w = np.stack([Jn[:, 1, 2] - Jn[:, 2, 1], Jn[:, 2, 0] - Jn[:, 0, 2], Jn[:, 0, 1] - Jn[:, 1, 0]], 1)
+    ref = [0.5 * h ** 3 * np.sum(un * un), 0.5 * h ** 3 * np.sum(w * w), 0.5 * np.sum(a * a) / h ** 3]
+    assert np.allclose(d, ref, rtol=1e-13, atol=0)
+    d2 = ctx.diagnostics(u, J, _dev(a), h ** 3).cpu().numpy()
+    assert np.array_equal(d, d2)
