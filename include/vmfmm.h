@@ -200,11 +200,15 @@ vm_status vm_debug_list(int level, int periodic, int32_t key, int32_t *src, int8
 
 /*
  * Host-only: the translation operators in the library's real basis, FP64,
- * row-major C x C with C = (p+1)^2 (no device work).
+ * row-major C x C with C = (p+1)^2 unless stated (no device work).
  *   kind 0: M2L for offset index `index` (0..315, the vm_debug_offsets order)
  *   kind 1: M2M for child octant `index` (0..7)
  *   kind 2: L2L for child octant `index` (0..7)
  *   kind 3: periodic lattice operator for K = `index` (1..4)
+ *   kind 4: derivative table of the multipole basis, 3 p^2 x C (not C x C):
+ *           row a p^2 + s (a < 3, s < p^2) holds the coefficients of c_s in
+ *           dF/dY_a for F(Y) = sum_t f_t c_t(Y), c = [Rb^0, Re Rb^m, -Im Rb^m]
+ *           (index is ignored)
  * The basis: solid harmonics R_n^m = r^n P_n^m(cos t) e^{i m phi} / (n+m)!
  * (P with the Condon-Shortley phase) scaled by sqrt((n+m)!(n-m)!); a cell of
  * width w stores M_n^m = sum_j q_j conj(R_n^m((x_j - c)/w)) and locals with

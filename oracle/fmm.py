@@ -171,3 +171,115 @@ def fmm(x, alpha, sigma, p, level, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, 
         J_near[ids] = J
     del leaf_of
     return u_far + u_near, J_far + J_near
+
+
+def fmm_at(x, alpha, sigma, p, level, targets, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, periodic=0,
+           chunk=1 << 18):
+    """u and J of ``fmm`` at the particles ``targets`` only (indices in caller order).
+
+    Same steps and arithmetic as ``fmm``: P2M for every leaf and M2M for every
+    cell, but the downward pass only along the ancestors of the targets'
+    leaves, and L2P / P2P only at the targets.  Used to check the full-size
+    workloads one sampled particle at a time.
+    """
+    x = np.asarray(x, np.float64)
+    alpha = np.asarray(alpha, np.float64)
+    targets = np.asarray(targets, np.int64)
+    lo = np.asarray(box_lo, np.float64)
+    tr = T.build(x, lo, box_len, level, periodic)
+    xw, perm, start, count, keys = tr["xw"], tr["perm"], tr["start"], tr["count"], tr["keys"]
+    nleaf = 1 << (3 * level)
+    C = H.ncoef(p)
+    lmin = 0 if periodic else 2
+    far = level >= lmin
+    nt = len(targets)
+    u = np.zeros((nt, 3))
+    J = np.zeros((nt, 3, 3))
+    tleaf = keys[targets]
+    if far:
+        centres = _centres(np.arange(nleaf), level, lo, box_len)
+        neg = np.array([H.idx(n, -m) for n in range(p + 1) for m in range(-n, n + 1)])
+        M = {level: np.zeros((nleaf, 3, C), np.complex128)}
+        # P2M, a run of whole leaves at a time (particles are contiguous per leaf);
+        # M[leaf] = sum over its particles of alpha_j R^{-m}(y_j)
+        leaf_lo = 0
+        while leaf_lo < nleaf:
+            leaf_hi = leaf_lo
+            while leaf_hi < nleaf and start[leaf_hi] + count[leaf_hi] - start[leaf_lo] <= chunk:
+                leaf_hi += 1
+            leaf_hi = max(leaf_hi, leaf_lo + 1)
+            a0, a1 = start[leaf_lo], start[leaf_hi - 1] + count[leaf_hi - 1]
+            if a1 > a0:
+                ids = perm[a0:a1]
+                lf = keys[ids]
+                R = H.regular(xw[ids] - centres[lf], p)[:, neg]
+                al = alpha[ids]
+                cnts = count[leaf_lo:leaf_hi]
+                if np.all(cnts == cnts[0]):
+                    k = int(cnts[0])
+                    M[level][leaf_lo:leaf_hi] = np.einsum("lpk,lpc->lkc", al.reshape(-1, k, 3),
+                                                          R.reshape(-1, k, C))
+                else:
+                    segs = start[leaf_lo:leaf_hi] - a0
+                    occupied = cnts > 0
+                    sums = np.add.reduceat(al[:, :, None] * R[:, None, :], segs[occupied], axis=0)
+                    M[level][np.arange(leaf_lo, leaf_hi)[occupied]] = sums
+            leaf_lo = leaf_hi
+        for l in range(level - 1, lmin - 1, -1):
+            wc = box_len / (1 << (l + 1))
+            M[l] = np.zeros((1 << (3 * l), 3, C), np.complex128)
+            for o in range(8):
+                ob = np.array([(o >> d) & 1 for d in range(3)], np.float64)
+                M[l] += M[l + 1][o::8] @ H.m2m_matrix((ob - 0.5) * wc, p).T
+        # downward pass along the ancestor chains
+        Lc = {}
+        if periodic:
+            Lc[0] = {0: lattice_local(M[0][0], p, box_len, periodic)}
+        for l in range(1 if periodic else lmin, level + 1):
+            cells = np.unique(tleaf >> (3 * (level - l)))
+            Ll = {int(c): np.zeros((3, C), np.complex128) for c in cells}
+            if (l - 1) in Lc:
+                w = box_len / (1 << l)
+                for c in cells:
+                    o = int(c) & 7
+                    ob = np.array([(o >> d) & 1 for d in range(3)], np.float64)
+                    Ll[int(c)] += (H.l2l_matrix(-(ob - 0.5) * w, p) @ Lc[l - 1][int(c) >> 3].T).T
+            mats = _m2l_matrices(l, p, box_len)
+            side = 1 << l
+            coords = T.demorton(cells, l)
+            for c, cc in zip(cells, coords):
+                o = int(c) & 7
+                for d in T.offsets_for_octant(o):
+                    sc = cc + np.array(d)
+                    if periodic:
+                        sc = np.mod(sc, side)
+                    elif np.any(sc < 0) or np.any(sc >= side):
+                        continue
+                    sk = int(T.morton(sc[None], l)[0])
+                    Ll[int(c)] += (mats[d] @ M[l][sk].T).T
+            Lc[l] = Ll
+        centres_t = centres[tleaf]
+        for i, t in enumerate(targets):
+            g, h = H.local_derivs(Lc[level][int(tleaf[i])], (xw[t] - centres_t[i])[None], p)
+            u[i] = [g[0, 2, 1] - g[0, 1, 2], g[0, 0, 2] - g[0, 2, 0], g[0, 1, 0] - g[0, 0, 1]]
+            for a in range(3):
+                J[i, a] = [h[0, 2, a, 1] - h[0, 1, a, 2], h[0, 0, a, 2] - h[0, 2, a, 0],
+                           h[0, 1, a, 0] - h[0, 0, a, 1]]
+        u *= INV4PI
+        J *= INV4PI
+    coords_leaf = T.demorton(np.unique(tleaf), level)
+    leaf_coord = dict(zip(np.unique(tleaf).tolist(), coords_leaf))
+    for i, t in enumerate(targets):
+        srcs, shifts = [], []
+        for nk, img in T.neighbours(leaf_coord[int(tleaf[i])], level, periodic):
+            if count[nk] == 0:
+                continue
+            sid = perm[start[nk]:start[nk] + count[nk]]
+            srcs.append(sid)
+            shifts.append(np.broadcast_to(np.array(img, np.float64) * box_len, (len(sid), 3)))
+        sid = np.concatenate(srcs)
+        xs = xw[sid] + np.concatenate(shifts)
+        un, Jn = _direct.direct(xw[t][None], xs, alpha[sid], sigma, box_len, K=0)
+        u[i] += un[0]
+        J[i] += Jn[0]
+    return u, J

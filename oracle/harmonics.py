@@ -66,13 +66,21 @@ def regular(x, deg):
     X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
     r2 = X * X + Y * Y + Z * Z
     w = X + 1j * Y
+    # power tables z^e, (r^2)^k, (x + i y)^m
+    zp = [np.ones_like(Z)]
+    r2p = [np.ones_like(Z)]
+    wp = [np.ones_like(w)]
+    for _ in range(deg):
+        zp.append(zp[-1] * Z)
+        r2p.append(r2p[-1] * r2)
+        wp.append(wp[-1] * w)
     out = np.zeros((x.shape[0], ncoef(deg)), np.complex128)
     for n in range(deg + 1):
         for m in range(n + 1):
             s = np.zeros_like(X)
             for k, c in _legendre_deriv(n, m):
-                s = s + c * Z ** (n - 2 * k - m) * r2 ** k
-            v = _norm(n, m) * w ** m * s
+                s = s + c * (zp[n - 2 * k - m] * r2p[k])
+            v = _norm(n, m) * wp[m] * s
             out[:, idx(n, m)] = v
             out[:, idx(n, -m)] = np.conj(v)
     return out

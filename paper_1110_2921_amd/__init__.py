@@ -270,7 +270,7 @@ def debug_list(level, periodic, key):
 def debug_operator(kind, p, index):
     lib = _lib.load()
     C = (p + 1) ** 2
-    out = np.zeros((C, C), np.float64)
+    out = np.zeros((3 * p * p if kind == 4 else C, C), np.float64)
     st = lib.vm_debug_operator(int(kind), int(p), int(index), out.ctypes.data)
     if st != _lib.VM_OK:
         raise _lib.VmError(st, "vm_debug_operator")

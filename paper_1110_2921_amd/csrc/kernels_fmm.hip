@@ -148,16 +148,16 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
 }
 
 // ----------------------------------------------------------- translate ----
-// One workgroup (4 waves) owns TT target cells that share one pair list.
-// For each pair (operator op, sources of the TT targets) the sources'
-// coefficients are staged in LDS and every wave multiplies its row blocks
-// of the operator (pre-swizzled into MFMA A fragments) against them:
-//   out[tile] (Cp x 3TT) += Op (Cp x kp) * Src (kp x 3TT).
+// One workgroup (4 waves) owns TTN = 16 NT target cells that share one pair
+// list (M2L: one octant).  For each pair (operator op, one source per target)
+// the sources' coefficients are staged in LDS and every wave multiplies its
+// row blocks of the operator (pre-swizzled into MFMA A fragments, read
+// straight from memory with a one-step prefetch) against all 3 TTN columns:
+//   out[tile] (Cp x 3 TTN) += Op (Cp x kp) * Src (kp x 3 TTN).
+// The local coefficients stay in accumulator registers across the 189 pairs.
 // MFMA 16x16x4: A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16);
 // accumulator register r of lane l holds column l%16 and row (l/16) + 4r for
 // FP64, 4(l/16) + r for FP32 (both checked on gfx950).
-constexpr int TT = 16;
-
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
     typedef double v4 __attribute__((ext_vector_type(4)));
@@ -190,23 +190,36 @@ __device__ __forceinline__ int demorton1(uint32_t k, int d, int level) {
     return c;
 }
 
-template <typename T, int NRBW, int mode>
-__global__ void __launch_bounds__(256) k_translate(int level, int periodic, int C, int kp,
-                                                   int nrb, const T *__restrict__ ops,
-                                                   const int16_t *__restrict__ oct_lists,
-                                                   const int8_t *__restrict__ offsets,
-                                                   const T *__restrict__ src, T *__restrict__ dst,
-                                                   int accumulate) {
+// Workgroup of 8 waves (two per SIMD); wave w owns the row blocks w, w+8, ...
+// PF > 0: the sources of pair k+1 are loaded into registers (PF per thread)
+// while pair k runs on the MFMA units, then written to the other LDS buffer,
+// so each pair costs one barrier and the loads overlap the matrix work.
+// PF = 0: single buffer, loads and compute in turn (large p).
+constexpr int kTrThreads = 512;
+constexpr int kTrWaves = kTrThreads / 64;
+
+template <typename T, int NRBW, int NT, int mode, int PF>
+__global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodic, int C, int kp,
+                                                          int nrb, const T *__restrict__ ops,
+                                                          const int16_t *__restrict__ oct_lists,
+                                                          const int8_t *__restrict__ offsets,
+                                                          const T *__restrict__ src, T *__restrict__ dst,
+                                                          int accumulate) {
     using V = typename Mfma<T>::v4;
+    constexpr int TTN = 16 * NT;
+    constexpr int NCB = 3 * NT;                          // column blocks: (group, component)
+    constexpr int NBUF = PF > 0 ? 2 : 1;
     extern __shared__ unsigned char smem_raw[];
     const int ks_stride = kp + 1;                       // odd row stride: conflict-free B reads
-    T *bs = reinterpret_cast<T *>(smem_raw);             // [TT * 3][ks_stride]
-    __shared__ int32_t tkey[TT];
-    __shared__ int32_t skey[TT];
+    const int buf_elems = TTN * 3 * ks_stride;
+    T *bs = reinterpret_cast<T *>(smem_raw);             // [NBUF][TTN * 3][ks_stride]
+    __shared__ int32_t tkey[TTN];
+    __shared__ int32_t skey[2][TTN];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nks = kp / 4;
+    const int per_cell = 3 * kp;
+    const int stage_elems = TTN * per_cell;
 
-    // target cells of this tile
     int octant = 0, tile = blockIdx.x, npair = 1;
     int64_t ncell_t;
     if (mode == 2) {                  // M2M: targets are the parents at `level`
@@ -215,95 +228,172 @@ __global__ void __launch_bounds__(256) k_translate(int level, int periodic, int 
     } else {                          // M2L / L2L: targets at `level`, grouped by octant
         octant = blockIdx.x & 7;
         tile = blockIdx.x >> 3;
-        ncell_t = int64_t(1) << (3 * (level - 1));   // parents at level - 1
+        ncell_t = int64_t(1) << (3 * (level - 1));
         npair = mode == 0 ? 189 : 1;
     }
-    if (tid < TT) {
-        const int64_t slot = int64_t(tile) * TT + tid;
+    if (tid < TTN) {
+        const int64_t slot = int64_t(tile) * TTN + tid;
         int32_t k = -1;
         if (slot < ncell_t) k = mode == 2 ? int32_t(slot) : int32_t((slot << 3) | octant);
         tkey[tid] = k;
     }
-    V acc[NRBW][3];
+    const int side = 1 << level;
+    auto op_of = [&](int pr) -> int {
+        if (mode == 0) return oct_lists[octant * 189 + pr];
+        if (mode == 1) return octant;
+        return pr;
+    };
+    // source cell of target slot `tid` for pair `pr` (or -1)
+    auto source_key = [&](int pr) -> int32_t {
+        const int32_t t = tkey[tid];
+        if (t < 0) return -1;
+        if (mode == 0) {
+            const int op = op_of(pr);
+            int c[3];
+            for (int d = 0; d < 3; ++d) {
+                c[d] = demorton1(uint32_t(t), d, level) + offsets[op * 3 + d];
+                if (periodic) c[d] = (c[d] % side + side) % side;
+                else if (c[d] < 0 || c[d] >= side) return -1;
+            }
+            return int32_t(morton3(c[0], c[1], c[2], level));
+        }
+        if (mode == 1) return t >> 3;
+        return (t << 3) | pr;
+    };
+    // staging map: thread tid serves target slot tid / TPT and walks that cell's
+    // 3 kp coefficients with stride TPT (coalesced within the slot's threads)
+    constexpr int TPT = kTrThreads / TTN;
+    const int st_t = tid / TPT, st_r0 = tid % TPT;
+    auto stage_direct = [&](int kb, T *buf) {
+        const int32_t sk = skey[kb][st_t];
+        int c = 0, k = st_r0;
+        for (int r = st_r0; r < per_cell; r += TPT) {
+            while (k >= kp) { k -= kp; ++c; }
+            buf[(st_t * 3 + c) * ks_stride + k] = sk >= 0 ? src[size_t(sk) * per_cell + r] : T(0);
+            k += TPT;
+        }
+    };
+    V acc[NRBW][NCB];
 #pragma unroll
     for (int i = 0; i < NRBW; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[i][c] = V{T(0), T(0), T(0), T(0)};
+        for (int c = 0; c < NCB; ++c) acc[i][c] = V{T(0), T(0), T(0), T(0)};
     __syncthreads();
 
-    const int side = 1 << level;
-    for (int pr = 0; pr < npair; ++pr) {
-        int op;
-        if (mode == 0) op = oct_lists[octant * 189 + pr];
-        else if (mode == 1) op = octant;
-        else op = pr;
-        if (tid < TT) {
-            const int32_t t = tkey[tid];
-            int32_t sk = -1;
-            if (t >= 0) {
-                if (mode == 0) {
-                    int c[3];
-                    bool ok = true;
-                    for (int d = 0; d < 3; ++d) {
-                        c[d] = demorton1(uint32_t(t), d, level) + offsets[op * 3 + d];
-                        if (periodic) c[d] = (c[d] % side + side) % side;
-                        else if (c[d] < 0 || c[d] >= side) ok = false;
-                    }
-                    if (ok) sk = int32_t(morton3(c[0], c[1], c[2], level));
-                } else if (mode == 1) {
-                    sk = t >> 3;
-                } else {
-                    sk = (t << 3) | pr;
-                }
-            }
-            skey[tid] = sk;
-        }
-        __syncthreads();
-        // stage the sources: TT cells x 3 components x kp, each cell contiguous
-        const int per_cell = 3 * kp;
-        for (int e = tid; e < TT * per_cell; e += 256) {
-            const int t = e / per_cell, r = e - t * per_cell;
-            const int c = r / kp, k = r - c * kp;
-            const int32_t sk = skey[t];
-            bs[(t * 3 + c) * ks_stride + k] = sk >= 0 ? src[size_t(sk) * per_cell + r] : T(0);
-        }
-        __syncthreads();
-        const T *opb = ops + size_t(op) * nrb * nks * 64;
-        for (int ks = 0; ks < nks; ++ks) {
-            T bfrag[3];
+    // A fragments stream from memory through a ring of APF registers per row
+    // block (prefetch distance APF k steps) to cover the L2 latency.
+    constexpr int APF = 8;
+    auto mfma_pair = [&](int pr, const T *buf) {
+        const T *opb = ops + size_t(op_of(pr)) * nrb * nks * 64;
+        T ring[APF][NRBW];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) bfrag[c] = bs[((lane & 15) * 3 + c) * ks_stride + ks * 4 + (lane >> 4)];
+        for (int d = 0; d < APF; ++d)
 #pragma unroll
             for (int i = 0; i < NRBW; ++i) {
-                const int rb = wave + 4 * i;
-                if (rb < nrb) {
-                    const T a = opb[(size_t(rb) * nks + ks) * 64 + lane];
+                const int rb = wave + kTrWaves * i;
+                ring[d][i] = (rb < nrb && d < nks) ? opb[(size_t(rb) * nks + d) * 64 + lane] : T(0);
+            }
+        for (int ks0 = 0; ks0 < nks; ks0 += APF) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[i][c] = Mfma<T>::op(a, bfrag[c], acc[i][c]);
+            for (int d = 0; d < APF; ++d) {
+                const int ks = ks0 + d;
+                if (ks < nks) {
+                    T a_use[NRBW];
+                    const int kn = ks + APF;
+#pragma unroll
+                    for (int i = 0; i < NRBW; ++i) {
+                        const int rb = wave + kTrWaves * i;
+                        a_use[i] = ring[d][i];
+                        if (rb < nrb && kn < nks) ring[d][i] = opb[(size_t(rb) * nks + kn) * 64 + lane];
+                    }
+                    T bfrag[NCB];
+#pragma unroll
+                    for (int g = 0; g < NT; ++g)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            bfrag[g * 3 + c] = buf[((g * 16 + (lane & 15)) * 3 + c) * ks_stride + ks * 4 + (lane >> 4)];
+#pragma unroll
+                    for (int i = 0; i < NRBW; ++i) {
+                        if (wave + kTrWaves * i < nrb) {
+#pragma unroll
+                            for (int cb = 0; cb < NCB; ++cb)
+                                acc[i][cb] = Mfma<T>::op(a_use[i], bfrag[cb], acc[i][cb]);
+                        }
+                    }
                 }
             }
         }
+    };
+
+    if constexpr (PF > 0) {
+        if (tid < TTN) skey[0][tid] = source_key(0);
         __syncthreads();
-    }
-    // write back: lane holds rows rb*16 + Mfma::row(lane, r) of target column lane%16
-    const int32_t t = tkey[lane & 15];
-    if (t < 0) return;
-    T *out = dst + size_t(t) * 3 * kp;
+        stage_direct(0, bs);
+        if (tid < TTN && npair > 1) skey[1][tid] = source_key(1);
+        __syncthreads();
+        for (int pr = 0; pr < npair; ++pr) {
+            const int cur = pr & 1, nxt = cur ^ 1;
+            const bool more = pr + 1 < npair;
+            T pf[PF];
+            if (more) {
+                const int32_t sk = skey[nxt][st_t];
+                const T *sp = src + size_t(sk >= 0 ? sk : 0) * per_cell;
 #pragma unroll
-    for (int i = 0; i < NRBW; ++i) {
-        const int rb = wave + 4 * i;
-        if (rb >= nrb) continue;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = rb * 16 + Mfma<T>::row(lane, r);
-                if (row < C) {
-                    const T v = acc[i][c][r];
-                    T *o = out + c * kp + row;
-                    *o = accumulate ? *o + v : v;
+                for (int j = 0; j < PF; ++j) {
+                    const int r = st_r0 + TPT * j;
+                    pf[j] = (sk >= 0 && r < per_cell) ? sp[r] : T(0);
                 }
             }
+            mfma_pair(pr, bs + cur * buf_elems);
+            if (more) {
+                T *nb = bs + nxt * buf_elems + st_t * 3 * ks_stride;
+                int c = 0, k = st_r0;
+#pragma unroll
+                for (int j = 0; j < PF; ++j) {
+                    const int r = st_r0 + TPT * j;
+                    if (r < per_cell) {
+                        while (k >= kp) { k -= kp; ++c; }
+                        nb[c * ks_stride + k] = pf[j];
+                        k += TPT;
+                    }
+                }
+            }
+            if (tid < TTN && pr + 2 < npair) skey[cur][tid] = source_key(pr + 2);
+            __syncthreads();
+        }
+    } else {
+        for (int pr = 0; pr < npair; ++pr) {
+            if (tid < TTN) skey[0][tid] = source_key(pr);
+            __syncthreads();
+            stage_direct(0, bs);
+            __syncthreads();
+            mfma_pair(pr, bs);
+            __syncthreads();
+        }
+    }
+    (void)NBUF;
+    // write back: lane holds rows rb*16 + Mfma::row(lane, r) of target column lane%16 of each group
+#pragma unroll
+    for (int g = 0; g < NT; ++g) {
+        const int32_t t = tkey[g * 16 + (lane & 15)];
+        if (t < 0) continue;
+        T *out = dst + size_t(t) * 3 * kp;
+#pragma unroll
+        for (int i = 0; i < NRBW; ++i) {
+            const int rb = wave + kTrWaves * i;
+            if (rb >= nrb) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rb * 16 + Mfma<T>::row(lane, r);
+                    if (row < C) {
+                        const T v = acc[i][g * 3 + c][r];
+                        T *o = out + c * kp + row;
+                        *o = accumulate ? *o + v : v;
+                    }
+                }
+        }
     }
 }
 
@@ -349,41 +439,80 @@ hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const 
     return hipGetLastError();
 }
 
+// Tile shape: FP32 takes 32 targets per workgroup, FP64 16.  The pipelined
+// form needs two staging buffers within 128 KB of LDS and at most 24 prefetch
+// registers per thread; larger p falls back to one buffer and 16 targets.
+struct TrShape {
+    int nt, pf;   // 16-target groups; prefetch registers (0 = single buffer)
+};
+
+template <typename T>
+TrShape translate_shape(int kp) {
+    const int nt = sizeof(T) == 4 ? 2 : 1;
+    const int tpt = kTrThreads / (16 * nt);
+    const size_t lds = 2 * sizeof(T) * size_t(16) * nt * 3 * (kp + 1);
+    if (lds <= 128 * 1024 && (3 * kp + tpt - 1) / tpt <= 24) return {nt, 24};
+    return {1, 0};
+}
+
+template <typename T, int NT, int PF, int NR>
+void launch_translate_k(hipStream_t s, int mode, int grid, size_t smem, int level, int periodic, int C, int kp,
+                        int nrb, const T *ops, const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
+                        int accumulate) {
+    if (mode == 0)
+        hipLaunchKernelGGL((k_translate<T, NR, NT, 0, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
+                           C, kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_translate<T, NR, NT, 1, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
+                           C, kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);
+    else
+        hipLaunchKernelGGL((k_translate<T, NR, NT, 2, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
+                           C, kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);
+}
+
+template <typename T, int NT, int PF>
+hipError_t launch_translate_rows(hipStream_t s, int mode, int nrbw, int grid, size_t smem, int level, int periodic,
+                                 int C, int kp, int nrb, const T *ops, const int16_t *oct_lists,
+                                 const int8_t *offsets, const T *src, T *dst, int accumulate) {
+    switch (nrbw) {
+        case 1: launch_translate_k<T, NT, PF, 1>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
+                                                 offsets, src, dst, accumulate); break;
+        case 2: launch_translate_k<T, NT, PF, 2>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
+                                                 offsets, src, dst, accumulate); break;
+        case 3: launch_translate_k<T, NT, PF, 3>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
+                                                 offsets, src, dst, accumulate); break;
+        case 4: launch_translate_k<T, NT, PF, 4>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
+                                                 offsets, src, dst, accumulate); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp, const T *ops,
                             const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
                             int accumulate) {
     const int C = (p + 1) * (p + 1);
     const int nrb = pad16(C) / 16;
-    const int nrbw = (nrb + 3) / 4;
+    const int nrbw = (nrb + kTrWaves - 1) / kTrWaves;
+    const TrShape sh = translate_shape<T>(kp);
+    const int ttn = 16 * sh.nt;
     int64_t ncell;
     int grid;
     if (mode == 2) {
         ncell = int64_t(1) << (3 * level);
-        grid = int((ncell + TT - 1) / TT);
+        grid = int((ncell + ttn - 1) / ttn);
     } else {
         ncell = int64_t(1) << (3 * (level - 1));
-        grid = int((ncell + TT - 1) / TT) * 8;
+        grid = int((ncell + ttn - 1) / ttn) * 8;
     }
-    const size_t smem = sizeof(T) * size_t(TT) * 3 * (kp + 1);
-#define VM_TR(NR)                                                                                          \
-    case NR:                                                                                               \
-        if (mode == 0)                                                                                     \
-            hipLaunchKernelGGL((k_translate<T, NR, 0>), dim3(grid), dim3(256), smem, s, level, periodic, C, \
-                               kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);                    \
-        else if (mode == 1)                                                                                \
-            hipLaunchKernelGGL((k_translate<T, NR, 1>), dim3(grid), dim3(256), smem, s, level, periodic, C, \
-                               kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);                    \
-        else                                                                                               \
-            hipLaunchKernelGGL((k_translate<T, NR, 2>), dim3(grid), dim3(256), smem, s, level, periodic, C, \
-                               kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);                    \
-        break;
-    switch (nrbw) {
-        VM_TR(1) VM_TR(2) VM_TR(3) VM_TR(4) VM_TR(5) VM_TR(6) VM_TR(7)
-        default: return hipErrorInvalidValue;
-    }
-#undef VM_TR
-    return hipGetLastError();
+    const size_t smem = sizeof(T) * size_t(ttn) * 3 * (kp + 1) * (sh.pf > 0 ? 2 : 1);
+    constexpr int NTP = sizeof(T) == 4 ? 2 : 1;
+    if (sh.pf > 0)
+        return launch_translate_rows<T, NTP, 24>(s, mode, nrbw, grid, smem, level, periodic, C, kp, nrb, ops,
+                                                 oct_lists, offsets, src, dst, accumulate);
+    return launch_translate_rows<T, 1, 0>(s, mode, nrbw, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
+                                          offsets, src, dst, accumulate);
 }
 
 template <typename T>

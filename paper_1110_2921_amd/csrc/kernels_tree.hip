@@ -89,28 +89,69 @@ __global__ void __launch_bounds__(kRadixThreads) k_radix_hist(int n, int shift, 
     for (int b = threadIdx.x; b < nb; b += kRadixThreads) hist[size_t(b) * gridDim.x + blockIdx.x] = cnt[b];
 }
 
-// Exclusive scan of `total` counts by one workgroup (segments per thread).
-__global__ void __launch_bounds__(1024) k_scan(int total, uint32_t *__restrict__ data) {
-    __shared__ uint32_t part[1024];
+// Exclusive scan of `total` counts in three coalesced steps: each block scans
+// a tile of kScanTile entries and records the tile total; one block scans the
+// totals; each block adds its tile's offset.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
     const int t = threadIdx.x;
-    const int seg = (total + 1023) / 1024;
-    const int b = t * seg, e = min(total, b + seg);
-    uint32_t s = 0;
-    for (int i = b; i < e; ++i) s += data[i];
-    part[t] = s;
+    sh[t] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? part[t - off] : 0u;
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const uint32_t w = t >= off ? sh[t - off] : 0u;
         __syncthreads();
-        part[t] += v;
+        sh[t] += w;
         __syncthreads();
     }
-    uint32_t run = part[t] - s;   // exclusive prefix of this segment
-    for (int i = b; i < e; ++i) {
-        const uint32_t v = data[i];
-        data[i] = run;
-        run += v;
+    total = sh[kScanThreads - 1];
+    const uint32_t excl = sh[t] - v;
+    __syncthreads();
+    return excl;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(int total, uint32_t *__restrict__ data,
+                                                            uint32_t *__restrict__ tile_sums) {
+    __shared__ uint32_t sh[kScanThreads];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = base + i < total ? data[base + i] : 0u;
+        s += v[i];
     }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, sh, tot);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < total) data[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(int ntiles, uint32_t *__restrict__ tile_sums) {
+    __shared__ uint32_t sh[kScanThreads];
+    uint32_t carry = 0;
+    for (int b = 0; b < ntiles; b += kScanThreads) {
+        const int i = b + threadIdx.x;
+        const uint32_t v = i < ntiles ? tile_sums[i] : 0u;
+        uint32_t tot;
+        const uint32_t e = block_exclusive_scan(v, sh, tot);
+        if (i < ntiles) tile_sums[i] = carry + e;
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_add(int total, uint32_t *__restrict__ data,
+                                                          const uint32_t *__restrict__ tile_sums) {
+    const uint32_t off = tile_sums[blockIdx.x];
+    const int base = blockIdx.x * kScanTile;
+    for (int i = threadIdx.x; i < kScanTile; i += kScanThreads)
+        if (base + i < total) data[base + i] += off;
 }
 
 // Stable scatter: wave w of a block owns the contiguous quarter of its tile,
@@ -244,7 +285,12 @@ hipError_t launch_radix_pass(hipStream_t s, int n, int shift, int bits, const ui
                              const int32_t *vin, uint32_t *kout, int32_t *vout, uint32_t *hist) {
     const int nblk = blocks(n, kRadixTile);
     hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, n, shift, bits, kin, hist);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, nblk << bits, hist);
+    const int total = nblk << bits;
+    const int ntiles = (total + kScanTile - 1) / kScanTile;
+    uint32_t *tile_sums = hist + size_t(nblk) * 256;   // the histogram buffer carries room for the tile sums
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanThreads), 0, s, total, hist, tile_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, ntiles, tile_sums);
+    hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kScanThreads), 0, s, total, hist, (const uint32_t *)tile_sums);
     hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kRadixThreads), 0, s, n, shift, bits, kin, vin,
                        kout, vout, (const uint32_t *)hist);
     return hipGetLastError();

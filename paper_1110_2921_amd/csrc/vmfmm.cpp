@@ -404,7 +404,9 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     VM_HIP(ctx->keys_b.reserve(sizeof(uint32_t) * n), "alloc keys");
     VM_HIP(ctx->vals_a.reserve(sizeof(int32_t) * n), "alloc perm");
     VM_HIP(ctx->vals_b.reserve(sizeof(int32_t) * n), "alloc perm");
-    VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * size_t(nblk) * 256), "alloc histogram");
+    // digit counts [256][nblk] followed by the scan's tile sums
+    VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * (size_t(nblk) * 256 + size_t(nblk) * 256 / 4096 + 256)),
+           "alloc histogram");
     VM_HIP(ctx->start.reserve(sizeof(int32_t) * size_t(nleaf + 1)), "alloc leaf ranges");
     if (mixed) VM_HIP(ctx->p32.reserve(sizeof(Part32) * n), "alloc particles");
     else VM_HIP(ctx->p64.reserve(sizeof(Part64) * n), "alloc particles");
@@ -854,6 +856,15 @@ vm_status vm_debug_operator(int kind, int p, int index, double *out) {
     if (kind == 3) {
         if (index < 1 || index > 4) return VM_EINVAL;
         lattice_matrix(p, index, out);
+        return VM_OK;
+    }
+    if (kind == 4) {
+        // gradient of F(Y) = sum_t f_t c_t(Y): out[a][s][t], a < 3, s < p^2, t < C
+        const AdjTables a = adj_tables(p);
+        const int C = ncoef(p), rows = 3 * p * p;
+        std::fill(out, out + size_t(rows) * C, 0.0);
+        for (int r = 0; r < rows; ++r)
+            for (int e = 0; e < a.width_g; ++e) out[size_t(r) * C + a.g_idx[size_t(r) * a.width_g + e]] += a.g_w[size_t(r) * a.width_g + e];
         return VM_OK;
     }
     return VM_EINVAL;

@@ -1,0 +1,70 @@
+"""Parity at the full workload sizes (N = 128^3 and 256^3, p = 10, 27^3 images),
+in the launch configuration the benchmark times, on sampled particles.
+
+The oracle evaluates the same FMM at 96 sampled particles (``oracle.fmm.fmm_at``:
+full upward pass, downward pass along the sampled leaves' ancestors, L2P and
+P2P at the samples).  Tolerances (relative L2 over the samples):
+  FP64 GPU vs oracle: 1e-10 for u and J;  mixed GPU vs oracle: 1e-5 for u, 1e-4 for J.
+Properties over all N: the transpose stretching form conserves sum alpha to the
+FMM's accuracy, and a repeated evaluation is bitwise identical.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct as D
+from oracle import fmm as OF
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1110_2921_amd as vm
+    return vm.FMM(0)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["rand128_periodic", "rand256_periodic"])
+def test_full_size_sampled_parity(ctx, name):
+    import torch
+    w = W.WORKLOADS[name]
+    x_np, a_np = W.make(w)
+    x = torch.from_numpy(np.ascontiguousarray(x_np.T)).cuda()
+    a = torch.from_numpy(np.ascontiguousarray(a_np.T)).cuda()
+    t = np.sort(np.random.default_rng(7).choice(w.n, 96, replace=False))
+    tt = torch.from_numpy(t).cuda()
+    out = {}
+    for prec in ("fp64", "mixed"):
+        u, da, J = ctx.eval(x, a, w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len,
+                            precision=prec, want_grad=True)
+        out[prec] = (u[:, tt].cpu().numpy().T, J[:, tt].cpu().numpy().T.reshape(-1, 3, 3),
+                     da[:, tt].cpu().numpy().T)
+        del u, da, J
+    # repeated mixed evaluation: bitwise identical (no atomics in the reductions)
+    u2, _, _ = ctx.eval(x, a, w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len,
+                        precision="mixed", want_dalpha=False)
+    assert np.array_equal(u2[:, tt].cpu().numpy().T, out["mixed"][0])
+    del u2
+    # transpose stretching conserves the total vorticity
+    _, dt, _ = ctx.eval(x, a, w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len,
+                        precision="fp64", scheme="transpose")
+    tot = dt.sum(dim=1).abs().max().item() / dt.abs().sum().item()
+    assert tot < 1e-6
+    del dt, x, a
+    torch.cuda.empty_cache()
+    uo, Jo = OF.fmm_at(x_np, a_np, w.sigma, w.p, w.level, t, periodic=w.periodic, box_len=w.box_len)
+    u64, J64, d64 = out["fp64"]
+    assert rel(u64, uo) < 1e-10
+    assert rel(J64, Jo) < 1e-10
+    assert rel(d64, D.stretching(Jo, a_np[t])) < 1e-10
+    um, Jm, _ = out["mixed"]
+    assert rel(um, uo) < 1e-5
+    assert rel(Jm, Jo) < 1e-4

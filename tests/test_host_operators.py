@@ -145,3 +145,32 @@ def test_lists_match_oracle():
             ref = T.interaction_list(key, level, periodic)
             got = [(int(s), tuple(map(int, dd)), tuple(map(int, ii))) for s, dd, ii in zip(src, d, img)]
             assert got == ref
+
+
+def _cvec(Y, p):
+    R = lib_regular(Y, p)
+    out = np.zeros((len(np.atleast_2d(Y)), (p + 1) ** 2))
+    for (n, m), v in R.items():
+        if m == 0:
+            out[:, n * n] = v.real
+        else:
+            out[:, n * n + 2 * m - 1] = v.real
+            out[:, n * n + 2 * m] = -v.imag
+    return out
+
+
+@pytest.mark.parametrize("p", [4, 10])
+def test_multipole_basis_gradient_table(p):
+    """Table behind the source-position term of the adjoint P2M."""
+    C, nu = (p + 1) ** 2, p * p
+    G = lib.debug_operator(4, p, 0)
+    rng = np.random.default_rng(p)
+    f = rng.standard_normal(C)
+    Y = rng.uniform(-0.5, 0.5, (4, 3))
+    h = 1e-5
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd = (_cvec(Y + e, p) @ f - _cvec(Y - e, p) @ f) / (2 * h)
+        an = _cvec(Y, p)[:, :nu] @ (G[a * nu:(a + 1) * nu] @ f)
+        assert np.abs(fd - an).max() < 1e-8 * np.abs(fd).max()

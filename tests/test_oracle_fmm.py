@@ -151,3 +151,15 @@ def test_level_zero_periodic_is_images_plus_lattice():
         u, J = F.fmm(x, a, sigma, p, 0, periodic=2)
         errs.append(np.linalg.norm(u - u2) / np.linalg.norm(u2 - u1))
     assert errs[1] < errs[0] / 4 and errs[2] < errs[1] / 4
+
+
+@pytest.mark.parametrize("periodic,level", [(3, 2), (0, 2), (1, 1), (2, 0)])
+def test_sampled_fmm_equals_full_fmm(periodic, level):
+    """The per-target variant used at full sizes repeats the full oracle's arithmetic."""
+    x, a = W.random_field(16, 4.0, 3)
+    h = L / 16
+    u, J = F.fmm(x, a, h, 6, level, periodic=periodic)
+    t = np.random.default_rng(0).choice(len(x), 40, replace=False)
+    us, Js = F.fmm_at(x, a, h, 6, level, t, periodic=periodic, chunk=1000)
+    assert np.abs(us - u[t]).max() < 1e-14 * np.abs(u).max()
+    assert np.abs(Js - J[t]).max() < 1e-14 * np.abs(J).max()
