@@ -1,10 +1,12 @@
-"""Throughput of the FMM evaluation on one MI355X.
+"""Throughput of the FMM vortex-particle step on one MI355X.
 
-A step is one full evaluation of the regularised Biot-Savart velocity and the
+A step is one Heun (RK2) step of the convection and stretching ODEs over
+N = 256^3 vortex particles of a seeded random isotropic field (p = 10, leaf
+level 6, 27^3 periodic images), inputs resident in HBM: two full FMM
+evaluations of the regularised Biot-Savart velocity, its gradient and the
 stretching term (tree build, P2M, M2M, lattice, L2L/M2L, L2P, P2P, combine)
-over N = 256^3 vortex particles of a seeded random isotropic field (p = 10,
-leaf level 6, 27^3 periodic images), inputs resident in HBM.  Prints one JSON
-line (see the design doc for the field definitions).
+and the update.  ``value`` counts evaluations per second (two per step).
+Prints one JSON line (see the design doc for the field definitions).
 
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
 """
@@ -98,14 +100,23 @@ def near_pairs(start, level, periodic):
     return total
 
 
+def tree_bytes_per_particle(level, f32):
+    """Algorithmic HBM bytes of the tree build per particle: keys (read x 24 B, write key and
+    index 8 B), per radix pass (histogram reads the key 4 B; scatter reads and writes key and
+    index 16 B), ranges (read the key 4 B), permute (read index 4 B, gather x and alpha 48 B,
+    write the 32 B or 64 B particle record)."""
+    npass = (3 * level + 7) // 8
+    return 32 + 20 * npass + 4 + 52 + (32 if f32 else 64)
+
+
 def cpu_baseline(w, budget_s=30.0):
-    """The oracle FMM timed on the host on a 16^3 sample of the same recipe."""
+    """The oracle FMM timed on the host on a 32^3 sample of the same recipe."""
     import workloads as W
     from oracle import fmm as oracle_fmm
-    ng = 16
-    x, a = W.random_field(ng, 4.0, seed=w.seed)
+    ng = 32
+    x, a = W.random_field(ng, w.k0, seed=w.seed)
     h = 2 * math.pi / ng
-    level = 2                     # 64 particles per leaf, as in the full workload
+    level = 3                     # 64 particles per leaf, as in the full workload
     t0 = time.perf_counter()
     oracle_fmm.fmm(x, a, h, w.p, level, periodic=w.periodic)
     t = time.perf_counter() - t0
@@ -113,7 +124,7 @@ def cpu_baseline(w, budget_s=30.0):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": (n_sample / w.n) / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"oracle CPU FMM (NumPy + C/OpenMP, FP64) on N={ng}^3 particles of the same recipe "
-                      f"(k0=4, 64/leaf, p={w.p}, {3 ** w.periodic}^3 images) in {t:.1f} s, scaled by "
+                      f"(k0={w.k0:g}, 64/leaf, p={w.p}, {3 ** w.periodic}^3 images) in {t:.1f} s, scaled by "
                       f"{n_sample}/{w.n} (cost linear in N at fixed particles per leaf)",
             "seconds": t}
 
@@ -127,6 +138,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="one 1 GiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -148,36 +161,64 @@ def main():
     a = torch.from_numpy(np.ascontiguousarray(a_np.T)).to(dev)
     del x_np
     n = w.n
+    x0, a0 = x.clone(), a.clone()            # initial state, kept for the FP64 comparison
     u = torch.empty((3, n), dtype=torch.float64, device=dev)
     da = torch.empty((3, n), dtype=torch.float64, device=dev)
+    J = torch.empty((9, n), dtype=torch.float64, device=dev)
     ctx = vm.FMM(0)
     kw = dict(periodic=w.periodic, box_len=w.box_len, scheme="classic")
+    dt = 0.005                               # the paper's time step (Sec. 4.1)
+    h3 = w.h ** 3
 
-    def step(prec, out):
-        ctx.eval(x, a, w.sigma, w.p, w.level, precision=prec, out=(out[0], out[1], None), **kw)
+    def step(prec, xs, as_):
+        ctx.rk2_step(xs, as_, w.sigma, w.p, w.level, dt, precision=prec, want_initial=True, out=(u, J), **kw)
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(args.warmup):
-        step(args.precision, (u, da))
+        step(args.precision, x, a)
         log(f"[bench] warmup {i + 1}/{args.warmup}")
+    x.copy_(x0)
+    a.copy_(a0)
     torch.cuda.synchronize()
 
     ctx.set_timing(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    diag0 = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
     for i in range(args.steps):
-        step(args.precision, (u, da))
+        step(args.precision, x, a)
+        if i == 0:
+            diag0 = ctx.diagnostics(u, J, a0, h3)   # (E, Omega, Omega_p) at the initial state
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     phases = ctx.timing()
     ctx.set_timing(False)
     gpu_ms = ev0.elapsed_time(ev1)
+    n_eval = 2 * args.steps
     ms_per_step = 1000.0 * wall / args.steps
-    log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step (events {gpu_ms / args.steps:.2f} ms)")
+    log(f"[bench] {args.steps} RK2 steps: {ms_per_step:.2f} ms/step (events {gpu_ms / args.steps:.2f} ms)")
     for k, (ms, cnt) in phases.items():
-        log(f"[bench]   {k:8s} {ms / args.steps:9.3f} ms/step  launches {cnt / args.steps:.0f}")
+        log(f"[bench]   {k:8s} {ms / n_eval:9.3f} ms/eval  launches {cnt / n_eval:.0f}")
+
+    # energy / enstrophy after the steps (one more evaluation, untimed)
+    ctx.eval(x, a, w.sigma, w.p, w.level, precision=args.precision, out=(u, da, J), **kw)
+    diag1 = ctx.diagnostics(u, J, a, h3)
+    d0 = diag0.cpu().numpy()
+    d1 = diag1.cpu().numpy()
+    drift = {"energy": float((d1[0] - d0[0]) / d0[0]), "enstrophy": float((d1[1] - d0[1]) / d0[1]),
+             "particle_enstrophy": float((d1[2] - d0[2]) / d0[2]), "steps": args.steps, "dt": dt}
+    log(f"[bench] relative drift over {args.steps} steps: E {drift['energy']:.3e} "
+        f"Omega {drift['enstrophy']:.3e}")
 
     # work counts
     _, _, start = ctx.debug_tree(n, w.level)
@@ -185,9 +226,9 @@ def main():
     ntr = m2l_translations(w.level, w.periodic > 0)
     C = (w.p + 1) ** 2
     m2l_flop = 6.0 * C * C * ntr
-    p2p_ms = phases["p2p"][0] / args.steps
-    m2l_ms = phases["m2l"][0] / args.steps
-    m2l_launch = phases["m2l"][1] / args.steps
+    p2p_ms = phases["p2p"][0] / n_eval
+    m2l_ms = phases["m2l"][0] / n_eval
+    m2l_launch = phases["m2l"][1] / n_eval
     p2p_flop = P2P_FLOP_PER_PAIR[args.precision] * pairs
     f32 = args.precision == "mixed"
     roof_m2l = {"bound": "mfma", "kernel": "k_translate<M2L>",
@@ -201,10 +242,16 @@ def main():
                 "traffic": None}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
     dominant = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
+    tree_ms = phases["tree"][0] / n_eval
+    tree_bytes = tree_bytes_per_particle(w.level, f32) * n
+    roof_tree = {"bound": "hbm", "kernel": "tree (keys, radix passes, ranges, permute)",
+                 "achieved": tree_bytes / (tree_ms * 1e-3) / 1e9, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+                 "traffic": None}
+    roof_tree["frac"] = roof_tree["achieved"] / roof_tree["peak"]
 
     result = {
         "metric": "FMM evals/sec and P2P Ginteractions/s at N=256^3, p=10, rel-L2 err vs FP64",
-        "value": args.steps / wall,
+        "value": n_eval / wall,
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -218,35 +265,51 @@ def main():
         "config": {"workload": f"{w.name}: N={w.ng}^3 cell-centred lattice in [0,2pi)^3, random-phase "
                                f"solenoidal field E(k)~k^4 exp(-2k^2/k0^2), k0={w.k0:g}, sigma=h, "
                                f"p={w.p}, leaf level {w.level} (64/leaf), {3 ** w.periodic}^3 periodic images, "
-                               f"{args.precision} precision, classic stretching",
+                               f"{args.precision} precision, classic stretching; step = one Heun RK2 step "
+                               f"(2 evaluations, dt={dt})",
                    "n": n, "p": w.p, "level": w.level, "periodic_K": w.periodic,
                    "precision": args.precision, "parallelism": "single GPU"},
         "p2p_gpairs_per_s": pairs / (p2p_ms * 1e-3) / 1e9,
         "p2p_pairs": pairs,
         "m2l_translations": ntr,
-        "phase_ms_per_step": {k: v[0] / args.steps for k, v in phases.items()},
+        "phase_ms_per_eval": {k: v[0] / n_eval for k, v in phases.items()},
+        "evals_per_step": 2,
+        "drift": drift,
         "roofline": dominant,
-        "roofline_kernels": {"m2l": roof_m2l, "p2p": roof_p2p},
+        "roofline_kernels": {"m2l": roof_m2l, "p2p": roof_p2p, "tree": roof_tree},
     }
 
     if not args.no_fp64_check and args.precision == "mixed":
-        u64 = torch.empty_like(u)
-        da64 = torch.empty_like(da)
-        step("fp64", (u64, da64))
+        # accuracy at the initial state, FP64 throughput and the FP64 drift
+        um, dam = torch.empty_like(u), torch.empty_like(da)
+        ctx.eval(x0, a0, w.sigma, w.p, w.level, precision="mixed", out=(um, dam, None), **kw)
+        u64, da64 = torch.empty_like(u), torch.empty_like(da)
+        ctx.eval(x0, a0, w.sigma, w.p, w.level, precision="fp64", out=(u64, da64, None), **kw)
+        eu = float(torch.linalg.norm(um - u64) / torch.linalg.norm(u64))
+        ed = float(torch.linalg.norm(dam - da64) / torch.linalg.norm(da64))
+        del um, dam, u64, da64
+        x.copy_(x0)
+        a.copy_(a0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        nf = 2
-        for _ in range(nf):
-            step("fp64", (u64, da64))
+        d64_0 = None
+        for i in range(args.steps):
+            step("fp64", x, a)
+            if i == 0:
+                d64_0 = ctx.diagnostics(u, J, a0, h3)
         torch.cuda.synchronize()
-        t64 = (time.perf_counter() - t0) / nf
-        eu = float(torch.linalg.norm(u - u64) / torch.linalg.norm(u64))
-        ed = float(torch.linalg.norm(da - da64) / torch.linalg.norm(da64))
+        t64 = (time.perf_counter() - t0) / (2 * args.steps)
+        ctx.eval(x, a, w.sigma, w.p, w.level, precision="fp64", out=(u, da, J), **kw)
+        e0 = d64_0.cpu().numpy()
+        e1 = ctx.diagnostics(u, J, a, h3).cpu().numpy()
         result["rel_l2_u_vs_fp64"] = eu
         result["rel_l2_dalpha_vs_fp64"] = ed
         result["fp64_evals_per_s"] = 1.0 / t64
-        result["mixed_speedup_vs_fp64"] = (args.steps / wall) * t64
-        log(f"[bench] fp64 {t64 * 1e3:.1f} ms/eval; mixed vs fp64 rel-L2 u {eu:.2e} dalpha {ed:.2e}")
+        result["mixed_speedup_vs_fp64"] = result["value"] * t64
+        result["drift_fp64"] = {"energy": float((e1[0] - e0[0]) / e0[0]),
+                                "enstrophy": float((e1[1] - e0[1]) / e0[1])}
+        log(f"[bench] fp64 {t64 * 1e3:.1f} ms/eval; mixed vs fp64 rel-L2 u {eu:.2e} dalpha {ed:.2e}; "
+            f"fp64 drift E {result['drift_fp64']['energy']:.3e}")
 
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

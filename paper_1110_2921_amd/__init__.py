@@ -123,10 +123,11 @@ class FMM:
 
     def rk2_step(self, x, alpha, sigma, p, level, dt, periodic=0, box_lo=(0.0, 0.0, 0.0),
                  box_len=2 * math.pi, precision="fp64", scheme="classic", want_initial=False,
-                 stream=None):
+                 stream=None, out=None):
         """Heun step, in place on x and alpha ((3, n) contiguous float64 CUDA tensors).
 
-        Returns (u0, J0) at the initial state when ``want_initial``, else None."""
+        Returns (u0, J0) at the initial state when ``want_initial`` (written into
+        ``out`` = (u0, J0) when given), else None."""
         torch = self._torch
         for t in (x, alpha):
             if t.dim() != 2 or t.shape[0] != 3 or not t.is_contiguous() or t.dtype != torch.float64:
@@ -135,8 +136,11 @@ class FMM:
         self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
         u0 = J0 = None
         if want_initial:
-            u0 = torch.empty((3, n), dtype=torch.float64, device=x.device)
-            J0 = torch.empty((9, n), dtype=torch.float64, device=x.device)
+            if out is not None:
+                u0, J0 = out
+            else:
+                u0 = torch.empty((3, n), dtype=torch.float64, device=x.device)
+                J0 = torch.empty((9, n), dtype=torch.float64, device=x.device)
         opts = self._opts(periodic, box_lo, box_len, precision, scheme, False)
         self._check(self._lib.vm_rk2_step(self._h, n, ctypes.c_void_p(x.data_ptr()),
                                           ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(level),

@@ -109,4 +109,13 @@ hipError_t launch_diagnostics(hipStream_t s, int n, const double *u, const doubl
 inline int pad16(int c) { return (c + 15) / 16 * 16; }
 inline int pad4(int c) { return (c + 3) / 4 * 4; }
 
+// Operator fragment layout of the translation GEMMs: [op][row block][k step][64
+// lanes], row blocks padded to whole groups of 8 (one per wave), k steps (4
+// coefficients each) padded to a multiple of 8, the padding zero.  No guard
+// is then needed inside the MFMA loop.
+constexpr int kTrWaveCount = 8;
+inline int tr_nrb(int C) { return (pad16(C) / 16 + kTrWaveCount - 1) / kTrWaveCount * kTrWaveCount; }
+inline int tr_nks(int C) { return (pad4(C) + 31) / 32 * 8; }
+inline size_t tr_frag(int C) { return size_t(tr_nrb(C)) * tr_nks(C) * 64; }
+
 }  // namespace vmfmm

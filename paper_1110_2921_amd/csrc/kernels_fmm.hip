@@ -197,10 +197,11 @@ __device__ __forceinline__ int demorton1(uint32_t k, int d, int level) {
 // PF = 0: single buffer, loads and compute in turn (large p).
 constexpr int kTrThreads = 512;
 constexpr int kTrWaves = kTrThreads / 64;
+static_assert(kTrWaves == kTrWaveCount, "operator padding assumes one row-block group per wave");
 
 template <typename T, int NRBW, int NT, int mode, int PF>
 __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodic, int C, int kp,
-                                                          int nrb, const T *__restrict__ ops,
+                                                          int nrb, int nks, const T *__restrict__ ops,
                                                           const int16_t *__restrict__ oct_lists,
                                                           const int8_t *__restrict__ offsets,
                                                           const T *__restrict__ src, T *__restrict__ dst,
@@ -209,16 +210,16 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
     constexpr int TTN = 16 * NT;
     constexpr int NCB = 3 * NT;                          // column blocks: (group, component)
     constexpr int NBUF = PF > 0 ? 2 : 1;
+    constexpr int APF = 8;                               // operator prefetch distance (k steps)
     extern __shared__ unsigned char smem_raw[];
-    const int ks_stride = kp + 1;                       // odd row stride: conflict-free B reads
+    const int ks_stride = 4 * nks + 1;                   // odd row stride: conflict-free B reads
     const int buf_elems = TTN * 3 * ks_stride;
     T *bs = reinterpret_cast<T *>(smem_raw);             // [NBUF][TTN * 3][ks_stride]
     __shared__ int32_t tkey[TTN];
     __shared__ int32_t skey[2][TTN];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int nks = kp / 4;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int per_cell = 3 * kp;
-    const int stage_elems = TTN * per_cell;
 
     int octant = 0, tile = blockIdx.x, npair = 1;
     int64_t ncell_t;
@@ -237,6 +238,8 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
         if (slot < ncell_t) k = mode == 2 ? int32_t(slot) : int32_t((slot << 3) | octant);
         tkey[tid] = k;
     }
+    // the K padding of the staging buffers stays zero
+    for (int e = tid; e < NBUF * buf_elems; e += kTrThreads) bs[e] = T(0);
     const int side = 1 << level;
     auto op_of = [&](int pr) -> int {
         if (mode == 0) return oct_lists[octant * 189 + pr];
@@ -273,6 +276,7 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
             k += TPT;
         }
     };
+
     V acc[NRBW][NCB];
 #pragma unroll
     for (int i = 0; i < NRBW; ++i)
@@ -280,47 +284,37 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
         for (int c = 0; c < NCB; ++c) acc[i][c] = V{T(0), T(0), T(0), T(0)};
     __syncthreads();
 
-    // A fragments stream from memory through a ring of APF registers per row
-    // block (prefetch distance APF k steps) to cover the L2 latency.
-    constexpr int APF = 8;
+    // One pair: out += Op * Src.  Straight-line k steps: the A fragments stream
+    // through a ring of APF registers, the B fragments of a step are all read
+    // before its MFMAs issue.
     auto mfma_pair = [&](int pr, const T *buf) {
-        const T *opb = ops + size_t(op_of(pr)) * nrb * nks * 64;
+        const T *opb = ops + size_t(op_of(pr)) * nrb * nks * 64 + lane;
         T ring[APF][NRBW];
 #pragma unroll
         for (int d = 0; d < APF; ++d)
 #pragma unroll
-            for (int i = 0; i < NRBW; ++i) {
-                const int rb = wave + kTrWaves * i;
-                ring[d][i] = (rb < nrb && d < nks) ? opb[(size_t(rb) * nks + d) * 64 + lane] : T(0);
-            }
+            for (int i = 0; i < NRBW; ++i) ring[d][i] = opb[(size_t(wave + kTrWaves * i) * nks + d) * 64];
+        const T *bl = buf + (lane & 15) * 3 * ks_stride + (lane >> 4);
         for (int ks0 = 0; ks0 < nks; ks0 += APF) {
 #pragma unroll
             for (int d = 0; d < APF; ++d) {
                 const int ks = ks0 + d;
-                if (ks < nks) {
-                    T a_use[NRBW];
-                    const int kn = ks + APF;
+                const int kn = ks + APF < nks ? ks + APF : nks - 1;
+                T a_use[NRBW];
 #pragma unroll
-                    for (int i = 0; i < NRBW; ++i) {
-                        const int rb = wave + kTrWaves * i;
-                        a_use[i] = ring[d][i];
-                        if (rb < nrb && kn < nks) ring[d][i] = opb[(size_t(rb) * nks + kn) * 64 + lane];
-                    }
-                    T bfrag[NCB];
-#pragma unroll
-                    for (int g = 0; g < NT; ++g)
-#pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            bfrag[g * 3 + c] = buf[((g * 16 + (lane & 15)) * 3 + c) * ks_stride + ks * 4 + (lane >> 4)];
-#pragma unroll
-                    for (int i = 0; i < NRBW; ++i) {
-                        if (wave + kTrWaves * i < nrb) {
-#pragma unroll
-                            for (int cb = 0; cb < NCB; ++cb)
-                                acc[i][cb] = Mfma<T>::op(a_use[i], bfrag[cb], acc[i][cb]);
-                        }
-                    }
+                for (int i = 0; i < NRBW; ++i) {
+                    a_use[i] = ring[d][i];
+                    ring[d][i] = opb[(size_t(wave + kTrWaves * i) * nks + kn) * 64];
                 }
+                T bfrag[NCB];
+#pragma unroll
+                for (int g = 0; g < NT; ++g)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) bfrag[g * 3 + c] = bl[(g * 16 * 3 + c) * ks_stride + ks * 4];
+#pragma unroll
+                for (int i = 0; i < NRBW; ++i)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) acc[i][cb] = Mfma<T>::op(a_use[i], bfrag[cb], acc[i][cb]);
             }
         }
     };
@@ -371,7 +365,6 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
             __syncthreads();
         }
     }
-    (void)NBUF;
     // write back: lane holds rows rb*16 + Mfma::row(lane, r) of target column lane%16 of each group
 #pragma unroll
     for (int g = 0; g < NT; ++g) {
@@ -381,7 +374,6 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
 #pragma unroll
         for (int i = 0; i < NRBW; ++i) {
             const int rb = wave + kTrWaves * i;
-            if (rb >= nrb) continue;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -450,7 +442,8 @@ template <typename T>
 TrShape translate_shape(int kp) {
     const int nt = sizeof(T) == 4 ? 2 : 1;
     const int tpt = kTrThreads / (16 * nt);
-    const size_t lds = 2 * sizeof(T) * size_t(16) * nt * 3 * (kp + 1);
+    const int kpad = (kp + 31) / 32 * 32;
+    const size_t lds = 2 * sizeof(T) * size_t(16) * nt * 3 * (kpad + 1);
     if (lds <= 128 * 1024 && (3 * kp + tpt - 1) / tpt <= 24) return {nt, 24};
     return {1, 0};
 }
@@ -459,15 +452,16 @@ template <typename T, int NT, int PF, int NR>
 void launch_translate_k(hipStream_t s, int mode, int grid, size_t smem, int level, int periodic, int C, int kp,
                         int nrb, const T *ops, const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
                         int accumulate) {
+    const int nks = tr_nks(C);
     if (mode == 0)
         hipLaunchKernelGGL((k_translate<T, NR, NT, 0, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate);
     else if (mode == 1)
         hipLaunchKernelGGL((k_translate<T, NR, NT, 1, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate);
     else
         hipLaunchKernelGGL((k_translate<T, NR, NT, 2, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, ops, oct_lists, offsets, src, dst, accumulate);
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate);
 }
 
 template <typename T, int NT, int PF>
@@ -493,8 +487,8 @@ hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, in
                             const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
                             int accumulate) {
     const int C = (p + 1) * (p + 1);
-    const int nrb = pad16(C) / 16;
-    const int nrbw = (nrb + kTrWaves - 1) / kTrWaves;
+    const int nrb = tr_nrb(C);
+    const int nrbw = nrb / kTrWaves;
     const TrShape sh = translate_shape<T>(kp);
     const int ttn = 16 * sh.nt;
     int64_t ncell;
@@ -506,7 +500,7 @@ hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, in
         ncell = int64_t(1) << (3 * (level - 1));
         grid = int((ncell + ttn - 1) / ttn) * 8;
     }
-    const size_t smem = sizeof(T) * size_t(ttn) * 3 * (kp + 1) * (sh.pf > 0 ? 2 : 1);
+    const size_t smem = sizeof(T) * size_t(ttn) * 3 * (4 * tr_nks(C) + 1) * (sh.pf > 0 ? 2 : 1);
     constexpr int NTP = sizeof(T) == 4 ? 2 : 1;
     if (sh.pf > 0)
         return launch_translate_rows<T, NTP, 24>(s, mode, nrbw, grid, smem, level, periodic, C, kp, nrb, ops,

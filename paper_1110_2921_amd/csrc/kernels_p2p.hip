@@ -23,9 +23,10 @@ constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
 constexpr double kSqrt2OverPi = 0.79788456080286535587989211986876373;
 
 // a_n = (-1/2)^n / (n! (2n+3)): g / rho^3 = sqrt(2/pi) sum a_n rho^{2n}
-template <typename T>
+// Horner in t = rho^2 over n = 0..NTERM-1; h1 = 2 d(h0)/dt = sum 2 n a_n t^{n-1}.
+template <typename T, int NTERM>
 __device__ __forceinline__ void small_rho(T t, T &h0, T &h1) {
-    // Horner in t = rho^2; h1 = d(h0)/dt * 2 = sum 2 n a_n t^{n-1}
+    static_assert(NTERM >= 3 && NTERM <= 14, "series length");
     constexpr double a[14] = {
         1.0 / 3.0,
         -0.5 / 5.0,
@@ -42,9 +43,10 @@ __device__ __forceinline__ void small_rho(T t, T &h0, T &h1) {
         0.000244140625 / (479001600.0 * 27.0),
         -0.0001220703125 / (6227020800.0 * 29.0),
     };
-    T s0 = T(a[13]), s1 = T(2.0 * 13.0 * a[13]);
+    constexpr int top = NTERM - 1;
+    T s0 = T(a[top]), s1 = T(2.0 * top * a[top]);
 #pragma unroll
-    for (int k = 12; k >= 1; --k) {
+    for (int k = top - 1; k >= 1; --k) {
         s0 = s0 * t + T(a[k]);
         s1 = s1 * t + T(2.0 * k * a[k]);
     }
@@ -68,7 +70,7 @@ __device__ __forceinline__ void pair64(double r2, const Consts64 &k, double &q, 
         dq = (kSqrt2OverPi * k.is3 * e - 3.0 * q) * ir2;
     } else {
         double h0, h1;
-        small_rho<double>(r2 * k.inv_s2, h0, h1);
+        small_rho<double, 9>(r2 * k.inv_s2, h0, h1);
         q = kSqrt2OverPi * k.is3 * h0;
         dq = kSqrt2OverPi * k.is5 * h1;
     }
@@ -78,10 +80,13 @@ struct Consts32 {
     float inv_sigma, inv_s2, is3, is5, thr2, w;
 };
 
-// FP32 pair kernel.  For rho < 2 the series (13 terms) is used; beyond, the
-// erf of Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7), whose exp(-s^2)
-// factor is shared with the Gaussian term:
-//   1 - g = exp(-rho^2/2) (P(t) + sqrt(2/pi) rho),  t = 1 / (1 + p rho/sqrt2).
+// FP32 pair kernel.  For rho < 1 the series (9 terms, truncation < 1e-9
+// relative) is used; beyond, the erf of Abramowitz & Stegun 7.1.26
+// (|error| <= 1.5e-7), whose exp(-s^2) factor is shared with the Gaussian term:
+//   1 - g = exp(-rho^2/2) (P(t) + sqrt(2/pi) rho),  t = 1 / (1 + p rho/sqrt2);
+// at rho >= 1 that gives q to 6e-7 and q'/r to 2e-6 relative.  The series
+// branch diverges within a wave whenever one lane is close to the source, so
+// its threshold is kept as small as that accuracy allows.
 __device__ __forceinline__ void pair32(float r2, const Consts32 &k, float &q, float &dq) {
     if (r2 >= k.thr2) {
         const float rinv = __frsqrt_rn(r2);
@@ -96,7 +101,7 @@ __device__ __forceinline__ void pair32(float r2, const Consts32 &k, float &q, fl
         dq = (float(kSqrt2OverPi) * k.is3 * e - 3.0f * q) * ir2;
     } else {
         float h0, h1;
-        small_rho<float>(r2 * k.inv_s2, h0, h1);
+        small_rho<float, 9>(r2 * k.inv_s2, h0, h1);
         q = float(kSqrt2OverPi) * k.is3 * h0;
         dq = float(kSqrt2OverPi) * k.is5 * h1;
     }
@@ -216,7 +221,7 @@ __global__ void __launch_bounds__(64) k_p2p32(P2PArgs a, const Part32 *__restric
     k.inv_s2 = float(inv_sigma * inv_sigma);
     k.is3 = float(inv_sigma * inv_sigma * inv_sigma);
     k.is5 = float(inv_sigma * inv_sigma * inv_sigma * inv_sigma * inv_sigma);
-    k.thr2 = float(4.0 * a.sigma * a.sigma);
+    k.thr2 = float(a.sigma * a.sigma);
     const float w = float(a.w);
     for (int base = 0; base < cnt; base += 64) {
         const int i = base + lane;

@@ -58,10 +58,10 @@ hipError_t upload(DevBuf &b, const std::vector<T> &v) {
 }
 
 // Operator matrices swizzled into MFMA A fragments: [op][rb][ks][64],
-// element (rb*16 + l%16, ks*4 + l/16) of the zero-padded Cp x kp matrix.
+// element (rb*16 + l%16, ks*4 + l/16) of the zero-padded operator.
 template <typename T>
 void swizzle(const std::vector<double> &m, int C, std::vector<T> &out, size_t base) {
-    const int cp = pad16(C), kp = pad4(C), nrb = cp / 16, nks = kp / 4;
+    const int nrb = tr_nrb(C), nks = tr_nks(C);
     for (int rb = 0; rb < nrb; ++rb)
         for (int ks = 0; ks < nks; ++ks)
             for (int l = 0; l < 64; ++l) {
@@ -176,8 +176,8 @@ vm_status ensure_ops(vm_ctx *ctx, int p, OpSet **out) {
     }
     auto set = std::make_unique<OpSet>();
     set->p = p;
-    const int C = ncoef(p), cp = pad16(C), kp = pad4(C);
-    const size_t frag = size_t(cp) * kp;
+    const int C = ncoef(p);
+    const size_t frag = tr_frag(C);
     const OffsetTable &t = offset_table();
     std::vector<double> m(size_t(C) * C);
     {
@@ -252,8 +252,8 @@ vm_status ensure_lattice(vm_ctx *ctx, int p, int K, const double **out) {
 vm_status ensure_adj_ops(vm_ctx *ctx, OpSet *set) {
     if (set->adj_ready) return VM_OK;
     const int p = set->p;
-    const int C = ncoef(p), cp = pad16(C), kp = pad4(C);
-    const size_t frag = size_t(cp) * kp;
+    const int C = ncoef(p);
+    const size_t frag = tr_frag(C);
     const OffsetTable &t = offset_table();
     std::vector<double> m(size_t(C) * C), mt(size_t(C) * C);
     auto transpose = [&]() {
