@@ -58,10 +58,13 @@ hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const 
                       const T *l_leaf, double *far);
 
 // Generic translation GEMM on MFMA: mode 0 = M2L, 1 = L2L, 2 = M2M.
+// `part` (part_elems elements of T, may be null) is scratch for M2L launches
+// split over the offsets at coarse levels; without it no split is made.
 template <typename T>
 hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp,
                             const T *ops, const int16_t *oct_lists, const int8_t *offsets,
-                            const T *src, T *dst, int accumulate);
+                            const T *src, T *dst, int accumulate, T *part = nullptr,
+                            size_t part_elems = 0);
 
 template <typename T>
 hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, const T *m0, T *l0);
@@ -112,10 +115,13 @@ inline int pad4(int c) { return (c + 3) / 4 * 4; }
 // Operator fragment layout of the translation GEMMs: [op][row block][k step][64
 // lanes], row blocks padded to whole groups of 8 (one per wave), k steps (4
 // coefficients each) padded to a multiple of 8, the padding zero.  No guard
-// is then needed inside the MFMA loop.
+// is then needed inside the MFMA loop.  Lane l of fragment (rb, ks) holds
+// element (rb*16 + l%16, tr_col(ks, l/16)) of the operator: k step 4b+s
+// takes column 16b + 4h + s in lane group h.
 constexpr int kTrWaveCount = 8;
 inline int tr_nrb(int C) { return (pad16(C) / 16 + kTrWaveCount - 1) / kTrWaveCount * kTrWaveCount; }
 inline int tr_nks(int C) { return (pad4(C) + 31) / 32 * 8; }
 inline size_t tr_frag(int C) { return size_t(tr_nrb(C)) * tr_nks(C) * 64; }
+inline int tr_col(int ks, int h) { return 16 * (ks >> 2) + 4 * h + (ks & 3); }
 
 }  // namespace vmfmm

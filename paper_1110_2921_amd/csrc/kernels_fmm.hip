@@ -195,9 +195,41 @@ __device__ __forceinline__ int demorton1(uint32_t k, int d, int level) {
 // while pair k runs on the MFMA units, then written to the other LDS buffer,
 // so each pair costs one barrier and the loads overlap the matrix work.
 // PF = 0: single buffer, loads and compute in turn (large p).
+//
+// K order: within each block of 16 coefficients, MFMA k step 4b+s takes
+// coefficient 16b + 4h + s in lane group h (the operator fragments are built
+// on the host in the same order), so a lane reads the B values of four k
+// steps as one 16-byte LDS load.  With the row stride S of the staging
+// buffer chosen so that S/4 (FP32) or S/2 (FP64) is odd, the 16 lanes of a
+// group hit 16 distinct 16-byte bank groups.
+//
+// Split form (M2L at coarse levels, where there are too few target tiles to
+// fill the chip): blockIdx.y selects a contiguous range of the 189 offsets
+// and the partial sums go to `part` ([split][cell][3][kp]), reduced in
+// order by k_split_reduce.
 constexpr int kTrThreads = 512;
 constexpr int kTrWaves = kTrThreads / 64;
 static_assert(kTrWaves == kTrWaveCount, "operator padding assumes one row-block group per wave");
+
+template <typename T>
+__host__ __device__ constexpr int tr_row_stride(int nks) { return 4 * nks + (sizeof(T) == 4 ? 4 : 2); }
+
+template <typename T>
+struct Quad {                               // four consecutive T from 16-byte aligned LDS
+    T v[4];
+    __device__ __forceinline__ void load(const T *p) {
+        if constexpr (sizeof(T) == 4) {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 q = *reinterpret_cast<const f4 *>(p);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            const d2 q0 = *reinterpret_cast<const d2 *>(p);
+            const d2 q1 = *reinterpret_cast<const d2 *>(p + 2);
+            v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+        }
+    }
+};
 
 template <typename T, int NRBW, int NT, int mode, int PF>
 __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodic, int C, int kp,
@@ -205,14 +237,15 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
                                                           const int16_t *__restrict__ oct_lists,
                                                           const int8_t *__restrict__ offsets,
                                                           const T *__restrict__ src, T *__restrict__ dst,
-                                                          int accumulate) {
+                                                          int accumulate, int nsplit, T *__restrict__ part) {
     using V = typename Mfma<T>::v4;
     constexpr int TTN = 16 * NT;
     constexpr int NCB = 3 * NT;                          // column blocks: (group, component)
     constexpr int NBUF = PF > 0 ? 2 : 1;
     constexpr int APF = 8;                               // operator prefetch distance (k steps)
-    extern __shared__ unsigned char smem_raw[];
-    const int ks_stride = 4 * nks + 1;                   // odd row stride: conflict-free B reads
+    static_assert(APF % 4 == 0, "B quads span four k steps");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int ks_stride = tr_row_stride<T>(nks);
     const int buf_elems = TTN * 3 * ks_stride;
     T *bs = reinterpret_cast<T *>(smem_raw);             // [NBUF][TTN * 3][ks_stride]
     __shared__ int32_t tkey[TTN];
@@ -221,7 +254,7 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int per_cell = 3 * kp;
 
-    int octant = 0, tile = blockIdx.x, npair = 1;
+    int octant = 0, tile = blockIdx.x, npair = 1, pr0 = 0;
     int64_t ncell_t;
     if (mode == 2) {                  // M2M: targets are the parents at `level`
         ncell_t = int64_t(1) << (3 * level);
@@ -230,7 +263,10 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
         octant = blockIdx.x & 7;
         tile = blockIdx.x >> 3;
         ncell_t = int64_t(1) << (3 * (level - 1));
-        npair = mode == 0 ? 189 : 1;
+        if (mode == 0) {
+            pr0 = int(blockIdx.y) * 189 / nsplit;
+            npair = (int(blockIdx.y) + 1) * 189 / nsplit - pr0;
+        }
     }
     if (tid < TTN) {
         const int64_t slot = int64_t(tile) * TTN + tid;
@@ -241,17 +277,18 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
     // the K padding of the staging buffers stays zero
     for (int e = tid; e < NBUF * buf_elems; e += kTrThreads) bs[e] = T(0);
     const int side = 1 << level;
-    auto op_of = [&](int pr) -> int {
-        if (mode == 0) return oct_lists[octant * 189 + pr];
+    // operator of local pair i
+    auto op_of = [&](int i) -> int {
+        if (mode == 0) return oct_lists[octant * 189 + pr0 + i];
         if (mode == 1) return octant;
-        return pr;
+        return i;
     };
-    // source cell of target slot `tid` for pair `pr` (or -1)
-    auto source_key = [&](int pr) -> int32_t {
+    // source cell of target slot `tid` for local pair i (or -1)
+    auto source_key = [&](int i) -> int32_t {
         const int32_t t = tkey[tid];
         if (t < 0) return -1;
         if (mode == 0) {
-            const int op = op_of(pr);
+            const int op = op_of(i);
             int c[3];
             for (int d = 0; d < 3; ++d) {
                 c[d] = demorton1(uint32_t(t), d, level) + offsets[op * 3 + d];
@@ -261,7 +298,7 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
             return int32_t(morton3(c[0], c[1], c[2], level));
         }
         if (mode == 1) return t >> 3;
-        return (t << 3) | pr;
+        return (t << 3) | i;
     };
     // staging map: thread tid serves target slot tid / TPT and walks that cell's
     // 3 kp coefficients with stride TPT (coalesced within the slot's threads)
@@ -285,20 +322,27 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
     __syncthreads();
 
     // One pair: out += Op * Src.  Straight-line k steps: the A fragments stream
-    // through a ring of APF registers, the B fragments of a step are all read
-    // before its MFMAs issue.
-    auto mfma_pair = [&](int pr, const T *buf) {
-        const T *opb = ops + size_t(op_of(pr)) * nrb * nks * 64 + lane;
+    // through a ring of APF registers; the B values of four k steps arrive in
+    // one 16-byte LDS read per column block.
+    auto mfma_pair = [&](int i_pair, const T *buf) {
+        const T *opb = ops + size_t(op_of(i_pair)) * nrb * nks * 64 + lane;
         T ring[APF][NRBW];
 #pragma unroll
         for (int d = 0; d < APF; ++d)
 #pragma unroll
             for (int i = 0; i < NRBW; ++i) ring[d][i] = opb[(size_t(wave + kTrWaves * i) * nks + d) * 64];
-        const T *bl = buf + (lane & 15) * 3 * ks_stride + (lane >> 4);
+        const T *bl = buf + (lane & 15) * 3 * ks_stride + 4 * (lane >> 4);
         for (int ks0 = 0; ks0 < nks; ks0 += APF) {
+            Quad<T> bq[NCB];
 #pragma unroll
             for (int d = 0; d < APF; ++d) {
                 const int ks = ks0 + d;
+                if (d % 4 == 0) {
+#pragma unroll
+                    for (int g = 0; g < NT; ++g)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) bq[g * 3 + c].load(bl + (g * 16 * 3 + c) * ks_stride + 4 * ks);
+                }
                 const int kn = ks + APF < nks ? ks + APF : nks - 1;
                 T a_use[NRBW];
 #pragma unroll
@@ -306,15 +350,11 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
                     a_use[i] = ring[d][i];
                     ring[d][i] = opb[(size_t(wave + kTrWaves * i) * nks + kn) * 64];
                 }
-                T bfrag[NCB];
-#pragma unroll
-                for (int g = 0; g < NT; ++g)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) bfrag[g * 3 + c] = bl[(g * 16 * 3 + c) * ks_stride + ks * 4];
 #pragma unroll
                 for (int i = 0; i < NRBW; ++i)
 #pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb) acc[i][cb] = Mfma<T>::op(a_use[i], bfrag[cb], acc[i][cb]);
+                    for (int cb = 0; cb < NCB; ++cb)
+                        acc[i][cb] = Mfma<T>::op(a_use[i], bq[cb].v[d % 4], acc[i][cb]);
             }
         }
     };
@@ -366,11 +406,13 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
         }
     }
     // write back: lane holds rows rb*16 + Mfma::row(lane, r) of target column lane%16 of each group
+    const bool split = part != nullptr;
 #pragma unroll
     for (int g = 0; g < NT; ++g) {
         const int32_t t = tkey[g * 16 + (lane & 15)];
         if (t < 0) continue;
-        T *out = dst + size_t(t) * 3 * kp;
+        T *out = split ? part + (size_t(blockIdx.y) * (size_t(1) << (3 * level)) + t) * per_cell
+                       : dst + size_t(t) * per_cell;
 #pragma unroll
         for (int i = 0; i < NRBW; ++i) {
             const int rb = wave + kTrWaves * i;
@@ -382,11 +424,24 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
                     if (row < C) {
                         const T v = acc[i][g * 3 + c][r];
                         T *o = out + c * kp + row;
-                        *o = accumulate ? *o + v : v;
+                        *o = (accumulate && !split) ? *o + v : v;
                     }
                 }
         }
     }
+}
+
+// dst[cell] (+)= sum over splits of part[split][cell], rows < C only, fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_split_reduce(int64_t nelem, int kp, int C, int nsplit,
+                                                      const T *__restrict__ part, T *__restrict__ dst,
+                                                      int accumulate) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= nelem) return;
+    if (int(e % kp) >= C) return;
+    T s = T(0);
+    for (int k = 0; k < nsplit; ++k) s += part[size_t(k) * nelem + e];
+    dst[e] = accumulate ? dst[e] + s : s;
 }
 
 // ------------------------------------------------------------- lattice ----
@@ -442,50 +497,69 @@ template <typename T>
 TrShape translate_shape(int kp) {
     const int nt = sizeof(T) == 4 ? 2 : 1;
     const int tpt = kTrThreads / (16 * nt);
-    const int kpad = (kp + 31) / 32 * 32;
-    const size_t lds = 2 * sizeof(T) * size_t(16) * nt * 3 * (kpad + 1);
+    const int nks = (kp + 31) / 32 * 8;
+    const size_t lds = 2 * sizeof(T) * size_t(16) * nt * 3 * tr_row_stride<T>(nks);
     if (lds <= 128 * 1024 && (3 * kp + tpt - 1) / tpt <= 24) return {nt, 24};
     return {1, 0};
 }
 
 template <typename T, int NT, int PF, int NR>
-void launch_translate_k(hipStream_t s, int mode, int grid, size_t smem, int level, int periodic, int C, int kp,
+void launch_translate_k(hipStream_t s, int mode, dim3 grid, size_t smem, int level, int periodic, int C, int kp,
                         int nrb, const T *ops, const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
-                        int accumulate) {
+                        int accumulate, int nsplit, T *part) {
     const int nks = tr_nks(C);
     if (mode == 0)
-        hipLaunchKernelGGL((k_translate<T, NR, NT, 0, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate);
+        hipLaunchKernelGGL((k_translate<T, NR, NT, 0, PF>), grid, dim3(kTrThreads), smem, s, level, periodic,
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, part);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_translate<T, NR, NT, 1, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate);
+        hipLaunchKernelGGL((k_translate<T, NR, NT, 1, PF>), grid, dim3(kTrThreads), smem, s, level, periodic,
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, 1, (T *)nullptr);
     else
-        hipLaunchKernelGGL((k_translate<T, NR, NT, 2, PF>), dim3(grid), dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate);
+        hipLaunchKernelGGL((k_translate<T, NR, NT, 2, PF>), grid, dim3(kTrThreads), smem, s, level, periodic,
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, 1, (T *)nullptr);
 }
 
 template <typename T, int NT, int PF>
-hipError_t launch_translate_rows(hipStream_t s, int mode, int nrbw, int grid, size_t smem, int level, int periodic,
-                                 int C, int kp, int nrb, const T *ops, const int16_t *oct_lists,
-                                 const int8_t *offsets, const T *src, T *dst, int accumulate) {
+hipError_t launch_translate_rows(hipStream_t s, int mode, int nrbw, dim3 grid, size_t smem, int level,
+                                 int periodic, int C, int kp, int nrb, const T *ops, const int16_t *oct_lists,
+                                 const int8_t *offsets, const T *src, T *dst, int accumulate, int nsplit,
+                                 T *part) {
     switch (nrbw) {
         case 1: launch_translate_k<T, NT, PF, 1>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                                 offsets, src, dst, accumulate); break;
+                                                 offsets, src, dst, accumulate, nsplit, part); break;
         case 2: launch_translate_k<T, NT, PF, 2>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                                 offsets, src, dst, accumulate); break;
+                                                 offsets, src, dst, accumulate, nsplit, part); break;
         case 3: launch_translate_k<T, NT, PF, 3>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                                 offsets, src, dst, accumulate); break;
+                                                 offsets, src, dst, accumulate, nsplit, part); break;
         case 4: launch_translate_k<T, NT, PF, 4>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                                 offsets, src, dst, accumulate); break;
+                                                 offsets, src, dst, accumulate, nsplit, part); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+// Number of offset ranges an M2L launch at `level` is split into: enough
+// workgroups to fill the chip, bounded by the partial-sum buffer.
+constexpr int kTrFillWorkgroups = 1024;
+
+template <typename T>
+int translate_splits(int level, int p, int kp, size_t part_elems) {
+    const TrShape sh = translate_shape<T>(kp);
+    const int64_t ncell = int64_t(1) << (3 * (level - 1));
+    const int64_t wgs = (ncell + 16 * sh.nt - 1) / (16 * sh.nt) * 8;
+    if (wgs >= kTrFillWorkgroups) return 1;
+    int ns = int((kTrFillWorkgroups + wgs - 1) / wgs);
+    if (ns > 189) ns = 189;
+    const size_t per_split = size_t(ncell) * 8 * 3 * kp;
+    while (ns > 1 && size_t(ns) * per_split > part_elems) --ns;
+    (void)p;
+    return ns;
+}
+
 template <typename T>
 hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp, const T *ops,
                             const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
-                            int accumulate) {
+                            int accumulate, T *part, size_t part_elems) {
     const int C = (p + 1) * (p + 1);
     const int nrb = tr_nrb(C);
     const int nrbw = nrb / kTrWaves;
@@ -500,13 +574,23 @@ hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, in
         ncell = int64_t(1) << (3 * (level - 1));
         grid = int((ncell + ttn - 1) / ttn) * 8;
     }
-    const size_t smem = sizeof(T) * size_t(ttn) * 3 * (4 * tr_nks(C) + 1) * (sh.pf > 0 ? 2 : 1);
+    const int nsplit = (mode == 0 && part) ? translate_splits<T>(level, p, kp, part_elems) : 1;
+    T *pbuf = nsplit > 1 ? part : nullptr;
+    const size_t smem = sizeof(T) * size_t(ttn) * 3 * tr_row_stride<T>(tr_nks(C)) * (sh.pf > 0 ? 2 : 1);
     constexpr int NTP = sizeof(T) == 4 ? 2 : 1;
+    const dim3 g3(grid, nsplit);
+    hipError_t e;
     if (sh.pf > 0)
-        return launch_translate_rows<T, NTP, 24>(s, mode, nrbw, grid, smem, level, periodic, C, kp, nrb, ops,
-                                                 oct_lists, offsets, src, dst, accumulate);
-    return launch_translate_rows<T, 1, 0>(s, mode, nrbw, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                          offsets, src, dst, accumulate);
+        e = launch_translate_rows<T, NTP, 24>(s, mode, nrbw, g3, smem, level, periodic, C, kp, nrb, ops, oct_lists,
+                                              offsets, src, dst, accumulate, nsplit, pbuf);
+    else
+        e = launch_translate_rows<T, 1, 0>(s, mode, nrbw, g3, smem, level, periodic, C, kp, nrb, ops, oct_lists,
+                                           offsets, src, dst, accumulate, nsplit, pbuf);
+    if (e != hipSuccess || nsplit == 1) return e;
+    const int64_t nelem = (int64_t(1) << (3 * level)) * 3 * kp;
+    hipLaunchKernelGGL(k_split_reduce<T>, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, nelem, kp, C,
+                       nsplit, (const T *)pbuf, dst, accumulate);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -522,7 +606,8 @@ hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, cons
     template hipError_t launch_l2p<T>(hipStream_t, int, int, const void *, const int32_t *, int, int,       \
                                       double, double, const DevTables &, const T *, double *);              \
     template hipError_t launch_translate<T>(hipStream_t, int, int, int, int, int, const T *,                \
-                                            const int16_t *, const int8_t *, const T *, T *, int);          \
+                                            const int16_t *, const int8_t *, const T *, T *, int, T *,      \
+                                            size_t);                                                        \
     template hipError_t launch_lattice<T>(hipStream_t, int, int, const double *, const T *, T *);
 VM_INST(double)
 VM_INST(float)

@@ -152,12 +152,77 @@ __device__ __forceinline__ void epilogue(const P2PArgs &a, int gi, const double 
     }
 }
 
+// Target blocks of a leaf: whole blocks of 64 targets, one target per lane, take
+// every source at a wave-uniform address (scalar loads).  A last block of
+// rem <= 32 targets would leave most lanes idle, so there the wave splits into
+// g = 64 / E lane groups (E = rem rounded up to a power of two): lane group k
+// takes target t = lane % E against every g-th source of each neighbour leaf,
+// and the groups' partial sums are combined in FP64 by a fixed butterfly.
+__device__ __forceinline__ int pow2_ceil(int v) {
+    int e = 1;
+    while (e < v) e <<= 1;
+    return e;
+}
+
+__device__ __forceinline__ void group_reduce(double *v, int nv, int E) {
+    for (int off = E; off < 64; off <<= 1)
+        for (int k = 0; k < nv; ++k) v[k] += __shfl_xor(v[k], off);
+}
+
+struct LeafGeom {
+    int cx, cy, cz, side;
+};
+
+// neighbour nb of the target leaf: source range and the offset d (source - target cell)
+__device__ __forceinline__ bool neighbour(const P2PArgs &a, const LeafGeom &L, int nb, int &js, int &je, int &dx,
+                                          int &dy, int &dz) {
+    dx = nb % 3 - 1;
+    dy = (nb / 3) % 3 - 1;
+    dz = nb / 9 - 1;
+    int nx = L.cx + dx, ny = L.cy + dy, nz = L.cz + dz;
+    if (a.periodic) {
+        nx = (nx + L.side) % L.side;
+        ny = (ny + L.side) % L.side;
+        nz = (nz + L.side) % L.side;
+    } else if (nx < 0 || ny < 0 || nz < 0 || nx >= L.side || ny >= L.side || nz >= L.side) {
+        return false;
+    }
+    const int nk = morton(nx, ny, nz, a.level);
+    js = a.start[nk];
+    je = a.start[nk + 1];
+    return true;
+}
+
+__device__ __forceinline__ void acc64(const Part64 &s, double tx, double ty, double tz, const Consts64 &k,
+                                      double u[3], double Jr[9], double S[3]) {
+    const double rx = tx - s.dx, ry = ty - s.dy, rz = tz - s.dz;
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    double q, dq;
+    pair64(r2, k, q, dq);
+    const double c0 = s.ay * rz - s.az * ry;
+    const double c1 = s.az * rx - s.ax * rz;
+    const double c2 = s.ax * ry - s.ay * rx;
+    u[0] += q * c0;
+    u[1] += q * c1;
+    u[2] += q * c2;
+    S[0] += q * s.ax;
+    S[1] += q * s.ay;
+    S[2] += q * s.az;
+    const double t0 = dq * c0, t1 = dq * c1, t2 = dq * c2;
+    Jr[0] += rx * t0; Jr[1] += rx * t1; Jr[2] += rx * t2;
+    Jr[3] += ry * t0; Jr[4] += ry * t1; Jr[5] += ry * t2;
+    Jr[6] += rz * t0; Jr[7] += rz * t1; Jr[8] += rz * t2;
+}
+
 __global__ void __launch_bounds__(64) k_p2p64(P2PArgs a, const Part64 *__restrict__ parts) {
     const int leaf = blockIdx.x, lane = threadIdx.x;
     const int s0 = a.start[leaf], cnt = a.start[leaf + 1] - s0;
     if (cnt == 0) return;
-    const int side = 1 << a.level;
-    const int cx = demorton(leaf, 0, a.level), cy = demorton(leaf, 1, a.level), cz = demorton(leaf, 2, a.level);
+    LeafGeom L;
+    L.side = 1 << a.level;
+    L.cx = demorton(leaf, 0, a.level);
+    L.cy = demorton(leaf, 1, a.level);
+    L.cz = demorton(leaf, 2, a.level);
     Consts64 k;
     k.inv_sigma = 1.0 / a.sigma;
     k.inv_s2 = k.inv_sigma * k.inv_sigma;
@@ -165,47 +230,62 @@ __global__ void __launch_bounds__(64) k_p2p64(P2PArgs a, const Part64 *__restric
     k.is5 = k.is3 * k.inv_s2;
     k.thr2 = 0.0625 * a.sigma * a.sigma;
     for (int base = 0; base < cnt; base += 64) {
-        const int i = base + lane;
-        const bool valid = i < cnt;
-        const Part64 me = parts[s0 + (valid ? i : cnt - 1)];
+        const int rem = cnt - base;
+        const bool grouped = rem <= 32;
+        const int E = grouped ? pow2_ceil(rem) : 64;
+        const int t = grouped ? (lane & (E - 1)) : lane;
+        const int gi = grouped ? lane / E : 0, ng = 64 / E;
+        const bool valid = t < rem;
+        const Part64 me = parts[s0 + base + (valid ? t : 0)];
         double u[3] = {0, 0, 0}, Jr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
         for (int nb = 0; nb < 27; ++nb) {
-            const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
-            int nx = cx + dx, ny = cy + dy, nz = cz + dz;
-            if (a.periodic) {
-                nx = (nx + side) % side;
-                ny = (ny + side) % side;
-                nz = (nz + side) % side;
-            } else if (nx < 0 || ny < 0 || nz < 0 || nx >= side || ny >= side || nz >= side) {
-                continue;
-            }
-            const int nk = morton(nx, ny, nz, a.level);
-            const int js = a.start[nk], je = a.start[nk + 1];
+            int js, je, dx, dy, dz;
+            if (!neighbour(a, L, nb, js, je, dx, dy, dz)) continue;
             // x_i - x_j = (delta_i - d w) - delta_j, d = source - target cell offset
             const double tx = me.dx - dx * a.w, ty = me.dy - dy * a.w, tz = me.dz - dz * a.w;
-            for (int j = js; j < je; ++j) {
-                const Part64 s = parts[j];
-                const double rx = tx - s.dx, ry = ty - s.dy, rz = tz - s.dz;
-                const double r2 = rx * rx + ry * ry + rz * rz;
-                double q, dq;
-                pair64(r2, k, q, dq);
-                const double c0 = s.ay * rz - s.az * ry;
-                const double c1 = s.az * rx - s.ax * rz;
-                const double c2 = s.ax * ry - s.ay * rx;
-                u[0] += q * c0;
-                u[1] += q * c1;
-                u[2] += q * c2;
-                S[0] += q * s.ax;
-                S[1] += q * s.ay;
-                S[2] += q * s.az;
-                const double t0 = dq * c0, t1 = dq * c1, t2 = dq * c2;
-                Jr[0] += rx * t0; Jr[1] += rx * t1; Jr[2] += rx * t2;
-                Jr[3] += ry * t0; Jr[4] += ry * t1; Jr[5] += ry * t2;
-                Jr[6] += rz * t0; Jr[7] += rz * t1; Jr[8] += rz * t2;
+            if (grouped) {
+                for (int j = js + gi; j < je; j += ng) acc64(parts[j], tx, ty, tz, k, u, Jr, S);
+            } else {
+                for (int j = js; j < je; ++j) acc64(parts[j], tx, ty, tz, k, u, Jr, S);
             }
         }
-        if (valid) epilogue(a, s0 + i, u, Jr, S);
+        if (grouped) {
+            double v[15];
+            for (int c = 0; c < 3; ++c) { v[c] = u[c]; v[3 + c] = S[c]; }
+            for (int c = 0; c < 9; ++c) v[6 + c] = Jr[c];
+            group_reduce(v, 15, E);
+            for (int c = 0; c < 3; ++c) { u[c] = v[c]; S[c] = v[3 + c]; }
+            for (int c = 0; c < 9; ++c) Jr[c] = v[6 + c];
+        }
+        if (valid && gi == 0) epilogue(a, s0 + base + t, u, Jr, S);
+        if (grouped) break;
     }
+}
+
+struct Acc32 {
+    float us[3], uc[3], Jr[9], S[3];
+};
+
+__device__ __forceinline__ void acc32(const Part32 &s, float tx, float ty, float tz, const Consts32 &k, Acc32 &A) {
+    const float rx = tx - s.dx, ry = ty - s.dy, rz = tz - s.dz;
+    const float r2 = rx * rx + ry * ry + rz * rz;
+    float q, dq;
+    pair32(r2, k, q, dq);
+    const float c[3] = {s.ay * rz - s.az * ry, s.az * rx - s.ax * rz, s.ax * ry - s.ay * rx};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const float y = q * c[b] - A.uc[b];
+        const float t = A.us[b] + y;
+        A.uc[b] = (t - A.us[b]) - y;
+        A.us[b] = t;
+    }
+    A.S[0] += q * s.ax;
+    A.S[1] += q * s.ay;
+    A.S[2] += q * s.az;
+    const float t0 = dq * c[0], t1 = dq * c[1], t2 = dq * c[2];
+    A.Jr[0] += rx * t0; A.Jr[1] += rx * t1; A.Jr[2] += rx * t2;
+    A.Jr[3] += ry * t0; A.Jr[4] += ry * t1; A.Jr[5] += ry * t2;
+    A.Jr[6] += rz * t0; A.Jr[7] += rz * t1; A.Jr[8] += rz * t2;
 }
 
 // Mixed precision: FP32 pair arithmetic, Kahan-compensated velocity sums.
@@ -213,8 +293,11 @@ __global__ void __launch_bounds__(64) k_p2p32(P2PArgs a, const Part32 *__restric
     const int leaf = blockIdx.x, lane = threadIdx.x;
     const int s0 = a.start[leaf], cnt = a.start[leaf + 1] - s0;
     if (cnt == 0) return;
-    const int side = 1 << a.level;
-    const int cx = demorton(leaf, 0, a.level), cy = demorton(leaf, 1, a.level), cz = demorton(leaf, 2, a.level);
+    LeafGeom L;
+    L.side = 1 << a.level;
+    L.cx = demorton(leaf, 0, a.level);
+    L.cy = demorton(leaf, 1, a.level);
+    L.cz = demorton(leaf, 2, a.level);
     Consts32 k;
     const double inv_sigma = 1.0 / a.sigma;
     k.inv_sigma = float(inv_sigma);
@@ -224,56 +307,42 @@ __global__ void __launch_bounds__(64) k_p2p32(P2PArgs a, const Part32 *__restric
     k.thr2 = float(a.sigma * a.sigma);
     const float w = float(a.w);
     for (int base = 0; base < cnt; base += 64) {
-        const int i = base + lane;
-        const bool valid = i < cnt;
-        const Part32 me = parts[s0 + (valid ? i : cnt - 1)];
-        float us[3] = {0, 0, 0}, uc[3] = {0, 0, 0};
-        float Jr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
+        const int rem = cnt - base;
+        const bool grouped = rem <= 32;
+        const int E = grouped ? pow2_ceil(rem) : 64;
+        const int t = grouped ? (lane & (E - 1)) : lane;
+        const int gi = grouped ? lane / E : 0, ng = 64 / E;
+        const bool valid = t < rem;
+        const Part32 me = parts[s0 + base + (valid ? t : 0)];
+        Acc32 A;
+        for (int c = 0; c < 3; ++c) A.us[c] = A.uc[c] = A.S[c] = 0.0f;
+        for (int c = 0; c < 9; ++c) A.Jr[c] = 0.0f;
         for (int nb = 0; nb < 27; ++nb) {
-            const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
-            int nx = cx + dx, ny = cy + dy, nz = cz + dz;
-            if (a.periodic) {
-                nx = (nx + side) % side;
-                ny = (ny + side) % side;
-                nz = (nz + side) % side;
-            } else if (nx < 0 || ny < 0 || nz < 0 || nx >= side || ny >= side || nz >= side) {
-                continue;
-            }
-            const int nk = morton(nx, ny, nz, a.level);
-            const int js = a.start[nk], je = a.start[nk + 1];
+            int js, je, dx, dy, dz;
+            if (!neighbour(a, L, nb, js, je, dx, dy, dz)) continue;
             const float tx = me.dx - float(dx) * w, ty = me.dy - float(dy) * w, tz = me.dz - float(dz) * w;
-            for (int j = js; j < je; ++j) {
-                const Part32 s = parts[j];
-                const float rx = tx - s.dx, ry = ty - s.dy, rz = tz - s.dz;
-                const float r2 = rx * rx + ry * ry + rz * rz;
-                float q, dq;
-                pair32(r2, k, q, dq);
-                const float c[3] = {s.ay * rz - s.az * ry, s.az * rx - s.ax * rz, s.ax * ry - s.ay * rx};
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const float y = q * c[b] - uc[b];
-                    const float t = us[b] + y;
-                    uc[b] = (t - us[b]) - y;
-                    us[b] = t;
-                }
-                S[0] += q * s.ax;
-                S[1] += q * s.ay;
-                S[2] += q * s.az;
-                const float t0 = dq * c[0], t1 = dq * c[1], t2 = dq * c[2];
-                Jr[0] += rx * t0; Jr[1] += rx * t1; Jr[2] += rx * t2;
-                Jr[3] += ry * t0; Jr[4] += ry * t1; Jr[5] += ry * t2;
-                Jr[6] += rz * t0; Jr[7] += rz * t1; Jr[8] += rz * t2;
+            if (grouped) {
+                for (int j = js + gi; j < je; j += ng) acc32(parts[j], tx, ty, tz, k, A);
+            } else {
+                for (int j = js; j < je; ++j) acc32(parts[j], tx, ty, tz, k, A);
             }
         }
-        if (valid) {
-            double ud[3], Jd[9], Sd[3];
-            for (int b = 0; b < 3; ++b) {
-                ud[b] = double(us[b]) - double(uc[b]);
-                Sd[b] = double(S[b]);
-            }
-            for (int kk = 0; kk < 9; ++kk) Jd[kk] = double(Jr[kk]);
-            epilogue(a, s0 + i, ud, Jd, Sd);
+        double ud[3], Jd[9], Sd[3];
+        for (int b = 0; b < 3; ++b) {
+            ud[b] = double(A.us[b]) - double(A.uc[b]);
+            Sd[b] = double(A.S[b]);
         }
+        for (int kk = 0; kk < 9; ++kk) Jd[kk] = double(A.Jr[kk]);
+        if (grouped) {
+            double v[15];
+            for (int c = 0; c < 3; ++c) { v[c] = ud[c]; v[3 + c] = Sd[c]; }
+            for (int c = 0; c < 9; ++c) v[6 + c] = Jd[c];
+            group_reduce(v, 15, E);
+            for (int c = 0; c < 3; ++c) { ud[c] = v[c]; Sd[c] = v[3 + c]; }
+            for (int c = 0; c < 9; ++c) Jd[c] = v[6 + c];
+        }
+        if (valid && gi == 0) epilogue(a, s0 + base + t, ud, Jd, Sd);
+        if (grouped) break;
     }
 }
 

@@ -21,6 +21,8 @@ using namespace vmfmm;
 
 namespace {
 
+constexpr size_t kTrPartBytes = size_t(64) << 20;   // scratch of split M2L launches
+
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -58,14 +60,14 @@ hipError_t upload(DevBuf &b, const std::vector<T> &v) {
 }
 
 // Operator matrices swizzled into MFMA A fragments: [op][rb][ks][64],
-// element (rb*16 + l%16, ks*4 + l/16) of the zero-padded operator.
+// element (rb*16 + l%16, tr_col(ks, l/16)) of the zero-padded operator.
 template <typename T>
 void swizzle(const std::vector<double> &m, int C, std::vector<T> &out, size_t base) {
     const int nrb = tr_nrb(C), nks = tr_nks(C);
     for (int rb = 0; rb < nrb; ++rb)
         for (int ks = 0; ks < nks; ++ks)
             for (int l = 0; l < 64; ++l) {
-                const int row = rb * 16 + (l & 15), col = ks * 4 + (l >> 4);
+                const int row = rb * 16 + (l & 15), col = tr_col(ks, l >> 4);
                 const double v = (row < C && col < C) ? m[size_t(row) * C + col] : 0.0;
                 out[base + (size_t(rb) * nks + ks) * 64 + l] = T(v);
             }
@@ -93,6 +95,7 @@ struct vm_ctx {
 
     // workspace
     DevBuf keys_a, keys_b, vals_a, vals_b, hist, start, p64, p32, far, flag, mbuf, lbuf;
+    DevBuf trpart;   // partial sums of M2L launches split over the offsets (coarse levels)
     DevBuf rk_u, rk_s, rk_x, rk_a, diag;
     DevBuf adj_u, adj_J, adj_v, adj_Jv, adj_far, adj_p64, adj_p32;
     std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice_t;
@@ -412,6 +415,7 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     else VM_HIP(ctx->p64.reserve(sizeof(Part64) * n), "alloc particles");
     VM_HIP(ctx->far.reserve(sizeof(double) * 12 * n), "alloc far field");
     VM_HIP(ctx->flag.reserve(sizeof(int)), "alloc flag");
+    VM_HIP(ctx->trpart.reserve(kTrPartBytes), "alloc split partials");
     const size_t cbytes = size_t(ncells) * 3 * kp * esz;
     const bool relayout = ctx->layout_p != p || ctx->layout_prec != mixed;
     if (relayout || ctx->mbuf.bytes < cbytes) {
@@ -511,7 +515,7 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
                 }
                 Timed tm(ctx, VM_PH_M2L);
                 VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
-                                           have_parent ? 1 : 0),
+                                           have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T)),
                        "M2L");
                 have_parent = true;
             }
@@ -636,7 +640,7 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
                                                lev(Mb, l), 0),
                            "M2M^T");
                 VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2lT, lists, offs, lev(Lb, l), lev(Mb, l),
-                                           parent ? 1 : 0),
+                                           parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T)),
                        "M2L^T");
                 parent = true;
             }

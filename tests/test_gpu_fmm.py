@@ -116,6 +116,29 @@ def test_rand32_periodic_matches_oracle(ctx):
     assert rel(Jm, J) < 1e-4
 
 
+# leaf populations around the kernel's block boundaries: empty, a few (lane groups
+# of 1..32), one full block of 64 and partial second blocks of both forms
+COUNTS = [0, 1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 33, 47, 63, 64, 65, 66, 80, 95, 96, 97,
+          127, 128, 129, 150, 6, 40, 70, 100]
+
+
+@pytest.mark.parametrize("periodic", [0, 3])
+def test_uneven_leaf_populations(ctx, periodic):
+    level = 2
+    counts = [COUNTS[i % len(COUNTS)] for i in range(8 ** level)]
+    x, a = W.particles_with_leaf_counts(counts, level, seed=61)
+    sigma, p = 0.15, 6
+    u, da, J = _run(ctx, x, a, sigma, p, level, periodic)
+    uo, Jo = OF.fmm(x, a, sigma, p, level, periodic=periodic)
+    assert rel(u, uo) < 1e-10
+    assert rel(J, Jo) < 1e-10
+    assert rel(da, D.stretching(Jo, a)) < 1e-10
+    um, dam, Jm = _run(ctx, x, a, sigma, p, level, periodic, precision="mixed")
+    assert rel(um, u) < 1e-5
+    assert rel(Jm, J) < 1e-4
+    assert rel(dam, da) < 1e-4
+
+
 def test_transpose_scheme_conserves_vorticity(ctx):
     x, a = W.random_field(16, 4.0, 23)
     h = L / 16

@@ -181,3 +181,23 @@ def random_particles(n: int, seed: int, box_len: float = TWO_PI, lo=(0.0, 0.0, 0
     if zero_sum and n > 1:
         a -= a.mean(axis=0, keepdims=True)
     return x, a
+
+
+def particles_with_leaf_counts(counts, level: int, seed: int, box_len: float = TWO_PI):
+    """Particles placed uniformly inside the leaves of a uniform octree at
+    `level`, counts[i] of them in the leaf with cell coordinates
+    (i % s, (i // s) % s, i // s^2), s = 2^level; N(0,1) strengths, zero sum.
+    Points keep a margin of 1e-3 leaf widths from the leaf faces so rounding
+    cannot move them across."""
+    rng = np.random.default_rng(seed)
+    side = 1 << level
+    wl = box_len / side
+    xs = []
+    for i, c in enumerate(counts):
+        cell = np.array([i % side, (i // side) % side, i // (side * side)], np.float64)
+        xs.append((cell + rng.uniform(1e-3, 1 - 1e-3, size=(int(c), 3))) * wl)
+    x = np.concatenate(xs, axis=0)
+    a = rng.standard_normal(x.shape)
+    if len(x) > 1:
+        a -= a.mean(axis=0, keepdims=True)
+    return x, a
