@@ -60,11 +60,16 @@ hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const 
 // Generic translation GEMM on MFMA: mode 0 = M2L, 1 = L2L, 2 = M2M.
 // `part` (part_elems elements of T, may be null) is scratch for M2L launches
 // split over the offsets at coarse levels; without it no split is made.
+// `zero_cell` (may be null) points at tr_zero_elems(kp) zeros; with it the
+// FP32 M2L takes its operator-stationary form, which also needs
+// tr_slack_elems(kp) readable elements after the end of `src`.
 template <typename T>
 hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp,
                             const T *ops, const int16_t *oct_lists, const int8_t *offsets,
                             const T *src, T *dst, int accumulate, T *part = nullptr,
-                            size_t part_elems = 0);
+                            size_t part_elems = 0, const T *zero_cell = nullptr);
+inline size_t tr_slack_elems(int kp) { return size_t((kp + 31) / 32 * 32 - kp) + 4; }
+inline size_t tr_zero_elems(int kp) { return size_t(3) * kp + tr_slack_elems(kp) + 4; }
 
 template <typename T>
 hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, const T *m0, T *l0);
@@ -112,12 +117,13 @@ hipError_t launch_diagnostics(hipStream_t s, int n, const double *u, const doubl
 inline int pad16(int c) { return (c + 15) / 16 * 16; }
 inline int pad4(int c) { return (c + 3) / 4 * 4; }
 
-// Operator fragment layout of the translation GEMMs: [op][row block][k step][64
-// lanes], row blocks padded to whole groups of 8 (one per wave), k steps (4
-// coefficients each) padded to a multiple of 8, the padding zero.  No guard
-// is then needed inside the MFMA loop.  Lane l of fragment (rb, ks) holds
-// element (rb*16 + l%16, tr_col(ks, l/16)) of the operator: k step 4b+s
-// takes column 16b + 4h + s in lane group h.
+// Operator fragment layout of the translation GEMMs: [op][row block][k block]
+// [64 lanes][4], row blocks padded to whole groups of 8 (one per wave), k
+// steps (4 coefficients each) padded to a multiple of 8, the padding zero, so
+// no guard is needed inside the MFMA loop.  A k block is four k steps: lane l
+// of row block rb holds, for k step 4b+s, element (rb*16 + l%16,
+// tr_col(4b+s, l/16)) of the operator at position s of its 16-byte quad:
+// k step 4b+s takes column 16b + 4h + s in lane group h.
 constexpr int kTrWaveCount = 8;
 inline int tr_nrb(int C) { return (pad16(C) / 16 + kTrWaveCount - 1) / kTrWaveCount * kTrWaveCount; }
 inline int tr_nks(int C) { return (pad4(C) + 31) / 32 * 8; }

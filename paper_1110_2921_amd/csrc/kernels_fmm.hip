@@ -215,7 +215,7 @@ template <typename T>
 __host__ __device__ constexpr int tr_row_stride(int nks) { return 4 * nks + (sizeof(T) == 4 ? 4 : 2); }
 
 template <typename T>
-struct Quad {                               // four consecutive T from 16-byte aligned LDS
+struct Quad {                               // four consecutive T from 16-byte aligned memory
     T v[4];
     __device__ __forceinline__ void load(const T *p) {
         if constexpr (sizeof(T) == 4) {
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
     constexpr int NCB = 3 * NT;                          // column blocks: (group, component)
     constexpr int NBUF = PF > 0 ? 2 : 1;
     constexpr int APF = 8;                               // operator prefetch distance (k steps)
-    static_assert(APF % 4 == 0, "B quads span four k steps");
+    static_assert(APF % 8 == 0, "the ring holds whole pairs of k blocks (k blocks per operator are even)");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int ks_stride = tr_row_stride<T>(nks);
     const int buf_elems = TTN * 3 * ks_stride;
@@ -321,40 +321,42 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
         for (int c = 0; c < NCB; ++c) acc[i][c] = V{T(0), T(0), T(0), T(0)};
     __syncthreads();
 
-    // One pair: out += Op * Src.  Straight-line k steps: the A fragments stream
-    // through a ring of APF registers; the B values of four k steps arrive in
-    // one 16-byte LDS read per column block.
+    // One pair: out += Op * Src.  Straight-line k blocks (four k steps): the A
+    // quads stream from L2 through a ring of RQ blocks; the B values of a k
+    // block arrive in one 16-byte LDS read per column block.
+    constexpr int RQ = APF / 4;
+    const int nkb = nks / 4;
     auto mfma_pair = [&](int i_pair, const T *buf) {
-        const T *opb = ops + size_t(op_of(i_pair)) * nrb * nks * 64 + lane;
-        T ring[APF][NRBW];
+        const T *opb = ops + size_t(op_of(i_pair)) * nrb * nks * 64 + 4 * lane;
+        Quad<T> ring[RQ][NRBW];
 #pragma unroll
-        for (int d = 0; d < APF; ++d)
+        for (int q = 0; q < RQ; ++q)
 #pragma unroll
-            for (int i = 0; i < NRBW; ++i) ring[d][i] = opb[(size_t(wave + kTrWaves * i) * nks + d) * 64];
+            for (int i = 0; i < NRBW; ++i) ring[q][i].load(opb + (size_t(wave + kTrWaves * i) * nkb + q) * 256);
         const T *bl = buf + (lane & 15) * 3 * ks_stride + 4 * (lane >> 4);
-        for (int ks0 = 0; ks0 < nks; ks0 += APF) {
-            Quad<T> bq[NCB];
+        for (int kb0 = 0; kb0 < nkb; kb0 += RQ) {
 #pragma unroll
-            for (int d = 0; d < APF; ++d) {
-                const int ks = ks0 + d;
-                if (d % 4 == 0) {
+            for (int q = 0; q < RQ; ++q) {
+                const int kb = kb0 + q;
+                Quad<T> bq[NCB];
 #pragma unroll
-                    for (int g = 0; g < NT; ++g)
+                for (int g = 0; g < NT; ++g)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) bq[g * 3 + c].load(bl + (g * 16 * 3 + c) * ks_stride + 4 * ks);
-                }
-                const int kn = ks + APF < nks ? ks + APF : nks - 1;
-                T a_use[NRBW];
+                    for (int c = 0; c < 3; ++c) bq[g * 3 + c].load(bl + (g * 16 * 3 + c) * ks_stride + 16 * kb);
+                const int kn = kb + RQ < nkb ? kb + RQ : nkb - 1;
+                Quad<T> a_use[NRBW];
 #pragma unroll
                 for (int i = 0; i < NRBW; ++i) {
-                    a_use[i] = ring[d][i];
-                    ring[d][i] = opb[(size_t(wave + kTrWaves * i) * nks + kn) * 64];
+                    a_use[i] = ring[q][i];
+                    ring[q][i].load(opb + (size_t(wave + kTrWaves * i) * nkb + kn) * 256);
                 }
 #pragma unroll
-                for (int i = 0; i < NRBW; ++i)
+                for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb)
-                        acc[i][cb] = Mfma<T>::op(a_use[i], bq[cb].v[d % 4], acc[i][cb]);
+                    for (int i = 0; i < NRBW; ++i)
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb)
+                            acc[i][cb] = Mfma<T>::op(a_use[i].v[s4], bq[cb].v[s4], acc[i][cb]);
             }
         }
     };
@@ -442,6 +444,161 @@ __global__ void __launch_bounds__(256) k_split_reduce(int64_t nelem, int kp, int
     T s = T(0);
     for (int k = 0; k < nsplit; ++k) s += part[size_t(k) * nelem + e];
     dst[e] = accumulate ? dst[e] + s : s;
+}
+
+// M2L in FP32, operator-stationary form.  A workgroup of 8 waves takes 64
+// same-octant target cells; wave w serves targets 16 (w/2) .. +15 and row
+// blocks NRBH (w%2) .. +NRBH-1.  Per interaction offset the operator (2 NRBH
+// row blocks x NB k blocks of A quads) sits in LDS, double-buffered and
+// shared by all waves, while each lane holds its own target's source
+// coefficients as B quads in registers (NB x 3 quads).  The next offset's
+// operator is copied into the other LDS buffer a chunk per k block and the
+// next offset's sources are loaded into a B quad right after its last use,
+// so the loads overlap the MFMAs and each offset costs one barrier.
+//
+// Source loads are unconditional: a missing source (no target in the slot,
+// or a free-space offset leaving the domain) reads `zero_cell`, and the last
+// k block may read up to 4 nks - kp values past a component, which meet zero
+// operator columns (the expansion buffers carry that much slack at their end).
+// Scheduling barriers keep each k block in the order chunk store, chunk load,
+// A reads, MFMAs, source loads, so the wait for a chunk never covers the
+// newer source loads.
+template <int NRBH, int NB>
+__global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, int C, int kp, int nrb_pad,
+                                                       int nks, const float *__restrict__ ops,
+                                                       const int16_t *__restrict__ oct_lists,
+                                                       const int8_t *__restrict__ offsets,
+                                                       const float *__restrict__ src, float *__restrict__ dst,
+                                                       int accumulate, int nsplit, float *__restrict__ part,
+                                                       const float *__restrict__ zero_cell) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    using V = Mfma<float>::v4;
+    constexpr int TT = 64;                               // target cells per workgroup
+    constexpr int OPF = 2 * NRBH * NB * 256;             // floats of one operator in LDS
+    constexpr int CHUNK = 4 * kTrThreads;                // floats copied per k block
+    constexpr int NCHUNK = (OPF + CHUNK - 1) / CHUNK;
+    constexpr bool EXACT = OPF % CHUNK == 0;
+    static_assert(NCHUNK <= NB, "the operator copy must finish within one offset");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *opl = reinterpret_cast<float *>(smem_raw);    // [2][OPF]
+    __shared__ int32_t tkey[TT];
+    __shared__ int32_t pinfo[189];                       // per local offset: op | (d + 8) in 4-bit fields
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tg = wave >> 1, rh = wave & 1, h = lane >> 4;
+    const int octant = blockIdx.x & 7, tile = blockIdx.x >> 3;
+    const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
+    const int pr0 = int(blockIdx.y) * 189 / nsplit;
+    const int npair = (int(blockIdx.y) + 1) * 189 / nsplit - pr0;
+    const size_t op_stride = size_t(nrb_pad) * nks * 64;
+    const int per_cell = 3 * kp;
+    const int side = 1 << level;
+    if (tid < TT) {
+        const int64_t slot = int64_t(tile) * TT + tid;
+        tkey[tid] = slot < ncell_t ? int32_t((slot << 3) | octant) : -1;
+    }
+    if (tid < npair) {
+        const int op = oct_lists[octant * 189 + pr0 + tid];
+        pinfo[tid] = op | ((offsets[op * 3] + 8) << 16) | ((offsets[op * 3 + 1] + 8) << 20) |
+                     ((offsets[op * 3 + 2] + 8) << 24);
+    }
+    __syncthreads();
+    const int32_t t = tkey[tg * 16 + (lane & 15)];
+    int tc[3] = {0, 0, 0};
+    if (t >= 0)
+        for (int d = 0; d < 3; ++d) tc[d] = demorton1(uint32_t(t), d, level);
+    // this lane's source cell for local offset i (zero_cell: none), k offset of its lane group
+    auto src_of = [&](int i) -> const float * {
+        const int info = pinfo[i];
+        int c[3];
+        bool ok = t >= 0;
+        for (int d = 0; d < 3; ++d) {
+            c[d] = tc[d] + ((info >> (16 + 4 * d)) & 15) - 8;
+            if (periodic) c[d] &= side - 1;
+            else ok = ok && c[d] >= 0 && c[d] < side;
+        }
+        const float *sp = ok ? src + size_t(morton3(c[0], c[1], c[2], level)) * per_cell : zero_cell;
+        return sp + 4 * h;
+    };
+    auto op_of = [&](int i) { return ops + size_t(pinfo[i] & 0xffff) * op_stride; };
+    f4 B[NB][3];
+    auto load_b = [&](int b, const float *sp) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) B[b][c] = *reinterpret_cast<const f4 *>(sp + c * kp + 16 * b);
+    };
+    {
+        const float *og = op_of(0);
+        for (int e = 4 * tid; e < OPF; e += CHUNK)
+            *reinterpret_cast<f4 *>(opl + e) = *reinterpret_cast<const f4 *>(og + e);
+        const float *sp = src_of(0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) load_b(b, sp);
+    }
+    V acc[NRBH][3];
+#pragma unroll
+    for (int i = 0; i < NRBH; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[i][c] = V{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+
+    for (int pr = 0; pr < npair; ++pr) {
+        const int cur = pr & 1;
+        const bool more = pr + 1 < npair;
+        const float *spn = src_of(more ? pr + 1 : pr);     // wave-uniform choice
+        const float *ogn = op_of(more ? pr + 1 : pr) + 4 * tid;
+        float *oln = opl + (cur ^ 1) * OPF + 4 * tid;
+        const float *olc = opl + cur * OPF + 4 * lane + (rh * NRBH) * NB * 256;
+        f4 stage = f4{0.f, 0.f, 0.f, 0.f};
+        f4 aq[2][NRBH];
+#pragma unroll
+        for (int i = 0; i < NRBH; ++i) aq[0][i] = *reinterpret_cast<const f4 *>(olc + (i * NB) * 256);
+        // The next offset's loads are issued unconditionally (on the last offset
+        // they re-read the current one into the idle buffer): a branch around
+        // them would make the wait for a chunk cover every newer load.
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (b >= 1 && b - 1 < NCHUNK && (EXACT || (b - 1) * CHUNK + 4 * tid < OPF))
+                *reinterpret_cast<f4 *>(oln + (b - 1) * CHUNK) = stage;
+            if (b < NCHUNK && (EXACT || b * CHUNK + 4 * tid < OPF))
+                stage = *reinterpret_cast<const f4 *>(ogn + b * CHUNK);
+            __builtin_amdgcn_sched_barrier(0);
+            if (b + 1 < NB)
+#pragma unroll
+                for (int i = 0; i < NRBH; ++i)
+                    aq[(b + 1) & 1][i] = *reinterpret_cast<const f4 *>(olc + (i * NB + b + 1) * 256);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int i = 0; i < NRBH; ++i)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        acc[i][c] = Mfma<float>::op(aq[b & 1][i][s4], B[b][c][s4], acc[i][c]);
+            __builtin_amdgcn_sched_barrier(0);
+            load_b(b, spn);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (NCHUNK == NB && (EXACT || (NB - 1) * CHUNK + 4 * tid < OPF))
+            *reinterpret_cast<f4 *>(oln + (NB - 1) * CHUNK) = stage;
+        __syncthreads();
+    }
+    if (t < 0) return;
+    const bool split = part != nullptr;
+    float *out = split ? part + (size_t(blockIdx.y) * (size_t(1) << (3 * level)) + t) * per_cell
+                       : dst + size_t(t) * per_cell;
+#pragma unroll
+    for (int i = 0; i < NRBH; ++i) {
+        const int rb = rh * NRBH + i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rb * 16 + Mfma<float>::row(lane, r);
+                if (row < C) {
+                    float *o = out + c * kp + row;
+                    *o = (accumulate && !split) ? *o + acc[i][c][r] : acc[i][c][r];
+                }
+            }
+    }
 }
 
 // ------------------------------------------------------------- lattice ----
@@ -542,24 +699,21 @@ hipError_t launch_translate_rows(hipStream_t s, int mode, int nrbw, dim3 grid, s
 // workgroups to fill the chip, bounded by the partial-sum buffer.
 constexpr int kTrFillWorkgroups = 1024;
 
-template <typename T>
-int translate_splits(int level, int p, int kp, size_t part_elems) {
-    const TrShape sh = translate_shape<T>(kp);
+int translate_splits(int level, int ttn, int kp, size_t part_elems) {
     const int64_t ncell = int64_t(1) << (3 * (level - 1));
-    const int64_t wgs = (ncell + 16 * sh.nt - 1) / (16 * sh.nt) * 8;
+    const int64_t wgs = (ncell + ttn - 1) / ttn * 8;
     if (wgs >= kTrFillWorkgroups) return 1;
     int ns = int((kTrFillWorkgroups + wgs - 1) / wgs);
     if (ns > 189) ns = 189;
     const size_t per_split = size_t(ncell) * 8 * 3 * kp;
     while (ns > 1 && size_t(ns) * per_split > part_elems) --ns;
-    (void)p;
     return ns;
 }
 
 template <typename T>
 hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp, const T *ops,
                             const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
-                            int accumulate, T *part, size_t part_elems) {
+                            int accumulate, T *part, size_t part_elems, const T *zero_cell) {
     const int C = (p + 1) * (p + 1);
     const int nrb = tr_nrb(C);
     const int nrbw = nrb / kTrWaves;
@@ -574,7 +728,38 @@ hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, in
         ncell = int64_t(1) << (3 * (level - 1));
         grid = int((ncell + ttn - 1) / ttn) * 8;
     }
-    const int nsplit = (mode == 0 && part) ? translate_splits<T>(level, p, kp, part_elems) : 1;
+    if constexpr (sizeof(T) == 4) {
+        // operator-stationary M2L where its register and LDS budget allows
+        const int nrbh = (pad16(C) / 16 + 1) / 2, nb = tr_nks(C) / 4;
+        const bool os = mode == 0 && zero_cell != nullptr &&
+                        ((nrbh == 4 && nb == 8) || (nrbh == 3 && nb == 6) || (nrbh <= 2 && nb == 4));
+        if (os) {
+            const int nsplit = part ? translate_splits(level, 64, kp, part_elems) : 1;
+            T *pbuf = nsplit > 1 ? part : nullptr;
+            const dim3 g3(unsigned((ncell + 63) / 64 * 8), unsigned(nsplit));
+            const int nks = tr_nks(C);
+            if (nb == 8) {
+                const size_t smem = 2 * sizeof(float) * size_t(2 * 4 * 8 * 256);
+                hipLaunchKernelGGL((k_m2l_os<4, 8>), g3, dim3(kTrThreads), smem, s, level, periodic, C, kp, nrb,
+                                   nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, pbuf, zero_cell);
+            } else if (nb == 6) {
+                const size_t smem = 2 * sizeof(float) * size_t(2 * 3 * 6 * 256);
+                hipLaunchKernelGGL((k_m2l_os<3, 6>), g3, dim3(kTrThreads), smem, s, level, periodic, C, kp, nrb,
+                                   nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, pbuf, zero_cell);
+            } else {
+                const size_t smem = 2 * sizeof(float) * size_t(2 * 2 * 4 * 256);
+                hipLaunchKernelGGL((k_m2l_os<2, 4>), g3, dim3(kTrThreads), smem, s, level, periodic, C, kp, nrb,
+                                   nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, pbuf, zero_cell);
+            }
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess || nsplit == 1) return e;
+            const int64_t nelem = (int64_t(1) << (3 * level)) * 3 * kp;
+            hipLaunchKernelGGL(k_split_reduce<T>, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, nelem, kp,
+                               C, nsplit, (const T *)pbuf, dst, accumulate);
+            return hipGetLastError();
+        }
+    }
+    const int nsplit = (mode == 0 && part) ? translate_splits(level, ttn, kp, part_elems) : 1;
     T *pbuf = nsplit > 1 ? part : nullptr;
     const size_t smem = sizeof(T) * size_t(ttn) * 3 * tr_row_stride<T>(tr_nks(C)) * (sh.pf > 0 ? 2 : 1);
     constexpr int NTP = sizeof(T) == 4 ? 2 : 1;
@@ -607,7 +792,7 @@ hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, cons
                                       double, double, const DevTables &, const T *, double *);              \
     template hipError_t launch_translate<T>(hipStream_t, int, int, int, int, int, const T *,                \
                                             const int16_t *, const int8_t *, const T *, T *, int, T *,      \
-                                            size_t);                                                        \
+                                            size_t, const T *);                                             \
     template hipError_t launch_lattice<T>(hipStream_t, int, int, const double *, const T *, T *);
 VM_INST(double)
 VM_INST(float)

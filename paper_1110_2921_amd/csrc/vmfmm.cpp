@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -59,18 +60,20 @@ hipError_t upload(DevBuf &b, const std::vector<T> &v) {
     return hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
-// Operator matrices swizzled into MFMA A fragments: [op][rb][ks][64],
-// element (rb*16 + l%16, tr_col(ks, l/16)) of the zero-padded operator.
+// Operator matrices swizzled into MFMA A fragments: [op][rb][kb][64][4],
+// quad element s of lane l is (rb*16 + l%16, tr_col(4 kb + s, l/16)) of the
+// zero-padded operator.
 template <typename T>
 void swizzle(const std::vector<double> &m, int C, std::vector<T> &out, size_t base) {
-    const int nrb = tr_nrb(C), nks = tr_nks(C);
+    const int nrb = tr_nrb(C), nkb = tr_nks(C) / 4;
     for (int rb = 0; rb < nrb; ++rb)
-        for (int ks = 0; ks < nks; ++ks)
-            for (int l = 0; l < 64; ++l) {
-                const int row = rb * 16 + (l & 15), col = tr_col(ks, l >> 4);
-                const double v = (row < C && col < C) ? m[size_t(row) * C + col] : 0.0;
-                out[base + (size_t(rb) * nks + ks) * 64 + l] = T(v);
-            }
+        for (int kb = 0; kb < nkb; ++kb)
+            for (int l = 0; l < 64; ++l)
+                for (int q = 0; q < 4; ++q) {
+                    const int row = rb * 16 + (l & 15), col = tr_col(4 * kb + q, l >> 4);
+                    const double v = (row < C && col < C) ? m[size_t(row) * C + col] : 0.0;
+                    out[base + ((size_t(rb) * nkb + kb) * 64 + l) * 4 + q] = T(v);
+                }
 }
 
 struct OpSet {
@@ -96,6 +99,7 @@ struct vm_ctx {
     // workspace
     DevBuf keys_a, keys_b, vals_a, vals_b, hist, start, p64, p32, far, flag, mbuf, lbuf;
     DevBuf trpart;   // partial sums of M2L launches split over the offsets (coarse levels)
+    DevBuf zeros;    // a zero expansion cell read in place of missing M2L sources
     DevBuf rk_u, rk_s, rk_x, rk_a, diag;
     DevBuf adj_u, adj_J, adj_v, adj_Jv, adj_far, adj_p64, adj_p32;
     std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice_t;
@@ -163,8 +167,18 @@ vm_status ensure_tables(vm_ctx *ctx) {
     const OffsetTable &t = offset_table();
     std::vector<int8_t> offs(316 * 3);
     std::memcpy(offs.data(), t.d, sizeof(t.d));
+    // Device order of each octant's 189 offsets: grouped by the parity of d
+    // (the parity class of the source cells), (dz, dy, dx) order inside a
+    // group.  Consecutive offsets then read source cells one parent apart,
+    // which the workgroups of an XCD share in L2; the plain (dz, dy, dx) order
+    // alternates between disjoint parity classes.
     std::vector<int16_t> lists(8 * 189);
-    std::memcpy(lists.data(), t.list, sizeof(t.list));
+    for (int o = 0; o < 8; ++o) {
+        int16_t *l = lists.data() + o * 189;
+        std::memcpy(l, t.list[o], sizeof(t.list[o]));
+        auto cls = [&](int16_t i) { return (t.d[i][0] & 1) | ((t.d[i][1] & 1) << 1) | ((t.d[i][2] & 1) << 2); };
+        std::stable_sort(l, l + 189, [&](int16_t a, int16_t b) { return cls(a) < cls(b); });
+    }
     VM_HIP(upload(ctx->offsets, offs), "upload offsets");
     VM_HIP(upload(ctx->octlists, lists), "upload octant lists");
     ctx->tables_ready = true;
@@ -416,7 +430,10 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     VM_HIP(ctx->far.reserve(sizeof(double) * 12 * n), "alloc far field");
     VM_HIP(ctx->flag.reserve(sizeof(int)), "alloc flag");
     VM_HIP(ctx->trpart.reserve(kTrPartBytes), "alloc split partials");
-    const size_t cbytes = size_t(ncells) * 3 * kp * esz;
+    if (ctx->zeros.bytes == 0) VM_HIP(ctx->zeros.reserve(tr_zero_elems(pad4(ncoef(VM_MAX_P))) * sizeof(double), true),
+                                      "alloc zero cell");
+    // slack after the last cell: the FP32 M2L reads up to a k block past a component
+    const size_t cbytes = (size_t(ncells) * 3 * kp + tr_slack_elems(kp)) * esz;
     const bool relayout = ctx->layout_p != p || ctx->layout_prec != mixed;
     if (relayout || ctx->mbuf.bytes < cbytes) {
         // coefficient padding (rows C..kp-1) must stay zero: clear on any change of layout
@@ -515,7 +532,8 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
                 }
                 Timed tm(ctx, VM_PH_M2L);
                 VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
-                                           have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T)),
+                                           have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
+                                           ctx->zeros.as<T>()),
                        "M2L");
                 have_parent = true;
             }
@@ -640,7 +658,8 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
                                                lev(Mb, l), 0),
                            "M2M^T");
                 VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2lT, lists, offs, lev(Lb, l), lev(Mb, l),
-                                           parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T)),
+                                           parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
+                                           ctx->zeros.as<T>()),
                        "M2L^T");
                 parent = true;
             }
