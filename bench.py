@@ -109,6 +109,22 @@ def tree_bytes_per_particle(level, f32):
     return 32 + 20 * npass + 4 + 52 + (32 if f32 else 64)
 
 
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a 1 GiB copy), or None when there is
+    none or the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    from paper_1110_2921_amd.rocprof_summary import sources_sha256
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("sources_sha256") != sources_sha256():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(w, budget_s=30.0):
     """The oracle FMM timed on the host on a 32^3 sample of the same recipe."""
     import workloads as W
@@ -231,15 +247,26 @@ def main():
     m2l_launch = phases["m2l"][1] / n_eval
     p2p_flop = P2P_FLOP_PER_PAIR[args.precision] * pairs
     f32 = args.precision == "mixed"
-    roof_m2l = {"bound": "mfma", "kernel": "k_translate<M2L>",
+    kp = (C + 3) // 4 * 4
+    esz = 4 if f32 else 8
+    m2l_kernel = "k_m2l_os<4,8>" if (f32 and w.p in (9, 10)) else ("k_translate<double,1,1,0,24>" if not f32
+                                                                 else "k_m2l_os")
+    m2l_traffic = measured_traffic(w.name, args.precision, m2l_kernel)
+    # algorithmic bytes of the M2L phase: read M, read and write L at every level, the operators once
+    cells = sum(8 ** l for l in range(1 if w.periodic else 2, w.level + 1))
+    m2l_alg_bytes = (cells * 3 * kp * esz * 3 + 316 * C * C * esz) / m2l_launch
+    roof_m2l = {"bound": "mfma", "kernel": f"{m2l_kernel} (M2L, all levels)",
                 "achieved": m2l_flop / m2l_launch / (m2l_ms / m2l_launch * 1e-3) / 1e12,
                 "peak": PEAKS["mfma_f32_tflops" if f32 else "mfma_f64_tflops"], "unit": "TFLOP/s",
-                "traffic": None}
+                "traffic": m2l_traffic, "traffic_unit": "bytes per launch",
+                "algorithmic_bytes_per_launch": m2l_alg_bytes, "launches_per_eval": m2l_launch}
     roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
-    roof_p2p = {"bound": "alu", "kernel": "k_p2p32" if f32 else "k_p2p64",
+    p2p_kernel = "k_p2p32" if f32 else "k_p2p64"
+    roof_p2p = {"bound": "alu", "kernel": p2p_kernel,
                 "achieved": p2p_flop / (p2p_ms * 1e-3) / 1e12,
                 "peak": PEAKS["valu_f32_tflops" if f32 else "valu_f64_tflops"], "unit": "TFLOP/s",
-                "traffic": None}
+                "traffic": measured_traffic(w.name, args.precision, p2p_kernel), "traffic_unit": "bytes per launch",
+                "algorithmic_bytes_per_launch": n * (32 if f32 else 64) + n * 8 * (12 + 3 + 3 + 9 + 3) + n * 4}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
     dominant = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
     tree_ms = phases["tree"][0] / n_eval

@@ -452,9 +452,10 @@ __global__ void __launch_bounds__(256) k_split_reduce(int64_t nelem, int kp, int
 // row blocks x NB k blocks of A quads) sits in LDS, double-buffered and
 // shared by all waves, while each lane holds its own target's source
 // coefficients as B quads in registers (NB x 3 quads).  The next offset's
-// operator is copied into the other LDS buffer a chunk per k block and the
-// next offset's sources are loaded into a B quad right after its last use,
-// so the loads overlap the MFMAs and each offset costs one barrier.
+// operator is copied into the other LDS buffer in 8 KB chunks held two k blocks
+// in registers, and the next offset's sources are loaded into a B quad right
+// after its last use, so the loads overlap the MFMAs and each offset costs one
+// barrier.
 //
 // Source loads are unconditional: a missing source (no target in the slot,
 // or a free-space offset leaving the domain) reads `zero_cell`, and the last
@@ -478,7 +479,8 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
     constexpr int CHUNK = 4 * kTrThreads;                // floats copied per k block
     constexpr int NCHUNK = (OPF + CHUNK - 1) / CHUNK;
     constexpr bool EXACT = OPF % CHUNK == 0;
-    static_assert(NCHUNK <= NB, "the operator copy must finish within one offset");
+    constexpr int NPAIRC = (NCHUNK + 1) / 2;             // k blocks that load two chunks each
+    static_assert(NPAIRC + 2 <= NB, "the operator copy must finish within one offset");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float *opl = reinterpret_cast<float *>(smem_raw);    // [2][OPF]
     __shared__ int32_t tkey[TT];
@@ -548,19 +550,32 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
         const float *ogn = op_of(more ? pr + 1 : pr) + 4 * tid;
         float *oln = opl + (cur ^ 1) * OPF + 4 * tid;
         const float *olc = opl + cur * OPF + 4 * lane + (rh * NRBH) * NB * 256;
-        f4 stage = f4{0.f, 0.f, 0.f, 0.f};
+        f4 stage[2][2];
         f4 aq[2][NRBH];
 #pragma unroll
         for (int i = 0; i < NRBH; ++i) aq[0][i] = *reinterpret_cast<const f4 *>(olc + (i * NB) * 256);
         // The next offset's loads are issued unconditionally (on the last offset
         // they re-read the current one into the idle buffer): a branch around
-        // them would make the wait for a chunk cover every newer load.
+        // them would make the wait for a chunk cover every newer load.  Chunks
+        // 2b and 2b+1 are loaded in k block b and stored two k blocks later.
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            if (b >= 1 && b - 1 < NCHUNK && (EXACT || (b - 1) * CHUNK + 4 * tid < OPF))
-                *reinterpret_cast<f4 *>(oln + (b - 1) * CHUNK) = stage;
-            if (b < NCHUNK && (EXACT || b * CHUNK + 4 * tid < OPF))
-                stage = *reinterpret_cast<const f4 *>(ogn + b * CHUNK);
+            if (b >= 2 && b - 2 < NPAIRC) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int ch = 2 * (b - 2) + u;
+                    if (ch < NCHUNK && (EXACT || ch * CHUNK + 4 * tid < OPF))
+                        *reinterpret_cast<f4 *>(oln + ch * CHUNK) = stage[b & 1][u];
+                }
+            }
+            if (b < NPAIRC) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int ch = 2 * b + u;
+                    if (ch < NCHUNK && (EXACT || ch * CHUNK + 4 * tid < OPF))
+                        stage[b & 1][u] = *reinterpret_cast<const f4 *>(ogn + ch * CHUNK);
+                }
+            }
             __builtin_amdgcn_sched_barrier(0);
             if (b + 1 < NB)
 #pragma unroll
@@ -577,8 +592,6 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
             load_b(b, spn);
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (NCHUNK == NB && (EXACT || (NB - 1) * CHUNK + 4 * tid < OPF))
-            *reinterpret_cast<f4 *>(oln + (NB - 1) * CHUNK) = stage;
         __syncthreads();
     }
     if (t < 0) return;

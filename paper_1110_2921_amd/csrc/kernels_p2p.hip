@@ -215,8 +215,17 @@ __device__ __forceinline__ void acc64(const Part64 &s, double tx, double ty, dou
     Jr[6] += rz * t0; Jr[7] += rz * t1; Jr[8] += rz * t2;
 }
 
+// Workgroups are handed to the 8 XCDs round-robin; leaf (blockIdx mod 8) *
+// nleaf/8 + blockIdx/8 gives each XCD one contiguous Morton range, whose
+// neighbour leaves its L2 then shares.
+__device__ __forceinline__ int xcd_leaf(int nleaf) {
+    const int b = blockIdx.x;
+    if (nleaf % 8 != 0) return b;
+    return (b & 7) * (nleaf >> 3) + (b >> 3);
+}
+
 __global__ void __launch_bounds__(64) k_p2p64(P2PArgs a, const Part64 *__restrict__ parts) {
-    const int leaf = blockIdx.x, lane = threadIdx.x;
+    const int leaf = xcd_leaf(a.nleaf), lane = threadIdx.x;
     const int s0 = a.start[leaf], cnt = a.start[leaf + 1] - s0;
     if (cnt == 0) return;
     LeafGeom L;
@@ -291,7 +300,7 @@ __device__ __forceinline__ void acc32(const Part32 &s, float tx, float ty, float
 
 // Mixed precision: FP32 pair arithmetic, Kahan-compensated velocity sums.
 __global__ void __launch_bounds__(64) k_p2p32(P2PArgs a, const Part32 *__restrict__ parts) {
-    const int leaf = blockIdx.x, lane = threadIdx.x;
+    const int leaf = xcd_leaf(a.nleaf), lane = threadIdx.x;
     const int s0 = a.start[leaf], cnt = a.start[leaf + 1] - s0;
     if (cnt == 0) return;
     LeafGeom L;
