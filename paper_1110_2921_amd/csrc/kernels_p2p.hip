@@ -77,8 +77,26 @@ __device__ __forceinline__ void pair64(double r2, const Consts64 &k, double &q, 
 }
 
 struct Consts32 {
-    float inv_sigma, inv_s2, is3, is5, thr2, w;
+    float inv_s2, thr2;
+    float ka;          // p / (sqrt2 sigma): t = 1 / (1 + ka r)
+    float ke;          // -log2(e) / (2 sigma^2): exp(-rho^2/2) = 2^(ke r^2)
+    float ks;          // sqrt(2/pi) / sigma: sqrt(2/pi) rho = ks r
+    float kd;          // sqrt(2/pi) / sigma^3
+    float kd5;         // sqrt(2/pi) / sigma^5
 };
+
+__device__ __forceinline__ Consts32 consts32(double sigma) {
+    const double is = 1.0 / sigma;
+    Consts32 k;
+    k.inv_s2 = float(is * is);
+    k.thr2 = float(sigma * sigma);
+    k.ka = float(0.3275911 * 0.70710678118654752440 * is);
+    k.ke = float(-0.5 * 1.4426950408889634074 * is * is);
+    k.ks = float(kSqrt2OverPi * is);
+    k.kd = float(kSqrt2OverPi * is * is * is);
+    k.kd5 = float(kSqrt2OverPi * is * is * is * is * is);
+    return k;
+}
 
 // FP32 pair kernel.  For rho < 1 the series (9 terms, truncation < 1e-9
 // relative) is used; beyond, the erf of Abramowitz & Stegun 7.1.26
@@ -86,25 +104,25 @@ struct Consts32 {
 //   1 - g = exp(-rho^2/2) (P(t) + sqrt(2/pi) rho),  t = 1 / (1 + p rho/sqrt2);
 // at rho >= 1 that gives q to 6e-7 and q'/r to 2e-6 relative.  The series
 // branch diverges within a wave whenever one lane is close to the source, so
-// its threshold is kept as small as that accuracy allows.
+// its threshold is kept as small as that accuracy allows.  1/sigma is folded
+// into the constants; the Gaussian is one hardware exp2 of r^2 ke, the
+// reciprocal the hardware one (1 ulp, far below the approximation's error).
 __device__ __forceinline__ void pair32(float r2, const Consts32 &k, float &q, float &dq) {
     if (r2 >= k.thr2) {
         const float rinv = __frsqrt_rn(r2);
         const float r = r2 * rinv;
-        const float rho = r * k.inv_sigma;
-        const float e = __expf(-0.5f * rho * rho);
-        // hardware reciprocal (1 ulp): far below the 1.5e-7 of the approximation
-        const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * 0.70710678f * rho);
+        const float e = __builtin_amdgcn_exp2f(r2 * k.ke);
+        const float t = __builtin_amdgcn_rcpf(fmaf(k.ka, r, 1.0f));
         const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-        const float g = 1.0f - e * (poly + float(kSqrt2OverPi) * rho);
+        const float g = fmaf(-e, fmaf(k.ks, r, poly), 1.0f);
         const float ir2 = rinv * rinv;
-        q = g * ir2 * rinv;
-        dq = (float(kSqrt2OverPi) * k.is3 * e - 3.0f * q) * ir2;
+        q = g * rinv * ir2;
+        dq = fmaf(k.kd, e, -3.0f * q) * ir2;
     } else {
         float h0, h1;
         small_rho<float, 9>(r2 * k.inv_s2, h0, h1);
-        q = float(kSqrt2OverPi) * k.is3 * h0;
-        dq = float(kSqrt2OverPi) * k.is5 * h1;
+        q = k.kd * h0;
+        dq = k.kd5 * h1;
     }
 }
 
@@ -308,13 +326,7 @@ __global__ void __launch_bounds__(64) k_p2p32(P2PArgs a, const Part32 *__restric
     L.cx = demorton(leaf, 0, a.level);
     L.cy = demorton(leaf, 1, a.level);
     L.cz = demorton(leaf, 2, a.level);
-    Consts32 k;
-    const double inv_sigma = 1.0 / a.sigma;
-    k.inv_sigma = float(inv_sigma);
-    k.inv_s2 = float(inv_sigma * inv_sigma);
-    k.is3 = float(inv_sigma * inv_sigma * inv_sigma);
-    k.is5 = float(inv_sigma * inv_sigma * inv_sigma * inv_sigma * inv_sigma);
-    k.thr2 = float(a.sigma * a.sigma);
+    const Consts32 k = consts32(a.sigma);
     const float w = float(a.w);
     for (int base = 0; base < cnt; base += 64) {
         const int rem = cnt - base;
