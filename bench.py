@@ -32,7 +32,7 @@ PEAKS = {  # MI355X published peaks
     "valu_f64_tflops": 78.6,
 }
 # Algorithmic work per unit (derived in the design doc):
-P2P_FLOP_PER_PAIR = {"mixed": 89.0, "fp64": 80.0}   # counted from the pair kernels, FMA = 2
+P2P_FLOP_PER_PAIR = {"mixed": 86.0, "fp64": 69.0}   # counted from the pair kernels, FMA = 2
 
 
 def log(*a):
@@ -109,20 +109,38 @@ def tree_bytes_per_particle(level, f32):
     return 32 + 20 * npass + 4 + 52 + (32 if f32 else 64)
 
 
-def measured_traffic(workload, precision, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE, calibrated on a 1 GiB copy), or None when there is
-    none or the kernel sources have changed since the counters were taken."""
+TREE_KERNELS = ("k_keys", "k_iota", "k_radix_hist", "k_radix_scatter", "k_scan_tiles", "k_scan_sums",
+                "k_scan_add", "k_ranges", "k_permute")
+
+
+def _traffic_summary(workload, precision):
+    """The committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated
+    on a 1 GiB copy), or None when there is none or the kernel sources have changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None
     from paper_1110_2921_amd.rocprof_summary import sources_sha256
     with open(path) as f:
         d = json.load(f)
-    if d.get("sources_sha256") != sources_sha256():
-        return None
-    k = d.get("kernels", {}).get(kernel)
+    return d if d.get("sources_sha256") == sources_sha256() else None
+
+
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` (see _traffic_summary), or None."""
+    d = _traffic_summary(workload, precision)
+    k = None if d is None else d.get("kernels", {}).get(kernel)
     return None if k is None else k["hbm_bytes_per_launch"]
+
+
+def measured_tree_bytes(workload, precision):
+    """HBM bytes of the tree build per evaluation (sum over its kernels), or None."""
+    d = _traffic_summary(workload, precision)
+    if d is None or "k_keys" not in d.get("kernels", {}):
+        return None
+    ks = d["kernels"]
+    evals = ks["k_keys"]["dispatches"]          # one key pass per evaluation
+    return sum(ks[k]["hbm_bytes_per_launch"] * ks[k]["dispatches"] / evals for k in TREE_KERNELS if k in ks)
 
 
 def cpu_baseline(w, budget_s=30.0):
@@ -133,14 +151,30 @@ def cpu_baseline(w, budget_s=30.0):
     x, a = W.random_field(ng, w.k0, seed=w.seed)
     h = 2 * math.pi / ng
     level = 3                     # 64 particles per leaf, as in the full workload
-    t0 = time.perf_counter()
-    oracle_fmm.fmm(x, a, h, w.p, level, periodic=w.periodic)
-    t = time.perf_counter() - t0
+    reps = []
+    for _ in range(3):            # median of three runs (about 5 s each on 16 cores)
+        t0 = time.perf_counter()
+        oracle_fmm.fmm(x, a, h, w.p, level, periodic=w.periodic)
+        reps.append(time.perf_counter() - t0)
+    t = sorted(reps)[1]
     n_sample = ng ** 3
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the oracle's direct sum (C, OpenMP, FP64) on 2048 targets of the sample
+    from oracle import direct as oracle_direct
+    t0 = time.perf_counter()
+    oracle_direct.direct(x[:2048], x, a, h, 2 * math.pi, K=1)
+    td = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": (n_sample / w.n) / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "os_cpu_count": os.cpu_count(),
+            "direct_pairs_per_s": 2048 * n_sample * 27 / td,
             "sample": f"oracle CPU FMM (NumPy + C/OpenMP, FP64) on N={ng}^3 particles of the same recipe "
-                      f"(k0={w.k0:g}, 64/leaf, p={w.p}, {3 ** w.periodic}^3 images) in {t:.1f} s, scaled by "
+                      f"(k0={w.k0:g}, 64/leaf, p={w.p}, {3 ** w.periodic}^3 images), median of 3 runs {t:.1f} s, scaled by "
                       f"{n_sample}/{w.n} (cost linear in N at fixed particles per leaf)",
             "seconds": t}
 
@@ -154,6 +188,7 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one 1 GiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -247,14 +282,13 @@ def main():
     m2l_launch = phases["m2l"][1] / n_eval
     p2p_flop = P2P_FLOP_PER_PAIR[args.precision] * pairs
     f32 = args.precision == "mixed"
-    kp = (C + 3) // 4 * 4
     esz = 4 if f32 else 8
     m2l_kernel = "k_m2l_os<4,8>" if (f32 and w.p in (9, 10)) else ("k_translate<double,1,1,0,24>" if not f32
                                                                  else "k_m2l_os")
     m2l_traffic = measured_traffic(w.name, args.precision, m2l_kernel)
     # algorithmic bytes of the M2L phase: read M, read and write L at every level, the operators once
     cells = sum(8 ** l for l in range(1 if w.periodic else 2, w.level + 1))
-    m2l_alg_bytes = (cells * 3 * kp * esz * 3 + 316 * C * C * esz) / m2l_launch
+    m2l_alg_bytes = (cells * 3 * C * esz * 3 + 316 * C * C * esz) / m2l_launch
     roof_m2l = {"bound": "mfma", "kernel": f"{m2l_kernel} (M2L, all levels)",
                 "achieved": m2l_flop / m2l_launch / (m2l_ms / m2l_launch * 1e-3) / 1e12,
                 "peak": PEAKS["mfma_f32_tflops" if f32 else "mfma_f64_tflops"], "unit": "TFLOP/s",
@@ -271,9 +305,11 @@ def main():
     dominant = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
     tree_ms = phases["tree"][0] / n_eval
     tree_bytes = tree_bytes_per_particle(w.level, f32) * n
+    tree_meas = measured_tree_bytes(w.name, args.precision)
     roof_tree = {"bound": "hbm", "kernel": "tree (keys, radix passes, ranges, permute)",
                  "achieved": tree_bytes / (tree_ms * 1e-3) / 1e9, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-                 "traffic": None}
+                 "traffic": tree_meas, "traffic_unit": "bytes per evaluation",
+                 "measured_gbs": None if tree_meas is None else tree_meas / (tree_ms * 1e-3) / 1e9}
     roof_tree["frac"] = roof_tree["achieved"] / roof_tree["peak"]
 
     result = {
@@ -337,6 +373,23 @@ def main():
                                 "enstrophy": float((e1[1] - e0[1]) / e0[1])}
         log(f"[bench] fp64 {t64 * 1e3:.1f} ms/eval; mixed vs fp64 rel-L2 u {eu:.2e} dalpha {ed:.2e}; "
             f"fp64 drift E {result['drift_fp64']['energy']:.3e}")
+
+    if not args.no_adjoint:
+        # reverse pass: gradient of L = h^3/2 sum |u|^2 with respect to x and alpha (the
+        # forward evaluation is recomputed inside, the tree and expansions are not stored)
+        ub = h3 * u
+        ctx.adjoint(x, a, ub, w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len,
+                    precision=args.precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            ctx.adjoint(x, a, ub, w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len,
+                        precision=args.precision)
+        torch.cuda.synchronize()
+        ta = (time.perf_counter() - t0) / 3
+        result["adjoint"] = {"gradients_per_s": 1.0 / ta, "ms": 1e3 * ta, "precision": args.precision,
+                             "what": "dL/dx and dL/dalpha of L = h^3/2 sum |u|^2 (forward recomputed)"}
+        log(f"[bench] adjoint {1e3 * ta:.1f} ms per gradient")
 
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

@@ -177,7 +177,7 @@ vm_status vm_debug_tree(vm_ctx *ctx, uint32_t *keys, int32_t *perm, int32_t *lea
 /*
  * Debug views of the expansions of the last vm_fmm_eval (stream-ordered copies):
  *   which 0: multipoles, 1: locals, at `level`; raw layout [8^level][3][kp] with
- *   kp = (p+1)^2 rounded up to a multiple of 4, element type double (FP64
+ *   kp = (p+1)^2 rounded up to a multiple of 32, element type double (FP64
  *   form) or float (mixed form); *bytes receives the size.  `out` is a device
  *   buffer of at least that size, or NULL to query the size only.
  * vm_debug_far: far-field velocity and gradient per particle in sorted order,

@@ -194,7 +194,7 @@ class FMM:
                                                   ctypes.byref(nbytes)))
         torch.cuda.synchronize()
         C = (p + 1) ** 2
-        kp = (C + 3) // 4 * 4
+        kp = (C + 31) // 32 * 32
         arr = buf.cpu().numpy().view(np.float32 if mixed else np.float64).reshape(-1, 3, kp)
         return arr[:, :, :C].astype(np.float64)
 

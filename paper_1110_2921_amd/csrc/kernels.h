@@ -116,6 +116,10 @@ hipError_t launch_diagnostics(hipStream_t s, int n, const double *u, const doubl
 // rows of the translation-operator GEMM tile
 inline int pad16(int c) { return (c + 15) / 16 * 16; }
 inline int pad4(int c) { return (c + 3) / 4 * 4; }
+// Per-component stride of the expansion buffers, [cell][3][kp]: C rounded up to
+// a multiple of 32, so that every k block of 16 coefficients is one aligned
+// half of a 128-byte line (FP32) and the MFMA K padding is part of the layout.
+inline int coef_stride(int c) { return (c + 31) / 32 * 32; }
 
 // Operator fragment layout of the translation GEMMs: [op][row block][k block]
 // [64 lanes][4], row blocks padded to whole groups of 8 (one per wave), k

@@ -413,7 +413,7 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
         if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
 
     // workspace
-    const int C = ncoef(p), kp = pad4(C);
+    const int C = ncoef(p), kp = coef_stride(C);
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
     const int64_t ncells = ((int64_t(1) << (3 * (level + 1))) - 1) / 7;
     const int nblk = (ni + kRadixTile - 1) / kRadixTile;
@@ -430,7 +430,7 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     VM_HIP(ctx->far.reserve(sizeof(double) * 12 * n), "alloc far field");
     VM_HIP(ctx->flag.reserve(sizeof(int)), "alloc flag");
     VM_HIP(ctx->trpart.reserve(kTrPartBytes), "alloc split partials");
-    if (ctx->zeros.bytes == 0) VM_HIP(ctx->zeros.reserve(tr_zero_elems(pad4(ncoef(VM_MAX_P))) * sizeof(double), true),
+    if (ctx->zeros.bytes == 0) VM_HIP(ctx->zeros.reserve(tr_zero_elems(coef_stride(ncoef(VM_MAX_P))) * sizeof(double), true),
                                       "alloc zero cell");
     // slack after the last cell: the FP32 M2L reads up to a k block past a component
     const size_t cbytes = (size_t(ncells) * 3 * kp + tr_slack_elems(kp)) * esz;
@@ -600,7 +600,7 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
     const int K = opts->periodic, periodic = K > 0;
     const int ni = int(n);
     const int64_t nleaf = int64_t(1) << (3 * level);
-    const int C = ncoef(p), kp = pad4(C);
+    const int C = ncoef(p), kp = coef_stride(C);
     OpSet *ops = ctx->ops[p].get();
     if (vm_status e = ensure_adj_ops(ctx, ops); e != VM_OK) return e;
     const double *tlat_t = nullptr;
@@ -789,7 +789,7 @@ vm_status vm_debug_expansions(vm_ctx *ctx, int which, int level, void *out, int6
     if (!ctx || !bytes || (which != 0 && which != 1)) return VM_EINVAL;
     if (ctx->last_level < 0 || level < 0 || level > ctx->last_level)
         return fail(ctx, VM_EINVAL, "level not in the last evaluation");
-    const int kp = pad4(ncoef(ctx->last_p));
+    const int kp = coef_stride(ncoef(ctx->last_p));
     const size_t esz = ctx->last_mixed ? 4 : 8;
     const size_t row = size_t(3) * kp * esz;
     const size_t before = size_t(((int64_t(1) << (3 * level)) - 1) / 7);

@@ -2,7 +2,7 @@
 
     python -m paper_1110_2921_amd.rocprof_summary trace  TRACE_DIR  [--command CMD]
     python -m paper_1110_2921_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR --workload NAME [--command CMD]
-    python -m paper_1110_2921_amd.rocprof_summary counters PMC_DIR [--command CMD]
+    python -m paper_1110_2921_amd.rocprof_summary counters PMC_DIR [--command CMD] [--top N]
 
 ``trace`` reads ``*_kernel_stats.csv`` and ``*_kernel_trace.csv`` of a
 ``rocprofv3 --kernel-trace --stats --output-format csv`` run and prints the
@@ -110,7 +110,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, workload: str, command: str 
     kernels = {}
     for name in sorted(set(fetch) | set(write)):
         if not name.startswith(("k_m2l_os", "k_translate", "k_p2p", "k_split_reduce", "k_permute",
-                                "k_radix", "k_keys", "k_p2m", "k_l2p")):
+                                "k_radix", "k_keys", "k_iota", "k_scan", "k_ranges", "k_p2m", "k_l2p")):
             continue
         fv, wv = fetch.get(name, []), write.get(name, [])
         if not fv or not wv:
@@ -124,9 +124,9 @@ def traffic_summary(fetch_dir: str, write_dir: str, workload: str, command: str 
             "sources_sha256": sources_sha256(), "kernels": kernels}
 
 
-def counters_summary(d: str, command: str | None) -> str:
-    """Average of every collected counter per dispatch, for the library's kernels
-    and per launch shape (grid x, grid y)."""
+def counters_summary(d: str, command: str | None, top: int = 8) -> str:
+    """Average of every collected counter per dispatch, for the `top` library kernel
+    launch shapes with the largest counts."""
     rows = list(csv.DictReader(open(_one(d, "*counter_collection.csv"))))
     per = collections.defaultdict(lambda: collections.defaultdict(list))
     for r in rows:
@@ -135,7 +135,7 @@ def counters_summary(d: str, command: str | None) -> str:
             continue
         per[(n, int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
     out = [f"command: {command}"] if command else []
-    for (n, g), cs in sorted(per.items(), key=lambda kv: -max(sum(v) for v in kv[1].values())):
+    for (n, g), cs in sorted(per.items(), key=lambda kv: -max(sum(v) for v in kv[1].values()))[:top]:
         first = next(iter(cs.values()))
         out.append(f"{n} grid {g} ({len(first)} dispatches)")
         for c, v in sorted(cs.items()):
@@ -157,11 +157,12 @@ def main(argv=None):
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--command")
+    c.add_argument("--top", type=int, default=8)
     a = ap.parse_args(argv)
     if a.mode == "trace":
         print(trace_summary(a.dir, a.command))
     elif a.mode == "counters":
-        print(counters_summary(a.dir, a.command))
+        print(counters_summary(a.dir, a.command, a.top))
     else:
         print(json.dumps(traffic_summary(a.fetch_dir, a.write_dir, a.workload, a.command), indent=1))
 

@@ -6,7 +6,10 @@ Tolerances (relative L2 over all particles unless stated):
   round-off apart: same tree, lists, truncation and lattice construction);
 * no far field (one leaf, free space): FP64 vs the direct sum 1e-13;
 * mixed (FP32 near field + FP32 MFMA expansions) vs FP64: 1e-5 for u,
-  1e-4 for dalpha/dt and J.
+  1e-4 for dalpha/dt and J;
+* compensated near-field sums: same-sign velocity terms summed over 16368
+  sources, mixed vs the FP64 direct sum within 1e-6, where plain FP32
+  accumulation in the same order (emulated on the CPU) is off by more than 2e-6.
 """
 import math
 
@@ -137,6 +140,42 @@ def test_uneven_leaf_populations(ctx, periodic):
     assert rel(um, u) < 1e-5
     assert rel(Jm, J) < 1e-4
     assert rel(dam, da) < 1e-4
+
+
+def test_compensated_near_field_sums(ctx):
+    """One leaf (level 0, free space): 16 targets with no strength at x ~ 1 and
+    16368 sources with equal strengths along z at x in [2, 5].  Every term of
+    u_y at a target has the same sign, so plain FP32 accumulation drifts like
+    sqrt(n) ulp of the running sum (emulated on the CPU in the kernel's order:
+    more than 2e-6 off at one of the targets); the compensated sums stay within
+    1e-6 of the FP64 direct sum."""
+    from scipy.special import erf
+    rng = np.random.default_rng(71)
+    n = 16384
+    ns = n - 16
+    xs = np.stack([rng.uniform(2.0, 5.0, ns), rng.uniform(2.0, 4.0, ns), rng.uniform(2.0, 4.0, ns)], 1)
+    xt = np.stack([rng.uniform(1.0, 1.1, 16), rng.uniform(2.9, 3.1, 16), rng.uniform(2.9, 3.1, 16)], 1)
+    x = np.concatenate([xt, xs])
+    a = np.zeros((n, 3))
+    a[16:, 2] = 1e-3
+    sigma = 0.05
+    t = np.arange(16)
+    um, _, _ = _run(ctx, x, a, sigma, 4, 0, 0, precision="mixed")
+    ud, _ = D.direct(x[t], x, a, sigma)
+    err = np.abs(um[t, 1] - ud[:, 1]) / np.abs(ud[:, 1])
+    assert err.max() < 1e-6, err.max()
+    naive = []
+    for i in t:
+        r = (x[i] - x).astype(np.float32)
+        r2 = np.sum(r.astype(np.float64) ** 2, axis=1)
+        rr = np.sqrt(r2)
+        rho = rr / sigma
+        g = erf(rho / math.sqrt(2)) - math.sqrt(2 / math.pi) * rho * np.exp(-0.5 * rho * rho)
+        q = np.where(rr > 0, g / np.maximum(r2 * rr, 1e-300), 0.0)
+        terms = (q * a[:, 2] * r[:, 0] / (4 * math.pi)).astype(np.float32)   # (alpha x r)_y = alpha_z r_x
+        naive.append(np.add.accumulate(terms, dtype=np.float32)[-1])
+    nerr = np.abs(np.array(naive, np.float64) - ud[:, 1]) / np.abs(ud[:, 1])
+    assert nerr.max() > 2e-6, nerr.max()
 
 
 def test_transpose_scheme_conserves_vorticity(ctx):
