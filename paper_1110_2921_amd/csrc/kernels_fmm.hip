@@ -14,68 +14,143 @@ using dev::for_each_harmonic;
 using dev::PartOf;
 using dev::Tab;
 
+template <typename T>
+struct Quad {                               // four consecutive T from 16-byte aligned memory
+    T v[4];
+    __device__ __forceinline__ void load(const T *p) {
+        if constexpr (sizeof(T) == 4) {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 q = *reinterpret_cast<const f4 *>(p);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            const d2 q0 = *reinterpret_cast<const d2 *>(p);
+            const d2 q1 = *reinterpret_cast<const d2 *>(p + 2);
+            v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+        }
+    }
+};
+
 // ---------------------------------------------------------------- P2M ----
 // Mb[leaf][c][s] = sum_j alpha_j[c] c_s((x_j - centre) / w).
+// The orders m = 0..p are split into G >= 4 contiguous ranges of about equal
+// coefficient count, at most 64 each; one wave takes one (leaf, m range): lane j
+// evaluates the harmonics of particle j for its m range into LDS (row j),
+// then lane t sums coefficient t of the range over the particles for the
+// three strength components.  A wave needs only 64 rows of a quarter of the
+// coefficients, so four to five waves fit per SIMD.  The G waves of a leaf
+// are consecutive on one XCD (which serves a contiguous range of leaves).
+constexpr int kP2mMaxGroups = 16;
+
+struct MGroups {
+    int ng;                       // number of ranges G
+    int lo[kP2mMaxGroups + 1];    // range g takes orders lo[g] .. lo[g+1]-1
+    int maxn;                     // largest coefficient count of a range (<= 64)
+};
+
+__device__ __forceinline__ int group_count(int p, int mlo, int mhi) {
+    int c = 0;
+    for (int m = mlo; m < mhi; ++m) c += (p + 1 - m) * (m > 0 ? 2 : 1);
+    return c;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__restrict__ parts,
-                                            const int32_t *__restrict__ start, int p, int kp, T inv_w,
-                                            DevTables tab, int chunk, T *__restrict__ mout) {
-    extern __shared__ unsigned char smem_raw[];
-    T *cv = reinterpret_cast<T *>(smem_raw);          // [chunk][C]
-    T *al = cv + size_t(chunk) * (p + 1) * (p + 1);    // [chunk][3]
-    const int C = (p + 1) * (p + 1);
-    const int leaf = blockIdx.x, lane = threadIdx.x;
+                                            const int32_t *__restrict__ start, int nleaf, int p, int kp,
+                                            T inv_w, DevTables tab, MGroups grp, T *__restrict__ mout) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = threadIdx.x;
+    // XCD-aware: blockIdx mod 8 selects the XCD's leaf range; the 4 groups of a leaf follow
+    const int b = blockIdx.x, G = grp.ng;
+    int leaf, g;
+    if (nleaf % 8 == 0) {
+        const int k = b >> 3;
+        g = k % G;
+        leaf = (b & 7) * (nleaf >> 3) + k / G;
+    } else {
+        g = b % G;
+        leaf = b / G;
+    }
+    const int mlo = grp.lo[g], mhi = grp.lo[g + 1];
+    const int ng = group_count(p, mlo, mhi);
+    const int stride = grp.maxn + 1;                     // odd row stride: conflict-free column reads
+    T *rows = reinterpret_cast<T *>(smem_raw);           // [64][stride]
+    T *al = rows + 64 * stride;                          // [64][3]
     const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
-    constexpr int MAXS = 7;   // ceil(441 / 64)
-    T acc[3][MAXS];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int t = 0; t < MAXS; ++t) acc[c][t] = T(0);
     const T *c1 = Tab<T>::c1(tab), *c2 = Tab<T>::c2(tab), *dg = Tab<T>::dg(tab);
-    for (int base = 0; base < cnt; base += chunk) {
-        const int nj = min(chunk, cnt - base);
+    T acc[3] = {T(0), T(0), T(0)};
+    for (int base = 0; base < cnt; base += 64) {
+        const int nj = min(64, cnt - base);
         if (lane < nj) {
             const auto q = parts[s0 + base + lane];
-            T *row = cv + size_t(lane) * C;
-            for_each_harmonic<T>(T(q.dx) * inv_w, T(q.dy) * inv_w, T(q.dz) * inv_w, p, c1, c2, dg,
-                                 [&](int n, int m, T re, T nim) {
-                                     if (m == 0) {
-                                         row[n * n] = re;
-                                     } else {
-                                         row[n * n + 2 * m - 1] = re;
-                                         row[n * n + 2 * m] = nim;
-                                     }
-                                 });
+            T *row = rows + lane * stride;
+            const T X = T(q.dx) * inv_w, Y = T(q.dy) * inv_w, Z = T(q.dz) * inv_w;
+            const T r2 = X * X + Y * Y + Z * Z;
+            // diagonal Rb_m^m = -(X + iY) diag[m] Rb_{m-1}^{m-1} up to the range start
+            T dre = T(1), dim = T(0);
+            for (int m = 1; m <= mlo; ++m) {
+                const T sc = -dg[m];
+                const T nre = sc * (X * dre - Y * dim);
+                const T nim = sc * (X * dim + Y * dre);
+                dre = nre;
+                dim = nim;
+            }
+            int o = 0;
+            for (int m = mlo; m < mhi; ++m) {
+                if (m > mlo) {
+                    const T sc = -dg[m];
+                    const T nre = sc * (X * dre - Y * dim);
+                    const T nim = sc * (X * dim + Y * dre);
+                    dre = nre;
+                    dim = nim;
+                }
+                T are = dre, aim = dim, bre = T(0), bim = T(0);
+                row[o++] = are;
+                if (m > 0) row[o++] = -aim;
+                for (int n = m + 1; n <= p; ++n) {
+                    const int e = n * (n + 1) / 2 + m;
+                    const T k1 = c1[e] * Z, k2 = c2[e] * r2;
+                    const T cre = k1 * are - k2 * bre;
+                    const T cim = k1 * aim - k2 * bim;
+                    bre = are;
+                    bim = aim;
+                    are = cre;
+                    aim = cim;
+                    row[o++] = are;
+                    if (m > 0) row[o++] = -aim;
+                }
+            }
             al[lane * 3 + 0] = q.ax;
             al[lane * 3 + 1] = q.ay;
             al[lane * 3 + 2] = q.az;
         }
         __syncthreads();
-        for (int j = 0; j < nj; ++j) {
-            const T a0 = al[j * 3 + 0], a1 = al[j * 3 + 1], a2 = al[j * 3 + 2];
-            const T *row = cv + size_t(j) * C;
-#pragma unroll
-            for (int t = 0; t < MAXS; ++t) {
-                const int s = lane + 64 * t;
-                if (s < C) {
-                    const T v = row[s];
-                    acc[0][t] += a0 * v;
-                    acc[1][t] += a1 * v;
-                    acc[2][t] += a2 * v;
-                }
+        if (lane < ng)
+            for (int j = 0; j < nj; ++j) {
+                const T v = rows[j * stride + lane];
+                acc[0] += al[j * 3 + 0] * v;
+                acc[1] += al[j * 3 + 1] * v;
+                acc[2] += al[j * 3 + 2] * v;
             }
-        }
         __syncthreads();
     }
-    T *dst = mout + size_t(leaf) * 3 * kp;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int t = 0; t < MAXS; ++t) {
-            const int s = lane + 64 * t;
-            if (s < kp) dst[c * kp + s] = s < C ? acc[c][t] : T(0);
+    if (lane >= ng) return;
+    // local index -> packed index: order m, then n, (re, -im) pairs for m > 0
+    int m = mlo, n = mlo, part = 0;
+    for (int o = 0; o < lane; ++o) {
+        if (m > 0 && part == 0) {
+            part = 1;
+            continue;
         }
+        part = 0;
+        if (++n > p) {
+            ++m;
+            n = m;
+        }
+    }
+    const int sidx = m == 0 ? n * n : n * n + 2 * m - 1 + part;
+    T *dst = mout + size_t(leaf) * 3 * kp;
+    for (int c = 0; c < 3; ++c) dst[c * kp + sidx] = acc[c];
 }
 
 // ---------------------------------------------------------------- L2P ----
@@ -87,11 +162,11 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
                                             const int32_t *__restrict__ start, int n, int p, int kp,
                                             T inv_w, double su, double sj, DevTables tab,
                                             const T *__restrict__ lleaf, double *__restrict__ far) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int C = (p + 1) * (p + 1);
     const int nu = tab.nu, ng = tab.ng, width = tab.l2p_width;
-    T *lam = reinterpret_cast<T *>(smem_raw);   // [3 C]
-    T *coef = lam + 3 * C;                      // [nu][12]: U_x U_y U_z G_00 .. G_22
+    T *coef = reinterpret_cast<T *>(smem_raw);  // [nu][12]: U_x U_y U_z G_00 .. G_22 (16-byte rows)
+    T *lam = coef + 12 * nu;                    // [3 C]
     const int leaf = blockIdx.x, lane = threadIdx.x;
     const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
     if (cnt == 0) return;
@@ -128,17 +203,20 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
         for_each_harmonic<T>(T(q.dx) * inv_w, T(q.dy) * inv_w, T(q.dz) * inv_w, p - 1, c1, c2, dg,
                              [&](int nn, int m, T re, T nim) {
                                  const int sr = m == 0 ? nn * nn : nn * nn + 2 * m - 1;
-                                 const T *cr = coef + sr * 12;
+                                 Quad<T> cq[3];
 #pragma unroll
-                                 for (int b = 0; b < 3; ++b) u[b] += cr[b] * re;
+                                 for (int q4 = 0; q4 < 3; ++q4) cq[q4].load(coef + sr * 12 + 4 * q4);
 #pragma unroll
-                                 for (int k = 0; k < 9; ++k) J[k] += cr[3 + k] * re;
+                                 for (int b = 0; b < 3; ++b) u[b] += cq[b / 4].v[b % 4] * re;
+#pragma unroll
+                                 for (int k = 0; k < 9; ++k) J[k] += cq[(3 + k) / 4].v[(3 + k) % 4] * re;
                                  if (m > 0) {
-                                     const T *ci = cr + 12;
 #pragma unroll
-                                     for (int b = 0; b < 3; ++b) u[b] += ci[b] * nim;
+                                     for (int q4 = 0; q4 < 3; ++q4) cq[q4].load(coef + (sr + 1) * 12 + 4 * q4);
 #pragma unroll
-                                     for (int k = 0; k < 9; ++k) J[k] += ci[3 + k] * nim;
+                                     for (int b = 0; b < 3; ++b) u[b] += cq[b / 4].v[b % 4] * nim;
+#pragma unroll
+                                     for (int k = 0; k < 9; ++k) J[k] += cq[(3 + k) / 4].v[(3 + k) % 4] * nim;
                                  }
                              });
         const size_t gi = size_t(s0) + i;
@@ -213,23 +291,6 @@ static_assert(kTrWaves == kTrWaveCount, "operator padding assumes one row-block 
 
 template <typename T>
 __host__ __device__ constexpr int tr_row_stride(int nks) { return 4 * nks + (sizeof(T) == 4 ? 4 : 2); }
-
-template <typename T>
-struct Quad {                               // four consecutive T from 16-byte aligned memory
-    T v[4];
-    __device__ __forceinline__ void load(const T *p) {
-        if constexpr (sizeof(T) == 4) {
-            typedef float f4 __attribute__((ext_vector_type(4)));
-            const f4 q = *reinterpret_cast<const f4 *>(p);
-            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-        } else {
-            typedef double d2 __attribute__((ext_vector_type(2)));
-            const d2 q0 = *reinterpret_cast<const d2 *>(p);
-            const d2 q1 = *reinterpret_cast<const d2 *>(p + 2);
-            v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
-        }
-    }
-};
 
 template <typename T, int NRBW, int NT, int mode, int PF>
 __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodic, int C, int kp,
@@ -634,13 +695,35 @@ __global__ void __launch_bounds__(256) k_lattice(int C, int kp, const double *__
 template <typename T>
 hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t *start, int p, int kp,
                       double inv_w, const DevTables &tab, T *m_out) {
+    // contiguous m ranges of about C / G coefficients each, G >= 4 and at most 64 per range
+    MGroups grp;
     const int C = (p + 1) * (p + 1);
-    int chunk = int(49152 / (sizeof(T) * (C + 3)));
-    if (chunk > 64) chunk = 64;
-    if (chunk < 1) chunk = 1;
-    const size_t smem = sizeof(T) * size_t(chunk) * (C + 3);
-    hipLaunchKernelGGL(k_p2m<T>, dim3(nleaf), dim3(64), smem, s,
-                       (const typename PartOf<T>::type *)parts, start, p, kp, T(inv_w), tab, chunk, m_out);
+    auto count = [&](int mm) { return (p + 1 - mm) * (mm > 0 ? 2 : 1); };
+    bool ok = false;
+    for (int G = 4; G <= kP2mMaxGroups && !ok; ++G) {
+        grp.ng = G;
+        int m = 0, done = 0;
+        for (int g = 0; g < G; ++g) {
+            grp.lo[g] = m;
+            const int target = (C * (g + 1) + G - 1) / G;
+            while (m <= p && (g == G - 1 || done + count(m) / 2 < target)) {
+                done += count(m);
+                ++m;
+            }
+        }
+        grp.lo[G] = p + 1;
+        grp.maxn = 0;
+        for (int g = 0; g < G; ++g) {
+            int c = 0;
+            for (int mm = grp.lo[g]; mm < grp.lo[g + 1]; ++mm) c += count(mm);
+            grp.maxn = c > grp.maxn ? c : grp.maxn;
+        }
+        ok = grp.maxn <= 64;
+    }
+    if (!ok) return hipErrorInvalidValue;
+    const size_t smem = sizeof(T) * (size_t(64) * (grp.maxn + 1) + 64 * 3);
+    hipLaunchKernelGGL(k_p2m<T>, dim3(unsigned(nleaf) * grp.ng), dim3(64), smem, s,
+                       (const typename PartOf<T>::type *)parts, start, nleaf, p, kp, T(inv_w), tab, grp, m_out);
     return hipGetLastError();
 }
 
