@@ -12,6 +12,8 @@ Tolerances:
     dL/dalpha_k = h^3 v_k,  dL/dx_k = h^3 (J_k u_k + J^v_k alpha_k)
   with v, J^v the field and gradient of strengths u: 1e-4 (FMM truncation at p = 10);
 * FP32 adjoint vs FP64 adjoint: 1e-4;
+* the 64^3 backward case at its full size: central differences (eps = 1e-6) on 32
+  particles and 8 strengths, floor 2e-7 max|grad| (the noise grows like sqrt(N));
 * Heun step against the same step built from the oracle FMM: 1e-10.
 """
 import math
@@ -190,3 +192,52 @@ def test_diagnostics(ctx):
     assert np.allclose(d, ref, rtol=1e-13, atol=0)
     d2 = ctx.diagnostics(u, J, _dev(a), h ** 3).cpu().numpy()
     assert np.array_equal(d, d2)
+
+
+@pytest.mark.parametrize("precision", ["fp64"])
+def test_backward_case_at_full_size(ctx, precision):
+    """The 64^3 backward case (p = 8, level 4, 27^3 images): central differences
+    with eps = 1e-6 on 32 random particles (positions, random directions) and on
+    8 strengths.  Moving one particle re-rounds all N far fields, so the noise
+    floor grows like sqrt(N) against the 16^3 case: 2e-7 max|grad| at eps = 1e-6.
+    The FP32 adjoint matches the FP64 one to 1e-4."""
+    import torch
+    w = W.WORKLOADS["rand64_periodic"]
+    x, a = W.make(w)
+    h = w.h
+    eps, floor = 1e-6, 2e-7
+    kw = dict(periodic=w.periodic, box_len=w.box_len)
+
+    def loss_u(xx, aa):
+        u, _, _ = ctx.eval(_dev(xx), _dev(aa), w.sigma, w.p, w.level, precision="fp64", want_dalpha=False, **kw)
+        torch.cuda.synchronize()
+        return _host(u)
+
+    u = loss_u(x, a)
+    ub = _dev(h ** 3 * u)
+    xb, ab = ctx.adjoint(_dev(x), _dev(a), ub, w.sigma, w.p, w.level, precision="fp64", **kw)
+    xb, ab = _host(xb), _host(ab)
+    rng = np.random.default_rng(5)
+
+    def fd(xp, xm, ap, am):
+        up, um = loss_u(xp, ap), loss_u(xm, am)
+        return 0.5 * h ** 3 * np.sum((up - um) * (up + um)) / (2 * eps)
+
+    for k in rng.choice(w.n, 32, replace=False):
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        xp, xm = x.copy(), x.copy()
+        xp[k] += eps * e
+        xm[k] -= eps * e
+        an = float(xb[k] @ e)
+        assert abs(fd(xp, xm, a, a) - an) < 1e-6 * abs(an) + floor * np.abs(xb).max(), k
+    for k in rng.choice(w.n, 8, replace=False):
+        e = rng.standard_normal(3)
+        ap, am = a.copy(), a.copy()
+        ap[k] += eps * e
+        am[k] -= eps * e
+        an = float(ab[k] @ e)
+        assert abs(fd(x, x, ap, am) - an) < 1e-6 * abs(an) + floor * np.abs(ab).max(), k
+    xm32, am32 = ctx.adjoint(_dev(x), _dev(a), ub, w.sigma, w.p, w.level, precision="mixed", **kw)
+    assert rel(_host(am32), ab) < 1e-4
+    assert rel(_host(xm32), xb) < 1e-4
