@@ -139,37 +139,65 @@ __device__ __forceinline__ int morton(int cx, int cy, int cz, int level) {
     return k;
 }
 
-// Writes u, dalpha/dt and J for sorted particle gi (caller index oi).
-__device__ __forceinline__ void epilogue(const P2PArgs &a, int gi, const double un[3], const double Jr[9],
-                                         const double S[3]) {
-    const int n = a.n;
-    const int oi = a.perm[gi];
-    double u[3], J[9];
-    // near gradient = rank-one part + antisymmetric part eps_abc S_c
-    J[0] = Jr[0];          J[1] = Jr[1] + S[2];   J[2] = Jr[2] - S[1];
-    J[3] = Jr[3] - S[2];   J[4] = Jr[4];          J[5] = Jr[5] + S[0];
-    J[6] = Jr[6] + S[1];   J[7] = Jr[7] - S[0];   J[8] = Jr[8];
-    for (int b = 0; b < 3; ++b) u[b] = un[b] * kInv4Pi;
-    for (int k = 0; k < 9; ++k) J[k] *= kInv4Pi;
-    if (a.have_far) {
-        for (int b = 0; b < 3; ++b) u[b] += a.far[size_t(b) * n + gi];
-        for (int k = 0; k < 9; ++k) J[k] += a.far[size_t(3 + k) * n + gi];
-    }
-    for (int b = 0; b < 3; ++b) a.u[size_t(b) * n + oi] = u[b];
-    if (a.grad)
-        for (int k = 0; k < 9; ++k) a.grad[size_t(k) * n + oi] = J[k];
-    if (a.dalpha) {
-        const double al[3] = {a.alpha[oi], a.alpha[size_t(n) + oi], a.alpha[2 * size_t(n) + oi]};
-        for (int b = 0; b < 3; ++b) {
-            double s = 0.0;
-            if (a.scheme == 0)
-                for (int c = 0; c < 3; ++c) s += al[c] * J[3 * c + b];
-            else
-                for (int c = 0; c < 3; ++c) s += J[3 * b + c] * al[c];
-            a.dalpha[size_t(b) * n + oi] = s;
+// Writes u, dalpha/dt and J for sorted particle gi (caller index oi) from the
+// near sums (velocity us - uc, rank-one gradient part Jr, S = sum q alpha) plus
+// the far field.  Every near value passes through `red` on its way (the
+// identity, or the sum over the lane groups of a split target block: then all
+// lanes run this, and only those with `write` set store).  Streamed value by
+// value, J row by row with the stretching contraction accumulated on the way,
+// so that few values are live at once: the kernels' register budget, hence
+// their occupancy, is set here.
+template <typename A, typename R>
+__device__ __forceinline__ void epilogue(const P2PArgs &a, int gi, bool write, const A us[3], const A uc[3],
+                                         const A Jr[9], const A S[3], R red) {
+    const size_t n = size_t(a.n);
+    const int oi = write ? a.perm[gi] : 0;
+    for (int b = 0; b < 3; ++b) {
+        double u = red(double(us[b]) - double(uc[b])) * kInv4Pi;
+        if (write) {
+            if (a.have_far) u += a.far[b * n + gi];
+            a.u[b * n + oi] = u;
         }
     }
+    if (!a.grad && !a.dalpha) return;
+    double Sd[3];
+    for (int c = 0; c < 3; ++c) Sd[c] = red(double(S[c]));
+    double al[3] = {0.0, 0.0, 0.0};
+    if (write && a.dalpha)
+        for (int c = 0; c < 3; ++c) al[c] = a.alpha[c * n + oi];
+    double da[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            // antisymmetric part eps_abc S_c of the near gradient J[r][c]
+            const int k = 3 - r - c;
+            const double anti = r == c ? 0.0 : ((c == (r + 1) % 3) ? Sd[k] : -Sd[k]);
+            double J = (red(double(Jr[3 * r + c])) + anti) * kInv4Pi;
+            if (write) {
+                if (a.have_far) J += a.far[(3 + 3 * r + c) * n + gi];
+                if (a.grad) a.grad[(3 * r + c) * n + oi] = J;
+            }
+            if (a.scheme == 0) da[c] += al[r] * J;      // classic: sum_a alpha_a J[a][b]
+            else da[r] += J * al[c];                     // transpose: sum_c J[b][c] alpha_c
+        }
+    }
+    if (write && a.dalpha)
+        for (int b = 0; b < 3; ++b) a.dalpha[b * n + oi] = da[b];
 }
+
+struct NoReduce {
+    __device__ double operator()(double v) const { return v; }
+};
+
+// sum over the lane groups of a split block (lanes l, l ^ E, l ^ 2E, ...), fixed order
+struct GroupSum {
+    int E;
+    __device__ double operator()(double v) const {
+        for (int off = E; off < 64; off <<= 1) v += __shfl_xor(v, off);
+        return v;
+    }
+};
 
 // Target blocks of a leaf: whole blocks of 64 targets, one target per lane, take
 // every source at a wave-uniform address (scalar loads).  A last block of
@@ -181,11 +209,6 @@ __device__ __forceinline__ int pow2_ceil(int v) {
     int e = 1;
     while (e < v) e <<= 1;
     return e;
-}
-
-__device__ __forceinline__ void group_reduce(double *v, int nv, int E) {
-    for (int off = E; off < 64; off <<= 1)
-        for (int k = 0; k < nv; ++k) v[k] += __shfl_xor(v[k], off);
 }
 
 struct LeafGeom {
@@ -257,37 +280,39 @@ __global__ void __launch_bounds__(64) k_p2p64(P2PArgs a, const Part64 *__restric
     k.is3 = k.inv_s2 * k.inv_sigma;
     k.is5 = k.is3 * k.inv_s2;
     k.thr2 = 0.0625 * a.sigma * a.sigma;
-    for (int base = 0; base < cnt; base += 64) {
+    const double zero[3] = {0.0, 0.0, 0.0};
+    // whole-wave blocks: one target per lane, wave-uniform sources
+    const int nfull = cnt - cnt % 64 + (cnt % 64 > 32 ? 64 : 0);
+    for (int base = 0; base < nfull; base += 64) {
         const int rem = cnt - base;
-        const bool grouped = rem <= 32;
-        const int E = grouped ? pow2_ceil(rem) : 64;
-        const int t = grouped ? (lane & (E - 1)) : lane;
-        const int gi = grouped ? lane / E : 0, ng = 64 / E;
-        const bool valid = t < rem;
-        const Part64 me = parts[s0 + base + (valid ? t : 0)];
+        const bool valid = lane < rem;
+        const Part64 me = parts[s0 + base + (valid ? lane : 0)];
         double u[3] = {0, 0, 0}, Jr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
         for (int nb = 0; nb < 27; ++nb) {
             int js, je, dx, dy, dz;
             if (!neighbour(a, L, nb, js, je, dx, dy, dz)) continue;
             // x_i - x_j = (delta_i - d w) - delta_j, d = source - target cell offset
             const double tx = me.dx - dx * a.w, ty = me.dy - dy * a.w, tz = me.dz - dz * a.w;
-            if (grouped) {
-                for (int j = js + gi; j < je; j += ng) acc64(parts[j], tx, ty, tz, k, u, Jr, S);
-            } else {
-                for (int j = js; j < je; ++j) acc64(parts[j], tx, ty, tz, k, u, Jr, S);
-            }
+            for (int j = js; j < je; ++j) acc64(parts[j], tx, ty, tz, k, u, Jr, S);
         }
-        if (grouped) {
-            double v[15];
-            for (int c = 0; c < 3; ++c) { v[c] = u[c]; v[3 + c] = S[c]; }
-            for (int c = 0; c < 9; ++c) v[6 + c] = Jr[c];
-            group_reduce(v, 15, E);
-            for (int c = 0; c < 3; ++c) { u[c] = v[c]; S[c] = v[3 + c]; }
-            for (int c = 0; c < 9; ++c) Jr[c] = v[6 + c];
-        }
-        if (valid && gi == 0) epilogue(a, s0 + base + t, u, Jr, S);
-        if (grouped) break;
+        if (valid) epilogue(a, s0 + base + lane, true, u, zero, Jr, S, NoReduce{});
     }
+    // a last block of rem <= 32 targets: lane groups share out the sources
+    const int rem = cnt - nfull;
+    if (rem <= 0) return;
+    const int E = pow2_ceil(rem);
+    const int t = lane & (E - 1), gi = lane / E, ng = 64 / E;
+    const bool valid = t < rem;
+    const Part64 me = parts[s0 + nfull + (valid ? t : 0)];
+    double u[3] = {0, 0, 0}, Jr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
+    for (int nb = 0; nb < 27; ++nb) {
+        int js, je, dx, dy, dz;
+        if (!neighbour(a, L, nb, js, je, dx, dy, dz)) continue;
+        const double tx = me.dx - dx * a.w, ty = me.dy - dy * a.w, tz = me.dz - dz * a.w;
+#pragma unroll 1
+        for (int j = js + gi; j < je; j += ng) acc64(parts[j], tx, ty, tz, k, u, Jr, S);
+    }
+    epilogue(a, s0 + nfull + t, valid && gi == 0, u, zero, Jr, S, GroupSum{E});
 }
 
 struct Acc32 {
@@ -328,52 +353,49 @@ __global__ void __launch_bounds__(64) k_p2p32(P2PArgs a, const Part32 *__restric
     L.cz = demorton(leaf, 2, a.level);
     const Consts32 k = consts32(a.sigma);
     const float w = float(a.w);
-    for (int base = 0; base < cnt; base += 64) {
+    // whole-wave blocks: one target per lane, wave-uniform sources
+    const int nfull = cnt - cnt % 64 + (cnt % 64 > 32 ? 64 : 0);
+    for (int base = 0; base < nfull; base += 64) {
         const int rem = cnt - base;
-        const bool grouped = rem <= 32;
-        const int E = grouped ? pow2_ceil(rem) : 64;
-        const int t = grouped ? (lane & (E - 1)) : lane;
-        const int gi = grouped ? lane / E : 0, ng = 64 / E;
-        const bool valid = t < rem;
-        const Part32 me = parts[s0 + base + (valid ? t : 0)];
+        const bool valid = lane < rem;
+        const Part32 me = parts[s0 + base + (valid ? lane : 0)];
         Acc32 A;
         for (int c = 0; c < 3; ++c) A.us[c] = A.uc[c] = A.S[c] = 0.0f;
         for (int c = 0; c < 9; ++c) A.Jr[c] = 0.0f;
         for (int nb = 0; nb < 27; ++nb) {
             int js, je, dx, dy, dz;
-            if (!neighbour(a, L, nb, js, je, dx, dy, dz)) continue;
+            if (!neighbour(a, L, nb, js, je, dx, dy, dz) || js >= je) continue;
             const float tx = me.dx - float(dx) * w, ty = me.dy - float(dy) * w, tz = me.dz - float(dz) * w;
-            if (grouped) {
-                for (int j = js + gi; j < je; j += ng) acc32(parts[j], tx, ty, tz, k, A);
-            } else if (js < je) {
-                // wave-uniform records: the next one is fetched (scalar load) while
-                // the current one is evaluated
-                Part32 cur = parts[js];
+            // the next record is fetched (scalar load) while the current one is evaluated
+            Part32 cur = parts[js];
 #pragma unroll 2
-                for (int j = js; j < je; ++j) {
-                    const Part32 nxt = parts[j + 1 < je ? j + 1 : j];
-                    acc32(cur, tx, ty, tz, k, A);
-                    cur = nxt;
-                }
+            for (int j = js; j < je; ++j) {
+                const Part32 nxt = parts[j + 1 < je ? j + 1 : j];
+                acc32(cur, tx, ty, tz, k, A);
+                cur = nxt;
             }
         }
-        double ud[3], Jd[9], Sd[3];
-        for (int b = 0; b < 3; ++b) {
-            ud[b] = double(A.us[b]) - double(A.uc[b]);
-            Sd[b] = double(A.S[b]);
-        }
-        for (int kk = 0; kk < 9; ++kk) Jd[kk] = double(A.Jr[kk]);
-        if (grouped) {
-            double v[15];
-            for (int c = 0; c < 3; ++c) { v[c] = ud[c]; v[3 + c] = Sd[c]; }
-            for (int c = 0; c < 9; ++c) v[6 + c] = Jd[c];
-            group_reduce(v, 15, E);
-            for (int c = 0; c < 3; ++c) { ud[c] = v[c]; Sd[c] = v[3 + c]; }
-            for (int c = 0; c < 9; ++c) Jd[c] = v[6 + c];
-        }
-        if (valid && gi == 0) epilogue(a, s0 + base + t, ud, Jd, Sd);
-        if (grouped) break;
+        if (valid) epilogue(a, s0 + base + lane, true, A.us, A.uc, A.Jr, A.S, NoReduce{});
     }
+    // a last block of rem <= 32 targets: lane groups share out the sources, their
+    // partial sums are combined in FP64
+    const int rem = cnt - nfull;
+    if (rem <= 0) return;
+    const int E = pow2_ceil(rem);
+    const int t = lane & (E - 1), gi = lane / E, ng = 64 / E;
+    const bool valid = t < rem;
+    const Part32 me = parts[s0 + nfull + (valid ? t : 0)];
+    Acc32 A;
+    for (int c = 0; c < 3; ++c) A.us[c] = A.uc[c] = A.S[c] = 0.0f;
+    for (int c = 0; c < 9; ++c) A.Jr[c] = 0.0f;
+    for (int nb = 0; nb < 27; ++nb) {
+        int js, je, dx, dy, dz;
+        if (!neighbour(a, L, nb, js, je, dx, dy, dz)) continue;
+        const float tx = me.dx - float(dx) * w, ty = me.dy - float(dy) * w, tz = me.dz - float(dz) * w;
+#pragma unroll 1
+        for (int j = js + gi; j < je; j += ng) acc32(parts[j], tx, ty, tz, k, A);
+    }
+    epilogue(a, s0 + nfull + t, valid && gi == 0, A.us, A.uc, A.Jr, A.S, GroupSum{E});
 }
 
 }  // namespace
