@@ -2,7 +2,7 @@
 // GEMMs (M2M, M2L, L2L) on the MFMA units, and the periodic lattice operator.
 //
 // Coefficient layout: cell-major, [cell][component][kp] with kp = (p+1)^2
-// rounded up to a multiple of 4 (the MFMA K step); entries C..kp-1 are zero.
+// rounded up to a multiple of 32 (whole k blocks); entries C..kp-1 are zero.
 #include "device_harmonics.h"
 #include "kernels.h"
 
@@ -226,13 +226,11 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
 }
 
 // ----------------------------------------------------------- translate ----
-// One workgroup (4 waves) owns TTN = 16 NT target cells that share one pair
-// list (M2L: one octant).  For each pair (operator op, one source per target)
-// the sources' coefficients are staged in LDS and every wave multiplies its
-// row blocks of the operator (pre-swizzled into MFMA A fragments, read
-// straight from memory with a one-step prefetch) against all 3 TTN columns:
-//   out[tile] (Cp x 3 TTN) += Op (Cp x kp) * Src (kp x 3 TTN).
-// The local coefficients stay in accumulator registers across the 189 pairs.
+// The translations are GEMMs over a tile of target cells that share one list
+// of (operator, source) pairs (M2L: one octant and its 189 offsets; L2L: one
+// child octant; M2M: the 8 children of each parent):
+//   out[tile] (C x 3 tile) += sum over pairs Op (C x C) * Src (C x 3 tile),
+// with the sums kept in MFMA accumulators across all pairs.
 // MFMA 16x16x4: A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16);
 // accumulator register r of lane l holds column l%16 and row (l/16) + 4r for
 // FP64, 4(l/16) + r for FP32 (both checked on gfx950).

@@ -11,8 +11,10 @@
 //   J[a][b] += (q'/r) r_a (alpha_j x r)_b + q eps_abc alpha_j,c
 // For small rho both q and q'/r are even power series in rho (g is the
 // integral of the Gaussian mass, g' = sqrt(2/pi) rho^2 exp(-rho^2/2)).
-// The epilogue adds the far field computed by L2P, contracts the gradient
-// into the stretching term and scatters to the caller's particle order.
+// A leaf's last target block of 32 or fewer particles is split over lane
+// groups that share out the sources.  The epilogue adds the far field
+// computed by L2P, contracts the gradient into the stretching term and
+// scatters to the caller's particle order.
 #include "kernels.h"
 
 namespace vmfmm {
