@@ -63,7 +63,7 @@ typedef struct {
 } vm_opts;
 
 /* Limits checked on every call. */
-#define VM_MAX_P 20
+#define VM_MAX_P 18   /* the FP64 translation tile's LDS staging bounds the degree */
 #define VM_MAX_LEVEL 10
 
 /* Creates a context bound to HIP device `device` and stream `hip_stream`

@@ -386,7 +386,7 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     if (misaligned(x) || misaligned(alpha) || misaligned(u) || misaligned(dalpha_dt) || misaligned(grad))
         return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(ctx, VM_EINVAL, "sigma must be positive");
-    if (p < 1 || p > VM_MAX_P) return fail(ctx, VM_EINVAL, "p out of range [1, 20]");
+    if (p < 1 || p > VM_MAX_P) return fail(ctx, VM_EINVAL, "p out of range [1, VM_MAX_P = 18]");
     if (level < 0 || level > VM_MAX_LEVEL) return fail(ctx, VM_EINVAL, "level out of range [0, 10]");
     if (!(opts->box_len > 0.0) || !std::isfinite(opts->box_len))
         return fail(ctx, VM_EINVAL, "box_len must be positive");

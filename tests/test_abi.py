@@ -36,7 +36,7 @@ def test_host_entry_points_validate_arguments():
     assert lib.vm_debug_operator(3, 10, 0, out.ctypes.data) == _lib.VM_EINVAL
     assert lib.vm_debug_operator(7, 10, 0, out.ctypes.data) == _lib.VM_EINVAL
     assert lib.vm_debug_operator(0, 0, 0, out.ctypes.data) == _lib.VM_EINVAL
-    assert lib.vm_debug_operator(0, 21, 0, out.ctypes.data) == _lib.VM_EINVAL
+    assert lib.vm_debug_operator(0, 19, 0, out.ctypes.data) == _lib.VM_EINVAL   # VM_MAX_P = 18
     assert lib.vm_debug_operator(0, 10, 0, None) == _lib.VM_EINVAL
     cnt = ctypes.c_int()
     src = np.zeros(189, np.int32)
@@ -56,7 +56,7 @@ def test_offset_table_is_the_oracles():
     assert offs == T.all_offsets()
 
 
-@pytest.mark.parametrize("p", [1, 3, 10, 20])
+@pytest.mark.parametrize("p", [1, 3, 10, 18])     # 18 = VM_MAX_P
 def test_operator_generation_is_finite(p):
     import paper_1110_2921_amd as vm
     for kind, idx in ((0, 0), (0, 315), (1, 7), (2, 3), (3, 2)):

@@ -178,6 +178,27 @@ def test_compensated_near_field_sums(ctx):
     assert nerr.max() > 2e-6, nerr.max()
 
 
+@pytest.mark.parametrize("periodic", [0, 2])
+def test_largest_degree(ctx, periodic):
+    """p = 18, the largest degree (single-buffered translation tiles, 7 P2M
+    order ranges, the widest L2P tables): against the direct sum with the
+    far-field model (g = 1 beyond adjacent leaves), to which the FMM converges
+    as p grows.  FP64 at p = 18 within 1e-6 of it and at least 10x closer than
+    at p = 12; mixed within 1e-5 (u) and 1e-4 (J) of FP64."""
+    x, a = W.random_particles(3000, 43)
+    sigma, level = 0.15, 2
+    tr = T.build(x, (0, 0, 0), L, level, periodic)
+    c = tr["coords"]            # input order, as xw
+    ud, Jd = D.direct(tr["xw"], tr["xw"], a, sigma, L, K=periodic, cells_t=c, cells_s=c, level=level)
+    u12, _, J12 = _run(ctx, x, a, sigma, 12, level, periodic)
+    u, _, J = _run(ctx, x, a, sigma, 18, level, periodic)
+    assert rel(u, ud) < 1e-6 and rel(J, Jd) < 1e-6
+    assert rel(u, ud) < rel(u12, ud) / 10 and rel(J, Jd) < rel(J12, Jd) / 10
+    um, _, Jm = _run(ctx, x, a, sigma, 18, level, periodic, precision="mixed")
+    assert rel(um, u) < 1e-5
+    assert rel(Jm, J) < 1e-4
+
+
 def test_transpose_scheme_conserves_vorticity(ctx):
     x, a = W.random_field(16, 4.0, 23)
     h = L / 16
@@ -202,7 +223,7 @@ def test_runs_are_bitwise_reproducible(ctx, precision):
 def test_invalid_arguments_are_rejected(ctx):
     import paper_1110_2921_amd as vm
     x, a = W.random_particles(64, 3)
-    for kw in (dict(p=0), dict(p=21), dict(level=11), dict(periodic=5)):
+    for kw in (dict(p=0), dict(p=19), dict(level=11), dict(periodic=5)):
         args = dict(p=4, level=1, periodic=0)
         args.update(kw)
         with pytest.raises(vm._lib.VmError) as e:
