@@ -101,3 +101,31 @@ def test_full_size_against_direct_sum(ctx, name):
     assert eu < 1e-3 and ej < 1e-3
     assert rel(res["mixed"][0], ud) < eu + 1e-5
     assert rel(res["mixed"][1], Jd) < ej + 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_degree_sweep_against_direct_sum(ctx):
+    """FMM (FP64, images S_1) against the exact direct sum over S_1 at 32 sampled
+    particles of the 128^3 field, p = 6 .. 18: the error falls with p and crosses
+    1e-6 (the FP64 accuracy asked of the evaluation) at some p <= 18; the table
+    is printed."""
+    import torch
+    w = W.WORKLOADS["rand128_periodic"]
+    x_np, a_np = W.make(w)
+    xw = T.wrap(x_np, (0.0, 0.0, 0.0), w.box_len)
+    x = torch.from_numpy(np.ascontiguousarray(x_np.T)).cuda()
+    a = torch.from_numpy(np.ascontiguousarray(a_np.T)).cuda()
+    t = np.sort(np.random.default_rng(13).choice(w.n, 32, replace=False))
+    tt = torch.from_numpy(t).cuda()
+    ud, Jd = D.direct(xw[t], xw, a_np, w.sigma, w.box_len, K=1)
+    errs = {}
+    for p in (6, 8, 10, 12, 14, 16, 18):
+        u, _, J = ctx.eval(x, a, w.sigma, p, w.level, periodic=1, box_len=w.box_len, precision="fp64",
+                           want_grad=True, want_dalpha=False)
+        errs[p] = (rel(u[:, tt].cpu().numpy().T, ud), rel(J[:, tt].cpu().numpy().T.reshape(-1, 3, 3), Jd))
+        del u, J
+    for p, (eu, ej) in errs.items():
+        print(f"p={p:2d}: u {eu:.2e}  J {ej:.2e}")
+    ps = sorted(errs)
+    assert all(errs[b][0] < errs[a][0] for a, b in zip(ps, ps[1:]))
+    assert min(e[0] for e in errs.values()) < 1e-6
