@@ -1,0 +1,86 @@
+"""Gaussian smoothing sums and RBF interpolation (test infrastructure: the oracle).
+
+Definitions (Sec. 2):
+
+* the vorticity carried by the particles is the superposition of Gaussian
+  bases, omega(x) = sum_j gamma_j zeta_sigma(x - x_j) (the smoothing-function
+  equation), with zeta_sigma(r) = (2 pi sigma^2)^(-3/2) exp(-r^2 / (2 sigma^2))
+  (the Gaussian equation);
+* the sum is taken over neighbouring particles only, through the neighbour
+  list of the FMM tree: for a target in leaf c, the sources in the 27 leaves
+  c + d, d in {-1, 0, 1}^3, each counted once per d.  Periodic: the leaf index
+  is taken modulo 2^level and the source shifted by the image n L, n = floor
+  ((c + d) / 2^level); free space: leaves outside the domain are skipped.
+  Positions of a periodic problem are wrapped into the box first (tree.wrap);
+* RBF interpolation solves that linear system, A gamma = omega with
+  A_ij = sum over the neighbour-list images of zeta_sigma(x_i - x_j - n L),
+  for gamma given omega at the particle positions.  The paper iterates with
+  GMRES from the initial guess gamma = omega h^3; here the system is solved
+  directly (dense LU), the reference the iterative GPU solve converges to.
+
+Everything is FP64 and meant for small N (the matrix is dense).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+from . import tree as T
+
+
+def zeta(r2, sigma):
+    """Gaussian basis at squared distance r2 (the Gaussian equation)."""
+    return np.exp(-0.5 * r2 / (sigma * sigma)) / (2.0 * math.pi * sigma * sigma) ** 1.5
+
+
+def _neighbour_pairs(x, level, box_len, periodic, lo=(0.0, 0.0, 0.0)):
+    """Yields (targets, sources, shift) per (target leaf, d): particle index
+    arrays and the image shift added to the source positions."""
+    side = 1 << level
+    c = T.leaf_coords(x, lo, box_len, level)
+    key = c[:, 0] + side * (c[:, 1] + side * c[:, 2])
+    order = np.argsort(key, kind="stable")
+    sk = key[order]
+    bounds = np.searchsorted(sk, np.arange(side ** 3 + 1))
+    members = lambda k: order[bounds[k]:bounds[k + 1]]
+    for ck in itertools.product(range(side), repeat=3):
+        tgt = members(ck[0] + side * (ck[1] + side * ck[2]))
+        if tgt.size == 0:
+            continue
+        for d in itertools.product((-1, 0, 1), repeat=3):
+            cs = [ck[a] + d[a] for a in range(3)]
+            if periodic:
+                n = np.array([math.floor(v / side) for v in cs], np.float64)
+                cs = [v % side for v in cs]
+            else:
+                if any(v < 0 or v >= side for v in cs):
+                    continue
+                n = np.zeros(3)
+            src = members(cs[0] + side * (cs[1] + side * cs[2]))
+            if src.size:
+                yield tgt, src, n * box_len
+
+
+def gauss_matrix(x, sigma, level, box_len=2 * math.pi, periodic=0):
+    """Dense A (n, n): A[i, j] = sum over neighbour-list images of zeta(x_i - x_j - shift)."""
+    x = np.asarray(x, np.float64)
+    if periodic:
+        x = T.wrap(x, (0.0, 0.0, 0.0), box_len)
+    A = np.zeros((len(x), len(x)))
+    for tgt, src, shift in _neighbour_pairs(x, level, box_len, periodic):
+        r = x[tgt][:, None, :] - (x[src][None, :, :] + shift)
+        A[np.ix_(tgt, src)] += zeta(np.sum(r * r, axis=2), sigma)
+    return A
+
+
+def gauss_sum(x, gamma, sigma, level, box_len=2 * math.pi, periodic=0):
+    """omega (n, 3) = A gamma."""
+    return gauss_matrix(x, sigma, level, box_len, periodic) @ np.asarray(gamma, np.float64)
+
+
+def rbf_solve(x, omega, sigma, level, box_len=2 * math.pi, periodic=0):
+    """gamma (n, 3) with A gamma = omega, by a dense solve."""
+    A = gauss_matrix(x, sigma, level, box_len, periodic)
+    return np.linalg.solve(A, np.asarray(omega, np.float64))
