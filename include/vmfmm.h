@@ -141,11 +141,67 @@ vm_status vm_diagnostics(vm_ctx *ctx, int64_t n, const double *u, const double *
                          double h3, double *out);
 
 /*
+ * Gaussian smoothing sum over the neighbour list (Sec. 2.2, eqs. 3-4, and the
+ * reinitialisation paragraph there): the vorticity the particles carry, at
+ * the particles,
+ *   omega_i = sum_j gamma_j zeta_sigma(x_i - x_j - n L),
+ *   zeta_sigma(r) = (2 pi sigma^2)^(-3/2) exp(-|r|^2 / (2 sigma^2)),
+ * with j over the particles of the 27 leaves adjacent to x_i's leaf (itself
+ * included) at leaf level `level`: free space skips leaves outside the box;
+ * periodic (opts->periodic > 0, any K) wraps the leaf index and shifts the
+ * source by its image n L, so a source counts once per adjacent leaf slot
+ * (twice or more when 2^level < 3).  No far field: the Gaussian is taken to
+ * vanish beyond the neighbour leaves, the truncation the paper makes.
+ *   x, gamma   device [3][n]: positions (periodic: modulo the box), strengths
+ *   omega      device [3][n] out, caller order
+ * opts->precision: VM_FP64 computes in FP64; VM_MIXED takes FP32 differences
+ * and exponentials with FP32 sums over each source leaf, added in FP64.
+ * opts->scheme is ignored.  Same argument rules and errors as vm_fmm_eval
+ * (sigma > 0, 0 <= level <= VM_MAX_LEVEL, ...).  The context's tree
+ * workspace and debug tree view are reused (vm_debug_tree shows this call's
+ * tree afterwards; the expansion views report no expansions).
+ */
+vm_status vm_gauss_sum(vm_ctx *ctx, int64_t n, const double *x, const double *gamma, double sigma, int level,
+                       const vm_opts *opts, double *omega);
+
+/*
+ * RBF interpolation (Sec. 2.2, the reinitialisation paragraph; initial guess
+ * and tolerance as in Sec. 5's solver-tolerance study, default tolerance 1e-3
+ * in Sec. 4.1): the strengths gamma that reproduce a given vorticity at the
+ * particles, A gamma = omega with A the vm_gauss_sum operator, solved for each
+ * component by restarted GMRES(VM_RBF_RESTART) with the matrix-free product.
+ *   x, omega   device [3][n]: positions and the vorticity to interpolate
+ *   h3         the particle volume h^3: the initial guess is gamma_0 = h3 omega
+ *   tol        exit when every component's residual norm has dropped to
+ *              tol times its norm at gamma_0 (0 <= tol < 1; 0 runs max_iter)
+ *   max_iter   products after the initial residual, 0..VM_RBF_MAX_ITER
+ *   gamma      device [3][n] out, caller order
+ *   iters      out (may be NULL): the products spent (the three components
+ *              share each one)
+ *   resid      out (may be NULL): the largest relative residual reached, as
+ *              GMRES estimates it (exact at every restart)
+ * Orthogonalisation by classical Gram-Schmidt applied twice; dot products
+ * reduce in a fixed order, so results are reproducible run to run.  Each
+ * iteration reads the dot products back to the host (synchronises the
+ * stream).  The context keeps (VM_RBF_RESTART + 3) [3][n] FP64 vectors.
+ * Precision forms as vm_gauss_sum (the vectors and the iteration are FP64 in
+ * both).  Returns VM_OK also when max_iter ends the iteration first: compare
+ * *resid with tol.
+ */
+#define VM_RBF_RESTART 20
+#define VM_RBF_MAX_ITER 100000
+vm_status vm_rbf_solve(vm_ctx *ctx, int64_t n, const double *x, const double *omega, double sigma, double h3,
+                       int level, const vm_opts *opts, double tol, int max_iter, double *gamma, int *iters,
+                       double *resid);
+
+/*
  * Device-time accounting (HIP events on the context's stream around every
  * launch).  vm_set_timing(ctx, 1) starts a fresh account (and 0 stops it);
  * vm_get_timing reports, summed over every vm_fmm_eval since then, the
  * milliseconds and the number of launches of each phase (at most 32768
- * launches are recorded); it synchronises the stream.  Phases, in launch order:
+ * launches are recorded); it synchronises the stream.  vm_gauss_sum and
+ * vm_rbf_solve add their tree build to VM_PH_TREE and their own work to the
+ * last two phases.  Phases, in launch order:
  */
 enum {
     VM_PH_TREE = 0,   /* keys, radix sort passes, leaf ranges, permutation */
@@ -156,6 +212,8 @@ enum {
     VM_PH_M2L,
     VM_PH_L2P,
     VM_PH_P2P,        /* near field + combine + scatter to caller order */
+    VM_PH_GAUSS,      /* Gaussian sums of vm_gauss_sum / vm_rbf_solve (with the strength packing) */
+    VM_PH_KRYLOV,     /* vector work of vm_rbf_solve: dots, updates, gathers and scatters */
     VM_NPHASE
 };
 vm_status vm_set_timing(vm_ctx *ctx, int enable);

@@ -35,30 +35,44 @@ def zeta(r2, sigma):
     return np.exp(-0.5 * r2 / (sigma * sigma)) / (2.0 * math.pi * sigma * sigma) ** 1.5
 
 
-def _neighbour_pairs(x, level, box_len, periodic, lo=(0.0, 0.0, 0.0)):
+def _leaves(x, level, box_len):
+    """Leaf coordinates of every particle, the particles sorted by leaf index
+    (cx + side (cy + side cz)) and each leaf's range in that order."""
+    side = 1 << level
+    c = T.leaf_coords(x, (0.0, 0.0, 0.0), box_len, level)
+    key = c[:, 0] + side * (c[:, 1] + side * c[:, 2])
+    order = np.argsort(key, kind="stable")
+    bounds = np.searchsorted(key[order], np.arange(side ** 3 + 1))
+    return c, order, bounds
+
+
+def _slots(ck, side, periodic):
+    """The 27 neighbour slots d of leaf ck: (source leaf index, image n) for
+    each slot that exists (free space drops leaves outside the domain)."""
+    for d in itertools.product((-1, 0, 1), repeat=3):
+        cs = [ck[a] + d[a] for a in range(3)]
+        if periodic:
+            n = np.array([math.floor(v / side) for v in cs], np.float64)
+            cs = [v % side for v in cs]
+        else:
+            if any(v < 0 or v >= side for v in cs):
+                continue
+            n = np.zeros(3)
+        yield cs[0] + side * (cs[1] + side * cs[2]), n
+
+
+def _neighbour_pairs(x, level, box_len, periodic):
     """Yields (targets, sources, shift) per (target leaf, d): particle index
     arrays and the image shift added to the source positions."""
     side = 1 << level
-    c = T.leaf_coords(x, lo, box_len, level)
-    key = c[:, 0] + side * (c[:, 1] + side * c[:, 2])
-    order = np.argsort(key, kind="stable")
-    sk = key[order]
-    bounds = np.searchsorted(sk, np.arange(side ** 3 + 1))
+    _, order, bounds = _leaves(x, level, box_len)
     members = lambda k: order[bounds[k]:bounds[k + 1]]
     for ck in itertools.product(range(side), repeat=3):
         tgt = members(ck[0] + side * (ck[1] + side * ck[2]))
         if tgt.size == 0:
             continue
-        for d in itertools.product((-1, 0, 1), repeat=3):
-            cs = [ck[a] + d[a] for a in range(3)]
-            if periodic:
-                n = np.array([math.floor(v / side) for v in cs], np.float64)
-                cs = [v % side for v in cs]
-            else:
-                if any(v < 0 or v >= side for v in cs):
-                    continue
-                n = np.zeros(3)
-            src = members(cs[0] + side * (cs[1] + side * cs[2]))
+        for k, n in _slots(ck, side, periodic):
+            src = members(k)
             if src.size:
                 yield tgt, src, n * box_len
 
@@ -84,3 +98,21 @@ def rbf_solve(x, omega, sigma, level, box_len=2 * math.pi, periodic=0):
     """gamma (n, 3) with A gamma = omega, by a dense solve."""
     A = gauss_matrix(x, sigma, level, box_len, periodic)
     return np.linalg.solve(A, np.asarray(omega, np.float64))
+
+
+def gauss_sum_at(x, gamma, sigma, level, targets, box_len=2 * math.pi, periodic=0):
+    """Rows `targets` of A gamma (len(targets), 3), one target at a time: the
+    same neighbour-list sum, for inputs too large for the dense matrix."""
+    x = np.asarray(x, np.float64)
+    gamma = np.asarray(gamma, np.float64)
+    if periodic:
+        x = T.wrap(x, (0.0, 0.0, 0.0), box_len)
+    side = 1 << level
+    c, order, bounds = _leaves(x, level, box_len)
+    out = np.zeros((len(targets), 3))
+    for row, i in enumerate(targets):
+        for k, n in _slots(tuple(int(v) for v in c[i]), side, periodic):
+            src = order[bounds[k]:bounds[k + 1]]
+            r = x[i][None, :] - (x[src] + n * box_len)
+            out[row] = out[row] + zeta(np.sum(r * r, axis=1), sigma) @ gamma[src]
+    return out

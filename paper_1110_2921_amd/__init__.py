@@ -161,6 +161,45 @@ class FMM:
                                              float(h3), ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def gauss_sum(self, x, gamma, sigma, level, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi,
+                  precision="fp64", stream=None, out=None):
+        """Gaussian smoothing sum over the neighbour list, (3, n) float64."""
+        torch = self._torch
+        x = _soa(x, torch)
+        gamma = _soa(gamma, torch)
+        n = x.shape[1]
+        if gamma.shape[1] != n:
+            raise ValueError("x and gamma differ in length")
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        om = torch.empty((3, n), dtype=torch.float64, device=x.device) if out is None else out
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", False)
+        self._check(self._lib.vm_gauss_sum(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(gamma.data_ptr()), float(sigma), int(level),
+                                           ctypes.byref(opts), ctypes.c_void_p(om.data_ptr())))
+        return om
+
+    def rbf_solve(self, x, omega, sigma, h3, level, tol=1e-3, max_iter=100, periodic=0, box_lo=(0.0, 0.0, 0.0),
+                  box_len=2 * math.pi, precision="fp64", stream=None, out=None):
+        """Strengths (3, n) float64 reproducing omega at the particles, with the
+        products spent and the relative residual reached: (gamma, iters, resid)."""
+        torch = self._torch
+        x = _soa(x, torch)
+        omega = _soa(omega, torch)
+        n = x.shape[1]
+        if omega.shape[1] != n:
+            raise ValueError("x and omega differ in length")
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        gam = torch.empty((3, n), dtype=torch.float64, device=x.device) if out is None else out
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", False)
+        iters = ctypes.c_int(0)
+        resid = ctypes.c_double(0.0)
+        self._check(self._lib.vm_rbf_solve(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(omega.data_ptr()), float(sigma), float(h3), int(level),
+                                           ctypes.byref(opts), float(tol), int(max_iter),
+                                           ctypes.c_void_p(gam.data_ptr()), ctypes.byref(iters),
+                                           ctypes.byref(resid)))
+        return gam, iters.value, resid.value
+
     def set_timing(self, enable=True):
         self._check(self._lib.vm_set_timing(self._h, int(bool(enable))))
 

@@ -11,14 +11,14 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvmfmm.so")
 
-PHASES = ("tree", "p2m", "m2m", "lattice", "l2l", "m2l", "l2p", "p2p")
+PHASES = ("tree", "p2m", "m2m", "lattice", "l2l", "m2l", "l2p", "p2p", "gauss", "krylov")
 
 VM_OK, VM_EINVAL, VM_ENOMEM, VM_EDEVICE, VM_EDOMAIN = 0, -1, -2, -3, -4
 STATUS_NAMES = {0: "VM_OK", -1: "VM_EINVAL", -2: "VM_ENOMEM", -3: "VM_EDEVICE", -4: "VM_EDOMAIN"}
 
 # every symbol include/vmfmm.h declares
 EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_eval",
-           "vm_fmm_adjoint", "vm_rk2_step", "vm_diagnostics",
+           "vm_fmm_adjoint", "vm_rk2_step", "vm_diagnostics", "vm_gauss_sum", "vm_rbf_solve",
            "vm_set_timing", "vm_get_timing", "vm_debug_tree", "vm_debug_expansions", "vm_debug_far", "vm_debug_offsets", "vm_debug_list",
            "vm_debug_operator")
 
@@ -65,6 +65,12 @@ def load():
     lib.vm_rk2_step.restype = ctypes.c_int
     lib.vm_diagnostics.argtypes = [vp, i64, dp, dp, dp, ctypes.c_double, dp]
     lib.vm_diagnostics.restype = ctypes.c_int
+    lib.vm_gauss_sum.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(VmOpts), dp]
+    lib.vm_gauss_sum.restype = ctypes.c_int
+    lib.vm_rbf_solve.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.POINTER(VmOpts), ctypes.c_double, ctypes.c_int, dp,
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    lib.vm_rbf_solve.restype = ctypes.c_int
     lib.vm_set_timing.argtypes = [vp, ctypes.c_int]
     lib.vm_set_timing.restype = ctypes.c_int
     lib.vm_get_timing.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]

@@ -87,6 +87,34 @@ struct P2PArgs {
 hipError_t launch_p2p64(hipStream_t s, const P2PArgs &a, const Part64 *parts);
 hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts);
 
+// --- RBF interpolation (kernels_rbf.hip) --------------------------------------------
+struct GaussArgs {
+    int n, nleaf, level, periodic;
+    double w, sigma;
+    const int32_t *start;
+    double *out;   // sorted order [3][n]
+};
+// Gaussian sums of the strengths held in the records' a-fields
+hipError_t launch_gauss(hipStream_t s, const GaussArgs &a, const void *parts, int mixed);
+// records' a-fields <- gamma (sorted order [3][n])
+hipError_t launch_pack(hipStream_t s, int n, const double *gamma, void *parts, int mixed);
+hipError_t launch_gather3(hipStream_t s, int n, const int32_t *perm, const double *src, double *dst);
+hipError_t launch_scatter3(hipStream_t s, int n, const int32_t *perm, const double *src, double scale, double *dst);
+
+constexpr int kRbfDotBlocks = 512;
+constexpr int kRbfMaxVecs = 32;
+struct RbfCoefs {
+    double alpha[3];
+    double c[3 * kRbfMaxVecs];   // c[3 j + component]
+};
+// out[3 j + c] = <w_c, v_{j,c}>, j < k <= kRbfMaxVecs, v_j = V + j ldv, fixed
+// reduction order; `partial` holds 3 k kRbfDotBlocks doubles
+hipError_t launch_multidot(hipStream_t s, int n, const double *w, const double *V, int64_t ldv, int k,
+                           double *partial, double *out);
+// w_c <- alpha_c w_c + sum_{j < k} c_{j,c} v_{j,c}
+hipError_t launch_multiaxpy(hipStream_t s, int n, double *w, const double *V, int64_t ldv, int k,
+                            const RbfCoefs &c);
+
 // --- adjoint (kernels_adjoint.hip) ------------------------------------------------
 template <typename T>
 hipError_t launch_l2p_adj(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start,

@@ -102,6 +102,7 @@ struct vm_ctx {
     DevBuf zeros;    // a zero expansion cell read in place of missing M2L sources
     DevBuf rk_u, rk_s, rk_x, rk_a, diag;
     DevBuf adj_u, adj_J, adj_v, adj_Jv, adj_far, adj_p64, adj_p32;
+    DevBuf rbf_b, rbf_x, rbf_V, rbf_part, rbf_dots;   // RBF solve: right side, iterate, Krylov basis, reductions
     std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice_t;
     int layout_p = -1, layout_prec = -1;   // layout of mbuf/lbuf
     // results of the last evaluation, for the debug views
@@ -343,6 +344,107 @@ vm_status ensure_lattice_t(vm_ctx *ctx, int p, int K, const double **out) {
     return VM_OK;
 }
 
+bool misaligned(const void *q) { return q && (reinterpret_cast<uintptr_t>(q) & 7u); }
+
+// Checks shared by the entry points that build the tree.
+vm_status check_common(vm_ctx *ctx, int64_t n, double sigma, int level, const vm_opts *opts) {
+    if (!opts) return fail(ctx, VM_EINVAL, "opts is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(ctx, VM_EINVAL, "sigma must be positive");
+    if (level < 0 || level > VM_MAX_LEVEL) return fail(ctx, VM_EINVAL, "level out of range [0, 10]");
+    if (!(opts->box_len > 0.0) || !std::isfinite(opts->box_len))
+        return fail(ctx, VM_EINVAL, "box_len must be positive");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(opts->box_lo[d])) return fail(ctx, VM_EINVAL, "box_lo must be finite");
+    if (opts->periodic < 0 || opts->periodic > 4) return fail(ctx, VM_EINVAL, "periodic out of range [0, 4]");
+    if (opts->precision != VM_FP64 && opts->precision != VM_MIXED)
+        return fail(ctx, VM_EINVAL, "unknown precision");
+    return VM_OK;
+}
+
+// Tree of the particles (Sec. 3.1): Morton keys, stable LSD radix sort, leaf
+// ranges and the sorted particle records (positions relative to their leaf
+// centres, `alpha` in the strength fields), in the precision of opts.  On
+// return `perm` holds the caller index of each sorted particle; the keys,
+// permutation and ranges are kept for the debug views.
+vm_status build_tree(vm_ctx *ctx, int ni, const double *x, const double *alpha, int level, const vm_opts *opts,
+                     TreeGeom &g, int32_t *&perm) {
+    hipStream_t s = ctx->stream;
+    const int mixed = opts->precision == VM_MIXED;
+    const int64_t nleaf = int64_t(1) << (3 * level);
+    const size_t n = size_t(ni);
+    const int nblk = (ni + kRadixTile - 1) / kRadixTile;
+    VM_HIP(ctx->keys_a.reserve(sizeof(uint32_t) * n), "alloc keys");
+    VM_HIP(ctx->keys_b.reserve(sizeof(uint32_t) * n), "alloc keys");
+    VM_HIP(ctx->vals_a.reserve(sizeof(int32_t) * n), "alloc perm");
+    VM_HIP(ctx->vals_b.reserve(sizeof(int32_t) * n), "alloc perm");
+    // digit counts [256][nblk] followed by the scan's tile sums
+    VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * (size_t(nblk) * 256 + size_t(nblk) * 256 / 4096 + 256)),
+           "alloc histogram");
+    VM_HIP(ctx->start.reserve(sizeof(int32_t) * size_t(nleaf + 1)), "alloc leaf ranges");
+    if (mixed) VM_HIP(ctx->p32.reserve(sizeof(Part32) * n), "alloc particles");
+    else VM_HIP(ctx->p64.reserve(sizeof(Part64) * n), "alloc particles");
+    VM_HIP(ctx->flag.reserve(sizeof(int)), "alloc flag");
+
+    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
+    g.box_len = opts->box_len;
+    g.inv_len = 1.0 / opts->box_len;
+    g.inv_w = std::ldexp(g.inv_len, level);
+    g.w = std::ldexp(opts->box_len, -level);
+    g.level = level;
+    g.periodic = opts->periodic > 0;
+
+    int32_t *start = ctx->start.as<int32_t>();
+    if (opts->check_domain) VM_HIP(hipMemsetAsync(ctx->flag.ptr, 0, sizeof(int), s), "clear flag");
+    uint32_t *kin = ctx->keys_a.as<uint32_t>(), *kout = ctx->keys_b.as<uint32_t>();
+    int32_t *vin = ctx->vals_a.as<int32_t>(), *vout = ctx->vals_b.as<int32_t>();
+    Timed tm(ctx, VM_PH_TREE);
+    VM_HIP(launch_keys(s, ni, x, g, opts->check_domain, kin, vin, ctx->flag.as<int>()), "keys");
+    const int total_bits = 3 * level;
+    if (total_bits > 0) {
+        const int npass = (total_bits + 7) / 8;
+        const int bits = (total_bits + npass - 1) / npass;
+        for (int shift = 0; shift < total_bits; shift += bits) {
+            const int b = std::min(bits, total_bits - shift);
+            VM_HIP(launch_radix_pass(s, ni, shift, b, kin, vin, kout, vout, ctx->hist.as<uint32_t>()), "radix sort");
+            std::swap(kin, kout);
+            std::swap(vin, vout);
+        }
+    }
+    VM_HIP(launch_ranges(s, ni, int(nleaf), kin, start), "leaf ranges");
+    VM_HIP(launch_permute(s, ni, x, alpha, vin, kin, g, mixed ? nullptr : ctx->p64.as<Part64>(),
+                          mixed ? ctx->p32.as<Part32>() : nullptr), "permute");
+    ctx->last_keys = kin;
+    ctx->last_perm = vin;
+    ctx->last_n = int64_t(ni);
+    ctx->last_level = level;
+    ctx->last_p = -1;
+    ctx->last_far = 0;
+    perm = vin;
+    return VM_OK;
+}
+
+// Solution of the (j+1) x (j+1) upper triangular system R y = g of one
+// component's rotated Hessenberg matrix (column-major, leading dimension ld).
+void back_substitute(const std::vector<double> &R, int ld, const std::vector<double> &g, int cols, double *y) {
+    for (int i = cols - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int l = i + 1; l < cols; ++l) t -= R[size_t(l) * ld + i] * y[l];
+        const double d = R[size_t(i) * ld + i];
+        y[i] = d != 0.0 ? t / d : 0.0;
+    }
+}
+
+// With check_domain: reads the flag the key kernel raised (synchronises).
+vm_status check_flag(vm_ctx *ctx, const vm_opts *opts) {
+    if (!opts->check_domain) return VM_OK;
+    int flag = 0;
+    VM_HIP(hipMemcpyAsync(&flag, ctx->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "read flag");
+    VM_HIP(hipStreamSynchronize(ctx->stream), "synchronize");
+    if (flag) return fail(ctx, VM_EDOMAIN, "non-finite or out-of-box position");
+    return VM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -379,22 +481,11 @@ const char *vm_last_error(const vm_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
                       int level, const vm_opts *opts, double *u, double *dalpha_dt, double *grad) {
     if (!ctx) return VM_EINVAL;
-    if (!opts) return fail(ctx, VM_EINVAL, "opts is NULL");
-    if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
+    if (vm_status st = check_common(ctx, n, sigma, level, opts); st != VM_OK) return st;
     if (!x || !alpha || !u) return fail(ctx, VM_EINVAL, "x, alpha and u must be non-NULL");
-    auto misaligned = [](const void *q) { return q && (reinterpret_cast<uintptr_t>(q) & 7u); };
     if (misaligned(x) || misaligned(alpha) || misaligned(u) || misaligned(dalpha_dt) || misaligned(grad))
         return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
-    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(ctx, VM_EINVAL, "sigma must be positive");
     if (p < 1 || p > VM_MAX_P) return fail(ctx, VM_EINVAL, "p out of range [1, VM_MAX_P = 18]");
-    if (level < 0 || level > VM_MAX_LEVEL) return fail(ctx, VM_EINVAL, "level out of range [0, 10]");
-    if (!(opts->box_len > 0.0) || !std::isfinite(opts->box_len))
-        return fail(ctx, VM_EINVAL, "box_len must be positive");
-    for (int d = 0; d < 3; ++d)
-        if (!std::isfinite(opts->box_lo[d])) return fail(ctx, VM_EINVAL, "box_lo must be finite");
-    if (opts->periodic < 0 || opts->periodic > 4) return fail(ctx, VM_EINVAL, "periodic out of range [0, 4]");
-    if (opts->precision != VM_FP64 && opts->precision != VM_MIXED)
-        return fail(ctx, VM_EINVAL, "unknown precision");
     if (opts->scheme != VM_CLASSIC && opts->scheme != VM_TRANSPOSE) return fail(ctx, VM_EINVAL, "unknown scheme");
 
     VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
@@ -416,19 +507,7 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     const int C = ncoef(p), kp = coef_stride(C);
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
     const int64_t ncells = ((int64_t(1) << (3 * (level + 1))) - 1) / 7;
-    const int nblk = (ni + kRadixTile - 1) / kRadixTile;
-    VM_HIP(ctx->keys_a.reserve(sizeof(uint32_t) * n), "alloc keys");
-    VM_HIP(ctx->keys_b.reserve(sizeof(uint32_t) * n), "alloc keys");
-    VM_HIP(ctx->vals_a.reserve(sizeof(int32_t) * n), "alloc perm");
-    VM_HIP(ctx->vals_b.reserve(sizeof(int32_t) * n), "alloc perm");
-    // digit counts [256][nblk] followed by the scan's tile sums
-    VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * (size_t(nblk) * 256 + size_t(nblk) * 256 / 4096 + 256)),
-           "alloc histogram");
-    VM_HIP(ctx->start.reserve(sizeof(int32_t) * size_t(nleaf + 1)), "alloc leaf ranges");
-    if (mixed) VM_HIP(ctx->p32.reserve(sizeof(Part32) * n), "alloc particles");
-    else VM_HIP(ctx->p64.reserve(sizeof(Part64) * n), "alloc particles");
     VM_HIP(ctx->far.reserve(sizeof(double) * 12 * n), "alloc far field");
-    VM_HIP(ctx->flag.reserve(sizeof(int)), "alloc flag");
     VM_HIP(ctx->trpart.reserve(kTrPartBytes), "alloc split partials");
     if (ctx->zeros.bytes == 0) VM_HIP(ctx->zeros.reserve(tr_zero_elems(coef_stride(ncoef(VM_MAX_P))) * sizeof(double), true),
                                       "alloc zero cell");
@@ -445,42 +524,11 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
         ctx->layout_prec = mixed;
     }
 
-    TreeGeom g;
-    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
-    g.box_len = opts->box_len;
-    g.inv_len = 1.0 / opts->box_len;
-    g.inv_w = std::ldexp(g.inv_len, level);
-    g.w = std::ldexp(opts->box_len, -level);
-    g.level = level;
-    g.periodic = periodic;
-
     // --- tree ------------------------------------------------------------
+    TreeGeom g;
+    int32_t *vin = nullptr;
+    if (vm_status st = build_tree(ctx, ni, x, alpha, level, opts, g, vin); st != VM_OK) return st;
     int32_t *start = ctx->start.as<int32_t>();
-    if (opts->check_domain) VM_HIP(hipMemsetAsync(ctx->flag.ptr, 0, sizeof(int), s), "clear flag");
-    uint32_t *kin = ctx->keys_a.as<uint32_t>(), *kout = ctx->keys_b.as<uint32_t>();
-    int32_t *vin = ctx->vals_a.as<int32_t>(), *vout = ctx->vals_b.as<int32_t>();
-    {
-    Timed tm(ctx, VM_PH_TREE);
-    VM_HIP(launch_keys(s, ni, x, g, opts->check_domain, kin, vin, ctx->flag.as<int>()), "keys");
-    const int total_bits = 3 * level;
-    if (total_bits > 0) {
-        const int npass = (total_bits + 7) / 8;
-        const int bits = (total_bits + npass - 1) / npass;
-        for (int shift = 0; shift < total_bits; shift += bits) {
-            const int b = std::min(bits, total_bits - shift);
-            VM_HIP(launch_radix_pass(s, ni, shift, b, kin, vin, kout, vout, ctx->hist.as<uint32_t>()), "radix sort");
-            std::swap(kin, kout);
-            std::swap(vin, vout);
-        }
-    }
-    VM_HIP(launch_ranges(s, ni, int(nleaf), kin, start), "leaf ranges");
-    VM_HIP(launch_permute(s, ni, x, alpha, vin, kin, g, mixed ? nullptr : ctx->p64.as<Part64>(),
-                          mixed ? ctx->p32.as<Part32>() : nullptr), "permute");
-    }
-    ctx->last_keys = kin;
-    ctx->last_perm = vin;
-    ctx->last_n = n;
-    ctx->last_level = level;
     ctx->last_p = p;
     ctx->last_mixed = mixed;
     const void *parts = mixed ? (const void *)ctx->p32.ptr : (const void *)ctx->p64.ptr;
@@ -570,13 +618,7 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
         else VM_HIP(launch_p2p64(s, a, ctx->p64.as<Part64>()), "P2P");
     }
 
-    if (opts->check_domain) {
-        int flag = 0;
-        VM_HIP(hipMemcpyAsync(&flag, ctx->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s), "read flag");
-        VM_HIP(hipStreamSynchronize(s), "synchronize");
-        if (flag) return fail(ctx, VM_EDOMAIN, "non-finite or out-of-box position");
-    }
-    return VM_OK;
+    return check_flag(ctx, opts);
 }
 
 vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
@@ -749,6 +791,235 @@ vm_status vm_diagnostics(vm_ctx *ctx, int64_t n, const double *u, const double *
     return VM_OK;
 }
 
+vm_status vm_gauss_sum(vm_ctx *ctx, int64_t n, const double *x, const double *gamma, double sigma, int level,
+                       const vm_opts *opts, double *omega) {
+    if (!ctx) return VM_EINVAL;
+    if (vm_status st = check_common(ctx, n, sigma, level, opts); st != VM_OK) return st;
+    if (!x || !gamma || !omega) return fail(ctx, VM_EINVAL, "x, gamma and omega must be non-NULL");
+    if (misaligned(x) || misaligned(gamma) || misaligned(omega))
+        return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    const int ni = int(n), mixed = opts->precision == VM_MIXED;
+    VM_HIP(ctx->rbf_b.reserve(sizeof(double) * 3 * size_t(n)), "alloc gaussian sum");
+    TreeGeom g;
+    int32_t *perm = nullptr;
+    // the records carry gamma as their strengths
+    if (vm_status st = build_tree(ctx, ni, x, gamma, level, opts, g, perm); st != VM_OK) return st;
+    GaussArgs a;
+    a.n = ni;
+    a.nleaf = 1 << (3 * level);
+    a.level = level;
+    a.periodic = opts->periodic > 0;
+    a.w = g.w;
+    a.sigma = sigma;
+    a.start = ctx->start.as<int32_t>();
+    a.out = ctx->rbf_b.as<double>();
+    {
+        Timed tm(ctx, VM_PH_GAUSS);
+        VM_HIP(launch_gauss(s, a, mixed ? ctx->p32.ptr : ctx->p64.ptr, mixed), "gaussian sum");
+    }
+    {
+        Timed tm(ctx, VM_PH_KRYLOV);
+        VM_HIP(launch_scatter3(s, ni, perm, ctx->rbf_b.as<double>(), 1.0, omega), "scatter");
+    }
+    return check_flag(ctx, opts);
+}
+
+
+static_assert(VM_RBF_RESTART + 1 <= kRbfMaxVecs, "Krylov basis exceeds the multi-vector kernels");
+
+vm_status vm_rbf_solve(vm_ctx *ctx, int64_t n, const double *x, const double *omega, double sigma, double h3,
+                       int level, const vm_opts *opts, double tol, int max_iter, double *gamma, int *iters,
+                       double *resid) {
+    if (!ctx) return VM_EINVAL;
+    if (vm_status st = check_common(ctx, n, sigma, level, opts); st != VM_OK) return st;
+    if (!x || !omega || !gamma) return fail(ctx, VM_EINVAL, "x, omega and gamma must be non-NULL");
+    if (misaligned(x) || misaligned(omega) || misaligned(gamma))
+        return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    if (!(h3 > 0.0) || !std::isfinite(h3)) return fail(ctx, VM_EINVAL, "h3 must be positive");
+    if (!(tol >= 0.0) || !(tol < 1.0)) return fail(ctx, VM_EINVAL, "tol out of range [0, 1)");
+    if (max_iter < 0 || max_iter > VM_RBF_MAX_ITER) return fail(ctx, VM_EINVAL, "max_iter out of range");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    const int ni = int(n), mixed = opts->precision == VM_MIXED;
+    const int m = VM_RBF_RESTART;
+    const size_t vlen = 3 * size_t(n);
+    const int64_t ldv = int64_t(vlen);
+    VM_HIP(ctx->rbf_b.reserve(sizeof(double) * vlen), "alloc rbf");
+    VM_HIP(ctx->rbf_x.reserve(sizeof(double) * vlen), "alloc rbf");
+    VM_HIP(ctx->rbf_V.reserve(sizeof(double) * vlen * (m + 1)), "alloc rbf basis");
+    VM_HIP(ctx->rbf_part.reserve(sizeof(double) * 3 * kRbfMaxVecs * kRbfDotBlocks), "alloc rbf");
+    VM_HIP(ctx->rbf_dots.reserve(sizeof(double) * 3 * kRbfMaxVecs), "alloc rbf");
+    TreeGeom g;
+    int32_t *perm = nullptr;
+    // the records' strength fields are rewritten before every product
+    if (vm_status st = build_tree(ctx, ni, x, omega, level, opts, g, perm); st != VM_OK) return st;
+    if (vm_status st = check_flag(ctx, opts); st != VM_OK) return st;
+
+    void *parts = mixed ? ctx->p32.ptr : ctx->p64.ptr;
+    double *b = ctx->rbf_b.as<double>(), *xs = ctx->rbf_x.as<double>(), *V = ctx->rbf_V.as<double>();
+    auto vec = [&](int j) { return V + size_t(j) * vlen; };
+    GaussArgs ga;
+    ga.n = ni;
+    ga.nleaf = 1 << (3 * level);
+    ga.level = level;
+    ga.periodic = opts->periodic > 0;
+    ga.w = g.w;
+    ga.sigma = sigma;
+    ga.start = ctx->start.as<int32_t>();
+    auto matvec = [&](const double *v, double *out) -> vm_status {
+        Timed tm(ctx, VM_PH_GAUSS);
+        VM_HIP(launch_pack(s, ni, v, parts, mixed), "pack strengths");
+        ga.out = out;
+        VM_HIP(launch_gauss(s, ga, parts, mixed), "gaussian sum");
+        return VM_OK;
+    };
+    std::vector<double> dots(3 * kRbfMaxVecs);
+    // dots[3 j + c] = <w_c, v_{j,c}>, j < k (synchronises)
+    auto multidot = [&](const double *w, const double *Vb, int k) -> vm_status {
+        {
+            Timed tm(ctx, VM_PH_KRYLOV);
+            VM_HIP(launch_multidot(s, ni, w, Vb, ldv, k, ctx->rbf_part.as<double>(), ctx->rbf_dots.as<double>()),
+                   "dot products");
+        }
+        VM_HIP(hipMemcpyAsync(dots.data(), ctx->rbf_dots.ptr, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s),
+               "read dot products");
+        VM_HIP(hipStreamSynchronize(s), "synchronize");
+        return VM_OK;
+    };
+    auto axpy = [&](double *w, const double *Vb, int k, const RbfCoefs &cf) -> vm_status {
+        Timed tm(ctx, VM_PH_KRYLOV);
+        VM_HIP(launch_multiaxpy(s, ni, w, Vb, ldv, k, cf), "vector update");
+        return VM_OK;
+    };
+    RbfCoefs cf;
+    auto clear = [&]() { std::memset(&cf, 0, sizeof(cf)); };
+    vm_status st;
+
+    // right-hand side in sorted order; initial guess gamma_0 = h^3 omega
+    {
+        Timed tm(ctx, VM_PH_KRYLOV);
+        VM_HIP(launch_gather3(s, ni, perm, omega, b), "gather");
+        VM_HIP(hipMemcpyAsync(xs, b, sizeof(double) * vlen, hipMemcpyDeviceToDevice, s), "copy");
+    }
+    clear();
+    for (int c = 0; c < 3; ++c) cf.alpha[c] = h3;
+    if ((st = axpy(xs, V, 0, cf)) != VM_OK) return st;
+
+    // GMRES(m) on each component's system A gamma_c = omega_c, the three run
+    // in lockstep so that every product serves all of them
+    const int ld = m + 1;
+    std::vector<double> H[3], gv[3], cs[3], sn[3];
+    for (int c = 0; c < 3; ++c) {
+        H[c].assign(size_t(ld) * m, 0.0);
+        gv[c].assign(ld, 0.0);
+        cs[c].assign(m, 0.0);
+        sn[c].assign(m, 0.0);
+    }
+    double beta0[3] = {0, 0, 0}, rel[3] = {0, 0, 0};
+    bool done[3] = {false, false, false};
+    int total = 0;
+    for (int cycle = 0;; ++cycle) {
+        // r = omega - A gamma into v_0
+        if ((st = matvec(xs, vec(0))) != VM_OK) return st;
+        clear();
+        for (int c = 0; c < 3; ++c) {
+            cf.alpha[c] = -1.0;
+            cf.c[c] = 1.0;
+        }
+        if ((st = axpy(vec(0), b, 1, cf)) != VM_OK) return st;
+        if ((st = multidot(vec(0), vec(0), 1)) != VM_OK) return st;
+        double beta[3];
+        for (int c = 0; c < 3; ++c) {
+            beta[c] = std::sqrt(dots[c]);
+            if (cycle == 0) {
+                beta0[c] = beta[c];
+                done[c] = !(beta[c] > 0.0);
+            }
+            rel[c] = beta0[c] > 0.0 ? beta[c] / beta0[c] : 0.0;
+            if (rel[c] <= tol) done[c] = true;
+        }
+        if ((done[0] && done[1] && done[2]) || total >= max_iter) break;
+        bool active[3];
+        int cols[3] = {0, 0, 0};
+        clear();
+        for (int c = 0; c < 3; ++c) {
+            active[c] = !done[c];
+            cf.alpha[c] = active[c] ? 1.0 / beta[c] : 0.0;
+            std::fill(gv[c].begin(), gv[c].end(), 0.0);
+            gv[c][0] = beta[c];
+        }
+        if ((st = axpy(vec(0), V, 0, cf)) != VM_OK) return st;
+        for (int j = 0; j < m && total < max_iter && (active[0] || active[1] || active[2]); ++j) {
+            double *w = vec(j + 1);
+            if ((st = matvec(vec(j), w)) != VM_OK) return st;
+            ++total;
+            // classical Gram-Schmidt, twice
+            std::vector<double> h(3 * size_t(j + 1), 0.0);
+            for (int pass = 0; pass < 2; ++pass) {
+                if ((st = multidot(w, V, j + 1)) != VM_OK) return st;
+                clear();
+                for (int c = 0; c < 3; ++c) cf.alpha[c] = 1.0;
+                for (int i = 0; i <= j; ++i)
+                    for (int c = 0; c < 3; ++c)
+                        if (active[c]) {
+                            h[3 * i + c] += dots[3 * i + c];
+                            cf.c[3 * i + c] = -dots[3 * i + c];
+                        }
+                if ((st = axpy(w, V, j + 1, cf)) != VM_OK) return st;
+            }
+            if ((st = multidot(w, w, 1)) != VM_OK) return st;
+            clear();
+            for (int c = 0; c < 3; ++c) {
+                if (!active[c]) continue;
+                const double nrm = std::sqrt(dots[c]);
+                double *col = &H[c][size_t(j) * ld];
+                for (int i = 0; i <= j; ++i) col[i] = h[3 * i + c];
+                col[j + 1] = nrm;
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[c][i] * col[i] + sn[c][i] * col[i + 1];
+                    col[i + 1] = -sn[c][i] * col[i] + cs[c][i] * col[i + 1];
+                    col[i] = t;
+                }
+                const double r = std::hypot(col[j], col[j + 1]);
+                cs[c][j] = r > 0.0 ? col[j] / r : 1.0;
+                sn[c][j] = r > 0.0 ? col[j + 1] / r : 0.0;
+                col[j] = r;
+                col[j + 1] = 0.0;
+                gv[c][j + 1] = -sn[c][j] * gv[c][j];
+                gv[c][j] = cs[c][j] * gv[c][j];
+                cols[c] = j + 1;
+                rel[c] = std::fabs(gv[c][j + 1]) / beta0[c];
+                if (rel[c] <= tol) done[c] = true;
+                if (done[c] || !(nrm > 0.0)) active[c] = false;
+                cf.alpha[c] = active[c] ? 1.0 / nrm : 0.0;
+            }
+            if ((st = axpy(w, V, 0, cf)) != VM_OK) return st;
+        }
+        // gamma += V y for each component
+        clear();
+        int kmax = 0;
+        for (int c = 0; c < 3; ++c) {
+            cf.alpha[c] = 1.0;
+            if (cols[c] == 0) continue;
+            double y[VM_RBF_RESTART];
+            back_substitute(H[c], ld, gv[c], cols[c], y);
+            for (int i = 0; i < cols[c]; ++i) cf.c[3 * i + c] = y[i];
+            kmax = std::max(kmax, cols[c]);
+        }
+        if ((st = axpy(xs, V, kmax, cf)) != VM_OK) return st;
+        if ((done[0] && done[1] && done[2]) || total >= max_iter) break;
+    }
+    {
+        Timed tm(ctx, VM_PH_KRYLOV);
+        VM_HIP(launch_scatter3(s, ni, perm, xs, 1.0, gamma), "scatter");
+    }
+    if (iters) *iters = total;
+    if (resid) *resid = std::max(rel[0], std::max(rel[1], rel[2]));
+    return VM_OK;
+}
+
 vm_status vm_set_timing(vm_ctx *ctx, int enable) {
     if (!ctx) return VM_EINVAL;
     ctx->timing = enable != 0;
@@ -787,6 +1058,7 @@ vm_status vm_debug_tree(vm_ctx *ctx, uint32_t *keys, int32_t *perm, int32_t *lea
 
 vm_status vm_debug_expansions(vm_ctx *ctx, int which, int level, void *out, int64_t *bytes) {
     if (!ctx || !bytes || (which != 0 && which != 1)) return VM_EINVAL;
+    if (ctx->last_p < 1) return fail(ctx, VM_EINVAL, "no expansions in the last call");
     if (ctx->last_level < 0 || level < 0 || level > ctx->last_level)
         return fail(ctx, VM_EINVAL, "level not in the last evaluation");
     const int kp = coef_stride(ncoef(ctx->last_p));

@@ -77,3 +77,12 @@ def test_matrix_is_symmetric_positive_definite_and_local():
             d -= L * np.round(d / L)
         far = np.max(np.abs(d), axis=2) > 2 * L / 4
         assert np.all(A[far] == 0)
+
+
+def test_rows_at_targets_match_the_matrix():
+    x, g = W.random_particles(700, 9)
+    for periodic, level in ((0, 2), (1, 2), (1, 1)):
+        full = R.gauss_sum(x, g, 0.35, level=level, periodic=periodic)
+        t = np.array([0, 5, 133, 699])
+        rows = R.gauss_sum_at(x, g, 0.35, level, t, periodic=periodic)
+        assert np.allclose(rows, full[t], rtol=0, atol=1e-13 * np.abs(full).max())
