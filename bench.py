@@ -6,7 +6,10 @@ level 6, 27^3 periodic images), inputs resident in HBM: two full FMM
 evaluations of the regularised Biot-Savart velocity, its gradient and the
 stretching term (tree build, P2M, M2M, lattice, L2L/M2L, L2P, P2P, combine)
 and the update.  ``value`` counts evaluations per second (two per step).
-Prints one JSON line (see the design doc for the field definitions).
+Prints one JSON line: the headline fields, the roofline of the dominant
+kernel (M2L or P2P) and of the others, the FP64 comparison, the adjoint and
+the RBF reinitialisation of the initial lattice, and the CPU oracle's rate
+on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
 """
@@ -31,8 +34,10 @@ PEAKS = {  # MI355X published peaks
     "valu_f32_tflops": 157.3,
     "valu_f64_tflops": 78.6,
 }
-# Algorithmic work per unit (derived in the design doc):
-P2P_FLOP_PER_PAIR = {"mixed": 86.0, "fp64": 69.0}   # counted from the pair kernels, FMA = 2
+# Algorithmic work per unit, FMA = 2 flop:
+P2P_FLOP_PER_PAIR = {"mixed": 86.0, "fp64": 69.0}   # counted from the pair kernels
+# Gaussian sum: r = t - s (3), |r|^2 (5), scale (1), exp2 (1), three strength FMAs (6)
+GAUSS_FLOP_PER_PAIR = 16.0
 
 
 def log(*a):
@@ -189,6 +194,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-rbf", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one 1 GiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -390,6 +396,43 @@ def main():
         result["adjoint"] = {"gradients_per_s": 1.0 / ta, "ms": 1e3 * ta, "precision": args.precision,
                              "what": "dL/dx and dL/dalpha of L = h^3/2 sum |u|^2 (forward recomputed)"}
         log(f"[bench] adjoint {1e3 * ta:.1f} ms per gradient")
+
+    if not args.no_rbf:
+        # RBF reinitialisation of the initial lattice: strengths that reproduce
+        # omega = alpha / h^3 at the particles, GMRES from h^3 omega at the
+        # default tolerance 1e-3 (relative residual drop)
+        om = a0 / h3
+        gam = torch.empty_like(a0)
+        rkw = dict(periodic=w.periodic, box_len=w.box_len, precision=args.precision, out=gam)
+        ctx.rbf_solve(x0, om, w.sigma, h3, w.level, tol=1e-3, max_iter=100, **rkw)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, iters, resid = ctx.rbf_solve(x0, om, w.sigma, h3, w.level, tol=1e-3, max_iter=100, **rkw)
+        torch.cuda.synchronize()
+        tr = (time.perf_counter() - t0) / reps
+        ph = ctx.timing()
+        ctx.set_timing(False)
+        gauss_ms = ph["gauss"][0] / ph["gauss"][1]
+        products = ph["gauss"][1] / reps
+        gauss_kernel = "k_gauss<float,Part32>" if f32 else "k_gauss<double,Part64>"
+        roof_gauss = {"bound": "alu", "kernel": gauss_kernel + " (with the strength packing)",
+                      "achieved": GAUSS_FLOP_PER_PAIR * pairs / (gauss_ms * 1e-3) / 1e12,
+                      "peak": PEAKS["valu_f32_tflops" if f32 else "valu_f64_tflops"], "unit": "TFLOP/s",
+                      "traffic": None}
+        roof_gauss["frac"] = roof_gauss["achieved"] / roof_gauss["peak"]
+        result["rbf"] = {"ms": 1e3 * tr, "iterations": iters, "products": products, "resid": resid,
+                         "tol": 1e-3, "precision": args.precision, "gauss_ms_per_product": gauss_ms,
+                         "gauss_gpairs_per_s": pairs / (gauss_ms * 1e-3) / 1e9,
+                         "krylov_ms": ph["krylov"][0] / reps, "tree_ms": ph["tree"][0] / reps,
+                         "vs_rk2_step": 1e3 * tr / ms_per_step, "roofline": roof_gauss,
+                         "what": "gamma with A gamma = omega on the initial lattice (neighbour-list Gaussian "
+                                 "sums, GMRES(20) from h^3 omega)"}
+        log(f"[bench] rbf solve {1e3 * tr:.1f} ms, {iters} iterations ({products:.0f} products, "
+            f"{gauss_ms:.2f} ms each), resid {resid:.2e}; {1e3 * tr / ms_per_step:.2f} RK2 steps")
+        del om, gam
 
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

@@ -37,6 +37,21 @@ __device__ __forceinline__ int gauss_leaf(int nleaf) {
     return (b & 7) * (nleaf >> 3) + (b >> 3);
 }
 
+// One source against the lane's target: scaled coordinates, c = sqrt(log2(e)
+// / (2 sigma^2)), so that exp(-r^2 / (2 sigma^2)) = 2^-(|c r|^2) and c r =
+// c t - c s takes one FMA per axis.
+template <typename T, typename P>
+__device__ __forceinline__ void gauss_pair(const P &src, T ctx_, T cty, T ctz, T mc, T part[3]) {
+    const T rx = fma(T(src.dx), mc, ctx_), ry = fma(T(src.dy), mc, cty), rz = fma(T(src.dz), mc, ctz);
+    const T q = rx * rx + ry * ry + rz * rz;
+    T e;
+    if constexpr (sizeof(T) == 4) e = __builtin_amdgcn_exp2f(-q);
+    else e = exp2(-q);
+    part[0] = fma(T(src.ax), e, part[0]);
+    part[1] = fma(T(src.ay), e, part[1]);
+    part[2] = fma(T(src.az), e, part[2]);
+}
+
 // T: arithmetic of the pair (double: FP64 form; float: mixed form, FP32
 // differences, exponential and per-source-leaf sums, added into FP64 sums).
 template <typename T, typename P>
@@ -47,15 +62,15 @@ __global__ void __launch_bounds__(64) k_gauss(GaussArgs a, const P *__restrict__
     const int side = 1 << a.level;
     const int cx = leaf_coord(leaf, 0, a.level), cy = leaf_coord(leaf, 1, a.level), cz = leaf_coord(leaf, 2, a.level);
     const size_t n = size_t(a.n);
-    const T w = T(a.w);
-    // exp(-r^2 / (2 sigma^2)) = 2^(r^2 ke)
-    const T ke = T(-0.5 * 1.4426950408889634074 / (a.sigma * a.sigma));
+    const double c64 = sqrt(0.5 * 1.4426950408889634074) / a.sigma;
+    const T c = T(c64), mc = -c, cw = T(c64 * a.w);
     const double s2pi = 2.0 * 3.14159265358979323846 * a.sigma * a.sigma;
     const double norm = 1.0 / (s2pi * sqrt(s2pi));
     for (int base = 0; base < cnt; base += 64) {
         const int i = base + lane;
         const bool valid = i < cnt;
         const P me = parts[s0 + (valid ? i : 0)];
+        const T mx = T(me.dx) * c, my = T(me.dy) * c, mz = T(me.dz) * c;
         double acc[3] = {0.0, 0.0, 0.0};
         for (int nb = 0; nb < 27; ++nb) {
             const int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
@@ -68,30 +83,25 @@ __global__ void __launch_bounds__(64) k_gauss(GaussArgs a, const P *__restrict__
                 continue;
             }
             const int nk = leaf_key(nx, ny, nz, a.level);
-            const int js = a.start[nk], je = a.start[nk + 1];
-            if (js >= je) continue;
-            // x_i - x_j = (delta_i - d w) - delta_j, d = source - target cell offset
-            const T tx = T(me.dx) - T(dx) * w, ty = T(me.dy) - T(dy) * w, tz = T(me.dz) - T(dz) * w;
+            const int js = a.start[nk], m = a.start[nk + 1] - js;
+            if (m <= 0) continue;
+            // c (x_i - x_j) = c (delta_i - d w) - c delta_j, d = source - target cell offset
+            const T tx = mx - T(dx) * cw, ty = my - T(dy) * cw, tz = mz - T(dz) * cw;
             T part[3] = {T(0), T(0), T(0)};
-            // the next record is fetched (scalar load) while the current one is evaluated
-            P cur = parts[js];
-#pragma unroll 2
-            for (int j = js; j < je; ++j) {
-                const P nxt = parts[j + 1 < je ? j + 1 : j];
-                const T rx = tx - T(cur.dx), ry = ty - T(cur.dy), rz = tz - T(cur.dz);
-                const T r2 = rx * rx + ry * ry + rz * rz;
-                T e;
-                if constexpr (sizeof(T) == 4) e = __builtin_amdgcn_exp2f(r2 * ke);
-                else e = exp2(r2 * ke);
-                part[0] = fma(T(cur.ax), e, part[0]);
-                part[1] = fma(T(cur.ay), e, part[1]);
-                part[2] = fma(T(cur.az), e, part[2]);
-                cur = nxt;
+            const P *src = parts + js;
+            const P *const end4 = src + (m & ~3), *const end = src + m;
+            for (; src != end4; src += 4) {
+                const P s0_ = src[0], s1_ = src[1], s2_ = src[2], s3_ = src[3];
+                gauss_pair(s0_, tx, ty, tz, mc, part);
+                gauss_pair(s1_, tx, ty, tz, mc, part);
+                gauss_pair(s2_, tx, ty, tz, mc, part);
+                gauss_pair(s3_, tx, ty, tz, mc, part);
             }
-            for (int c = 0; c < 3; ++c) acc[c] += double(part[c]);
+            for (; src != end; ++src) gauss_pair(src[0], tx, ty, tz, mc, part);
+            for (int q = 0; q < 3; ++q) acc[q] += double(part[q]);
         }
         if (valid)
-            for (int c = 0; c < 3; ++c) a.out[c * n + s0 + i] = norm * acc[c];
+            for (int q = 0; q < 3; ++q) a.out[q * n + s0 + i] = norm * acc[q];
     }
 }
 

@@ -13,7 +13,8 @@ durations of the translation and near-field kernels.
 command (``FETCH_SIZE``, then ``WRITE_SIZE``), calibrates both counters against
 the largest device-to-device copy in the run (a copy of known size; bench.py
 makes a 1 GiB one with ``--copy-calibration``) and prints, as one JSON object,
-the HBM bytes per launch of the M2L and P2P kernels, together with a SHA-256
+the HBM bytes per launch of the tree, expansion, M2L, P2P and Gaussian-sum
+kernels, together with a SHA-256
 of the library's kernel sources, so that a reader can tell whether the
 figures still describe the code.
 """
@@ -33,10 +34,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CALIBRATION_BYTES = 1 << 30
 
 
-# the sources the measured kernels (tree, expansions, translations, near field)
-# and their launch configurations are built from
+# the sources the measured kernels (tree, expansions, translations, near field,
+# Gaussian sums) and their launch configurations are built from
 MEASURED_SOURCES = ("kernels.h", "device_harmonics.h", "kernels_tree.hip", "kernels_fmm.hip", "kernels_p2p.hip",
-                    "operators.h", "operators.cpp")
+                    "kernels_rbf.hip", "operators.h", "operators.cpp")
 
 
 def sources_sha256() -> str:
@@ -76,7 +77,7 @@ def trace_summary(d: str, command: str | None) -> str:
     shapes = collections.defaultdict(list)
     for r in trace:
         n = short_name(r["Kernel_Name"])
-        if n.startswith(("k_m2l_os", "k_translate", "k_p2p", "k_split_reduce")):
+        if n.startswith(("k_m2l_os", "k_translate", "k_p2p", "k_split_reduce", "k_gauss")):
             key = (n, int(r["Grid_Size_X"]), int(r.get("Grid_Size_Y", 1) or 1))
             shapes[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
     out.append("")
@@ -115,7 +116,8 @@ def traffic_summary(fetch_dir: str, write_dir: str, workload: str, command: str 
     kernels = {}
     for name in sorted(set(fetch) | set(write)):
         if not name.startswith(("k_m2l_os", "k_translate", "k_p2p", "k_split_reduce", "k_permute",
-                                "k_radix", "k_keys", "k_iota", "k_scan", "k_ranges", "k_p2m", "k_l2p")):
+                                "k_radix", "k_keys", "k_iota", "k_scan", "k_ranges", "k_p2m", "k_l2p",
+                                "k_gauss", "k_pack", "k_multidot", "k_multiaxpy", "k_gather3", "k_scatter3")):
             continue
         fv, wv = fetch.get(name, []), write.get(name, [])
         if not fv or not wv:
