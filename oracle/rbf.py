@@ -100,19 +100,50 @@ def rbf_solve(x, omega, sigma, level, box_len=2 * math.pi, periodic=0):
     return np.linalg.solve(A, np.asarray(omega, np.float64))
 
 
-def gauss_sum_at(x, gamma, sigma, level, targets, box_len=2 * math.pi, periodic=0):
-    """Rows `targets` of A gamma (len(targets), 3), one target at a time: the
-    same neighbour-list sum, for inputs too large for the dense matrix."""
+def gauss_eval(y, x, gamma, sigma, level, box_len=2 * math.pi, periodic=0):
+    """The vorticity the particles (x, gamma) carry, at points y (m, 3): for a
+    point in leaf c, the sources in the 27 leaves c + d as in the matrix (the
+    smoothing-function equation at arbitrary points, neighbour list only)."""
     x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
     gamma = np.asarray(gamma, np.float64)
     if periodic:
         x = T.wrap(x, (0.0, 0.0, 0.0), box_len)
+        y = T.wrap(y, (0.0, 0.0, 0.0), box_len)
     side = 1 << level
-    c, order, bounds = _leaves(x, level, box_len)
-    out = np.zeros((len(targets), 3))
-    for row, i in enumerate(targets):
-        for k, n in _slots(tuple(int(v) for v in c[i]), side, periodic):
+    _, order, bounds = _leaves(x, level, box_len)
+    cy = T.leaf_coords(y, (0.0, 0.0, 0.0), box_len, level)
+    out = np.zeros((len(y), 3))
+    for i in range(len(y)):
+        for k, n in _slots(tuple(int(v) for v in cy[i]), side, periodic):
             src = order[bounds[k]:bounds[k + 1]]
-            r = x[i][None, :] - (x[src] + n * box_len)
-            out[row] = out[row] + zeta(np.sum(r * r, axis=1), sigma) @ gamma[src]
+            r = y[i][None, :] - (x[src] + n * box_len)
+            out[i] = out[i] + zeta(np.sum(r * r, axis=1), sigma) @ gamma[src]
     return out
+
+
+def gauss_sum_at(x, gamma, sigma, level, targets, box_len=2 * math.pi, periodic=0):
+    """Rows `targets` of A gamma (len(targets), 3): the same neighbour-list
+    sum evaluated at the chosen particles, for inputs too large for the
+    dense matrix."""
+    return gauss_eval(np.asarray(x, np.float64)[np.asarray(targets)], x, gamma, sigma, level, box_len, periodic)
+
+
+def lattice_sites(ng, box_len=2 * math.pi):
+    """Cell centres (i + 1/2) h of the ng^3 lattice on the box, h = box_len / ng,
+    site (ix ng + iy) ng + iz (x index slowest)."""
+    h = box_len / ng
+    i = np.arange(ng ** 3)
+    ix, iy, iz = i // (ng * ng), (i // ng) % ng, i % ng
+    return (np.stack([ix, iy, iz], axis=1) + 0.5) * h
+
+
+def reinit(x, gamma, sigma, ng, sigma0, level, box_len=2 * math.pi, periodic=0):
+    """Reinitialisation onto the lattice (the reinitialisation paragraph of
+    Sec. 2.2): the vorticity the particles carry with core sigma, taken at the
+    ng^3 lattice sites, becomes the right-hand side of the interpolation with
+    the smaller core sigma0 on the lattice.  Returns (sites, new strengths,
+    vorticity at the sites)."""
+    y = lattice_sites(ng, box_len)
+    om = gauss_eval(y, x, gamma, sigma, level, box_len, periodic)
+    return y, rbf_solve(y, om, sigma0, level, box_len, periodic), om

@@ -86,3 +86,30 @@ def test_rows_at_targets_match_the_matrix():
         t = np.array([0, 5, 133, 699])
         rows = R.gauss_sum_at(x, g, 0.35, level, t, periodic=periodic)
         assert np.allclose(rows, full[t], rtol=0, atol=1e-13 * np.abs(full).max())
+
+
+def test_smoothed_mode_at_points_off_the_lattice():
+    """Poisson summation at any point y: sum_j omega(x_j) h^3 zeta(y - x_j) =
+    omega(y) exp(-sigma^2 k^2 / 2) up to the same alias bound."""
+    k = np.array([1.0, 0.0, -1.0])
+    x, om, h = _mode(16, k)
+    sigma = h
+    rng = np.random.default_rng(3)
+    y = rng.uniform(0, L, size=(40, 3))
+    got = R.gauss_eval(y, x, om * h ** 3, sigma, level=1, periodic=1)
+    phase = y @ k
+    want = np.stack([np.cos(phase), np.sin(phase), np.cos(phase + 0.3)], axis=1) * math.exp(-0.5 * sigma * sigma * (k @ k))
+    assert np.abs(got - want).max() < 2 * _alias_bound(h, k)
+
+
+def test_lattice_sites_and_reinit_of_a_lattice_is_the_identity():
+    y = R.lattice_sites(4, L)
+    assert np.array_equal(y[1], np.array([0.5, 0.5, 1.5]) * L / 4)
+    assert np.array_equal(y[4 * 4], np.array([1.5, 0.5, 0.5]) * L / 4)
+    x = R.lattice_sites(8, L)
+    h = L / 8
+    g = np.random.default_rng(4).standard_normal((512, 3)) * h ** 3
+    y, g2, om = R.reinit(x, g, h, 8, h, level=1, periodic=1)
+    assert np.array_equal(y, x)
+    assert np.allclose(om, R.gauss_sum(x, g, h, 1, periodic=1), rtol=0, atol=1e-14 * np.abs(om).max())
+    assert np.abs(g2 - g).max() < 1e-9 * np.abs(g).max()
