@@ -165,6 +165,22 @@ vm_status vm_gauss_sum(vm_ctx *ctx, int64_t n, const double *x, const double *ga
                        const vm_opts *opts, double *omega);
 
 /*
+ * The same neighbour-list Gaussian sum at m points y distinct from the
+ * particles (the smoothing-function equation evaluated anywhere):
+ *   omega(y_i) = sum_j gamma_j zeta_sigma(y_i - x_j - n L),
+ * j over the particles in the 27 leaves adjacent to y_i's leaf.  The points
+ * get a tree of their own at the same level (periodic: wrapped like the
+ * particles; free space: clamped into the edge leaves, reported by
+ * check_domain).
+ *   x, gamma   device [3][n]: particles and strengths
+ *   y          device [3][m]: the points, 1 <= m < 2^31
+ *   omega      device [3][m] out, in y's order
+ * Precision forms, errors and workspace as vm_gauss_sum.
+ */
+vm_status vm_gauss_eval(vm_ctx *ctx, int64_t n, const double *x, const double *gamma, int64_t m, const double *y,
+                        double sigma, int level, const vm_opts *opts, double *omega);
+
+/*
  * RBF interpolation (Sec. 2.2, the reinitialisation paragraph; initial guess
  * and tolerance as in Sec. 5's solver-tolerance study, default tolerance 1e-3
  * in Sec. 4.1): the strengths gamma that reproduce a given vorticity at the
@@ -193,6 +209,60 @@ vm_status vm_gauss_sum(vm_ctx *ctx, int64_t n, const double *x, const double *ga
 vm_status vm_rbf_solve(vm_ctx *ctx, int64_t n, const double *x, const double *omega, double sigma, double h3,
                        int level, const vm_opts *opts, double tol, int max_iter, double *gamma, int *iters,
                        double *resid);
+
+/*
+ * Reinitialisation onto the lattice (Sec. 2.2: core spreading grows sigma,
+ * and the particles are moved back to a regular lattice with smaller
+ * Gaussians by RBF interpolation; Sec. 5 studies how often):
+ *   1. the sites y_k = box_lo + (i + 1/2) h of the ng^3 lattice, h = box_len/ng,
+ *      k = (i_x ng + i_y) ng + i_z (x index slowest);
+ *   2. omega_k = vm_gauss_eval of the particles (x, alpha) with core sigma at y;
+ *   3. alpha <- vm_rbf_solve(y, omega, sigma0, h^3, tol, max_iter);
+ *   4. x <- y.
+ * n must equal ng^3 (one particle per site).  x and alpha (device [3][n]) are
+ * replaced in place; iters and resid as vm_rbf_solve (may be NULL).  Errors
+ * as vm_rbf_solve, plus VM_EINVAL when n != ng^3 or sigma0 <= 0.
+ */
+vm_status vm_reinit(vm_ctx *ctx, int64_t n, double *x, double *alpha, double sigma, int ng, double sigma0,
+                    int level, const vm_opts *opts, double tol, int max_iter, int *iters, double *resid);
+
+/*
+ * The vortex method's time loop (Sec. 2.2: convection eq. 7, stretching
+ * eq. 8 and core-spreading diffusion d sigma^2/dt = 2 nu update positions,
+ * strengths and core simultaneously; reinitialisation every few steps).
+ * Each step from (x, alpha, sigma) with the rates of vm_fmm_eval:
+ *   VM_EULER (the paper's integrator): x += dt u, alpha += dt dalpha/dt;
+ *   VM_HEUN: the trapezoid of the rates at the start (core sigma) and at the
+ *            Euler prediction (core sigma'), as vm_rk2_step;
+ * then sigma' = sqrt(sigma^2 + 2 nu dt), periodic positions wrapped, and after
+ * every reinit_every-th step vm_reinit onto the ng^3 lattice with the core
+ * the loop started with (sigma <- that core).
+ */
+typedef enum { VM_EULER = 0, VM_HEUN = 1 } vm_integrator;
+typedef struct {
+    int integrator;    /* vm_integrator */
+    double dt;         /* time step, >= 0 */
+    double nu;         /* kinematic viscosity, >= 0 */
+    int steps;         /* steps to take, >= 0 */
+    int reinit_every;  /* 0: never; k > 0: after every k-th step */
+    int ng;            /* lattice of the reinitialisation (n = ng^3) */
+    double tol;        /* GMRES tolerance of the reinitialisation (as vm_rbf_solve) */
+    int max_iter;      /* GMRES products per reinitialisation */
+} vm_loop;
+/*
+ *   x, alpha   device [3][n], advanced in place
+ *   sigma      host in/out: the core at the start (also the reinitialisation
+ *              core), the core at the end
+ *   p, level, opts as vm_fmm_eval (opts->scheme is the stretching form)
+ *   diag       device [steps][3] out or NULL: E, Omega, Omega_p (vm_diagnostics,
+ *              particle volume box_len^3 / n) of the state each step starts from
+ *   products, resid  host out or NULL: GMRES products summed over the
+ *              reinitialisations, the largest relative residual they ended with
+ * Stream-ordered; each reinitialisation synchronises (GMRES reads its dot
+ * products back).  Workspace as vm_rk2_step and vm_reinit.
+ */
+vm_status vm_run(vm_ctx *ctx, int64_t n, double *x, double *alpha, double *sigma, int p, int level,
+                 const vm_opts *opts, const vm_loop *loop, double *diag, int *products, double *resid);
 
 /*
  * Device-time accounting (HIP events on the context's stream around every

@@ -22,6 +22,7 @@ from . import _lib
 
 PRECISIONS = {"fp64": 0, "mixed": 1}
 SCHEMES = {"classic": 0, "transpose": 1}
+INTEGRATORS = {"euler": 0, "heun": 1}
 
 
 def _soa(t, torch):
@@ -177,6 +178,70 @@ class FMM:
                                            ctypes.c_void_p(gamma.data_ptr()), float(sigma), int(level),
                                            ctypes.byref(opts), ctypes.c_void_p(om.data_ptr())))
         return om
+
+    def gauss_eval(self, x, gamma, y, sigma, level, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi,
+                   precision="fp64", stream=None, out=None):
+        """Gaussian sum of the particles (x, gamma) at the points y, (3, m) float64."""
+        torch = self._torch
+        x = _soa(x, torch)
+        gamma = _soa(gamma, torch)
+        y = _soa(y, torch)
+        n, m = x.shape[1], y.shape[1]
+        if gamma.shape[1] != n:
+            raise ValueError("x and gamma differ in length")
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        om = torch.empty((3, m), dtype=torch.float64, device=x.device) if out is None else out
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", False)
+        self._check(self._lib.vm_gauss_eval(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(gamma.data_ptr()), m, ctypes.c_void_p(y.data_ptr()),
+                                            float(sigma), int(level), ctypes.byref(opts),
+                                            ctypes.c_void_p(om.data_ptr())))
+        return om
+
+    def reinit(self, x, alpha, sigma, ng, sigma0, level, tol=1e-3, max_iter=100, periodic=0,
+               box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, precision="fp64", stream=None):
+        """Reinitialisation onto the ng^3 lattice, in place on x and alpha ((3, n)
+        contiguous float64 CUDA tensors); returns (iters, resid) of the solve."""
+        torch = self._torch
+        self._inplace(x, alpha)
+        n = x.shape[1]
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", False)
+        iters = ctypes.c_int(0)
+        resid = ctypes.c_double(0.0)
+        self._check(self._lib.vm_reinit(self._h, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(alpha.data_ptr()),
+                                        float(sigma), int(ng), float(sigma0), int(level), ctypes.byref(opts),
+                                        float(tol), int(max_iter), ctypes.byref(iters), ctypes.byref(resid)))
+        return iters.value, resid.value
+
+    def run(self, x, alpha, sigma, p, level, dt, steps, nu=0.0, integrator="euler", reinit_every=0, ng=0,
+            tol=1e-3, max_iter=100, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, precision="fp64",
+            scheme="classic", want_diag=False, stream=None):
+        """The time loop, in place on x and alpha.  Returns (sigma at the end,
+        diagnostics (steps, 3) CUDA tensor or None, GMRES products, largest
+        relative residual of the reinitialisations)."""
+        torch = self._torch
+        self._inplace(x, alpha)
+        n = x.shape[1]
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        opts = self._opts(periodic, box_lo, box_len, precision, scheme, False)
+        loop = _lib.VmLoop(INTEGRATORS[integrator], float(dt), float(nu), int(steps), int(reinit_every), int(ng),
+                           float(tol), int(max_iter))
+        diag = torch.empty((max(steps, 1), 3), dtype=torch.float64, device=x.device) if want_diag else None
+        sg = ctypes.c_double(float(sigma))
+        prods = ctypes.c_int(0)
+        resid = ctypes.c_double(0.0)
+        self._check(self._lib.vm_run(self._h, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(alpha.data_ptr()),
+                                     ctypes.byref(sg), int(p), int(level), ctypes.byref(opts), ctypes.byref(loop),
+                                     ctypes.c_void_p(diag.data_ptr() if diag is not None else 0),
+                                     ctypes.byref(prods), ctypes.byref(resid)))
+        return sg.value, (diag[:steps] if diag is not None else None), prods.value, resid.value
+
+    def _inplace(self, x, alpha):
+        torch = self._torch
+        for t in (x, alpha):
+            if t.dim() != 2 or t.shape[0] != 3 or not t.is_contiguous() or t.dtype != torch.float64 or not t.is_cuda:
+                raise ValueError("x and alpha are updated in place: (3, n) contiguous float64 CUDA tensors")
 
     def rbf_solve(self, x, omega, sigma, h3, level, tol=1e-3, max_iter=100, periodic=0, box_lo=(0.0, 0.0, 0.0),
                   box_len=2 * math.pi, precision="fp64", stream=None, out=None):

@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "VM_OK", -1: "VM_EINVAL", -2: "VM_ENOMEM", -3: "VM_EDEVICE", 
 
 # every symbol include/vmfmm.h declares
 EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_eval",
-           "vm_fmm_adjoint", "vm_rk2_step", "vm_diagnostics", "vm_gauss_sum", "vm_rbf_solve",
+           "vm_fmm_adjoint", "vm_rk2_step", "vm_diagnostics", "vm_gauss_sum", "vm_gauss_eval", "vm_rbf_solve",
+           "vm_reinit", "vm_run",
            "vm_set_timing", "vm_get_timing", "vm_debug_tree", "vm_debug_expansions", "vm_debug_far", "vm_debug_offsets", "vm_debug_list",
            "vm_debug_operator")
 
@@ -27,6 +28,12 @@ class VmOpts(ctypes.Structure):
     _fields_ = [("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double),
                 ("periodic", ctypes.c_int), ("precision", ctypes.c_int), ("scheme", ctypes.c_int),
                 ("check_domain", ctypes.c_int)]
+
+
+class VmLoop(ctypes.Structure):
+    _fields_ = [("integrator", ctypes.c_int), ("dt", ctypes.c_double), ("nu", ctypes.c_double),
+                ("steps", ctypes.c_int), ("reinit_every", ctypes.c_int), ("ng", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
 
 
 class VmError(RuntimeError):
@@ -67,6 +74,17 @@ def load():
     lib.vm_diagnostics.restype = ctypes.c_int
     lib.vm_gauss_sum.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(VmOpts), dp]
     lib.vm_gauss_sum.restype = ctypes.c_int
+    lib.vm_gauss_eval.argtypes = [vp, i64, dp, dp, i64, dp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(VmOpts),
+                                  dp]
+    lib.vm_gauss_eval.restype = ctypes.c_int
+    lib.vm_reinit.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                              ctypes.POINTER(VmOpts), ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_double)]
+    lib.vm_reinit.restype = ctypes.c_int
+    lib.vm_run.argtypes = [vp, i64, dp, dp, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int,
+                           ctypes.POINTER(VmOpts), ctypes.POINTER(VmLoop), dp, ctypes.POINTER(ctypes.c_int),
+                           ctypes.POINTER(ctypes.c_double)]
+    lib.vm_run.restype = ctypes.c_int
     lib.vm_rbf_solve.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                  ctypes.POINTER(VmOpts), ctypes.c_double, ctypes.c_int, dp,
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]

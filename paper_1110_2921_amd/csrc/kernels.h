@@ -89,16 +89,20 @@ hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts);
 
 // --- RBF interpolation (kernels_rbf.hip) --------------------------------------------
 struct GaussArgs {
-    int n, nleaf, level, periodic;
+    int n, nleaf, level, periodic;   // n: number of targets
     double w, sigma;
-    const int32_t *start;
-    double *out;   // sorted order [3][n]
+    const int32_t *start;            // source leaf ranges
+    const int32_t *tstart;           // target leaf ranges (the source ranges for sums at the particles)
+    const void *tparts;              // target records (positions), same record type as the sources
+    double *out;                     // target sorted order [3][n]
 };
-// Gaussian sums of the strengths held in the records' a-fields
+// Gaussian sums at the targets of the strengths held in the source records' a-fields
 hipError_t launch_gauss(hipStream_t s, const GaussArgs &a, const void *parts, int mixed);
 // records' a-fields <- gamma (sorted order [3][n])
 hipError_t launch_pack(hipStream_t s, int n, const double *gamma, void *parts, int mixed);
 hipError_t launch_gather3(hipStream_t s, int n, const int32_t *perm, const double *src, double *dst);
+// cell centres of the ng^3 lattice, site (ix ng + iy) ng + iz, [3][ng^3]
+hipError_t launch_lattice_sites(hipStream_t s, int ng, const double lo[3], double h, double *out);
 hipError_t launch_scatter3(hipStream_t s, int n, const int32_t *perm, const double *src, double scale, double *dst);
 
 constexpr int kRbfDotBlocks = 512;

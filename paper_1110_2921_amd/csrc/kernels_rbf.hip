@@ -57,8 +57,9 @@ __device__ __forceinline__ void gauss_pair(const P &src, T ctx_, T cty, T ctz, T
 template <typename T, typename P>
 __global__ void __launch_bounds__(64) k_gauss(GaussArgs a, const P *__restrict__ parts) {
     const int leaf = gauss_leaf(a.nleaf), lane = threadIdx.x;
-    const int s0 = a.start[leaf], cnt = a.start[leaf + 1] - s0;
+    const int s0 = a.tstart[leaf], cnt = a.tstart[leaf + 1] - s0;
     if (cnt == 0) return;
+    const P *__restrict__ targets = static_cast<const P *>(a.tparts);
     const int side = 1 << a.level;
     const int cx = leaf_coord(leaf, 0, a.level), cy = leaf_coord(leaf, 1, a.level), cz = leaf_coord(leaf, 2, a.level);
     const size_t n = size_t(a.n);
@@ -69,7 +70,7 @@ __global__ void __launch_bounds__(64) k_gauss(GaussArgs a, const P *__restrict__
     for (int base = 0; base < cnt; base += 64) {
         const int i = base + lane;
         const bool valid = i < cnt;
-        const P me = parts[s0 + (valid ? i : 0)];
+        const P me = targets[s0 + (valid ? i : 0)];
         const T mx = T(me.dx) * c, my = T(me.dy) * c, mz = T(me.dz) * c;
         double acc[3] = {0.0, 0.0, 0.0};
         for (int nb = 0; nb < 27; ++nb) {
@@ -196,6 +197,20 @@ __global__ void __launch_bounds__(256) k_multiaxpy(int n, double *__restrict__ w
     }
 }
 
+// Cell centres of the ng^3 lattice on the box: site k = (ix ng + iy) ng + iz
+// at lo + (i + 1/2) h, written as [3][ng^3].
+__global__ void __launch_bounds__(256) k_lattice_sites(int ng, double lo0, double lo1, double lo2, double h,
+                                                       double *__restrict__ out) {
+    const int n = ng * ng * ng;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const int ix = k / (ng * ng), iy = (k / ng) % ng, iz = k % ng;
+    const size_t m = size_t(n);
+    out[k] = lo0 + (double(ix) + 0.5) * h;
+    out[m + k] = lo1 + (double(iy) + 0.5) * h;
+    out[2 * m + k] = lo2 + (double(iz) + 0.5) * h;
+}
+
 unsigned blocks256(int n) { return unsigned((n + 255) / 256); }
 
 }  // namespace
@@ -213,6 +228,12 @@ hipError_t launch_pack(hipStream_t s, int n, const double *gamma, void *parts, i
         hipLaunchKernelGGL((k_pack<Part32, float>), dim3(blocks256(n)), dim3(256), 0, s, n, gamma, (Part32 *)parts);
     else
         hipLaunchKernelGGL((k_pack<Part64, double>), dim3(blocks256(n)), dim3(256), 0, s, n, gamma, (Part64 *)parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_sites(hipStream_t s, int ng, const double lo[3], double h, double *out) {
+    const int n = ng * ng * ng;
+    hipLaunchKernelGGL(k_lattice_sites, dim3(blocks256(n)), dim3(256), 0, s, ng, lo[0], lo[1], lo[2], h, out);
     return hipGetLastError();
 }
 

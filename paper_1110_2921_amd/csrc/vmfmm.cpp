@@ -103,6 +103,9 @@ struct vm_ctx {
     DevBuf rk_u, rk_s, rk_x, rk_a, diag;
     DevBuf adj_u, adj_J, adj_v, adj_Jv, adj_far, adj_p64, adj_p32;
     DevBuf rbf_b, rbf_x, rbf_V, rbf_part, rbf_dots;   // RBF solve: right side, iterate, Krylov basis, reductions
+    // second tree over a distinct target set (Gaussian sums at other points)
+    DevBuf t_keys_a, t_keys_b, t_vals_a, t_vals_b, t_start, t_p64, t_p32;
+    DevBuf rin_y, rin_w, run_J;   // reinitialisation: lattice sites, vorticity there; loop: gradient
     std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice_t;
     int layout_p = -1, layout_prec = -1;   // layout of mbuf/lbuf
     // results of the last evaluation, for the debug views
@@ -362,29 +365,58 @@ vm_status check_common(vm_ctx *ctx, int64_t n, double sigma, int level, const vm
     return VM_OK;
 }
 
+// The buffers one tree lives in: the particle (source) tree, or a second
+// tree over a distinct set of target points.
+struct TreeBufs {
+    DevBuf *keys_a, *keys_b, *vals_a, *vals_b, *start, *p64, *p32;
+};
+TreeBufs source_bufs(vm_ctx *c) {
+    return {&c->keys_a, &c->keys_b, &c->vals_a, &c->vals_b, &c->start, &c->p64, &c->p32};
+}
+TreeBufs target_bufs(vm_ctx *c) {
+    return {&c->t_keys_a, &c->t_keys_b, &c->t_vals_a, &c->t_vals_b, &c->t_start, &c->t_p64, &c->t_p32};
+}
+
+// With check_domain: clears the flag the key kernels raise.
+vm_status clear_flag(vm_ctx *ctx, const vm_opts *opts) {
+    VM_HIP(ctx->flag.reserve(sizeof(int)), "alloc flag");
+    if (opts->check_domain) VM_HIP(hipMemsetAsync(ctx->flag.ptr, 0, sizeof(int), ctx->stream), "clear flag");
+    return VM_OK;
+}
+
+// With check_domain: reads the flag the key kernel raised (synchronises).
+vm_status check_flag(vm_ctx *ctx, const vm_opts *opts) {
+    if (!opts->check_domain) return VM_OK;
+    int flag = 0;
+    VM_HIP(hipMemcpyAsync(&flag, ctx->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "read flag");
+    VM_HIP(hipStreamSynchronize(ctx->stream), "synchronize");
+    if (flag) return fail(ctx, VM_EDOMAIN, "non-finite or out-of-box position");
+    return VM_OK;
+}
+
 // Tree of the particles (Sec. 3.1): Morton keys, stable LSD radix sort, leaf
 // ranges and the sorted particle records (positions relative to their leaf
-// centres, `alpha` in the strength fields), in the precision of opts.  On
-// return `perm` holds the caller index of each sorted particle; the keys,
-// permutation and ranges are kept for the debug views.
-vm_status build_tree(vm_ctx *ctx, int ni, const double *x, const double *alpha, int level, const vm_opts *opts,
-                     TreeGeom &g, int32_t *&perm) {
+// centres, `alpha` in the strength fields), in the precision of opts, in the
+// buffers `b`.  On return `perm` holds the caller index of each sorted
+// particle, `parts` the records.  The particle tree (`record`) is kept for
+// the debug views.  clear_flag must have run first.
+vm_status build_tree(vm_ctx *ctx, const TreeBufs &b, int ni, const double *x, const double *alpha, int level,
+                     const vm_opts *opts, TreeGeom &g, int32_t *&perm, void *&parts, bool record) {
     hipStream_t s = ctx->stream;
     const int mixed = opts->precision == VM_MIXED;
     const int64_t nleaf = int64_t(1) << (3 * level);
     const size_t n = size_t(ni);
     const int nblk = (ni + kRadixTile - 1) / kRadixTile;
-    VM_HIP(ctx->keys_a.reserve(sizeof(uint32_t) * n), "alloc keys");
-    VM_HIP(ctx->keys_b.reserve(sizeof(uint32_t) * n), "alloc keys");
-    VM_HIP(ctx->vals_a.reserve(sizeof(int32_t) * n), "alloc perm");
-    VM_HIP(ctx->vals_b.reserve(sizeof(int32_t) * n), "alloc perm");
+    VM_HIP(b.keys_a->reserve(sizeof(uint32_t) * n), "alloc keys");
+    VM_HIP(b.keys_b->reserve(sizeof(uint32_t) * n), "alloc keys");
+    VM_HIP(b.vals_a->reserve(sizeof(int32_t) * n), "alloc perm");
+    VM_HIP(b.vals_b->reserve(sizeof(int32_t) * n), "alloc perm");
     // digit counts [256][nblk] followed by the scan's tile sums
     VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * (size_t(nblk) * 256 + size_t(nblk) * 256 / 4096 + 256)),
            "alloc histogram");
-    VM_HIP(ctx->start.reserve(sizeof(int32_t) * size_t(nleaf + 1)), "alloc leaf ranges");
-    if (mixed) VM_HIP(ctx->p32.reserve(sizeof(Part32) * n), "alloc particles");
-    else VM_HIP(ctx->p64.reserve(sizeof(Part64) * n), "alloc particles");
-    VM_HIP(ctx->flag.reserve(sizeof(int)), "alloc flag");
+    VM_HIP(b.start->reserve(sizeof(int32_t) * size_t(nleaf + 1)), "alloc leaf ranges");
+    if (mixed) VM_HIP(b.p32->reserve(sizeof(Part32) * n), "alloc particles");
+    else VM_HIP(b.p64->reserve(sizeof(Part64) * n), "alloc particles");
 
     for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
     g.box_len = opts->box_len;
@@ -394,10 +426,9 @@ vm_status build_tree(vm_ctx *ctx, int ni, const double *x, const double *alpha, 
     g.level = level;
     g.periodic = opts->periodic > 0;
 
-    int32_t *start = ctx->start.as<int32_t>();
-    if (opts->check_domain) VM_HIP(hipMemsetAsync(ctx->flag.ptr, 0, sizeof(int), s), "clear flag");
-    uint32_t *kin = ctx->keys_a.as<uint32_t>(), *kout = ctx->keys_b.as<uint32_t>();
-    int32_t *vin = ctx->vals_a.as<int32_t>(), *vout = ctx->vals_b.as<int32_t>();
+    int32_t *start = b.start->as<int32_t>();
+    uint32_t *kin = b.keys_a->as<uint32_t>(), *kout = b.keys_b->as<uint32_t>();
+    int32_t *vin = b.vals_a->as<int32_t>(), *vout = b.vals_b->as<int32_t>();
     Timed tm(ctx, VM_PH_TREE);
     VM_HIP(launch_keys(s, ni, x, g, opts->check_domain, kin, vin, ctx->flag.as<int>()), "keys");
     const int total_bits = 3 * level;
@@ -405,22 +436,165 @@ vm_status build_tree(vm_ctx *ctx, int ni, const double *x, const double *alpha, 
         const int npass = (total_bits + 7) / 8;
         const int bits = (total_bits + npass - 1) / npass;
         for (int shift = 0; shift < total_bits; shift += bits) {
-            const int b = std::min(bits, total_bits - shift);
-            VM_HIP(launch_radix_pass(s, ni, shift, b, kin, vin, kout, vout, ctx->hist.as<uint32_t>()), "radix sort");
+            const int nb = std::min(bits, total_bits - shift);
+            VM_HIP(launch_radix_pass(s, ni, shift, nb, kin, vin, kout, vout, ctx->hist.as<uint32_t>()), "radix sort");
             std::swap(kin, kout);
             std::swap(vin, vout);
         }
     }
     VM_HIP(launch_ranges(s, ni, int(nleaf), kin, start), "leaf ranges");
-    VM_HIP(launch_permute(s, ni, x, alpha, vin, kin, g, mixed ? nullptr : ctx->p64.as<Part64>(),
-                          mixed ? ctx->p32.as<Part32>() : nullptr), "permute");
-    ctx->last_keys = kin;
-    ctx->last_perm = vin;
-    ctx->last_n = int64_t(ni);
-    ctx->last_level = level;
-    ctx->last_p = -1;
-    ctx->last_far = 0;
+    VM_HIP(launch_permute(s, ni, x, alpha, vin, kin, g, mixed ? nullptr : b.p64->as<Part64>(),
+                          mixed ? b.p32->as<Part32>() : nullptr), "permute");
+    if (record) {
+        ctx->last_keys = kin;
+        ctx->last_perm = vin;
+        ctx->last_n = int64_t(ni);
+        ctx->last_level = level;
+        ctx->last_p = -1;
+        ctx->last_far = 0;
+    }
     perm = vin;
+    parts = mixed ? b.p32->ptr : b.p64->ptr;
+    return VM_OK;
+}
+
+// Gaussian sums of the particles (x, gamma) at the m points y (y == nullptr:
+// at the particles themselves), into omega [3][m] in y's order.  The
+// particle tree is kept for the debug views; y gets a tree of its own.
+vm_status gauss_impl(vm_ctx *ctx, int ni, const double *x, const double *gamma, int mi, const double *y,
+                     double sigma, int level, const vm_opts *opts, double *omega) {
+    hipStream_t s = ctx->stream;
+    const int mixed = opts->precision == VM_MIXED;
+    VM_HIP(ctx->rbf_b.reserve(sizeof(double) * 3 * size_t(mi)), "alloc gaussian sum");
+    if (vm_status st = clear_flag(ctx, opts); st != VM_OK) return st;
+    TreeGeom g;
+    int32_t *perm = nullptr;
+    void *parts = nullptr;
+    // the records carry gamma as their strengths
+    if (vm_status st = build_tree(ctx, source_bufs(ctx), ni, x, gamma, level, opts, g, perm, parts, true);
+        st != VM_OK)
+        return st;
+    GaussArgs a;
+    a.start = ctx->start.as<int32_t>();
+    a.tstart = a.start;
+    a.tparts = parts;
+    int32_t *tperm = perm;
+    if (y) {
+        TreeGeom gt;
+        void *tp = nullptr;
+        if (vm_status st = build_tree(ctx, target_bufs(ctx), mi, y, y, level, opts, gt, tperm, tp, false);
+            st != VM_OK)
+            return st;
+        a.tstart = ctx->t_start.as<int32_t>();
+        a.tparts = tp;
+    }
+    a.n = mi;
+    a.nleaf = 1 << (3 * level);
+    a.level = level;
+    a.periodic = opts->periodic > 0;
+    a.w = g.w;
+    a.sigma = sigma;
+    a.out = ctx->rbf_b.as<double>();
+    {
+        Timed tm(ctx, VM_PH_GAUSS);
+        VM_HIP(launch_gauss(s, a, parts, mixed), "gaussian sum");
+    }
+    Timed tm(ctx, VM_PH_KRYLOV);
+    VM_HIP(launch_scatter3(s, mi, tperm, ctx->rbf_b.as<double>(), 1.0, omega), "scatter");
+    return VM_OK;
+}
+
+// One Heun step of eqs. 7-8 with the core sigma1 at the start and sigma2 at
+// the Euler prediction (sigma1 = sigma2 without diffusion).  u0, grad0: the
+// initial state's velocity and gradient (may be NULL); diag (device [3] or
+// NULL): E, Omega, Omega_p of the initial state for particle volume h3.
+vm_status heun_impl(vm_ctx *ctx, int64_t n, double *x, double *alpha, double sigma1, double sigma2, int p,
+                    int level, const vm_opts *opts, double dt, double *u0, double *grad0, double *diag, double h3) {
+    const size_t bytes = sizeof(double) * 3 * size_t(n);
+    VM_HIP(ctx->rk_u.reserve(bytes), "alloc rk");
+    VM_HIP(ctx->rk_s.reserve(bytes), "alloc rk");
+    VM_HIP(ctx->rk_x.reserve(bytes), "alloc rk");
+    VM_HIP(ctx->rk_a.reserve(bytes), "alloc rk");
+    double *u = u0 ? u0 : ctx->rk_u.as<double>();
+    double *sv = ctx->rk_s.as<double>();
+    double *J = grad0;
+    if (diag && !J) {
+        VM_HIP(ctx->run_J.reserve(sizeof(double) * 9 * size_t(n)), "alloc gradient");
+        J = ctx->run_J.as<double>();
+    }
+    vm_status st = vm_fmm_eval(ctx, n, x, alpha, sigma1, p, level, opts, u, sv, J);
+    if (st != VM_OK) return st;
+    const int ni = int(n);
+    if (diag) {
+        VM_HIP(ctx->diag.reserve(sizeof(double) * 3 * 1024), "alloc diagnostics");
+        VM_HIP(launch_diagnostics(ctx->stream, ni, u, J, alpha, h3, ctx->diag.as<double>(), diag), "diagnostics");
+    }
+    VM_HIP(launch_rk_stage1(ctx->stream, ni, x, alpha, u, sv, dt, ctx->rk_x.as<double>(), ctx->rk_a.as<double>()),
+           "rk stage 1");
+    u = ctx->rk_u.as<double>();
+    st = vm_fmm_eval(ctx, n, ctx->rk_x.as<double>(), ctx->rk_a.as<double>(), sigma2, p, level, opts, u, sv, nullptr);
+    if (st != VM_OK) return st;
+    TreeGeom g;
+    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
+    g.box_len = opts->box_len;
+    g.inv_len = 1.0 / opts->box_len;
+    g.inv_w = 0.0;
+    g.w = 0.0;
+    g.level = level;
+    g.periodic = opts->periodic > 0;
+    VM_HIP(launch_rk_stage2(ctx->stream, ni, x, alpha, u, sv, dt, g), "rk stage 2");
+    return VM_OK;
+}
+
+// One forward Euler step (the paper's integrator): x + dt u, alpha + dt
+// dalpha/dt, positions wrapped when periodic.  diag as for heun_impl.
+vm_status euler_impl(vm_ctx *ctx, int64_t n, double *x, double *alpha, double sigma, int p, int level,
+                     const vm_opts *opts, double dt, double *diag, double h3) {
+    const size_t bytes = sizeof(double) * 3 * size_t(n);
+    VM_HIP(ctx->rk_u.reserve(bytes), "alloc rk");
+    VM_HIP(ctx->rk_s.reserve(bytes), "alloc rk");
+    double *u = ctx->rk_u.as<double>(), *sv = ctx->rk_s.as<double>(), *J = nullptr;
+    if (diag) {
+        VM_HIP(ctx->run_J.reserve(sizeof(double) * 9 * size_t(n)), "alloc gradient");
+        J = ctx->run_J.as<double>();
+    }
+    vm_status st = vm_fmm_eval(ctx, n, x, alpha, sigma, p, level, opts, u, sv, J);
+    if (st != VM_OK) return st;
+    const int ni = int(n);
+    if (diag) {
+        VM_HIP(ctx->diag.reserve(sizeof(double) * 3 * 1024), "alloc diagnostics");
+        VM_HIP(launch_diagnostics(ctx->stream, ni, u, J, alpha, h3, ctx->diag.as<double>(), diag), "diagnostics");
+    }
+    TreeGeom g;
+    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
+    g.box_len = opts->box_len;
+    g.inv_len = 1.0 / opts->box_len;
+    g.inv_w = 0.0;
+    g.w = 0.0;
+    g.level = level;
+    g.periodic = opts->periodic > 0;
+    // the second Heun stage with twice the step is x + dt u, alpha + dt s
+    VM_HIP(launch_rk_stage2(ctx->stream, ni, x, alpha, u, sv, 2.0 * dt, g), "euler update");
+    return VM_OK;
+}
+
+// Reinitialisation onto the ng^3 lattice: the vorticity the particles carry
+// with core sigma at the lattice sites, interpolated with core sigma0 there
+// (GMRES from h^3 omega); x <- sites, alpha <- the new strengths.
+vm_status reinit_impl(vm_ctx *ctx, int64_t n, double *x, double *alpha, double sigma, int ng, double sigma0,
+                      int level, const vm_opts *opts, double tol, int max_iter, int *iters, double *resid) {
+    const size_t bytes = sizeof(double) * 3 * size_t(n);
+    VM_HIP(ctx->rin_y.reserve(bytes), "alloc reinitialisation");
+    VM_HIP(ctx->rin_w.reserve(bytes), "alloc reinitialisation");
+    const double h = opts->box_len / ng;
+    double *y = ctx->rin_y.as<double>(), *w = ctx->rin_w.as<double>();
+    VM_HIP(launch_lattice_sites(ctx->stream, ng, opts->box_lo, h, y), "lattice sites");
+    if (vm_status st = gauss_impl(ctx, int(n), x, alpha, int(n), y, sigma, level, opts, w); st != VM_OK) return st;
+    if (vm_status st = check_flag(ctx, opts); st != VM_OK) return st;
+    if (vm_status st = vm_rbf_solve(ctx, n, y, w, sigma0, h * h * h, level, opts, tol, max_iter, alpha, iters, resid);
+        st != VM_OK)
+        return st;
+    VM_HIP(hipMemcpyAsync(x, y, bytes, hipMemcpyDeviceToDevice, ctx->stream), "copy sites");
     return VM_OK;
 }
 
@@ -435,15 +609,6 @@ void back_substitute(const std::vector<double> &R, int ld, const std::vector<dou
     }
 }
 
-// With check_domain: reads the flag the key kernel raised (synchronises).
-vm_status check_flag(vm_ctx *ctx, const vm_opts *opts) {
-    if (!opts->check_domain) return VM_OK;
-    int flag = 0;
-    VM_HIP(hipMemcpyAsync(&flag, ctx->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream), "read flag");
-    VM_HIP(hipStreamSynchronize(ctx->stream), "synchronize");
-    if (flag) return fail(ctx, VM_EDOMAIN, "non-finite or out-of-box position");
-    return VM_OK;
-}
 
 }  // namespace
 
@@ -527,11 +692,14 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     // --- tree ------------------------------------------------------------
     TreeGeom g;
     int32_t *vin = nullptr;
-    if (vm_status st = build_tree(ctx, ni, x, alpha, level, opts, g, vin); st != VM_OK) return st;
+    void *pv = nullptr;
+    if (vm_status st = clear_flag(ctx, opts); st != VM_OK) return st;
+    if (vm_status st = build_tree(ctx, source_bufs(ctx), ni, x, alpha, level, opts, g, vin, pv, true); st != VM_OK)
+        return st;
     int32_t *start = ctx->start.as<int32_t>();
     ctx->last_p = p;
     ctx->last_mixed = mixed;
-    const void *parts = mixed ? (const void *)ctx->p32.ptr : (const void *)ctx->p64.ptr;
+    const void *parts = pv;
 
     // --- far field --------------------------------------------------------
     const int lmin = periodic ? 0 : 2;
@@ -752,30 +920,67 @@ vm_status vm_rk2_step(vm_ctx *ctx, int64_t n, double *x, double *alpha, double s
     if (!std::isfinite(dt)) return fail(ctx, VM_EINVAL, "dt must be finite");
     if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
     VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    const size_t bytes = sizeof(double) * 3 * size_t(n);
-    VM_HIP(ctx->rk_u.reserve(bytes), "alloc rk");
-    VM_HIP(ctx->rk_s.reserve(bytes), "alloc rk");
-    VM_HIP(ctx->rk_x.reserve(bytes), "alloc rk");
-    VM_HIP(ctx->rk_a.reserve(bytes), "alloc rk");
-    double *u = u0 ? u0 : ctx->rk_u.as<double>();
-    double *sv = ctx->rk_s.as<double>();
-    vm_status st = vm_fmm_eval(ctx, n, x, alpha, sigma, p, level, opts, u, sv, grad0);
-    if (st != VM_OK) return st;
-    const int ni = int(n);
-    VM_HIP(launch_rk_stage1(ctx->stream, ni, x, alpha, u, sv, dt, ctx->rk_x.as<double>(), ctx->rk_a.as<double>()),
-           "rk stage 1");
-    u = ctx->rk_u.as<double>();
-    st = vm_fmm_eval(ctx, n, ctx->rk_x.as<double>(), ctx->rk_a.as<double>(), sigma, p, level, opts, u, sv, nullptr);
-    if (st != VM_OK) return st;
-    TreeGeom g;
-    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
-    g.box_len = opts->box_len;
-    g.inv_len = 1.0 / opts->box_len;
-    g.inv_w = 0.0;
-    g.w = 0.0;
-    g.level = level;
-    g.periodic = opts->periodic > 0;
-    VM_HIP(launch_rk_stage2(ctx->stream, ni, x, alpha, u, sv, dt, g), "rk stage 2");
+    return heun_impl(ctx, n, x, alpha, sigma, sigma, p, level, opts, dt, u0, grad0, nullptr, 0.0);
+}
+
+vm_status vm_reinit(vm_ctx *ctx, int64_t n, double *x, double *alpha, double sigma, int ng, double sigma0,
+                    int level, const vm_opts *opts, double tol, int max_iter, int *iters, double *resid) {
+    if (!ctx) return VM_EINVAL;
+    if (vm_status st = check_common(ctx, n, sigma, level, opts); st != VM_OK) return st;
+    if (!x || !alpha) return fail(ctx, VM_EINVAL, "x and alpha must be non-NULL");
+    if (misaligned(x) || misaligned(alpha)) return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    if (!(sigma0 > 0.0) || !std::isfinite(sigma0)) return fail(ctx, VM_EINVAL, "sigma0 must be positive");
+    if (ng < 1 || int64_t(ng) * ng * ng != n) return fail(ctx, VM_EINVAL, "n must equal ng^3");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    return reinit_impl(ctx, n, x, alpha, sigma, ng, sigma0, level, opts, tol, max_iter, iters, resid);
+}
+
+vm_status vm_run(vm_ctx *ctx, int64_t n, double *x, double *alpha, double *sigma, int p, int level,
+                 const vm_opts *opts, const vm_loop *lp, double *diag, int *products, double *resid) {
+    if (!ctx) return VM_EINVAL;
+    if (!lp || !sigma) return fail(ctx, VM_EINVAL, "loop and sigma must be non-NULL");
+    if (vm_status st = check_common(ctx, n, *sigma, level, opts); st != VM_OK) return st;
+    if (!x || !alpha) return fail(ctx, VM_EINVAL, "x and alpha must be non-NULL");
+    if (misaligned(x) || misaligned(alpha) || misaligned(diag))
+        return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    if (p < 1 || p > VM_MAX_P) return fail(ctx, VM_EINVAL, "p out of range [1, VM_MAX_P = 18]");
+    if (opts->scheme != VM_CLASSIC && opts->scheme != VM_TRANSPOSE) return fail(ctx, VM_EINVAL, "unknown scheme");
+    if (lp->integrator != VM_EULER && lp->integrator != VM_HEUN) return fail(ctx, VM_EINVAL, "unknown integrator");
+    if (!std::isfinite(lp->dt) || !(lp->dt >= 0.0)) return fail(ctx, VM_EINVAL, "dt must be finite and >= 0");
+    if (!std::isfinite(lp->nu) || !(lp->nu >= 0.0)) return fail(ctx, VM_EINVAL, "nu must be finite and >= 0");
+    if (lp->steps < 0 || lp->reinit_every < 0) return fail(ctx, VM_EINVAL, "steps and reinit_every must be >= 0");
+    if (lp->reinit_every > 0) {
+        if (lp->ng < 1 || int64_t(lp->ng) * lp->ng * lp->ng != n) return fail(ctx, VM_EINVAL, "n must equal ng^3");
+        if (!(lp->tol >= 0.0) || !(lp->tol < 1.0)) return fail(ctx, VM_EINVAL, "tol out of range [0, 1)");
+        if (lp->max_iter < 0 || lp->max_iter > VM_RBF_MAX_ITER) return fail(ctx, VM_EINVAL, "max_iter out of range");
+    }
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    const double sigma0 = *sigma;
+    const double h3 = opts->box_len * opts->box_len * opts->box_len / double(n);
+    double sg = sigma0, worst = 0.0;
+    int total = 0;
+    for (int step = 0; step < lp->steps; ++step) {
+        // core spreading: d sigma^2 / dt = 2 nu, advanced with the step
+        const double sg_next = std::sqrt(sg * sg + 2.0 * lp->nu * lp->dt);
+        double *d = diag ? diag + 3 * size_t(step) : nullptr;
+        vm_status st = lp->integrator == VM_EULER
+                           ? euler_impl(ctx, n, x, alpha, sg, p, level, opts, lp->dt, d, h3)
+                           : heun_impl(ctx, n, x, alpha, sg, sg_next, p, level, opts, lp->dt, nullptr, nullptr, d, h3);
+        if (st != VM_OK) return st;
+        sg = sg_next;
+        if (lp->reinit_every > 0 && (step + 1) % lp->reinit_every == 0) {
+            int it = 0;
+            double r = 0.0;
+            st = reinit_impl(ctx, n, x, alpha, sg, lp->ng, sigma0, level, opts, lp->tol, lp->max_iter, &it, &r);
+            if (st != VM_OK) return st;
+            total += it;
+            worst = std::max(worst, r);
+            sg = sigma0;
+        }
+    }
+    *sigma = sg;
+    if (products) *products = total;
+    if (resid) *resid = worst;
     return VM_OK;
 }
 
@@ -799,33 +1004,24 @@ vm_status vm_gauss_sum(vm_ctx *ctx, int64_t n, const double *x, const double *ga
     if (misaligned(x) || misaligned(gamma) || misaligned(omega))
         return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
     VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    hipStream_t s = ctx->stream;
-    const int ni = int(n), mixed = opts->precision == VM_MIXED;
-    VM_HIP(ctx->rbf_b.reserve(sizeof(double) * 3 * size_t(n)), "alloc gaussian sum");
-    TreeGeom g;
-    int32_t *perm = nullptr;
-    // the records carry gamma as their strengths
-    if (vm_status st = build_tree(ctx, ni, x, gamma, level, opts, g, perm); st != VM_OK) return st;
-    GaussArgs a;
-    a.n = ni;
-    a.nleaf = 1 << (3 * level);
-    a.level = level;
-    a.periodic = opts->periodic > 0;
-    a.w = g.w;
-    a.sigma = sigma;
-    a.start = ctx->start.as<int32_t>();
-    a.out = ctx->rbf_b.as<double>();
-    {
-        Timed tm(ctx, VM_PH_GAUSS);
-        VM_HIP(launch_gauss(s, a, mixed ? ctx->p32.ptr : ctx->p64.ptr, mixed), "gaussian sum");
-    }
-    {
-        Timed tm(ctx, VM_PH_KRYLOV);
-        VM_HIP(launch_scatter3(s, ni, perm, ctx->rbf_b.as<double>(), 1.0, omega), "scatter");
-    }
+    if (vm_status st = gauss_impl(ctx, int(n), x, gamma, int(n), nullptr, sigma, level, opts, omega); st != VM_OK)
+        return st;
     return check_flag(ctx, opts);
 }
 
+vm_status vm_gauss_eval(vm_ctx *ctx, int64_t n, const double *x, const double *gamma, int64_t m, const double *y,
+                        double sigma, int level, const vm_opts *opts, double *omega) {
+    if (!ctx) return VM_EINVAL;
+    if (vm_status st = check_common(ctx, n, sigma, level, opts); st != VM_OK) return st;
+    if (m < 1 || m >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "m out of range [1, 2^31)");
+    if (!x || !gamma || !y || !omega) return fail(ctx, VM_EINVAL, "x, gamma, y and omega must be non-NULL");
+    if (misaligned(x) || misaligned(gamma) || misaligned(y) || misaligned(omega))
+        return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if (vm_status st = gauss_impl(ctx, int(n), x, gamma, int(m), y, sigma, level, opts, omega); st != VM_OK)
+        return st;
+    return check_flag(ctx, opts);
+}
 
 static_assert(VM_RBF_RESTART + 1 <= kRbfMaxVecs, "Krylov basis exceeds the multi-vector kernels");
 
@@ -853,11 +1049,14 @@ vm_status vm_rbf_solve(vm_ctx *ctx, int64_t n, const double *x, const double *om
     VM_HIP(ctx->rbf_dots.reserve(sizeof(double) * 3 * kRbfMaxVecs), "alloc rbf");
     TreeGeom g;
     int32_t *perm = nullptr;
+    void *parts = nullptr;
     // the records' strength fields are rewritten before every product
-    if (vm_status st = build_tree(ctx, ni, x, omega, level, opts, g, perm); st != VM_OK) return st;
+    if (vm_status st = clear_flag(ctx, opts); st != VM_OK) return st;
+    if (vm_status st = build_tree(ctx, source_bufs(ctx), ni, x, omega, level, opts, g, perm, parts, true);
+        st != VM_OK)
+        return st;
     if (vm_status st = check_flag(ctx, opts); st != VM_OK) return st;
 
-    void *parts = mixed ? ctx->p32.ptr : ctx->p64.ptr;
     double *b = ctx->rbf_b.as<double>(), *xs = ctx->rbf_x.as<double>(), *V = ctx->rbf_V.as<double>();
     auto vec = [&](int j) { return V + size_t(j) * vlen; };
     GaussArgs ga;
@@ -868,6 +1067,8 @@ vm_status vm_rbf_solve(vm_ctx *ctx, int64_t n, const double *x, const double *om
     ga.w = g.w;
     ga.sigma = sigma;
     ga.start = ctx->start.as<int32_t>();
+    ga.tstart = ga.start;
+    ga.tparts = parts;
     auto matvec = [&](const double *v, double *out) -> vm_status {
         Timed tm(ctx, VM_PH_GAUSS);
         VM_HIP(launch_pack(s, ni, v, parts, mixed), "pack strengths");
