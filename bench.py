@@ -7,9 +7,10 @@ evaluations of the regularised Biot-Savart velocity, its gradient and the
 stretching term (tree build, P2M, M2M, lattice, L2L/M2L, L2P, P2P, combine)
 and the update.  ``value`` counts evaluations per second (two per step).
 Prints one JSON line: the headline fields, the roofline of the dominant
-kernel (M2L or P2P) and of the others, the FP64 comparison, the adjoint and
-the RBF reinitialisation of the initial lattice, and the CPU oracle's rate
-on a bounded sample.
+kernel (M2L or P2P) and of the others, the FP64 comparison, the adjoint, the
+RBF interpolation of the initial lattice, the paper's time loop (Euler, core
+spreading, reinitialisation every 10 steps) and the CPU oracle's rate on a
+bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--precision mixed|fp64]
 """
@@ -195,6 +196,8 @@ def main():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-rbf", action="store_true")
+    ap.add_argument("--loop-steps", type=int, default=10,
+                    help="steps of the paper's time loop to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one 1 GiB device-to-device copy (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -433,6 +436,33 @@ def main():
         log(f"[bench] rbf solve {1e3 * tr:.1f} ms, {iters} iterations ({products:.0f} products, "
             f"{gauss_ms:.2f} ms each), resid {resid:.2e}; {1e3 * tr / ms_per_step:.2f} RK2 steps")
         del om, gam
+
+    if args.loop_steps > 0:
+        # the paper's loop from the initial state: forward Euler, dt = 0.005, core
+        # spreading with nu = lambda / Re_lambda (Re_lambda = 50, u' = 1, lambda = 2/k0
+        # for this spectrum), reinitialisation every 10 steps at tolerance 1e-3
+        nu = 2.0 / w.k0 / 50.0
+        x.copy_(x0)
+        a.copy_(a0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sg, diag, prods, resid = ctx.run(x, a, w.sigma, w.p, w.level, dt, args.loop_steps, nu=nu,
+                                         integrator="euler", reinit_every=10, ng=w.ng, tol=1e-3, max_iter=100,
+                                         periodic=w.periodic, box_len=w.box_len, precision=args.precision,
+                                         want_diag=True)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        dg = diag.cpu().numpy()
+        result["time_loop"] = {"steps": args.loop_steps, "ms_per_step": 1e3 * tl / args.loop_steps,
+                               "integrator": "euler", "dt": dt, "nu": nu, "reinit_every": 10, "tol": 1e-3,
+                               "gmres_products": prods, "gmres_resid": resid, "sigma_end": sg,
+                               "energy_drift": float((dg[-1, 0] - dg[0, 0]) / dg[0, 0]),
+                               "what": "Euler steps with core spreading and lattice reinitialisation (RBF), "
+                                       "diagnostics every step, from the initial state"}
+        log(f"[bench] time loop: {args.loop_steps} Euler steps with reinitialisation every 10: "
+            f"{1e3 * tl / args.loop_steps:.1f} ms/step ({prods} GMRES products)")
+        x.copy_(x0)
+        a.copy_(a0)
 
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
