@@ -97,6 +97,23 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
                       double *u, double *dalpha_dt, double *grad);
 
 /*
+ * The velocity and its gradient that the particles induce at m points y
+ * other than the particles (e.g. a lattice for spectra): the same model as
+ * vm_fmm_eval -- each point belongs to the leaf its position falls in
+ * (periodic: wrapped; free space: clamped into the edge leaf, reported by
+ * check_domain), the far field from that leaf's local expansion, the exact
+ * regularised sum over its 27 adjacent leaves -- with a second tree over the
+ * points.
+ *   x, alpha   device [3][n]: particles and strengths
+ *   y          device [3][m]: the points, 1 <= m < 2^31
+ *   u          device [3][m] out;  grad  device [9][m] out or NULL
+ * Precision forms and errors as vm_fmm_eval (no stretching: the points carry
+ * no strength).
+ */
+vm_status vm_fmm_eval_at(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, int64_t m, const double *y,
+                         double sigma, int p, int level, const vm_opts *opts, double *u, double *grad);
+
+/*
  * Discrete adjoint of vm_fmm_eval's velocity (the transposed FMM): for a
  * cotangent u_bar of u it returns
  *   alpha_bar = (du/dalpha)^T u_bar,   x_bar = (du/dx)^T u_bar

@@ -183,19 +183,33 @@ def fmm_at(x, alpha, sigma, p, level, targets, box_lo=(0.0, 0.0, 0.0), box_len=2
     workloads one sampled particle at a time.
     """
     x = np.asarray(x, np.float64)
+    return fmm_points(x, alpha, sigma, p, level, x[np.asarray(targets, np.int64)], box_lo, box_len, periodic,
+                      chunk)
+
+
+def fmm_points(x, alpha, sigma, p, level, y, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, periodic=0,
+               chunk=1 << 18):
+    """u and J that the particles (x, alpha) induce at the points y (m, 3).
+
+    The same model as at the particles: each point belongs to the leaf its
+    position falls in (periodic: after the wrap, free space: clamped like a
+    particle); the local expansion of that leaf gives the far field and the
+    exact regularised sum over the 27 adjacent leaves the near field.
+    """
+    x = np.asarray(x, np.float64)
     alpha = np.asarray(alpha, np.float64)
-    targets = np.asarray(targets, np.int64)
     lo = np.asarray(box_lo, np.float64)
     tr = T.build(x, lo, box_len, level, periodic)
     xw, perm, start, count, keys = tr["xw"], tr["perm"], tr["start"], tr["count"], tr["keys"]
+    yw = T.wrap(y, lo, box_len) if periodic else np.asarray(y, np.float64)
     nleaf = 1 << (3 * level)
     C = H.ncoef(p)
     lmin = 0 if periodic else 2
     far = level >= lmin
-    nt = len(targets)
+    nt = len(yw)
     u = np.zeros((nt, 3))
     J = np.zeros((nt, 3, 3))
-    tleaf = keys[targets]
+    tleaf = T.morton(T.leaf_coords(yw, lo, box_len, level), level)
     if far:
         centres = _centres(np.arange(nleaf), level, lo, box_len)
         neg = np.array([H.idx(n, -m) for n in range(p + 1) for m in range(-n, n + 1)])
@@ -259,8 +273,8 @@ def fmm_at(x, alpha, sigma, p, level, targets, box_lo=(0.0, 0.0, 0.0), box_len=2
                     Ll[int(c)] += (mats[d] @ M[l][sk].T).T
             Lc[l] = Ll
         centres_t = centres[tleaf]
-        for i, t in enumerate(targets):
-            g, h = H.local_derivs(Lc[level][int(tleaf[i])], (xw[t] - centres_t[i])[None], p)
+        for i in range(nt):
+            g, h = H.local_derivs(Lc[level][int(tleaf[i])], (yw[i] - centres_t[i])[None], p)
             u[i] = [g[0, 2, 1] - g[0, 1, 2], g[0, 0, 2] - g[0, 2, 0], g[0, 1, 0] - g[0, 0, 1]]
             for a in range(3):
                 J[i, a] = [h[0, 2, a, 1] - h[0, 1, a, 2], h[0, 0, a, 2] - h[0, 2, a, 0],
@@ -269,7 +283,7 @@ def fmm_at(x, alpha, sigma, p, level, targets, box_lo=(0.0, 0.0, 0.0), box_len=2
         J *= INV4PI
     coords_leaf = T.demorton(np.unique(tleaf), level)
     leaf_coord = dict(zip(np.unique(tleaf).tolist(), coords_leaf))
-    for i, t in enumerate(targets):
+    for i in range(nt):
         srcs, shifts = [], []
         for nk, img in T.neighbours(leaf_coord[int(tleaf[i])], level, periodic):
             if count[nk] == 0:
@@ -277,9 +291,11 @@ def fmm_at(x, alpha, sigma, p, level, targets, box_lo=(0.0, 0.0, 0.0), box_len=2
             sid = perm[start[nk]:start[nk] + count[nk]]
             srcs.append(sid)
             shifts.append(np.broadcast_to(np.array(img, np.float64) * box_len, (len(sid), 3)))
+        if not srcs:
+            continue
         sid = np.concatenate(srcs)
         xs = xw[sid] + np.concatenate(shifts)
-        un, Jn = _direct.direct(xw[t][None], xs, alpha[sid], sigma, box_len, K=0)
+        un, Jn = _direct.direct(yw[i][None], xs, alpha[sid], sigma, box_len, K=0)
         u[i] += un[0]
         J[i] += Jn[0]
     return u, J

@@ -99,6 +99,27 @@ class FMM:
         self._check(st)
         return u, da, J
 
+    def eval_at(self, x, alpha, y, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi,
+                precision="fp64", want_grad=False, check_domain=False, stream=None):
+        """Velocity (3, m) and gradient (9, m) or None at the points y."""
+        torch = self._torch
+        x = _soa(x, torch)
+        alpha = _soa(alpha, torch)
+        y = _soa(y, torch)
+        n, m = x.shape[1], y.shape[1]
+        if alpha.shape[1] != n:
+            raise ValueError("x and alpha differ in length")
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        u = torch.empty((3, m), dtype=torch.float64, device=x.device)
+        J = torch.empty((9, m), dtype=torch.float64, device=x.device) if want_grad else None
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", check_domain)
+        self._check(self._lib.vm_fmm_eval_at(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(alpha.data_ptr()), m, ctypes.c_void_p(y.data_ptr()),
+                                             float(sigma), int(p), int(level), ctypes.byref(opts),
+                                             ctypes.c_void_p(u.data_ptr()),
+                                             ctypes.c_void_p(J.data_ptr() if J is not None else 0)))
+        return u, J
+
     def adjoint(self, x, alpha, u_bar, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0),
                 box_len=2 * math.pi, precision="fp64", want_x=True, want_alpha=True, stream=None):
         """(x_bar, alpha_bar), each (3, n) or None: the transposed FMM applied to u_bar."""

@@ -76,10 +76,12 @@ hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, cons
 
 // --- near field (kernels_p2p.hip) ---------------------------------------------
 struct P2PArgs {
-    int n, nleaf, level, periodic, scheme, have_far;
+    int n, nleaf, level, periodic, scheme, have_far;   // n: number of targets
     double w, sigma;
-    const int32_t *start;
-    const int32_t *perm;
+    const int32_t *start;    // source leaf ranges
+    const int32_t *tstart;   // target leaf ranges (= start at the particles)
+    const void *tparts;      // target records, the sources' record type (= the sources at the particles)
+    const int32_t *perm;     // caller index of each sorted target
     const double *alpha;  // caller order [3][n] (stretching contraction in FP64)
     const double *far;    // sorted order: u[3][n], then J[9][n]
     double *u, *dalpha, *grad;   // caller order

@@ -598,6 +598,162 @@ vm_status reinit_impl(vm_ctx *ctx, int64_t n, double *x, double *alpha, double s
     return VM_OK;
 }
 
+// One evaluation (the launch sequence of Sec. 3.1): tree, upward pass,
+// lattice, downward pass, then L2P and P2P at the particles (y == nullptr)
+// or at the m points y, which get a tree of their own (then no stretching).
+vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, int64_t m, const double *y,
+                   double sigma, int p, int level, const vm_opts *opts, double *u, double *dalpha_dt, double *grad) {
+    hipStream_t s = ctx->stream;
+    const int mixed = opts->precision == VM_MIXED;
+    const int K = opts->periodic;
+    const int periodic = K > 0;
+    const int ni = int(n);
+    const int mi = y ? int(m) : ni;   // targets
+    const int64_t nleaf = int64_t(1) << (3 * level);
+
+    if (vm_status st = ensure_tables(ctx); st != VM_OK) return st;
+    OpSet *ops = nullptr;
+    if (vm_status st = ensure_ops(ctx, p, &ops); st != VM_OK) return st;
+    const double *tlat = nullptr;
+    if (K >= 2)
+        if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
+
+    // workspace
+    const int C = ncoef(p), kp = coef_stride(C);
+    const size_t esz = mixed ? sizeof(float) : sizeof(double);
+    const int64_t ncells = ((int64_t(1) << (3 * (level + 1))) - 1) / 7;
+    VM_HIP(ctx->far.reserve(sizeof(double) * 12 * size_t(mi)), "alloc far field");
+    VM_HIP(ctx->trpart.reserve(kTrPartBytes), "alloc split partials");
+    if (ctx->zeros.bytes == 0) VM_HIP(ctx->zeros.reserve(tr_zero_elems(coef_stride(ncoef(VM_MAX_P))) * sizeof(double), true),
+                                      "alloc zero cell");
+    // slack after the last cell: the FP32 M2L reads up to a k block past a component
+    const size_t cbytes = (size_t(ncells) * 3 * kp + tr_slack_elems(kp)) * esz;
+    const bool relayout = ctx->layout_p != p || ctx->layout_prec != mixed;
+    if (relayout || ctx->mbuf.bytes < cbytes) {
+        // coefficient padding (rows C..kp-1) must stay zero: clear on any change of layout
+        ctx->mbuf.release();
+        ctx->lbuf.release();
+        VM_HIP(ctx->mbuf.reserve(cbytes, true), "alloc multipoles");
+        VM_HIP(ctx->lbuf.reserve(cbytes, true), "alloc locals");
+        ctx->layout_p = p;
+        ctx->layout_prec = mixed;
+    }
+
+    // --- tree ------------------------------------------------------------
+    TreeGeom g;
+    int32_t *vin = nullptr;
+    void *pv = nullptr;
+    if (vm_status st = clear_flag(ctx, opts); st != VM_OK) return st;
+    if (vm_status st = build_tree(ctx, source_bufs(ctx), ni, x, alpha, level, opts, g, vin, pv, true); st != VM_OK)
+        return st;
+    int32_t *start = ctx->start.as<int32_t>();
+    ctx->last_p = p;
+    ctx->last_mixed = mixed;
+    const void *parts = pv;
+    // targets: the particles, or the points y in a second tree at the same level
+    const void *tparts = parts;
+    const int32_t *tstart = start;
+    int32_t *tperm = vin;
+    if (y) {
+        TreeGeom gt;
+        void *tp = nullptr;
+        if (vm_status st = build_tree(ctx, target_bufs(ctx), mi, y, y, level, opts, gt, tperm, tp, false);
+            st != VM_OK)
+            return st;
+        tparts = tp;
+        tstart = ctx->t_start.as<int32_t>();
+    }
+
+    // --- far field --------------------------------------------------------
+    const int lmin = periodic ? 0 : 2;
+    const bool far = level >= lmin && !(periodic && K < 2 && level == 0);
+    ctx->last_far = far;
+    if (far) {
+        DevTables tab;
+        tab.c1_64 = ops->c1_64.as<double>(); tab.c2_64 = ops->c2_64.as<double>(); tab.diag_64 = ops->dg_64.as<double>();
+        tab.c1_32 = ops->c1_32.as<float>(); tab.c2_32 = ops->c2_32.as<float>(); tab.diag_32 = ops->dg_32.as<float>();
+        tab.l2p_idx = ops->l2p_idx.as<int32_t>();
+        tab.l2p_w64 = ops->l2p_w64.as<double>();
+        tab.l2p_w32 = ops->l2p_w32.as<float>();
+        tab.l2p_width = ops->width;
+        tab.nu = ops->nu;
+        tab.ng = ops->ng;
+        auto run = [&](auto tag) -> vm_status {
+            using T = decltype(tag);
+            const bool f32 = sizeof(T) == 4;
+            T *M = ctx->mbuf.as<T>(), *L = ctx->lbuf.as<T>();
+            auto lev = [&](T *b, int l) { return b + size_t(((int64_t(1) << (3 * l)) - 1) / 7) * 3 * kp; };
+            const T *m2l = f32 ? (const T *)ops->m2l32.ptr : (const T *)ops->m2l64.ptr;
+            const T *m2m = f32 ? (const T *)ops->m2m32.ptr : (const T *)ops->m2m64.ptr;
+            const T *l2l = f32 ? (const T *)ops->l2l32.ptr : (const T *)ops->l2l64.ptr;
+            const int16_t *lists = ctx->octlists.as<int16_t>();
+            const int8_t *offs = ctx->offsets.as<int8_t>();
+            {
+                Timed tm(ctx, VM_PH_P2M);
+                VM_HIP(launch_p2m<T>(s, int(nleaf), parts, start, p, kp, g.inv_w, tab, lev(M, level)), "P2M");
+            }
+            for (int l = level - 1; l >= lmin; --l) {
+                Timed tm(ctx, VM_PH_M2M);
+                VM_HIP(launch_translate<T>(s, 2, l, periodic, p, kp, m2m, lists, offs, lev(M, l + 1), lev(M, l), 0),
+                       "M2M");
+            }
+            bool have_parent = false;   // L at level l-1 holds something
+            if (periodic && K >= 2) {
+                Timed tm(ctx, VM_PH_LATTICE);
+                VM_HIP(launch_lattice<T>(s, p, kp, tlat, lev(M, 0), lev(L, 0)), "lattice");
+                have_parent = true;
+            }
+            for (int l = periodic ? 1 : 2; l <= level; ++l) {
+                if (have_parent) {
+                    Timed tm(ctx, VM_PH_L2L);
+                    VM_HIP(launch_translate<T>(s, 1, l, periodic, p, kp, l2l, lists, offs, lev(L, l - 1), lev(L, l), 0),
+                           "L2L");
+                }
+                Timed tm(ctx, VM_PH_M2L);
+                VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
+                                           have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
+                                           ctx->zeros.as<T>()),
+                       "M2L");
+                have_parent = true;
+            }
+            Timed tm(ctx, VM_PH_L2P);
+            VM_HIP(launch_l2p<T>(s, int(nleaf), mi, tparts, tstart, p, kp, g.inv_w, g.w, tab, lev(L, level),
+                                 ctx->far.as<double>()),
+                   "L2P");
+            return VM_OK;
+        };
+        vm_status st = mixed ? run(float()) : run(double());
+        if (st != VM_OK) return st;
+    }
+
+    // --- near field + combine -----------------------------------------------
+    P2PArgs a;
+    a.n = mi;
+    a.nleaf = int(nleaf);
+    a.level = level;
+    a.periodic = periodic;
+    a.scheme = opts->scheme;
+    a.have_far = far ? 1 : 0;
+    a.w = g.w;
+    a.sigma = sigma;
+    a.start = start;
+    a.tstart = tstart;
+    a.tparts = tparts;
+    a.perm = tperm;
+    a.alpha = alpha;
+    a.far = ctx->far.as<double>();
+    a.u = u;
+    a.dalpha = y ? nullptr : dalpha_dt;
+    a.grad = grad;
+    {
+        Timed tm(ctx, VM_PH_P2P);
+        if (mixed) VM_HIP(launch_p2p32(s, a, ctx->p32.as<Part32>()), "P2P");
+        else VM_HIP(launch_p2p64(s, a, ctx->p64.as<Part64>()), "P2P");
+    }
+
+    return check_flag(ctx, opts);
+}
+
 // Solution of the (j+1) x (j+1) upper triangular system R y = g of one
 // component's rotated Hessenberg matrix (column-major, leading dimension ld).
 void back_substitute(const std::vector<double> &R, int ld, const std::vector<double> &g, int cols, double *y) {
@@ -654,139 +810,20 @@ vm_status vm_fmm_eval(vm_ctx *ctx, int64_t n, const double *x, const double *alp
     if (opts->scheme != VM_CLASSIC && opts->scheme != VM_TRANSPOSE) return fail(ctx, VM_EINVAL, "unknown scheme");
 
     VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-    hipStream_t s = ctx->stream;
-    const int mixed = opts->precision == VM_MIXED;
-    const int K = opts->periodic;
-    const int periodic = K > 0;
-    const int ni = int(n);
-    const int64_t nleaf = int64_t(1) << (3 * level);
+    return fmm_impl(ctx, n, x, alpha, 0, nullptr, sigma, p, level, opts, u, dalpha_dt, grad);
+}
 
-    if (vm_status st = ensure_tables(ctx); st != VM_OK) return st;
-    OpSet *ops = nullptr;
-    if (vm_status st = ensure_ops(ctx, p, &ops); st != VM_OK) return st;
-    const double *tlat = nullptr;
-    if (K >= 2)
-        if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
-
-    // workspace
-    const int C = ncoef(p), kp = coef_stride(C);
-    const size_t esz = mixed ? sizeof(float) : sizeof(double);
-    const int64_t ncells = ((int64_t(1) << (3 * (level + 1))) - 1) / 7;
-    VM_HIP(ctx->far.reserve(sizeof(double) * 12 * n), "alloc far field");
-    VM_HIP(ctx->trpart.reserve(kTrPartBytes), "alloc split partials");
-    if (ctx->zeros.bytes == 0) VM_HIP(ctx->zeros.reserve(tr_zero_elems(coef_stride(ncoef(VM_MAX_P))) * sizeof(double), true),
-                                      "alloc zero cell");
-    // slack after the last cell: the FP32 M2L reads up to a k block past a component
-    const size_t cbytes = (size_t(ncells) * 3 * kp + tr_slack_elems(kp)) * esz;
-    const bool relayout = ctx->layout_p != p || ctx->layout_prec != mixed;
-    if (relayout || ctx->mbuf.bytes < cbytes) {
-        // coefficient padding (rows C..kp-1) must stay zero: clear on any change of layout
-        ctx->mbuf.release();
-        ctx->lbuf.release();
-        VM_HIP(ctx->mbuf.reserve(cbytes, true), "alloc multipoles");
-        VM_HIP(ctx->lbuf.reserve(cbytes, true), "alloc locals");
-        ctx->layout_p = p;
-        ctx->layout_prec = mixed;
-    }
-
-    // --- tree ------------------------------------------------------------
-    TreeGeom g;
-    int32_t *vin = nullptr;
-    void *pv = nullptr;
-    if (vm_status st = clear_flag(ctx, opts); st != VM_OK) return st;
-    if (vm_status st = build_tree(ctx, source_bufs(ctx), ni, x, alpha, level, opts, g, vin, pv, true); st != VM_OK)
-        return st;
-    int32_t *start = ctx->start.as<int32_t>();
-    ctx->last_p = p;
-    ctx->last_mixed = mixed;
-    const void *parts = pv;
-
-    // --- far field --------------------------------------------------------
-    const int lmin = periodic ? 0 : 2;
-    const bool far = level >= lmin && !(periodic && K < 2 && level == 0);
-    ctx->last_far = far;
-    if (far) {
-        DevTables tab;
-        tab.c1_64 = ops->c1_64.as<double>(); tab.c2_64 = ops->c2_64.as<double>(); tab.diag_64 = ops->dg_64.as<double>();
-        tab.c1_32 = ops->c1_32.as<float>(); tab.c2_32 = ops->c2_32.as<float>(); tab.diag_32 = ops->dg_32.as<float>();
-        tab.l2p_idx = ops->l2p_idx.as<int32_t>();
-        tab.l2p_w64 = ops->l2p_w64.as<double>();
-        tab.l2p_w32 = ops->l2p_w32.as<float>();
-        tab.l2p_width = ops->width;
-        tab.nu = ops->nu;
-        tab.ng = ops->ng;
-        auto run = [&](auto tag) -> vm_status {
-            using T = decltype(tag);
-            const bool f32 = sizeof(T) == 4;
-            T *M = ctx->mbuf.as<T>(), *L = ctx->lbuf.as<T>();
-            auto lev = [&](T *b, int l) { return b + size_t(((int64_t(1) << (3 * l)) - 1) / 7) * 3 * kp; };
-            const T *m2l = f32 ? (const T *)ops->m2l32.ptr : (const T *)ops->m2l64.ptr;
-            const T *m2m = f32 ? (const T *)ops->m2m32.ptr : (const T *)ops->m2m64.ptr;
-            const T *l2l = f32 ? (const T *)ops->l2l32.ptr : (const T *)ops->l2l64.ptr;
-            const int16_t *lists = ctx->octlists.as<int16_t>();
-            const int8_t *offs = ctx->offsets.as<int8_t>();
-            {
-                Timed tm(ctx, VM_PH_P2M);
-                VM_HIP(launch_p2m<T>(s, int(nleaf), parts, start, p, kp, g.inv_w, tab, lev(M, level)), "P2M");
-            }
-            for (int l = level - 1; l >= lmin; --l) {
-                Timed tm(ctx, VM_PH_M2M);
-                VM_HIP(launch_translate<T>(s, 2, l, periodic, p, kp, m2m, lists, offs, lev(M, l + 1), lev(M, l), 0),
-                       "M2M");
-            }
-            bool have_parent = false;   // L at level l-1 holds something
-            if (periodic && K >= 2) {
-                Timed tm(ctx, VM_PH_LATTICE);
-                VM_HIP(launch_lattice<T>(s, p, kp, tlat, lev(M, 0), lev(L, 0)), "lattice");
-                have_parent = true;
-            }
-            for (int l = periodic ? 1 : 2; l <= level; ++l) {
-                if (have_parent) {
-                    Timed tm(ctx, VM_PH_L2L);
-                    VM_HIP(launch_translate<T>(s, 1, l, periodic, p, kp, l2l, lists, offs, lev(L, l - 1), lev(L, l), 0),
-                           "L2L");
-                }
-                Timed tm(ctx, VM_PH_M2L);
-                VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
-                                           have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
-                                           ctx->zeros.as<T>()),
-                       "M2L");
-                have_parent = true;
-            }
-            Timed tm(ctx, VM_PH_L2P);
-            VM_HIP(launch_l2p<T>(s, int(nleaf), ni, parts, start, p, kp, g.inv_w, g.w, tab, lev(L, level),
-                                 ctx->far.as<double>()),
-                   "L2P");
-            return VM_OK;
-        };
-        vm_status st = mixed ? run(float()) : run(double());
-        if (st != VM_OK) return st;
-    }
-
-    // --- near field + combine -----------------------------------------------
-    P2PArgs a;
-    a.n = ni;
-    a.nleaf = int(nleaf);
-    a.level = level;
-    a.periodic = periodic;
-    a.scheme = opts->scheme;
-    a.have_far = far ? 1 : 0;
-    a.w = g.w;
-    a.sigma = sigma;
-    a.start = start;
-    a.perm = vin;
-    a.alpha = alpha;
-    a.far = ctx->far.as<double>();
-    a.u = u;
-    a.dalpha = dalpha_dt;
-    a.grad = grad;
-    {
-        Timed tm(ctx, VM_PH_P2P);
-        if (mixed) VM_HIP(launch_p2p32(s, a, ctx->p32.as<Part32>()), "P2P");
-        else VM_HIP(launch_p2p64(s, a, ctx->p64.as<Part64>()), "P2P");
-    }
-
-    return check_flag(ctx, opts);
+vm_status vm_fmm_eval_at(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, int64_t m, const double *y,
+                         double sigma, int p, int level, const vm_opts *opts, double *u, double *grad) {
+    if (!ctx) return VM_EINVAL;
+    if (vm_status st = check_common(ctx, n, sigma, level, opts); st != VM_OK) return st;
+    if (m < 1 || m >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "m out of range [1, 2^31)");
+    if (!x || !alpha || !y || !u) return fail(ctx, VM_EINVAL, "x, alpha, y and u must be non-NULL");
+    if (misaligned(x) || misaligned(alpha) || misaligned(y) || misaligned(u) || misaligned(grad))
+        return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    if (p < 1 || p > VM_MAX_P) return fail(ctx, VM_EINVAL, "p out of range [1, VM_MAX_P = 18]");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    return fmm_impl(ctx, n, x, alpha, m, y, sigma, p, level, opts, u, nullptr, grad);
 }
 
 vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
@@ -893,6 +930,8 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
     a.w = w;
     a.sigma = sigma;
     a.start = start;
+    a.tstart = start;
+    a.tparts = mixed ? ctx->adj_p32.ptr : ctx->adj_p64.ptr;
     a.perm = perm;
     a.alpha = nullptr;
     a.far = nullptr;

@@ -1,0 +1,105 @@
+"""GPU parity of the FMM velocity at points other than the particles
+(vm_fmm_eval_at) against the oracle (oracle.fmm.fmm_points), through the C ABI.
+
+Tolerances (relative L2 over the points): FP64 vs the oracle 1e-10 (same
+model, round-off apart, as at the particles); mixed vs FP64 1e-5 for u and
+1e-4 for J.  At the particles themselves the point path repeats
+vm_fmm_eval bit for bit (same tree order, same arithmetic).  At N = 256^3
+(the benchmark's configuration) the velocity on the 64^3 lattice of cell
+corners is checked at 48 sampled points.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fmm as OF
+
+pytestmark = pytest.mark.gpu
+
+L = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1110_2921_amd as vm
+    return vm.FMM(0)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64).T)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().T
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("periodic,level", [(0, 2), (1, 2), (3, 2), (3, 3)])
+def test_points_match_oracle(ctx, periodic, level):
+    x, a = W.random_particles(2000, 41)
+    rng = np.random.default_rng(42)
+    y = rng.uniform(-3.0, L + 3.0, size=(500, 3)) if periodic else rng.uniform(0.0, L, size=(500, 3))
+    sigma, p = 0.2, 6
+    uo, Jo = OF.fmm_points(x, a, sigma, p, level, y, periodic=periodic)
+    u, J = ctx.eval_at(dev(x), dev(a), dev(y), sigma, p, level, periodic=periodic, want_grad=True)
+    u, J = host(u), host(J).reshape(-1, 3, 3)
+    assert rel(u, uo) < 1e-10
+    assert rel(J, Jo) < 1e-10
+    um, Jm = ctx.eval_at(dev(x), dev(a), dev(y), sigma, p, level, periodic=periodic, want_grad=True,
+                         precision="mixed")
+    assert rel(host(um), u) < 1e-5
+    assert rel(host(Jm).reshape(-1, 3, 3), J) < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_points_at_the_particles_repeat_the_evaluation(ctx, precision):
+    x, a = W.random_field(16, 4.0, 43)
+    h = L / 16
+    xt, at = dev(x), dev(a)
+    u, _, J = ctx.eval(xt, at, h, 8, 2, periodic=3, want_grad=True, precision=precision)
+    up, Jp = ctx.eval_at(xt, at, xt, h, 8, 2, periodic=3, want_grad=True, precision=precision)
+    assert np.array_equal(host(u), host(up))
+    assert np.array_equal(host(J), host(Jp))
+
+
+def test_points_edge_cases(ctx):
+    import paper_1110_2921_amd as vm
+    x, a = W.random_particles(300, 44)
+    # one point, in a leaf without particles (level 3 has 512 leaves for 300 particles)
+    y = np.array([[0.01, 0.02, 6.27]])
+    uo, Jo = OF.fmm_points(x, a, 0.3, 5, 3, y, periodic=1)
+    u, J = ctx.eval_at(dev(x), dev(a), dev(y), 0.3, 5, 3, periodic=1, want_grad=True)
+    assert rel(host(u), uo) < 1e-10 and rel(host(J).reshape(-1, 3, 3), Jo) < 1e-10
+    with pytest.raises(vm._lib.VmError):
+        ctx.eval_at(dev(x), dev(a), dev(y), 0.3, 19, 3, periodic=1)
+
+
+@pytest.mark.timeout(900)
+def test_lattice_velocity_at_full_size(ctx):
+    import torch
+    w = W.WORKLOADS["rand256_periodic"]
+    x_np, a_np = W.make(w)
+    g = 64
+    c = np.arange(g) * (L / g)
+    Y = np.stack(np.meshgrid(c, c, c, indexing="ij"), axis=-1).reshape(-1, 3)
+    t = np.sort(np.random.default_rng(45).choice(len(Y), 48, replace=False))
+    x, a, y = dev(x_np), dev(a_np), dev(Y)
+    u, J = ctx.eval_at(x, a, y, w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len, want_grad=True,
+                       precision="mixed")
+    tt = torch.from_numpy(t).cuda()
+    us = u[:, tt].cpu().numpy().T
+    Js = J[:, tt].cpu().numpy().T.reshape(-1, 3, 3)
+    del u, J, x, a, y
+    torch.cuda.empty_cache()
+    uo, Jo = OF.fmm_points(x_np, a_np, w.sigma, w.p, w.level, Y[t], periodic=w.periodic, box_len=w.box_len)
+    assert rel(us, uo) < 1e-5
+    assert rel(Js, Jo) < 1e-4

@@ -163,3 +163,28 @@ def test_sampled_fmm_equals_full_fmm(periodic, level):
     us, Js = F.fmm_at(x, a, h, 6, level, t, periodic=periodic, chunk=1000)
     assert np.abs(us - u[t]).max() < 1e-14 * np.abs(u).max()
     assert np.abs(Js - J[t]).max() < 1e-14 * np.abs(J).max()
+
+
+@pytest.mark.parametrize("periodic", [0, 1, 2])
+def test_fmm_at_points_converges_to_far_field_model(periodic):
+    """Velocity at points other than the particles: the same far-field model
+    (g = 1 between non-adjacent leaves, the point in the leaf its position
+    falls in) is approached at the FMM's rate; the points' own leaves may be
+    empty of particles."""
+    x, a = W.random_particles(300, 25)
+    rng = np.random.default_rng(26)
+    y = rng.uniform(-2.0, L + 2.0, size=(60, 3)) if periodic else rng.uniform(0.0, L, size=(60, 3))
+    sigma, level = 0.2, 2
+    tr = T.build(x, (0, 0, 0), L, level, periodic)
+    yw = T.wrap(y, (0, 0, 0), L) if periodic else y
+    cy = T.leaf_coords(yw, (0, 0, 0), L, level)
+    u0, J0 = D.direct(yw, tr["xw"], a, sigma, L, K=periodic, cells_t=cy, cells_s=tr["coords"], level=level)
+    eu, ej = [], []
+    for p in (3, 6, 9):
+        u, J = F.fmm_points(x, a, sigma, p, level, y, periodic=periodic)
+        eu.append(np.linalg.norm(u - u0) / np.linalg.norm(u0))
+        ej.append(np.linalg.norm(J - J0) / np.linalg.norm(J0))
+    assert eu[1] < eu[0] / 4 and eu[2] < eu[1] / 4
+    assert ej[1] < ej[0] / 4 and ej[2] < ej[1] / 4
+    # 60 points: the worst-placed ones weigh more than among 300 particles
+    assert eu[2] < 5e-4 and ej[2] < 5e-4
