@@ -282,6 +282,26 @@ vm_status vm_run(vm_ctx *ctx, int64_t n, double *x, double *alpha, double *sigma
                  const vm_opts *opts, const vm_loop *loop, double *diag, int *products, double *resid);
 
 /*
+ * Shell energy spectrum of a velocity sampled on the ng^3 lattice of the
+ * periodic cube (the diagnostic that the velocity at lattice points, e.g.
+ * vm_fmm_eval_at on the grid of a spectral method, makes possible):
+ *   E[s] = 1/2 sum over integer wavevectors m with rint(|m|) = s of |u_m|^2,
+ *   u_m = ng^-3 sum_x u(x) exp(-i 2 pi m.x / box_len),  s = 0 .. kmax,
+ * so that sum_s E[s] = <|u|^2>/2 once kmax >= sqrt(3) ng / 2.
+ *   ng    lattice points per side, 2..1290
+ *   u     device [3][ng^3]: the velocity at lattice point (i_x ng + i_y) ng + i_z
+ *         (x index slowest), any fixed offset of the lattice
+ *   kmax  last shell, 0..VM_SPECTRUM_MAX_K
+ *   E     device [kmax + 1] out
+ * A real-to-complex FFT per component (hipFFT; the plan is created on the
+ * first call for an ng and kept), then one fixed-order sum per shell over a
+ * host-built list of its entries (deterministic).  The context keeps the
+ * plan, (ng^3 + 3 ng^2 (ng/2+1)) doubles and the shell lists.
+ */
+#define VM_SPECTRUM_MAX_K 4096
+vm_status vm_energy_spectrum(vm_ctx *ctx, int ng, const double *u, int kmax, double *E);
+
+/*
  * Device-time accounting (HIP events on the context's stream around every
  * launch).  vm_set_timing(ctx, 1) starts a fresh account (and 0 stops it);
  * vm_get_timing reports, summed over every vm_fmm_eval since then, the

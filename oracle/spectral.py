@@ -52,3 +52,26 @@ def lattice_velocity(alpha, ng, sigma, box_len=2 * math.pi, alias=2):
     u = np.moveaxis(u, 0, -1).reshape(-1, 3)
     J = np.moveaxis(J, (0, 1), (-2, -1)).reshape(-1, 3, 3)
     return u, J
+
+
+def energy_spectrum(u, ng, kmax):
+    """Shell energy spectrum of a velocity sampled on an ng^3 lattice of the
+    periodic cube (lattice order, x index slowest; u (ng^3, 3)):
+
+        E(s) = 1/2 sum_{m : rint(|m|) = s} |u_m|^2,  s = 0 .. kmax,
+
+    u_m the Fourier coefficients (1/ng^3) sum_x u(x) exp(-i k.x) on the integer
+    wavevectors m of the DFT box (k = 2 pi m / box_len), so that sum_s E(s) is
+    1/2 <|u|^2> when kmax covers every shell.  Full complex FFT, no symmetry
+    folding.
+    """
+    u = np.asarray(u, np.float64).reshape(ng, ng, ng, 3)
+    U = np.fft.fftn(np.moveaxis(u, -1, 0), axes=(1, 2, 3)) / ng ** 3
+    m = np.fft.fftfreq(ng, d=1.0 / ng)
+    M = np.stack(np.meshgrid(m, m, m, indexing="ij"))
+    shell = np.rint(np.sqrt(np.sum(M * M, axis=0))).astype(np.int64)
+    power = 0.5 * np.sum(np.abs(U) ** 2, axis=0)
+    E = np.zeros(kmax + 1)
+    keep = shell <= kmax
+    np.add.at(E, shell[keep], power[keep])
+    return E

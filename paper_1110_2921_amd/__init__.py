@@ -258,6 +258,19 @@ class FMM:
                                      ctypes.byref(prods), ctypes.byref(resid)))
         return sg.value, (diag[:steps] if diag is not None else None), prods.value, resid.value
 
+    def energy_spectrum(self, u, ng, kmax, stream=None):
+        """Shell energy spectrum E[0..kmax] (CUDA float64) of a velocity (3, ng^3)
+        on the ng^3 lattice of the periodic cube (x index slowest)."""
+        torch = self._torch
+        u = _soa(u, torch)
+        if u.shape[1] != ng ** 3:
+            raise ValueError("u must hold ng^3 lattice points")
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        E = torch.empty(kmax + 1, dtype=torch.float64, device=u.device)
+        self._check(self._lib.vm_energy_spectrum(self._h, int(ng), ctypes.c_void_p(u.data_ptr()), int(kmax),
+                                                 ctypes.c_void_p(E.data_ptr())))
+        return E
+
     def _inplace(self, x, alpha):
         torch = self._torch
         for t in (x, alpha):

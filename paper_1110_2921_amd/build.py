@@ -21,7 +21,7 @@ COMMON = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 SOURCES = ["kernels_tree.hip", "kernels_fmm.hip", "kernels_p2p.hip", "kernels_step.hip", "kernels_adjoint.hip",
-           "kernels_rbf.hip",
+           "kernels_rbf.hip", "kernels_spectrum.hip",
            "operators.cpp",
            "vmfmm.cpp"]
 
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-L/opt/rocm/lib", "-lhipfft"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)
     return OUT

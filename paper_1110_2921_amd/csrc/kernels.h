@@ -121,6 +121,13 @@ hipError_t launch_multidot(hipStream_t s, int n, const double *w, const double *
 hipError_t launch_multiaxpy(hipStream_t s, int n, double *w, const double *V, int64_t ldv, int k,
                             const RbfCoefs &c);
 
+// --- energy spectrum (kernels_spectrum.hip) -----------------------------------------
+// power (+)= weighted |U|^2 scale over the ng x ng x (ng/2+1) half spectrum U (double2)
+hipError_t launch_spec_power(hipStream_t s, int ng, const void *U, double scale, int first, double *power);
+// E[s] = sum of power over list[start[s] .. start[s+1]), s < nshell
+hipError_t launch_shell_sum(hipStream_t s, int nshell, const int32_t *start, const int32_t *list,
+                            const double *power, double *E);
+
 // --- adjoint (kernels_adjoint.hip) ------------------------------------------------
 template <typename T>
 hipError_t launch_l2p_adj(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start,

@@ -4,6 +4,7 @@
 #include "../../include/vmfmm.h"
 
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -106,6 +107,10 @@ struct vm_ctx {
     // second tree over a distinct target set (Gaussian sums at other points)
     DevBuf t_keys_a, t_keys_b, t_vals_a, t_vals_b, t_start, t_p64, t_p32;
     DevBuf rin_y, rin_w, run_J;   // reinitialisation: lattice sites, vorticity there; loop: gradient
+    // energy spectrum: FFT plan and shell lists for one lattice size
+    hipfftHandle fft_plan = 0;
+    int fft_ng = -1, spec_ng = -1, spec_kmax = -1;
+    DevBuf spec_in, spec_U, spec_power, spec_start, spec_list;
     std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice_t;
     int layout_p = -1, layout_prec = -1;   // layout of mbuf/lbuf
     // results of the last evaluation, for the debug views
@@ -788,6 +793,7 @@ void vm_destroy(vm_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->fft_ng > 0) (void)hipfftDestroy(ctx->fft_plan);
     delete ctx;
 }
 
@@ -1257,6 +1263,69 @@ vm_status vm_rbf_solve(vm_ctx *ctx, int64_t n, const double *x, const double *om
     }
     if (iters) *iters = total;
     if (resid) *resid = std::max(rel[0], std::max(rel[1], rel[2]));
+    return VM_OK;
+}
+
+vm_status vm_energy_spectrum(vm_ctx *ctx, int ng, const double *u, int kmax, double *E) {
+    if (!ctx) return VM_EINVAL;
+    if (ng < 2 || ng > 1290) return fail(ctx, VM_EINVAL, "ng out of range [2, 1290]");
+    if (kmax < 0 || kmax > VM_SPECTRUM_MAX_K) return fail(ctx, VM_EINVAL, "kmax out of range");
+    if (!u || !E) return fail(ctx, VM_EINVAL, "u and E must be non-NULL");
+    if (misaligned(u) || misaligned(E)) return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = ctx->stream;
+    const int nzc = ng / 2 + 1;
+    const size_t n3 = size_t(ng) * ng * ng, total = size_t(ng) * ng * nzc;
+    if (ctx->fft_ng != ng) {
+        if (ctx->fft_ng > 0) (void)hipfftDestroy(ctx->fft_plan);
+        ctx->fft_ng = -1;
+        if (hipfftPlan3d(&ctx->fft_plan, ng, ng, ng, HIPFFT_D2Z) != HIPFFT_SUCCESS)
+            return fail(ctx, VM_EDEVICE, "hipfftPlan3d failed");
+        ctx->fft_ng = ng;
+    }
+    if (hipfftSetStream(ctx->fft_plan, s) != HIPFFT_SUCCESS) return fail(ctx, VM_EDEVICE, "hipfftSetStream failed");
+    if (ctx->spec_ng != ng || ctx->spec_kmax != kmax) {
+        // entries of the half spectrum by shell rint(|m|), m the signed integer wavevector
+        std::vector<int32_t> shell(total), start(size_t(kmax) + 2, 0), list;
+        auto sgn = [ng](int i) { return i <= ng / 2 ? i : i - ng; };
+        for (int ix = 0; ix < ng; ++ix)
+            for (int iy = 0; iy < ng; ++iy)
+                for (int kz = 0; kz < nzc; ++kz) {
+                    const double mx = sgn(ix), my = sgn(iy), mz = kz;
+                    const double r = std::nearbyint(std::sqrt(mx * mx + my * my + mz * mz));
+                    const size_t e = (size_t(ix) * ng + iy) * nzc + kz;
+                    shell[e] = r <= kmax ? int32_t(r) : -1;
+                    if (shell[e] >= 0) ++start[size_t(shell[e]) + 1];
+                }
+        for (int k = 0; k <= kmax; ++k) start[size_t(k) + 1] += start[size_t(k)];
+        list.resize(size_t(start[size_t(kmax) + 1]));
+        std::vector<int32_t> fill(start.begin(), start.end() - 1);
+        for (size_t e = 0; e < total; ++e)
+            if (shell[e] >= 0) list[size_t(fill[size_t(shell[e])]++)] = int32_t(e);
+        ctx->spec_ng = -1;
+        VM_HIP(upload(ctx->spec_start, start), "upload shells");
+        if (list.empty()) list.push_back(0);
+        VM_HIP(upload(ctx->spec_list, list), "upload shells");
+        ctx->spec_ng = ng;
+        ctx->spec_kmax = kmax;
+    }
+    VM_HIP(ctx->spec_in.reserve(sizeof(double) * n3), "alloc spectrum");
+    VM_HIP(ctx->spec_U.reserve(2 * sizeof(double) * total), "alloc spectrum");
+    VM_HIP(ctx->spec_power.reserve(sizeof(double) * total), "alloc spectrum");
+    const double inv = 1.0 / double(n3);
+    for (int c = 0; c < 3; ++c) {
+        // the transform may use its input as scratch: it works on a copy
+        VM_HIP(hipMemcpyAsync(ctx->spec_in.ptr, u + size_t(c) * n3, sizeof(double) * n3, hipMemcpyDeviceToDevice, s),
+               "copy component");
+        if (hipfftExecD2Z(ctx->fft_plan, ctx->spec_in.as<hipfftDoubleReal>(), ctx->spec_U.as<hipfftDoubleComplex>()) !=
+            HIPFFT_SUCCESS)
+            return fail(ctx, VM_EDEVICE, "hipfftExecD2Z failed");
+        VM_HIP(launch_spec_power(s, ng, ctx->spec_U.ptr, 0.5 * inv * inv, c == 0, ctx->spec_power.as<double>()),
+               "spectrum power");
+    }
+    VM_HIP(launch_shell_sum(s, kmax + 1, ctx->spec_start.as<int32_t>(), ctx->spec_list.as<int32_t>(),
+                            ctx->spec_power.as<double>(), E),
+           "shell sums");
     return VM_OK;
 }
 

@@ -103,3 +103,39 @@ def test_lattice_velocity_at_full_size(ctx):
     uo, Jo = OF.fmm_points(x_np, a_np, w.sigma, w.p, w.level, Y[t], periodic=w.periodic, box_len=w.box_len)
     assert rel(us, uo) < 1e-5
     assert rel(Js, Jo) < 1e-4
+
+
+@pytest.mark.parametrize("ng", [12, 16, 33])
+def test_energy_spectrum_matches_oracle(ctx, ng):
+    from oracle import spectral as S
+    u = np.random.default_rng(ng).standard_normal((ng ** 3, 3))
+    kmax = int(math.ceil(math.sqrt(3) * ng / 2))
+    want = S.energy_spectrum(u, ng, kmax)
+    got = ctx.energy_spectrum(dev(u), ng, kmax).cpu().numpy()
+    assert np.abs(got - want).max() < 1e-13 * want.sum()
+    assert abs(got.sum() - 0.5 * np.mean(np.sum(u * u, axis=1))) < 1e-13
+    # a shorter spectrum keeps the low shells, bit for bit across calls
+    got6 = ctx.energy_spectrum(dev(u), ng, 6).cpu().numpy()
+    again = ctx.energy_spectrum(dev(u), ng, 6).cpu().numpy()
+    assert np.array_equal(got6, again) and np.abs(got6 - want[:7]).max() < 1e-13 * want.sum()
+
+
+def test_spectrum_of_the_particle_velocity_on_the_grid(ctx):
+    """The 64^3 field's particles (sigma = h, 27^3 images) evaluated on the
+    lattice of cell centres (points distinct from the particle array, at the
+    same places): the spectrum of the infinite-lattice blob velocity there
+    (oracle.spectral) is matched per shell where it carries energy, up to the
+    FMM's accuracy at p = 8 and the cubic image sum's shape term (the mean,
+    shell 0, is left out)."""
+    from oracle import spectral as S
+    w = W.WORKLOADS["rand64_periodic"]
+    x_np, a_np = W.make(w)
+    g = w.ng
+    Y = W.lattice(g)
+    u, _ = ctx.eval_at(dev(x_np), dev(a_np), dev(Y), w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len)
+    kmax = 24
+    E = ctx.energy_spectrum(u, g, kmax).cpu().numpy()
+    us, _ = S.lattice_velocity(a_np, g, w.sigma)
+    Es = S.energy_spectrum(us, g, kmax)
+    big = Es > 1e-3 * Es.max()
+    assert np.all(np.abs(E[big] - Es[big]) < 2e-3 * Es[big])
