@@ -437,6 +437,35 @@ def main():
             f"{gauss_ms:.2f} ms each), resid {resid:.2e}; {1e3 * tr / ms_per_step:.2f} RK2 steps")
         del om, gam
 
+    if not args.no_rbf:
+        # velocity on the grid of the spectral method (cell corners, N points) from the
+        # particles, and its shell energy spectrum
+        c = torch.arange(w.ng, dtype=torch.float64, device=dev) * (w.box_len / w.ng)
+        Y = torch.stack(torch.meshgrid(c, c, c, indexing="ij"), dim=0).reshape(3, -1).contiguous()
+        del c
+        kmax = w.ng // 2
+        ctx.eval_at(x0, a0, Y, w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len,
+                    precision=args.precision)
+        ctx.energy_spectrum(u, w.ng, kmax)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ug, _ = ctx.eval_at(x0, a0, Y, w.sigma, w.p, w.level, periodic=w.periodic, box_len=w.box_len,
+                            precision=args.precision)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        spec = ctx.energy_spectrum(ug, w.ng, kmax)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sp = spec.cpu().numpy()
+        result["grid_spectrum"] = {"points": int(Y.shape[1]), "eval_at_ms": 1e3 * (t1 - t0),
+                                   "spectrum_ms": 1e3 * (t2 - t1), "kmax": kmax,
+                                   "peak_shell": int(np.argmax(sp)), "energy": float(sp.sum()),
+                                   "what": "velocity of the particles at the N grid points (vm_fmm_eval_at) "
+                                           "and its shell energy spectrum (vm_energy_spectrum)"}
+        log(f"[bench] grid velocity {1e3 * (t1 - t0):.1f} ms, spectrum {1e3 * (t2 - t1):.1f} ms "
+            f"(peak shell {int(np.argmax(sp))})")
+        del Y, ug, spec
+
     if args.loop_steps > 0:
         # the paper's loop from the initial state: forward Euler, dt = 0.005, core
         # spreading with nu = lambda / Re_lambda (Re_lambda = 50, u' = 1, lambda = 2/k0
