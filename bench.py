@@ -196,6 +196,7 @@ def main():
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-rbf", action="store_true")
+    ap.add_argument("--no-truncation", action="store_true")
     ap.add_argument("--loop-steps", type=int, default=10,
                     help="steps of the paper's time loop to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -399,6 +400,32 @@ def main():
         result["adjoint"] = {"gradients_per_s": 1.0 / ta, "ms": 1e3 * ta, "precision": args.precision,
                              "what": "dL/dx and dL/dalpha of L = h^3/2 sum |u|^2 (forward recomputed)"}
         log(f"[bench] adjoint {1e3 * ta:.1f} ms per gradient")
+
+    if not args.no_truncation:
+        # the M2L truncated to n + n' <= p: time and distance from the square truncation
+        ctx.eval(x0, a0, w.sigma, w.p, w.level, precision=args.precision, out=(u, da, None), **kw)
+        ut = torch.empty_like(u)
+        ctx.eval(x0, a0, w.sigma, w.p, w.level, precision=args.precision, out=(ut, None, None),
+                 truncation="triangular", **kw)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.eval(x0, a0, w.sigma, w.p, w.level, precision=args.precision, out=(ut, None, None),
+                     truncation="triangular", **kw)
+        torch.cuda.synchronize()
+        tt = (time.perf_counter() - t0) / reps
+        ph = ctx.timing()
+        ctx.set_timing(False)
+        dtri = float(torch.linalg.norm(ut - u) / torch.linalg.norm(u))
+        result["triangular_truncation"] = {
+            "evals_per_s": 1.0 / tt, "ms": 1e3 * tt, "m2l_ms": ph["m2l"][0] / reps,
+            "rel_l2_u_vs_square": dtri, "products_per_component": "2926 of 14641 at p = 10",
+            "what": "M2L keeping target degree n and source degree n' with n + n' <= p (zero tiles skipped)"}
+        log(f"[bench] triangular truncation: {1e3 * tt:.1f} ms/eval (M2L {ph['m2l'][0] / reps:.1f} ms), "
+            f"rel-L2 u vs square {dtri:.2e}")
+        del ut
 
     if not args.no_rbf:
         # RBF reinitialisation of the initial lattice: strengths that reproduce

@@ -63,14 +63,23 @@ def lattice_local(m0, p, box_len, K):
     return out
 
 
-def _m2l_matrices(level, p, box_len):
+def _m2l_matrices(level, p, box_len, truncation="square"):
+    """M2L operators of the 316 offsets at a level.  "triangular" keeps the
+    terms of target degree j and source degree n with j + n <= p only (the
+    classical truncation of the local expansion of eq. 13); "square" keeps
+    every j, n <= p."""
     w = box_len / (1 << level)
     offs = T.all_offsets()
     mats = H.m2l_matrices(np.array(offs, np.float64) * w, p)
+    if truncation == "triangular":
+        deg = np.floor(np.sqrt(np.arange(H.ncoef(p)) + 0.5)).astype(np.int64)
+        mats = [m * ((deg[:, None] + deg[None, :]) <= p) for m in mats]
+    elif truncation != "square":
+        raise ValueError(truncation)
     return dict(zip(offs, mats))
 
 
-def fmm(x, alpha, sigma, p, level, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, periodic=0):
+def fmm(x, alpha, sigma, p, level, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, periodic=0, truncation="square"):
     """u (N,3) and J (N,3,3) (J[a,b] = d u_b / d x_a) in the caller's order."""
     x = np.asarray(x, np.float64)
     alpha = np.asarray(alpha, np.float64)
@@ -115,7 +124,7 @@ def fmm(x, alpha, sigma, p, level, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, 
                     ob = np.array([(o >> d) & 1 for d in range(3)], np.float64)
                     Tl = H.l2l_matrix(-(ob - 0.5) * w, p)
                     Ll[o::8] += Lc[l - 1] @ Tl.T
-            mats = _m2l_matrices(l, p, box_len)
+            mats = _m2l_matrices(l, p, box_len, truncation)
             side = 1 << l
             keys = np.arange(ncell)
             coords = T.demorton(keys, l)
@@ -174,7 +183,7 @@ def fmm(x, alpha, sigma, p, level, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, 
 
 
 def fmm_at(x, alpha, sigma, p, level, targets, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, periodic=0,
-           chunk=1 << 18):
+           chunk=1 << 18, truncation="square"):
     """u and J of ``fmm`` at the particles ``targets`` only (indices in caller order).
 
     Same steps and arithmetic as ``fmm``: P2M for every leaf and M2M for every
@@ -184,11 +193,11 @@ def fmm_at(x, alpha, sigma, p, level, targets, box_lo=(0.0, 0.0, 0.0), box_len=2
     """
     x = np.asarray(x, np.float64)
     return fmm_points(x, alpha, sigma, p, level, x[np.asarray(targets, np.int64)], box_lo, box_len, periodic,
-                      chunk)
+                      chunk, truncation)
 
 
 def fmm_points(x, alpha, sigma, p, level, y, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, periodic=0,
-               chunk=1 << 18):
+               chunk=1 << 18, truncation="square"):
     """u and J that the particles (x, alpha) induce at the points y (m, 3).
 
     The same model as at the particles: each point belongs to the leaf its
@@ -258,7 +267,7 @@ def fmm_points(x, alpha, sigma, p, level, y, box_lo=(0.0, 0.0, 0.0), box_len=2 *
                     o = int(c) & 7
                     ob = np.array([(o >> d) & 1 for d in range(3)], np.float64)
                     Ll[int(c)] += (H.l2l_matrix(-(ob - 0.5) * w, p) @ Lc[l - 1][int(c) >> 3].T).T
-            mats = _m2l_matrices(l, p, box_len)
+            mats = _m2l_matrices(l, p, box_len, truncation)
             side = 1 << l
             coords = T.demorton(cells, l)
             for c, cc in zip(cells, coords):

@@ -23,6 +23,7 @@ from . import _lib
 PRECISIONS = {"fp64": 0, "mixed": 1}
 SCHEMES = {"classic": 0, "transpose": 1}
 INTEGRATORS = {"euler": 0, "heun": 1}
+TRUNCATIONS = {"square": 0, "triangular": 1}
 
 
 def _soa(t, torch):
@@ -74,7 +75,7 @@ class FMM:
 
     def eval(self, x, alpha, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0),
              box_len=2 * math.pi, precision="fp64", scheme="classic", want_grad=False,
-             want_dalpha=True, check_domain=False, stream=None, out=None):
+             want_dalpha=True, check_domain=False, stream=None, out=None, truncation="square"):
         """Velocity (3, n), stretching (3, n) or None, gradient (9, n) or None."""
         torch = self._torch
         x = _soa(x, torch)
@@ -89,8 +90,7 @@ class FMM:
             J = torch.empty((9, n), dtype=torch.float64, device=x.device) if want_grad else None
         else:
             u, da, J = out
-        opts = _lib.VmOpts((ctypes.c_double * 3)(*box_lo), float(box_len), int(periodic),
-                           PRECISIONS[precision], SCHEMES[scheme], int(bool(check_domain)))
+        opts = self._opts(periodic, box_lo, box_len, precision, scheme, check_domain, truncation)
         st = self._lib.vm_fmm_eval(self._h, n, ctypes.c_void_p(x.data_ptr()),
                                    ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(level),
                                    ctypes.byref(opts), ctypes.c_void_p(u.data_ptr()),
@@ -100,7 +100,7 @@ class FMM:
         return u, da, J
 
     def eval_at(self, x, alpha, y, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi,
-                precision="fp64", want_grad=False, check_domain=False, stream=None):
+                precision="fp64", want_grad=False, check_domain=False, stream=None, truncation="square"):
         """Velocity (3, m) and gradient (9, m) or None at the points y."""
         torch = self._torch
         x = _soa(x, torch)
@@ -112,7 +112,7 @@ class FMM:
         self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
         u = torch.empty((3, m), dtype=torch.float64, device=x.device)
         J = torch.empty((9, m), dtype=torch.float64, device=x.device) if want_grad else None
-        opts = self._opts(periodic, box_lo, box_len, precision, "classic", check_domain)
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", check_domain, truncation)
         self._check(self._lib.vm_fmm_eval_at(self._h, n, ctypes.c_void_p(x.data_ptr()),
                                              ctypes.c_void_p(alpha.data_ptr()), m, ctypes.c_void_p(y.data_ptr()),
                                              float(sigma), int(p), int(level), ctypes.byref(opts),
@@ -121,7 +121,8 @@ class FMM:
         return u, J
 
     def adjoint(self, x, alpha, u_bar, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0),
-                box_len=2 * math.pi, precision="fp64", want_x=True, want_alpha=True, stream=None):
+                box_len=2 * math.pi, precision="fp64", want_x=True, want_alpha=True, stream=None,
+                truncation="square"):
         """(x_bar, alpha_bar), each (3, n) or None: the transposed FMM applied to u_bar."""
         torch = self._torch
         x = _soa(x, torch)
@@ -131,7 +132,7 @@ class FMM:
         self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
         xb = torch.empty((3, n), dtype=torch.float64, device=x.device) if want_x else None
         ab = torch.empty((3, n), dtype=torch.float64, device=x.device) if want_alpha else None
-        opts = self._opts(periodic, box_lo, box_len, precision, "classic", False)
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", False, truncation)
         self._check(self._lib.vm_fmm_adjoint(self._h, n, ctypes.c_void_p(x.data_ptr()),
                                              ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(level),
                                              ctypes.byref(opts), ctypes.c_void_p(u_bar.data_ptr()),
@@ -139,13 +140,14 @@ class FMM:
                                              ctypes.c_void_p(ab.data_ptr() if ab is not None else 0)))
         return xb, ab
 
-    def _opts(self, periodic, box_lo, box_len, precision, scheme, check_domain):
+    def _opts(self, periodic, box_lo, box_len, precision, scheme, check_domain, truncation="square"):
         return _lib.VmOpts((ctypes.c_double * 3)(*box_lo), float(box_len), int(periodic),
-                           PRECISIONS[precision], SCHEMES[scheme], int(bool(check_domain)))
+                           PRECISIONS[precision], SCHEMES[scheme], int(bool(check_domain)),
+                           TRUNCATIONS[truncation])
 
     def rk2_step(self, x, alpha, sigma, p, level, dt, periodic=0, box_lo=(0.0, 0.0, 0.0),
                  box_len=2 * math.pi, precision="fp64", scheme="classic", want_initial=False,
-                 stream=None, out=None):
+                 stream=None, out=None, truncation="square"):
         """Heun step, in place on x and alpha ((3, n) contiguous float64 CUDA tensors).
 
         Returns (u0, J0) at the initial state when ``want_initial`` (written into
@@ -163,7 +165,7 @@ class FMM:
             else:
                 u0 = torch.empty((3, n), dtype=torch.float64, device=x.device)
                 J0 = torch.empty((9, n), dtype=torch.float64, device=x.device)
-        opts = self._opts(periodic, box_lo, box_len, precision, scheme, False)
+        opts = self._opts(periodic, box_lo, box_len, precision, scheme, False, truncation)
         self._check(self._lib.vm_rk2_step(self._h, n, ctypes.c_void_p(x.data_ptr()),
                                           ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(level),
                                           ctypes.byref(opts), float(dt),
@@ -237,7 +239,7 @@ class FMM:
 
     def run(self, x, alpha, sigma, p, level, dt, steps, nu=0.0, integrator="euler", reinit_every=0, ng=0,
             tol=1e-3, max_iter=100, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi, precision="fp64",
-            scheme="classic", want_diag=False, stream=None):
+            scheme="classic", want_diag=False, stream=None, truncation="square"):
         """The time loop, in place on x and alpha.  Returns (sigma at the end,
         diagnostics (steps, 3) CUDA tensor or None, GMRES products, largest
         relative residual of the reinitialisations)."""
@@ -245,7 +247,7 @@ class FMM:
         self._inplace(x, alpha)
         n = x.shape[1]
         self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
-        opts = self._opts(periodic, box_lo, box_len, precision, scheme, False)
+        opts = self._opts(periodic, box_lo, box_len, precision, scheme, False, truncation)
         loop = _lib.VmLoop(INTEGRATORS[integrator], float(dt), float(nu), int(steps), int(reinit_every), int(ng),
                            float(tol), int(max_iter))
         diag = torch.empty((max(steps, 1), 3), dtype=torch.float64, device=x.device) if want_diag else None

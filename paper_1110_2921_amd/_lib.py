@@ -27,7 +27,7 @@ EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_
 class VmOpts(ctypes.Structure):
     _fields_ = [("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double),
                 ("periodic", ctypes.c_int), ("precision", ctypes.c_int), ("scheme", ctypes.c_int),
-                ("check_domain", ctypes.c_int)]
+                ("check_domain", ctypes.c_int), ("truncation", ctypes.c_int)]
 
 
 class VmLoop(ctypes.Structure):

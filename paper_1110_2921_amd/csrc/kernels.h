@@ -62,12 +62,14 @@ hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const 
 // split over the offsets at coarse levels; without it no split is made.
 // `zero_cell` (may be null) points at tr_zero_elems(kp) zeros; with it the
 // FP32 M2L takes its operator-stationary form, which also needs
-// tr_slack_elems(kp) readable elements after the end of `src`.
+// tr_slack_elems(kp) readable elements after the end of `src`.  `tri`: the
+// operators are truncated to n + n' <= p (zero elsewhere); the
+// operator-stationary form then skips their zero tiles.
 template <typename T>
 hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp,
                             const T *ops, const int16_t *oct_lists, const int8_t *offsets,
                             const T *src, T *dst, int accumulate, T *part = nullptr,
-                            size_t part_elems = 0, const T *zero_cell = nullptr);
+                            size_t part_elems = 0, const T *zero_cell = nullptr, int tri = 0);
 inline size_t tr_slack_elems(int kp) { return size_t((kp + 31) / 32 * 32 - kp) + 4; }
 inline size_t tr_zero_elems(int kp) { return size_t(3) * kp + tr_slack_elems(kp) + 4; }
 

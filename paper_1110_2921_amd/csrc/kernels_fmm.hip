@@ -3,6 +3,8 @@
 //
 // Coefficient layout: cell-major, [cell][component][kp] with kp = (p+1)^2
 // rounded up to a multiple of 32 (whole k blocks); entries C..kp-1 are zero.
+#include <algorithm>
+
 #include "device_harmonics.h"
 #include "kernels.h"
 
@@ -523,14 +525,21 @@ __global__ void __launch_bounds__(256) k_split_reduce(int64_t nelem, int kp, int
 // Scheduling barriers keep each k block in the order chunk store, chunk load,
 // A reads, MFMAs, source loads, so the wait for a chunk never covers the
 // newer source loads.
-template <int NRBH, int NB>
+//
+// TRI: operators truncated to n + n' <= p (target degree n, source degree
+// n'), whose row block rb is zero beyond its first kb(rb) k blocks.  Slot i of
+// wave half rh then serves row block (rbmap >> 4 (rh NRBH + i)) & 15 and runs
+// its MFMAs and A reads for the first (kbmap >> 4 (rh NRBH + i)) & 15 k blocks
+// only; the host balances the two halves' k blocks.
+template <int NRBH, int NB, bool TRI>
 __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, int C, int kp, int nrb_pad,
                                                        int nks, const float *__restrict__ ops,
                                                        const int16_t *__restrict__ oct_lists,
                                                        const int8_t *__restrict__ offsets,
                                                        const float *__restrict__ src, float *__restrict__ dst,
                                                        int accumulate, int nsplit, float *__restrict__ part,
-                                                       const float *__restrict__ zero_cell) {
+                                                       const float *__restrict__ zero_cell, uint32_t rbmap,
+                                                       uint32_t kbmap) {
     typedef float f4 __attribute__((ext_vector_type(4)));
     using V = Mfma<float>::v4;
     constexpr int TT = 64;                               // target cells per workgroup
@@ -548,6 +557,12 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tg = wave >> 1, rh = wave & 1, h = lane >> 4;
     const int octant = blockIdx.x & 7, tile = blockIdx.x >> 3;
+    int rbs[NRBH], kbs[NRBH];   // row block of each slot and its k blocks (wave-uniform)
+#pragma unroll
+    for (int i = 0; i < NRBH; ++i) {
+        rbs[i] = TRI ? int((rbmap >> (4 * (rh * NRBH + i))) & 15u) : rh * NRBH + i;
+        kbs[i] = TRI ? int((kbmap >> (4 * (rh * NRBH + i))) & 15u) : NB;
+    }
     const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
     const int pr0 = int(blockIdx.y) * 189 / nsplit;
     const int npair = (int(blockIdx.y) + 1) * 189 / nsplit - pr0;
@@ -608,11 +623,12 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
         const float *spn = src_of(more ? pr + 1 : pr);     // wave-uniform choice
         const float *ogn = op_of(more ? pr + 1 : pr) + 4 * tid;
         float *oln = opl + (cur ^ 1) * OPF + 4 * tid;
-        const float *olc = opl + cur * OPF + 4 * lane + (rh * NRBH) * NB * 256;
+        const float *olc = opl + cur * OPF + 4 * lane;
         f4 stage[2][2];
         f4 aq[2][NRBH];
 #pragma unroll
-        for (int i = 0; i < NRBH; ++i) aq[0][i] = *reinterpret_cast<const f4 *>(olc + (i * NB) * 256);
+        for (int i = 0; i < NRBH; ++i)
+            if (!TRI || kbs[i] > 0) aq[0][i] = *reinterpret_cast<const f4 *>(olc + (rbs[i] * NB) * 256);
         // The next offset's loads are issued unconditionally (on the last offset
         // they re-read the current one into the idle buffer): a branch around
         // them would make the wait for a chunk cover every newer load.  Chunks
@@ -639,14 +655,16 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
             if (b + 1 < NB)
 #pragma unroll
                 for (int i = 0; i < NRBH; ++i)
-                    aq[(b + 1) & 1][i] = *reinterpret_cast<const f4 *>(olc + (i * NB + b + 1) * 256);
+                    if (!TRI || b + 1 < kbs[i])
+                        aq[(b + 1) & 1][i] = *reinterpret_cast<const f4 *>(olc + (rbs[i] * NB + b + 1) * 256);
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
                 for (int i = 0; i < NRBH; ++i)
+                    if (!TRI || b < kbs[i])
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        acc[i][c] = Mfma<float>::op(aq[b & 1][i][s4], B[b][c][s4], acc[i][c]);
+                        for (int c = 0; c < 3; ++c)
+                            acc[i][c] = Mfma<float>::op(aq[b & 1][i][s4], B[b][c][s4], acc[i][c]);
             __builtin_amdgcn_sched_barrier(0);
             load_b(b, spn);
             __builtin_amdgcn_sched_barrier(0);
@@ -659,7 +677,7 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
                        : dst + size_t(t) * per_cell;
 #pragma unroll
     for (int i = 0; i < NRBH; ++i) {
-        const int rb = rh * NRBH + i;
+        const int rb = rbs[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -807,7 +825,7 @@ int translate_splits(int level, int ttn, int kp, size_t part_elems) {
 template <typename T>
 hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, int p, int kp, const T *ops,
                             const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
-                            int accumulate, T *part, size_t part_elems, const T *zero_cell) {
+                            int accumulate, T *part, size_t part_elems, const T *zero_cell, int tri) {
     const int C = (p + 1) * (p + 1);
     const int nrb = tr_nrb(C);
     const int nrbw = nrb / kTrWaves;
@@ -832,19 +850,46 @@ hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, in
             T *pbuf = nsplit > 1 ? part : nullptr;
             const dim3 g3(unsigned((ncell + 63) / 64 * 8), unsigned(nsplit));
             const int nks = tr_nks(C);
-            if (nb == 8) {
-                const size_t smem = 2 * sizeof(float) * size_t(2 * 4 * 8 * 256);
-                hipLaunchKernelGGL((k_m2l_os<4, 8>), g3, dim3(kTrThreads), smem, s, level, periodic, C, kp, nrb,
-                                   nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, pbuf, zero_cell);
-            } else if (nb == 6) {
-                const size_t smem = 2 * sizeof(float) * size_t(2 * 3 * 6 * 256);
-                hipLaunchKernelGGL((k_m2l_os<3, 6>), g3, dim3(kTrThreads), smem, s, level, periodic, C, kp, nrb,
-                                   nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, pbuf, zero_cell);
-            } else {
-                const size_t smem = 2 * sizeof(float) * size_t(2 * 2 * 4 * 256);
-                hipLaunchKernelGGL((k_m2l_os<2, 4>), g3, dim3(kTrThreads), smem, s, level, periodic, C, kp, nrb,
-                                   nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, pbuf, zero_cell);
+            // truncated operators: k blocks each row block needs, and a split of the
+            // row blocks over the two wave halves with balanced k blocks
+            uint32_t rbmap = 0, kbmap = 0;
+            if (tri) {
+                int need[8], half_cost[2] = {0, 0}, half_n[2] = {0, 0};
+                for (int rb = 0; rb < 2 * nrbh; ++rb) {
+                    int nmin = 0;
+                    while ((nmin + 1) * (nmin + 1) <= 16 * rb) ++nmin;
+                    const int cols = 16 * rb < C ? (p - nmin + 1) * (p - nmin + 1) : 0;
+                    need[rb] = std::min(nb, (cols + 15) / 16);
+                }
+                int order[8];
+                for (int i = 0; i < 2 * nrbh; ++i) order[i] = i;
+                std::stable_sort(order, order + 2 * nrbh, [&](int a, int b) { return need[a] > need[b]; });
+                for (int k = 0; k < 2 * nrbh; ++k) {
+                    const int rb = order[k];
+                    int hh = half_cost[0] <= half_cost[1] ? 0 : 1;
+                    if (half_n[hh] == nrbh) hh ^= 1;
+                    const int slot = hh * nrbh + half_n[hh]++;
+                    half_cost[hh] += need[rb];
+                    rbmap |= uint32_t(rb) << (4 * slot);
+                    kbmap |= uint32_t(need[rb]) << (4 * slot);
+                }
             }
+#define VM_M2L_OS(NRBH_, NB_)                                                                                  \
+    do {                                                                                                        \
+        const size_t smem = 2 * sizeof(float) * size_t(2 * NRBH_ * NB_ * 256);                                \
+        if (tri)                                                                                                \
+            hipLaunchKernelGGL((k_m2l_os<NRBH_, NB_, true>), g3, dim3(kTrThreads), smem, s, level, periodic, C, \
+                               kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, pbuf,      \
+                               zero_cell, rbmap, kbmap);                                                        \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_m2l_os<NRBH_, NB_, false>), g3, dim3(kTrThreads), smem, s, level, periodic,   \
+                               C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, pbuf,   \
+                               zero_cell, rbmap, kbmap);                                                        \
+    } while (0)
+            if (nb == 8) VM_M2L_OS(4, 8);
+            else if (nb == 6) VM_M2L_OS(3, 6);
+            else VM_M2L_OS(2, 4);
+#undef VM_M2L_OS
             hipError_t e = hipGetLastError();
             if (e != hipSuccess || nsplit == 1) return e;
             const int64_t nelem = (int64_t(1) << (3 * level)) * 3 * kp;
@@ -886,7 +931,7 @@ hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, cons
                                       double, double, const DevTables &, const T *, double *);              \
     template hipError_t launch_translate<T>(hipStream_t, int, int, int, int, int, const T *,                \
                                             const int16_t *, const int8_t *, const T *, T *, int, T *,      \
-                                            size_t, const T *);                                             \
+                                            size_t, const T *, int);                                        \
     template hipError_t launch_lattice<T>(hipStream_t, int, int, const double *, const T *, T *);
 VM_INST(double)
 VM_INST(float)

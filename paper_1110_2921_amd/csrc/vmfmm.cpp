@@ -88,7 +88,19 @@ struct OpSet {
     DevBuf m2lT64, m2lT32, m2mT64, m2mT32, l2lT64, l2lT32;
     DevBuf t_idx, t_w64, t_w32, g_idx, g_w64, g_w32;
     int width_t = 0, width_g = 0;
+    // M2L operators truncated to n + n' <= p, and their transposes (built on first use)
+    bool tri_ready = false, tri_adj_ready = false;
+    DevBuf m2lt64, m2lt32, m2lTt64, m2lTt32;
 };
+
+// Zeroes the entries of a C x C operator that pair target degree n (row) with
+// source degree n' (column) beyond n + n' <= p.
+void triangular(std::vector<double> &m, int C, int p) {
+    auto deg = [](int i) { int n = 0; while ((n + 1) * (n + 1) <= i) ++n; return n; };
+    for (int i = 0; i < C; ++i)
+        for (int j = 0; j < C; ++j)
+            if (deg(i) + deg(j) > p) m[size_t(i) * C + j] = 0.0;
+}
 
 }  // namespace
 
@@ -335,6 +347,38 @@ vm_status ensure_adj_ops(vm_ctx *ctx, OpSet *set) {
     return VM_OK;
 }
 
+// M2L operators truncated to n + n' <= p (forward: `adjoint` 0; transposed: 1).
+vm_status ensure_tri_ops(vm_ctx *ctx, OpSet *set, int adjoint) {
+    if (adjoint ? set->tri_adj_ready : set->tri_ready) return VM_OK;
+    const int p = set->p;
+    const int C = ncoef(p);
+    const size_t frag = tr_frag(C);
+    const OffsetTable &t = offset_table();
+    std::vector<double> m(size_t(C) * C), mt(size_t(C) * C);
+    std::vector<double> o64(316 * frag);
+    std::vector<float> o32(316 * frag);
+    for (int i = 0; i < 316; ++i) {
+        // forward: offset d (source - target) takes T(-d); the adjoint gather T(d)^T
+        const double sg = adjoint ? 1.0 : -1.0;
+        const double D[3] = {sg * double(t.d[i][0]), sg * double(t.d[i][1]), sg * double(t.d[i][2])};
+        m2l_matrix(p, D, 1.0, 1.0, m.data());
+        triangular(m, C, p);
+        if (adjoint) {
+            for (int a = 0; a < C; ++a)
+                for (int b = 0; b < C; ++b) mt[size_t(b) * C + a] = m[size_t(a) * C + b];
+            swizzle(mt, C, o64, i * frag);
+            swizzle(mt, C, o32, i * frag);
+        } else {
+            swizzle(m, C, o64, i * frag);
+            swizzle(m, C, o32, i * frag);
+        }
+    }
+    VM_HIP(upload(adjoint ? set->m2lTt64 : set->m2lt64, o64), "upload truncated M2L");
+    VM_HIP(upload(adjoint ? set->m2lTt32 : set->m2lt32, o32), "upload truncated M2L");
+    (adjoint ? set->tri_adj_ready : set->tri_ready) = true;
+    return VM_OK;
+}
+
 vm_status ensure_lattice_t(vm_ctx *ctx, int p, int K, const double **out) {
     const auto key = std::make_pair(p, K);
     auto it = ctx->lattice_t.find(key);
@@ -367,6 +411,8 @@ vm_status check_common(vm_ctx *ctx, int64_t n, double sigma, int level, const vm
     if (opts->periodic < 0 || opts->periodic > 4) return fail(ctx, VM_EINVAL, "periodic out of range [0, 4]");
     if (opts->precision != VM_FP64 && opts->precision != VM_MIXED)
         return fail(ctx, VM_EINVAL, "unknown precision");
+    if (opts->truncation != VM_SQUARE && opts->truncation != VM_TRIANGULAR)
+        return fail(ctx, VM_EINVAL, "unknown truncation");
     return VM_OK;
 }
 
@@ -619,6 +665,8 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     if (vm_status st = ensure_tables(ctx); st != VM_OK) return st;
     OpSet *ops = nullptr;
     if (vm_status st = ensure_ops(ctx, p, &ops); st != VM_OK) return st;
+    if (opts->truncation == VM_TRIANGULAR)
+        if (vm_status st = ensure_tri_ops(ctx, ops, 0); st != VM_OK) return st;
     const double *tlat = nullptr;
     if (K >= 2)
         if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
@@ -688,7 +736,9 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
             const bool f32 = sizeof(T) == 4;
             T *M = ctx->mbuf.as<T>(), *L = ctx->lbuf.as<T>();
             auto lev = [&](T *b, int l) { return b + size_t(((int64_t(1) << (3 * l)) - 1) / 7) * 3 * kp; };
-            const T *m2l = f32 ? (const T *)ops->m2l32.ptr : (const T *)ops->m2l64.ptr;
+            const int tri = opts->truncation == VM_TRIANGULAR;
+            const T *m2l = tri ? (f32 ? (const T *)ops->m2lt32.ptr : (const T *)ops->m2lt64.ptr)
+                               : (f32 ? (const T *)ops->m2l32.ptr : (const T *)ops->m2l64.ptr);
             const T *m2m = f32 ? (const T *)ops->m2m32.ptr : (const T *)ops->m2m64.ptr;
             const T *l2l = f32 ? (const T *)ops->l2l32.ptr : (const T *)ops->l2l64.ptr;
             const int16_t *lists = ctx->octlists.as<int16_t>();
@@ -717,7 +767,7 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                 Timed tm(ctx, VM_PH_M2L);
                 VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
                                            have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
-                                           ctx->zeros.as<T>()),
+                                           ctx->zeros.as<T>(), tri),
                        "M2L");
                 have_parent = true;
             }
@@ -856,6 +906,8 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
     const int C = ncoef(p), kp = coef_stride(C);
     OpSet *ops = ctx->ops[p].get();
     if (vm_status e = ensure_adj_ops(ctx, ops); e != VM_OK) return e;
+    if (opts->truncation == VM_TRIANGULAR)
+        if (vm_status e = ensure_tri_ops(ctx, ops, 1); e != VM_OK) return e;
     const double *tlat_t = nullptr;
     if (K >= 2)
         if (vm_status e = ensure_lattice_t(ctx, p, K, &tlat_t); e != VM_OK) return e;
@@ -883,7 +935,9 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
             const bool f32 = sizeof(T) == 4;
             T *Mb = ctx->mbuf.as<T>(), *Lb = ctx->lbuf.as<T>();   // adjoints overwrite the forward state
             auto lev = [&](T *b, int l) { return b + size_t(((int64_t(1) << (3 * l)) - 1) / 7) * 3 * kp; };
-            const T *m2lT = f32 ? (const T *)ops->m2lT32.ptr : (const T *)ops->m2lT64.ptr;
+            const int tri = opts->truncation == VM_TRIANGULAR;
+            const T *m2lT = tri ? (f32 ? (const T *)ops->m2lTt32.ptr : (const T *)ops->m2lTt64.ptr)
+                                : (f32 ? (const T *)ops->m2lT32.ptr : (const T *)ops->m2lT64.ptr);
             const T *m2mT = f32 ? (const T *)ops->m2mT32.ptr : (const T *)ops->m2mT64.ptr;
             const T *l2lT = f32 ? (const T *)ops->l2lT32.ptr : (const T *)ops->l2lT64.ptr;
             const T *tw = f32 ? (const T *)ops->t_w32.ptr : (const T *)ops->t_w64.ptr;
@@ -912,7 +966,7 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
                            "M2M^T");
                 VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2lT, lists, offs, lev(Lb, l), lev(Mb, l),
                                            parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
-                                           ctx->zeros.as<T>()),
+                                           ctx->zeros.as<T>(), tri),
                        "M2L^T");
                 parent = true;
             }

@@ -48,6 +48,10 @@ def _run(ctx, x, a, sigma, p, level, periodic, precision="fp64", scheme="classic
     return u.cpu().numpy().T, da.cpu().numpy().T, J.cpu().numpy().T.reshape(-1, 3, 3)
 
 
+def _host(t):
+    return t.cpu().numpy().T
+
+
 def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
@@ -237,3 +241,38 @@ def test_invalid_arguments_are_rejected(ctx):
     with pytest.raises(vm._lib.VmError) as e:
         ctx.eval(_dev(xb), _dev(a), 0.1, 4, 2, check_domain=True)
     assert e.value.status == vm._lib.VM_EDOMAIN
+
+
+@pytest.mark.parametrize("p", [6, 8, 10])
+def test_triangular_truncation_matches_oracle(ctx, p):
+    """M2L truncated to n + n' <= p: FP64 against the oracle with the same
+    truncation (1e-10); the mixed form (whose operator-stationary M2L skips
+    the zero tiles, three kernel shapes for p = 6, 8, 10) against FP64 within
+    the usual 1e-5 / 1e-4."""
+    x, a = W.random_field(16, 4.0, 61)
+    h = L / 16
+    kw = dict(periodic=3, want_grad=True, truncation="triangular")
+    u, da, J = ctx.eval(_dev(x), _dev(a), h, p, 2, **kw)
+    uo, Jo = OF.fmm(x, a, h, p, 2, periodic=3, truncation="triangular")
+    u, J = _host(u), _host(J).reshape(-1, 3, 3)
+    assert rel(u, uo) < 1e-10 and rel(J, Jo) < 1e-10
+    um, _, Jm = ctx.eval(_dev(x), _dev(a), h, p, 2, precision="mixed", **kw)
+    assert rel(_host(um), u) < 1e-5
+    assert rel(_host(Jm).reshape(-1, 3, 3), J) < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_triangular_adjoint_is_the_transpose(ctx, precision):
+    """u is linear in alpha, so <u_bar, u(alpha)> = <alpha_bar(u_bar), alpha> for
+    the discrete adjoint of the truncated FMM (FP64 to round-off; mixed within
+    its 1e-5)."""
+    import torch
+    x, a = W.random_field(16, 4.0, 62)
+    h = L / 16
+    ub = np.random.default_rng(63).standard_normal(a.shape)
+    u, _, _ = ctx.eval(_dev(x), _dev(a), h, 8, 2, periodic=3, precision=precision, truncation="triangular")
+    _, ab = ctx.adjoint(_dev(x), _dev(a), _dev(ub), h, 8, 2, periodic=3, precision=precision,
+                        want_x=False, truncation="triangular")
+    lhs = float(np.sum(ub * _host(u)))
+    rhs = float(np.sum(_host(ab) * a))
+    assert abs(lhs - rhs) < (1e-12 if precision == "fp64" else 1e-5) * abs(lhs)

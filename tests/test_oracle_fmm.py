@@ -98,19 +98,25 @@ def _model(x, a, sigma, level, periodic):
     return D.direct(tr["xw"], tr["xw"], a, sigma, L, K=periodic, cells_t=c, cells_s=c, level=level)
 
 
+@pytest.mark.parametrize("truncation", ["square", "triangular"])
 @pytest.mark.parametrize("periodic", [0, 1, 2])
-def test_fmm_converges_to_far_field_model(periodic):
+def test_fmm_converges_to_far_field_model(periodic, truncation):
+    """Square truncation: error ratio below 1/4 per three degrees.  The
+    triangular one converges at the slower rate of its error bound, governed by
+    (a + b) / R = 0.87 per degree for cells one cell apart against
+    a / (R - b) = 0.76 for the square form: below 1/2.5 per three degrees."""
     x, a = W.random_particles(300, 21)
     sigma = 0.2
     u0, J0 = _model(x, a, sigma, 2, periodic)
     eu, ej = [], []
     for p in (3, 6, 9):
-        u, J = F.fmm(x, a, sigma, p, 2, periodic=periodic)
+        u, J = F.fmm(x, a, sigma, p, 2, periodic=periodic, truncation=truncation)
         eu.append(np.linalg.norm(u - u0) / np.linalg.norm(u0))
         ej.append(np.linalg.norm(J - J0) / np.linalg.norm(J0))
-    assert eu[1] < eu[0] / 4 and eu[2] < eu[1] / 4
-    assert ej[1] < ej[0] / 4 and ej[2] < ej[1] / 4
-    assert eu[2] < 2e-4 and ej[2] < 2e-4
+    f, last = (4, 2e-4) if truncation == "square" else (2.5, 2e-3)
+    assert eu[1] < eu[0] / f and eu[2] < eu[1] / f
+    assert ej[1] < ej[0] / f and ej[2] < ej[1] / f
+    assert eu[2] < last and ej[2] < last
 
 
 def test_fmm_without_far_field_is_direct_sum():
@@ -188,3 +194,17 @@ def test_fmm_at_points_converges_to_far_field_model(periodic):
     assert ej[1] < ej[0] / 4 and ej[2] < ej[1] / 4
     # 60 points: the worst-placed ones weigh more than among 300 particles
     assert eu[2] < 5e-4 and ej[2] < 5e-4
+
+
+def test_triangular_truncation_keeps_low_total_degree():
+    """n + n' <= p keeps 2926 of the 14641 products per component at p = 10;
+    below that bound the triangular operators equal the square ones."""
+    import oracle.harmonics as Hm
+    deg = np.floor(np.sqrt(np.arange(Hm.ncoef(10)) + 0.5)).astype(int)
+    assert int(((deg[:, None] + deg[None, :]) <= 10).sum()) == 2926
+    sq = F._m2l_matrices(2, 6, L)
+    tr = F._m2l_matrices(2, 6, L, "triangular")
+    d6 = deg[:Hm.ncoef(6)]
+    keep = (d6[:, None] + d6[None, :]) <= 6
+    for off in list(sq)[:20]:
+        assert np.array_equal(tr[off][keep], sq[off][keep]) and not np.any(tr[off][~keep])
