@@ -293,8 +293,8 @@ def main():
     p2p_flop = P2P_FLOP_PER_PAIR[args.precision] * pairs
     f32 = args.precision == "mixed"
     esz = 4 if f32 else 8
-    m2l_kernel = "k_m2l_os<4,8>" if (f32 and w.p in (9, 10)) else ("k_translate<double,1,1,0,24>" if not f32
-                                                                 else "k_m2l_os")
+    m2l_kernel = "k_m2l_os<4,8,false>" if (f32 and w.p in (9, 10)) else ("k_translate<double,1,1,0,24>"
+                                                                       if not f32 else "k_m2l_os")
     m2l_traffic = measured_traffic(w.name, args.precision, m2l_kernel)
     # algorithmic bytes of the M2L phase: read M, read and write L at every level, the operators once
     cells = sum(8 ** l for l in range(1 if w.periodic else 2, w.level + 1))
@@ -447,11 +447,12 @@ def main():
         ctx.set_timing(False)
         gauss_ms = ph["gauss"][0] / ph["gauss"][1]
         products = ph["gauss"][1] / reps
-        gauss_kernel = "k_gauss<float,Part32>" if f32 else "k_gauss<double,Part64>"
+        gauss_kernel = "k_gauss<float,vmfmm::Part32>" if f32 else "k_gauss<double,vmfmm::Part64>"
         roof_gauss = {"bound": "alu", "kernel": gauss_kernel + " (with the strength packing)",
                       "achieved": GAUSS_FLOP_PER_PAIR * pairs / (gauss_ms * 1e-3) / 1e12,
                       "peak": PEAKS["valu_f32_tflops" if f32 else "valu_f64_tflops"], "unit": "TFLOP/s",
-                      "traffic": None}
+                      "traffic": measured_traffic(w.name, args.precision, gauss_kernel),
+                      "traffic_unit": "bytes per launch"}
         roof_gauss["frac"] = roof_gauss["achieved"] / roof_gauss["peak"]
         result["rbf"] = {"ms": 1e3 * tr, "iterations": iters, "products": products, "resid": resid,
                          "tol": 1e-3, "precision": args.precision, "gauss_ms_per_product": gauss_ms,
