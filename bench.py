@@ -197,6 +197,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-rbf", action="store_true")
     ap.add_argument("--no-truncation", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--loop-steps", type=int, default=10,
                     help="steps of the paper's time loop to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -520,6 +521,42 @@ def main():
             f"{1e3 * tl / args.loop_steps:.1f} ms/step ({prods} GMRES products)")
         x.copy_(x0)
         a.copy_(a0)
+
+    if not args.no_graph:
+        # a small problem (32^3, p = 8) is launch-bound: one evaluation eagerly and
+        # replayed from a HIP graph captured on the library's stream
+        ws = W.WORKLOADS["rand32_periodic"]
+        xs_np, as_np = W.make(ws)
+        xs = torch.from_numpy(np.ascontiguousarray(xs_np.T)).to(dev)
+        as_ = torch.from_numpy(np.ascontiguousarray(as_np.T)).to(dev)
+        us = torch.empty((3, ws.n), dtype=torch.float64, device=dev)
+        das = torch.empty_like(us)
+        skw = dict(periodic=ws.periodic, box_len=ws.box_len, precision=args.precision, out=(us, das, None))
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            for _ in range(3):
+                ctx.eval(xs, as_, ws.sigma, ws.p, ws.level, **skw)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=st):
+            ctx.eval(xs, as_, ws.sigma, ws.p, ws.level, **skw)
+        torch.cuda.synchronize()
+        reps = 50
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.eval(xs, as_, ws.sigma, ws.p, ws.level, **skw)
+        torch.cuda.synchronize()
+        te = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - t0) / reps
+        result["graph_small"] = {"workload": f"{ws.name}: N={ws.ng}^3, p={ws.p}, level {ws.level}",
+                                 "eager_ms": 1e3 * te, "graph_ms": 1e3 * tg,
+                                 "what": "one evaluation, eager (host launches) and replayed from a captured HIP graph"}
+        log(f"[bench] 32^3 evaluation: eager {1e3 * te:.3f} ms, graph replay {1e3 * tg:.3f} ms")
+        del graph, xs, as_, us, das
 
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

@@ -28,7 +28,14 @@
  *     run in stream order;
  *   - argument errors return VM_EINVAL before anything is launched; HIP
  *     failures return VM_EDEVICE; allocation failures VM_ENOMEM; the text
- *     of the last error is kept in the context (vm_last_error).
+ *     of the last error is kept in the context (vm_last_error);
+ *   - graph capture: after one call with the same sizes and options (which
+ *     grows the workspace and builds the operator caches), vm_fmm_eval,
+ *     vm_fmm_eval_at, vm_rk2_step and vm_run without reinitialisation enqueue
+ *     kernels only -- no allocation, copy, memset or host synchronisation --
+ *     when check_domain is 0 and timing is off, so the caller may capture them
+ *     into a HIP graph on the context's stream and replay it.  The solvers
+ *     (vm_rbf_solve, vm_reinit) synchronise and cannot be captured.
  */
 #ifndef VMFMM_H
 #define VMFMM_H
