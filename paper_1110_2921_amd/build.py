@@ -1,6 +1,6 @@
 """Builds ``libvmfmm.so`` (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
 
-Usage: ``python -m paper_1110_2921_amd.build`` (or ``__graft_entry__.build()``).
+Usage: ``python -m paper_1110_2921_amd.build``.
 """
 from __future__ import annotations
 
