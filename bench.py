@@ -198,6 +198,7 @@ def main():
     ap.add_argument("--no-rbf", action="store_true")
     ap.add_argument("--no-truncation", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tuning", action="store_true")
     ap.add_argument("--loop-steps", type=int, default=10,
                     help="steps of the paper's time loop to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -521,6 +522,14 @@ def main():
             f"{1e3 * tl / args.loop_steps:.1f} ms/step ({prods} GMRES products)")
         x.copy_(x0)
         a.copy_(a0)
+
+    if not args.no_tuning:
+        # auto-tuned leaf level for the benchmark's particles (leaves >= 4 sigma)
+        lv, lms = ctx.tune_level(x0, a0, w.sigma, w.p, periodic=w.periodic, box_len=w.box_len,
+                                 precision=args.precision)
+        result["level_tuning"] = {"level": lv, "ms_per_level": {str(k): v for k, v in sorted(lms.items())},
+                                  "what": "fastest leaf level with leaves at least 4 sigma wide (vm_tune_level)"}
+        log(f"[bench] tuned leaf level {lv}: " + ", ".join(f"level {k} {v:.1f} ms" for k, v in sorted(lms.items())))
 
     if not args.no_graph:
         # a small problem (32^3, p = 8) is launch-bound: one evaluation eagerly and

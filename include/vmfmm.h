@@ -315,6 +315,25 @@ vm_status vm_run(vm_ctx *ctx, int64_t n, double *x, double *alpha, double *sigma
 vm_status vm_energy_spectrum(vm_ctx *ctx, int ng, const double *u, int kmax, double *E);
 
 /*
+ * Auto-tuned leaf level (Sec. 3.2: the number of tree levels that gives the
+ * shortest runtime depends on the problem and the hardware, and is chosen
+ * without user input).  Candidates are the levels whose leaf width
+ * box_len 2^-level is at least min_leaf_sigmas sigma -- the far field drops
+ * the cutoff beyond the adjacent leaves, and 4 sigma keeps that model error
+ * near 5e-7 on the lattice workloads -- and with no more leaves than
+ * particles, tried from the finest towards coarser ones while the time falls.  Each candidate runs vm_fmm_eval once untimed
+ * (workspace, caches) and `reps` times timed with HIP events on the context's
+ * stream, with the given p and options (velocity and stretching into context
+ * scratch).  Synchronises.
+ *   level  out: the fastest level tried
+ *   ms     out or NULL: [VM_MAX_LEVEL + 1] milliseconds per evaluation of each
+ *          level tried, -1 for the others
+ * Errors as vm_fmm_eval; VM_EINVAL for min_leaf_sigmas <= 0 or reps outside 1..100.
+ */
+vm_status vm_tune_level(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                        const vm_opts *opts, double min_leaf_sigmas, int reps, int *level, double *ms);
+
+/*
  * Device-time accounting (HIP events on the context's stream around every
  * launch).  vm_set_timing(ctx, 1) starts a fresh account (and 0 stops it);
  * vm_get_timing reports, summed over every vm_fmm_eval since then, the

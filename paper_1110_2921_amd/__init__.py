@@ -260,6 +260,23 @@ class FMM:
                                      ctypes.byref(prods), ctypes.byref(resid)))
         return sg.value, (diag[:steps] if diag is not None else None), prods.value, resid.value
 
+    def tune_level(self, x, alpha, sigma, p, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi,
+                   precision="mixed", min_leaf_sigmas=4.0, reps=2, truncation="square", stream=None):
+        """Fastest admissible leaf level for these particles: (level, {level: ms})."""
+        torch = self._torch
+        x = _soa(x, torch)
+        alpha = _soa(alpha, torch)
+        n = x.shape[1]
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        opts = self._opts(periodic, box_lo, box_len, precision, "classic", False, truncation)
+        level = ctypes.c_int(-1)
+        ms = np.zeros(11, np.float64)
+        self._check(self._lib.vm_tune_level(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p),
+                                            ctypes.byref(opts), float(min_leaf_sigmas), int(reps),
+                                            ctypes.byref(level), ctypes.c_void_p(ms.ctypes.data)))
+        return level.value, {l: float(v) for l, v in enumerate(ms) if v >= 0}
+
     def energy_spectrum(self, u, ng, kmax, stream=None):
         """Shell energy spectrum E[0..kmax] (CUDA float64) of a velocity (3, ng^3)
         on the ng^3 lattice of the periodic cube (x index slowest)."""

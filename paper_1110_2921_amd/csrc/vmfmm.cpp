@@ -1383,6 +1383,68 @@ vm_status vm_energy_spectrum(vm_ctx *ctx, int ng, const double *u, int kmax, dou
     return VM_OK;
 }
 
+vm_status vm_tune_level(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                        const vm_opts *opts, double min_leaf_sigmas, int reps, int *level, double *ms) {
+    if (!ctx) return VM_EINVAL;
+    if (!level) return fail(ctx, VM_EINVAL, "level must be non-NULL");
+    if (vm_status st = check_common(ctx, n, sigma, 0, opts); st != VM_OK) return st;
+    if (!(min_leaf_sigmas > 0.0) || !std::isfinite(min_leaf_sigmas))
+        return fail(ctx, VM_EINVAL, "min_leaf_sigmas must be positive");
+    if (reps < 1 || reps > 100) return fail(ctx, VM_EINVAL, "reps out of range [1, 100]");
+    if (ms)
+        for (int l = 0; l <= VM_MAX_LEVEL; ++l) ms[l] = -1.0;
+    // the finest level whose leaves are at least min_leaf_sigmas sigma wide and
+    // not more numerous than the particles
+    int lmax = 0;
+    while (lmax < VM_MAX_LEVEL && std::ldexp(opts->box_len, -(lmax + 1)) >= min_leaf_sigmas * sigma &&
+           (int64_t(1) << (3 * (lmax + 1))) <= n)
+        ++lmax;
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t bytes = sizeof(double) * 3 * size_t(n);
+    VM_HIP(ctx->rk_u.reserve(bytes), "alloc tuning");
+    VM_HIP(ctx->rk_s.reserve(bytes), "alloc tuning");
+    hipEvent_t e0, e1;
+    VM_HIP(hipEventCreate(&e0), "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, VM_EDEVICE, "event");
+    }
+    // from the finest admissible level towards coarser ones while the time falls
+    // (each coarser level has 8x the near-field pairs per leaf)
+    double best = -1.0, prev = -1.0;
+    int arg = lmax;
+    vm_status st = VM_OK;
+    for (int l = lmax; l >= 0; --l) {
+        // one untimed call grows the workspace and builds the caches for this level
+        st = vm_fmm_eval(ctx, n, x, alpha, sigma, p, l, opts, ctx->rk_u.as<double>(), ctx->rk_s.as<double>(), nullptr);
+        if (st != VM_OK) break;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = fail(ctx, VM_EDEVICE, "event"); break; }
+        for (int r = 0; r < reps && st == VM_OK; ++r)
+            st = vm_fmm_eval(ctx, n, x, alpha, sigma, p, l, opts, ctx->rk_u.as<double>(), ctx->rk_s.as<double>(),
+                             nullptr);
+        if (st != VM_OK) break;
+        float t = 0.0f;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+            st = fail(ctx, VM_EDEVICE, "event timing");
+            break;
+        }
+        const double avg = double(t) / reps;
+        if (ms) ms[l] = avg;
+        if (best < 0.0 || avg < best) {
+            best = avg;
+            arg = l;
+        }
+        if (prev >= 0.0 && avg > prev) break;
+        prev = avg;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != VM_OK) return st;
+    *level = arg;
+    return VM_OK;
+}
+
 vm_status vm_set_timing(vm_ctx *ctx, int enable) {
     if (!ctx) return VM_EINVAL;
     ctx->timing = enable != 0;

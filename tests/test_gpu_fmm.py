@@ -276,3 +276,22 @@ def test_triangular_adjoint_is_the_transpose(ctx, precision):
     lhs = float(np.sum(ub * _host(u)))
     rhs = float(np.sum(_host(ab) * a))
     assert abs(lhs - rhs) < (1e-12 if precision == "fp64" else 1e-5) * abs(lhs)
+
+
+def test_level_tuning(ctx):
+    """The tuner tries the finest level with leaves >= 4 sigma (and no more
+    leaves than particles) and coarser ones while the time falls, and returns
+    the fastest it tried; clustered particles in free space as well."""
+    import paper_1110_2921_amd as vm
+    w = W.WORKLOADS["rand32_periodic"]
+    x, a = W.make(w)
+    lv, ms = ctx.tune_level(_dev(x), _dev(a), w.sigma, w.p, periodic=w.periodic, box_len=w.box_len)
+    assert max(ms) == 3 and lv in ms and ms[lv] == min(ms.values())
+    rng = np.random.default_rng(81)
+    xc = 2.0 + rng.uniform(0.0, 1.0, size=(20000, 3))
+    ac = rng.standard_normal((20000, 3))
+    lv, ms = ctx.tune_level(_dev(xc), _dev(ac), 0.05, 6, periodic=0)
+    assert max(ms) == 4 and lv in ms and ms[lv] == min(ms.values())
+    for kw in ({"min_leaf_sigmas": 0.0}, {"reps": 0}):
+        with pytest.raises(vm._lib.VmError):
+            ctx.tune_level(_dev(x), _dev(a), w.sigma, w.p, periodic=w.periodic, **kw)
