@@ -145,6 +145,22 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
                          int level, const vm_opts *opts, const double *u_bar, double *x_bar, double *alpha_bar);
 
 /*
+ * vm_fmm_adjoint without the forward recomputation: the tree (leaf ranges,
+ * permutation, sorted records) is taken from the context and the total
+ * gradient from `grad` (device [9][n], the grad output of that evaluation).
+ * Valid only right after vm_fmm_eval on this context with the same x, alpha
+ * (pointers), n, sigma, p, level and opts (box, periodic, precision,
+ * truncation), no tree-building call in between, and x, alpha and grad
+ * unchanged since (the caller's responsibility); otherwise VM_EINVAL ("the
+ * context's last evaluation is not this one") before anything is launched.
+ * Further adjoints of the same evaluation may follow.  Results equal
+ * vm_fmm_adjoint's bit for bit.
+ */
+vm_status vm_fmm_adjoint_reuse(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                               int level, const vm_opts *opts, const double *grad, const double *u_bar,
+                               double *x_bar, double *alpha_bar);
+
+/*
  * One step of Heun's method (explicit trapezoidal RK2) for the convection and
  * stretching ODEs (eqs. 7-8; the paper integrates them with forward Euler,
  * Sec. 4.1).  With (u, s) = vm_fmm_eval(x, alpha) (s the opts->scheme form):

@@ -122,8 +122,12 @@ class FMM:
 
     def adjoint(self, x, alpha, u_bar, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0),
                 box_len=2 * math.pi, precision="fp64", want_x=True, want_alpha=True, stream=None,
-                truncation="square"):
-        """(x_bar, alpha_bar), each (3, n) or None: the transposed FMM applied to u_bar."""
+                truncation="square", grad=None):
+        """(x_bar, alpha_bar), each (3, n) or None: the transposed FMM applied to u_bar.
+
+        With ``grad`` (the (9, n) gradient output of the context's last ``eval``
+        of the same x and alpha) the forward state is reused instead of
+        recomputed (``vm_fmm_adjoint_reuse``)."""
         torch = self._torch
         x = _soa(x, torch)
         alpha = _soa(alpha, torch)
@@ -133,6 +137,13 @@ class FMM:
         xb = torch.empty((3, n), dtype=torch.float64, device=x.device) if want_x else None
         ab = torch.empty((3, n), dtype=torch.float64, device=x.device) if want_alpha else None
         opts = self._opts(periodic, box_lo, box_len, precision, "classic", False, truncation)
+        if grad is not None:
+            self._check(self._lib.vm_fmm_adjoint_reuse(
+                self._h, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p),
+                int(level), ctypes.byref(opts), ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(u_bar.data_ptr()),
+                ctypes.c_void_p(xb.data_ptr() if xb is not None else 0),
+                ctypes.c_void_p(ab.data_ptr() if ab is not None else 0)))
+            return xb, ab
         self._check(self._lib.vm_fmm_adjoint(self._h, n, ctypes.c_void_p(x.data_ptr()),
                                              ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(level),
                                              ctypes.byref(opts), ctypes.c_void_p(u_bar.data_ptr()),
@@ -371,10 +382,14 @@ def _velocity_function():
 
         @staticmethod
         def forward(ctx, x, alpha, fmm, kw):
-            u, _, _ = fmm.eval(x, alpha, want_dalpha=False, **kw)
+            # the gradient output lets the backward pass reuse this evaluation's tree
+            need = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
+            u, _, J = fmm.eval(x, alpha, want_dalpha=False, want_grad=need, **kw)
             ctx.save_for_backward(x, alpha)
             ctx.fmm = fmm
             ctx.kw = kw
+            ctx.J = J
+            ctx.versions = (x._version, alpha._version)
             return u
 
         @staticmethod
@@ -382,8 +397,17 @@ def _velocity_function():
             x, alpha = ctx.saved_tensors
             kw = dict(ctx.kw)
             kw.pop("scheme", None)
-            xb, ab = ctx.fmm.adjoint(x, alpha, u_bar.contiguous(), want_x=ctx.needs_input_grad[0],
-                                     want_alpha=ctx.needs_input_grad[1], **kw)
+            args = dict(want_x=ctx.needs_input_grad[0], want_alpha=ctx.needs_input_grad[1], **kw)
+            u_bar = u_bar.contiguous()
+            if ctx.J is not None and ctx.versions == (x._version, alpha._version):
+                try:
+                    xb, ab = ctx.fmm.adjoint(x, alpha, u_bar, grad=ctx.J, **args)
+                    return xb, ab, None, None
+                except _lib.VmError as e:
+                    # the context evaluated something else since the forward pass
+                    if e.status != _lib.VM_EINVAL:
+                        raise
+            xb, ab = ctx.fmm.adjoint(x, alpha, u_bar, **args)
             return xb, ab, None, None
 
     return VortexFMM

@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "VM_OK", -1: "VM_EINVAL", -2: "VM_ENOMEM", -3: "VM_EDEVICE", 
 
 # every symbol include/vmfmm.h declares
 EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_eval", "vm_fmm_eval_at",
-           "vm_fmm_adjoint", "vm_rk2_step", "vm_diagnostics", "vm_gauss_sum", "vm_gauss_eval", "vm_rbf_solve",
+           "vm_fmm_adjoint", "vm_fmm_adjoint_reuse", "vm_rk2_step", "vm_diagnostics", "vm_gauss_sum", "vm_gauss_eval", "vm_rbf_solve",
            "vm_reinit", "vm_run", "vm_energy_spectrum", "vm_tune_level",
            "vm_set_timing", "vm_get_timing", "vm_debug_tree", "vm_debug_expansions", "vm_debug_far", "vm_debug_offsets", "vm_debug_list",
            "vm_debug_operator")
@@ -64,6 +64,9 @@ def load():
     lib.vm_fmm_eval.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(VmOpts), dp, dp, dp]
     lib.vm_fmm_eval.restype = ctypes.c_int
+    lib.vm_fmm_adjoint_reuse.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(VmOpts), dp, dp, dp, dp]
+    lib.vm_fmm_adjoint_reuse.restype = ctypes.c_int
     lib.vm_fmm_eval_at.argtypes = [vp, i64, dp, dp, i64, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(VmOpts), dp, dp]
     lib.vm_fmm_eval_at.restype = ctypes.c_int

@@ -125,6 +125,18 @@ struct vm_ctx {
     DevBuf spec_in, spec_U, spec_power, spec_start, spec_list;
     std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice_t;
     int layout_p = -1, layout_prec = -1;   // layout of mbuf/lbuf
+    // the particle tree's generation (bumped by every build) and what the last
+    // evaluation at the particles was called with, for vm_fmm_adjoint_reuse
+    uint64_t tree_gen = 0;
+    struct {
+        bool valid = false;
+        const double *x = nullptr, *alpha = nullptr;
+        int64_t n = 0;
+        double sigma = 0.0;
+        int p = 0, level = 0;
+        vm_opts opts{};
+        uint64_t gen = 0;
+    } last_eval;
     // results of the last evaluation, for the debug views
     uint32_t *last_keys = nullptr;
     int32_t *last_perm = nullptr;
@@ -497,6 +509,8 @@ vm_status build_tree(vm_ctx *ctx, const TreeBufs &b, int ni, const double *x, co
     VM_HIP(launch_permute(s, ni, x, alpha, vin, kin, g, mixed ? nullptr : b.p64->as<Part64>(),
                           mixed ? b.p32->as<Part32>() : nullptr), "permute");
     if (record) {
+        ++ctx->tree_gen;
+        ctx->last_eval.valid = false;
         ctx->last_keys = kin;
         ctx->last_perm = vin;
         ctx->last_n = int64_t(ni);
@@ -806,6 +820,18 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
         else VM_HIP(launch_p2p64(s, a, ctx->p64.as<Part64>()), "P2P");
     }
 
+    if (!y) {
+        auto &le = ctx->last_eval;
+        le.valid = true;
+        le.x = x;
+        le.alpha = alpha;
+        le.n = n;
+        le.sigma = sigma;
+        le.p = p;
+        le.level = level;
+        le.opts = *opts;
+        le.gen = ctx->tree_gen;
+    }
     return check_flag(ctx, opts);
 }
 
@@ -882,8 +908,16 @@ vm_status vm_fmm_eval_at(vm_ctx *ctx, int64_t n, const double *x, const double *
     return fmm_impl(ctx, n, x, alpha, m, y, sigma, p, level, opts, u, nullptr, grad);
 }
 
-vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
-                         int level, const vm_opts *opts, const double *u_bar, double *x_bar, double *alpha_bar) {
+}  // extern "C"
+
+namespace {
+
+// The transposed FMM (vm_fmm_adjoint).  J_in: the total gradient of the
+// evaluation whose tree the context still holds (the forward state is then
+// not recomputed), or nullptr.
+vm_status adjoint_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                       int level, const vm_opts *opts, const double *u_bar, double *x_bar, double *alpha_bar,
+                       const double *J_in) {
     if (!ctx) return VM_EINVAL;
     if (!u_bar) return fail(ctx, VM_EINVAL, "u_bar must be non-NULL");
     if (reinterpret_cast<uintptr_t>(u_bar) & 7u) return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
@@ -892,12 +926,17 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
     if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
     VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     const size_t v3 = sizeof(double) * 3 * size_t(n), v9 = sizeof(double) * 9 * size_t(n);
-    VM_HIP(ctx->adj_u.reserve(v3), "alloc adjoint");
-    VM_HIP(ctx->adj_J.reserve(v9), "alloc adjoint");
     // 1. forward state: tree, expansions, far field and the total gradient J
-    vm_status st = vm_fmm_eval(ctx, n, x, alpha, sigma, p, level, opts, ctx->adj_u.as<double>(), nullptr,
-                               ctx->adj_J.as<double>());
-    if (st != VM_OK) return st;
+    vm_status st = VM_OK;
+    const double *Jf = J_in;
+    if (!Jf) {
+        VM_HIP(ctx->adj_u.reserve(v3), "alloc adjoint");
+        VM_HIP(ctx->adj_J.reserve(v9), "alloc adjoint");
+        st = vm_fmm_eval(ctx, n, x, alpha, sigma, p, level, opts, ctx->adj_u.as<double>(), nullptr,
+                         ctx->adj_J.as<double>());
+        if (st != VM_OK) return st;
+        Jf = ctx->adj_J.as<double>();
+    }
     hipStream_t s = ctx->stream;
     const int mixed = opts->precision == VM_MIXED;
     const int K = opts->periodic, periodic = K > 0;
@@ -1006,10 +1045,36 @@ vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *
         VM_HIP(launch_p2p64(s, a, ctx->adj_p64.as<Part64>()), "P2P^T");
     }
     // 4. combine
-    VM_HIP(launch_adj_combine(s, ni, perm, u_bar, alpha, ctx->adj_J.as<double>(), ctx->adj_v.as<double>(),
+    VM_HIP(launch_adj_combine(s, ni, perm, u_bar, alpha, Jf, ctx->adj_v.as<double>(),
                               ctx->adj_Jv.as<double>(), far ? ctx->adj_far.as<double>() : nullptr, x_bar, alpha_bar),
            "adjoint combine");
     return VM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vm_status vm_fmm_adjoint(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                         int level, const vm_opts *opts, const double *u_bar, double *x_bar, double *alpha_bar) {
+    return adjoint_impl(ctx, n, x, alpha, sigma, p, level, opts, u_bar, x_bar, alpha_bar, nullptr);
+}
+
+vm_status vm_fmm_adjoint_reuse(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                               int level, const vm_opts *opts, const double *grad, const double *u_bar,
+                               double *x_bar, double *alpha_bar) {
+    if (!ctx) return VM_EINVAL;
+    if (!opts || !grad) return fail(ctx, VM_EINVAL, "opts and grad must be non-NULL");
+    if (misaligned(grad)) return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    const auto &le = ctx->last_eval;
+    const vm_opts &o = le.opts;
+    const bool same = le.valid && le.gen == ctx->tree_gen && le.x == x && le.alpha == alpha && le.n == n &&
+                      le.sigma == sigma && le.p == p && le.level == level && o.box_lo[0] == opts->box_lo[0] &&
+                      o.box_lo[1] == opts->box_lo[1] && o.box_lo[2] == opts->box_lo[2] &&
+                      o.box_len == opts->box_len && o.periodic == opts->periodic &&
+                      o.precision == opts->precision && o.truncation == opts->truncation;
+    if (!same) return fail(ctx, VM_EINVAL, "the context's last evaluation is not this one");
+    return adjoint_impl(ctx, n, x, alpha, sigma, p, level, opts, u_bar, x_bar, alpha_bar, grad);
 }
 
 vm_status vm_rk2_step(vm_ctx *ctx, int64_t n, double *x, double *alpha, double sigma, int p, int level,

@@ -241,3 +241,49 @@ def test_backward_case_at_full_size(ctx, precision):
     xm32, am32 = ctx.adjoint(_dev(x), _dev(a), ub, w.sigma, w.p, w.level, precision="mixed", **kw)
     assert rel(_host(am32), ab) < 1e-4
     assert rel(_host(xm32), xb) < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adjoint_reuse_matches_recompute(ctx, precision):
+    """vm_fmm_adjoint_reuse takes the tree and gradient of the context's last
+    evaluation and gives vm_fmm_adjoint's result bit for bit; a stale call is
+    rejected before anything runs."""
+    import torch
+    import paper_1110_2921_amd as vm
+    x, a, h = _case()
+    xt, at = _dev(x), _dev(a)
+    kw = dict(periodic=CASE["K"], precision=precision)
+    ub = _dev(np.random.default_rng(91).standard_normal(a.shape))
+    u, _, J = ctx.eval(xt, at, h, CASE["p"], CASE["level"], want_grad=True, want_dalpha=False, **kw)
+    xr, ar = ctx.adjoint(xt, at, ub, h, CASE["p"], CASE["level"], grad=J, **kw)
+    xr2, ar2 = ctx.adjoint(xt, at, ub, h, CASE["p"], CASE["level"], grad=J, **kw)   # again, same evaluation
+    xf, af = ctx.adjoint(xt, at, ub, h, CASE["p"], CASE["level"], **kw)
+    assert torch.equal(xr, xf) and torch.equal(ar, af)
+    assert torch.equal(xr2, xf) and torch.equal(ar2, af)
+    # the recomputing call above rebuilt the tree, and another evaluation or tree
+    # build in between invalidates the reuse
+    ctx.eval(xt, at, h, CASE["p"], CASE["level"], want_grad=True, want_dalpha=False, **kw)
+    ctx.gauss_sum(xt, at, h, CASE["level"], periodic=CASE["K"])
+    with pytest.raises(vm._lib.VmError):
+        ctx.adjoint(xt, at, ub, h, CASE["p"], CASE["level"], grad=J, **kw)
+    a2 = at.clone()
+    ctx.eval(a2, at, h, CASE["p"], CASE["level"], want_grad=True, want_dalpha=False, **kw)
+    with pytest.raises(vm._lib.VmError):
+        ctx.adjoint(xt, at, ub, h, CASE["p"], CASE["level"], grad=J, **kw)
+
+
+def test_autograd_falls_back_when_the_context_moved_on(ctx):
+    """The backward pass reuses the forward evaluation when nothing ran in
+    between, and recomputes it otherwise: both give the adjoint's gradient."""
+    import torch
+    import paper_1110_2921_amd as vm
+    x, a, h = _case()
+    xt = _dev(x).requires_grad_(True)
+    at = _dev(a).requires_grad_(True)
+    u = vm.velocity(xt, at, ctx, h, CASE["p"], CASE["level"], periodic=CASE["K"])
+    ctx.eval(_dev(x + 0.01), _dev(a), h, CASE["p"], CASE["level"], periodic=CASE["K"])   # something else
+    loss = 0.5 * h ** 3 * (u * u).sum()
+    gx, ga = torch.autograd.grad(loss, (xt, at))
+    xb, ab = ctx.adjoint(_dev(x), _dev(a), (h ** 3 * u).detach(), h, CASE["p"], CASE["level"],
+                         periodic=CASE["K"])
+    assert torch.equal(gx, xb) and torch.equal(ga, ab)
