@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_multidot(int n, const double *__restric
         for (int j0 = 0; j0 < k; j0 += 4) {
             const int kk = k - j0 < 4 ? k - j0 : 4;
             double s[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int i = blockIdx.x * 256 + tid; i < n; i += kRbfDotBlocks * 256) {
+            for (int64_t i = int64_t(blockIdx.x) * 256 + tid; i < n; i += int64_t(kRbfDotBlocks) * 256) {
                 const double wi = wc[i];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
