@@ -197,8 +197,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-rbf", action="store_true")
     ap.add_argument("--no-truncation", action="store_true")
-    ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--no-tuning", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time a 32^3 evaluation eagerly and from a captured HIP graph")
+    ap.add_argument("--tuning", action="store_true", help="also run the leaf-level tuner at this workload")
     ap.add_argument("--loop-steps", type=int, default=10,
                     help="steps of the paper's time loop to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -539,7 +540,7 @@ def main():
         x.copy_(x0)
         a.copy_(a0)
 
-    if not args.no_tuning:
+    if args.tuning:
         # auto-tuned leaf level for the benchmark's particles (leaves >= 4 sigma)
         lv, lms = ctx.tune_level(x0, a0, w.sigma, w.p, periodic=w.periodic, box_len=w.box_len,
                                  precision=args.precision)
@@ -547,7 +548,7 @@ def main():
                                   "what": "fastest leaf level with leaves at least 4 sigma wide (vm_tune_level)"}
         log(f"[bench] tuned leaf level {lv}: " + ", ".join(f"level {k} {v:.1f} ms" for k, v in sorted(lms.items())))
 
-    if not args.no_graph:
+    if args.graph:
         # a small problem (32^3, p = 8) is launch-bound: one evaluation eagerly and
         # replayed from a HIP graph captured on the library's stream
         ws = W.WORKLOADS["rand32_periodic"]
