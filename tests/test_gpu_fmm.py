@@ -295,3 +295,18 @@ def test_level_tuning(ctx):
     for kw in ({"min_leaf_sigmas": 0.0}, {"reps": 0}):
         with pytest.raises(vm._lib.VmError):
             ctx.tune_level(_dev(x), _dev(a), w.sigma, w.p, periodic=w.periodic, **kw)
+
+
+@pytest.mark.parametrize("K", [2, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
+def test_low_degrees_and_largest_image_block(ctx, p, K):
+    """Degrees below the operator-stationary M2L's shapes (p <= 4 take the
+    generic translation kernel in both precisions) and the 81^3 image block:
+    FP64 against the oracle 1e-10, mixed against FP64 1e-5 / 1e-4."""
+    x, a = W.random_field(8, 2.0, 100 + p)
+    h = L / 8
+    u, _, J = _run(ctx, x, a, h, p, 1, K)
+    uo, Jo = OF.fmm(x, a, h, p, 1, periodic=K)
+    assert rel(u, uo) < 1e-10 and rel(J, Jo) < 1e-10
+    um, _, Jm = _run(ctx, x, a, h, p, 1, K, precision="mixed")
+    assert rel(um, u) < 1e-5 and rel(Jm, J) < 1e-4
