@@ -547,8 +547,8 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
     constexpr int CHUNK = 4 * kTrThreads;                // floats copied per k block
     constexpr int NCHUNK = (OPF + CHUNK - 1) / CHUNK;
     constexpr bool EXACT = OPF % CHUNK == 0;
-    constexpr int NPAIRC = (NCHUNK + 1) / 2;             // k blocks that load two chunks each
-    static_assert(NPAIRC + 2 <= NB, "the operator copy must finish within one offset");
+    constexpr int NPAIRC = (NCHUNK + 1) / 2;             // k blocks that store two chunks each
+    static_assert(NPAIRC <= NB, "the operator copy must finish within one offset");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float *opl = reinterpret_cast<float *>(smem_raw);    // [2][OPF]
     __shared__ int32_t tkey[TT];
@@ -624,31 +624,32 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
         const float *ogn = op_of(more ? pr + 1 : pr) + 4 * tid;
         float *oln = opl + (cur ^ 1) * OPF + 4 * tid;
         const float *olc = opl + cur * OPF + 4 * lane;
-        f4 stage[2][2];
+        // The next operator's chunks are all loaded first, ahead of this
+        // offset's source loads, and stored into the idle buffer in the last
+        // NPAIRC k blocks, two per k block.  Vector loads retire in order, so a
+        // wait for a chunk also waits for every older load: issued first, the
+        // chunks tie only the previous offset's source loads, which then have
+        // NB - NPAIRC k blocks to arrive, and none of this offset's.  The loads
+        // are issued unconditionally (on the last offset they re-read the
+        // current operator): a branch around them would make the wait for a
+        // chunk cover every newer load.
+        f4 stage[2 * NPAIRC];
+#pragma unroll
+        for (int ch = 0; ch < NCHUNK; ++ch)
+            if (EXACT || ch * CHUNK + 4 * tid < OPF) stage[ch] = *reinterpret_cast<const f4 *>(ogn + ch * CHUNK);
+        __builtin_amdgcn_sched_barrier(0);
         f4 aq[2][NRBH];
 #pragma unroll
         for (int i = 0; i < NRBH; ++i)
             if (!TRI || kbs[i] > 0) aq[0][i] = *reinterpret_cast<const f4 *>(olc + (rbs[i] * NB) * 256);
-        // The next offset's loads are issued unconditionally (on the last offset
-        // they re-read the current one into the idle buffer): a branch around
-        // them would make the wait for a chunk cover every newer load.  Chunks
-        // 2b and 2b+1 are loaded in k block b and stored two k blocks later.
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            if (b >= 2 && b - 2 < NPAIRC) {
+            if (b >= NB - NPAIRC) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const int ch = 2 * (b - 2) + u;
+                    const int ch = 2 * (b - (NB - NPAIRC)) + u;
                     if (ch < NCHUNK && (EXACT || ch * CHUNK + 4 * tid < OPF))
-                        *reinterpret_cast<f4 *>(oln + ch * CHUNK) = stage[b & 1][u];
-                }
-            }
-            if (b < NPAIRC) {
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int ch = 2 * b + u;
-                    if (ch < NCHUNK && (EXACT || ch * CHUNK + 4 * tid < OPF))
-                        stage[b & 1][u] = *reinterpret_cast<const f4 *>(ogn + ch * CHUNK);
+                        *reinterpret_cast<f4 *>(oln + ch * CHUNK) = stage[ch];
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
