@@ -602,10 +602,16 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
 #pragma unroll
         for (int c = 0; c < 3; ++c) B[b][c] = *reinterpret_cast<const f4 *>(sp + c * kp + 16 * b);
     };
+    // operator registers: the chunks of the operator after the current one
+    f4 stage[2 * NPAIRC];
     {
         const float *og = op_of(0);
         for (int e = 4 * tid; e < OPF; e += CHUNK)
             *reinterpret_cast<f4 *>(opl + e) = *reinterpret_cast<const f4 *>(og + e);
+        const float *og1 = op_of(npair > 1 ? 1 : 0) + 4 * tid;
+#pragma unroll
+        for (int ch = 0; ch < NCHUNK; ++ch)
+            if (EXACT || ch * CHUNK + 4 * tid < OPF) stage[ch] = *reinterpret_cast<const f4 *>(og1 + ch * CHUNK);
         const float *sp = src_of(0);
 #pragma unroll
         for (int b = 0; b < NB; ++b) load_b(b, sp);
@@ -621,22 +627,21 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
         const int cur = pr & 1;
         const bool more = pr + 1 < npair;
         const float *spn = src_of(more ? pr + 1 : pr);     // wave-uniform choice
-        const float *ogn = op_of(more ? pr + 1 : pr) + 4 * tid;
+        const float *ogn = op_of(pr + 2 < npair ? pr + 2 : npair - 1) + 4 * tid;
         float *oln = opl + (cur ^ 1) * OPF + 4 * tid;
         const float *olc = opl + cur * OPF + 4 * lane;
-        // The next operator's chunks are all loaded first, ahead of this
-        // offset's source loads, and stored into the idle buffer in the last
-        // NPAIRC k blocks, two per k block.  Vector loads retire in order, so a
-        // wait for a chunk also waits for every older load: issued first, the
-        // chunks tie only the previous offset's source loads, which then have
-        // NB - NPAIRC k blocks to arrive, and none of this offset's.  The loads
-        // are issued unconditionally (on the last offset they re-read the
-        // current operator): a branch around them would make the wait for a
-        // chunk cover every newer load.
-        f4 stage[2 * NPAIRC];
+        // The chunks of the operator two offsets ahead are loaded first, ahead
+        // of this offset's source loads, while the registers loaded one offset
+        // earlier go into the idle buffer, one chunk per k block.  Vector loads
+        // retire in order, so a wait for a chunk also waits for every older
+        // load: loaded a whole offset before their use, the chunks tie only
+        // source loads two offsets old.  The loads are issued unconditionally
+        // (near the end they re-read the last operator): a branch around them
+        // would make the wait for a chunk cover every newer load.
+        f4 ahead[2 * NPAIRC];
 #pragma unroll
         for (int ch = 0; ch < NCHUNK; ++ch)
-            if (EXACT || ch * CHUNK + 4 * tid < OPF) stage[ch] = *reinterpret_cast<const f4 *>(ogn + ch * CHUNK);
+            if (EXACT || ch * CHUNK + 4 * tid < OPF) ahead[ch] = *reinterpret_cast<const f4 *>(ogn + ch * CHUNK);
         __builtin_amdgcn_sched_barrier(0);
         f4 aq[2][NRBH];
 #pragma unroll
@@ -644,14 +649,9 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
             if (!TRI || kbs[i] > 0) aq[0][i] = *reinterpret_cast<const f4 *>(olc + (rbs[i] * NB) * 256);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            if (b >= NB - NPAIRC) {
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int ch = 2 * (b - (NB - NPAIRC)) + u;
-                    if (ch < NCHUNK && (EXACT || ch * CHUNK + 4 * tid < OPF))
-                        *reinterpret_cast<f4 *>(oln + ch * CHUNK) = stage[ch];
-                }
-            }
+            for (int ch = b * NCHUNK / NB; ch < (b + 1) * NCHUNK / NB; ++ch)
+                if (EXACT || ch * CHUNK + 4 * tid < OPF) *reinterpret_cast<f4 *>(oln + ch * CHUNK) = stage[ch];
             __builtin_amdgcn_sched_barrier(0);
             if (b + 1 < NB)
 #pragma unroll
@@ -670,6 +670,8 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
             load_b(b, spn);
             __builtin_amdgcn_sched_barrier(0);
         }
+#pragma unroll
+        for (int ch = 0; ch < NCHUNK; ++ch) stage[ch] = ahead[ch];
         __syncthreads();
     }
     if (t < 0) return;
