@@ -602,16 +602,20 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
 #pragma unroll
         for (int c = 0; c < 3; ++c) B[b][c] = *reinterpret_cast<const f4 *>(sp + c * kp + 16 * b);
     };
-    // operator registers: the chunks of the operator after the current one
-    f4 stage[2 * NPAIRC];
+    // Operators are loaded into registers AHEAD offsets before their use: two
+    // for the square form, one for the truncated form, whose row-block maps
+    // leave no registers for a second set.
+    constexpr int AHEAD = TRI ? 1 : 2;
+    f4 stage[2 * NPAIRC];   // the chunks of the operator after the current one
     {
         const float *og = op_of(0);
         for (int e = 4 * tid; e < OPF; e += CHUNK)
             *reinterpret_cast<f4 *>(opl + e) = *reinterpret_cast<const f4 *>(og + e);
         const float *og1 = op_of(npair > 1 ? 1 : 0) + 4 * tid;
+        if constexpr (AHEAD == 2)
 #pragma unroll
-        for (int ch = 0; ch < NCHUNK; ++ch)
-            if (EXACT || ch * CHUNK + 4 * tid < OPF) stage[ch] = *reinterpret_cast<const f4 *>(og1 + ch * CHUNK);
+            for (int ch = 0; ch < NCHUNK; ++ch)
+                if (EXACT || ch * CHUNK + 4 * tid < OPF) stage[ch] = *reinterpret_cast<const f4 *>(og1 + ch * CHUNK);
         const float *sp = src_of(0);
 #pragma unroll
         for (int b = 0; b < NB; ++b) load_b(b, sp);
@@ -627,21 +631,29 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
         const int cur = pr & 1;
         const bool more = pr + 1 < npair;
         const float *spn = src_of(more ? pr + 1 : pr);     // wave-uniform choice
-        const float *ogn = op_of(pr + 2 < npair ? pr + 2 : npair - 1) + 4 * tid;
+        const float *ogn = op_of(pr + AHEAD < npair ? pr + AHEAD : npair - 1) + 4 * tid;
         float *oln = opl + (cur ^ 1) * OPF + 4 * tid;
         const float *olc = opl + cur * OPF + 4 * lane;
-        // The chunks of the operator two offsets ahead are loaded first, ahead
-        // of this offset's source loads, while the registers loaded one offset
-        // earlier go into the idle buffer, one chunk per k block.  Vector loads
-        // retire in order, so a wait for a chunk also waits for every older
-        // load: loaded a whole offset before their use, the chunks tie only
-        // source loads two offsets old.  The loads are issued unconditionally
-        // (near the end they re-read the last operator): a branch around them
-        // would make the wait for a chunk cover every newer load.
+        // The chunks of the operator AHEAD offsets ahead are loaded first, ahead
+        // of this offset's source loads.  Vector loads retire in order, so a
+        // wait for a chunk also waits for every older load: issued first, the
+        // chunks tie only older offsets' source loads.  AHEAD = 2: the
+        // registers loaded one offset earlier go into the idle buffer, one chunk
+        // per k block, so the chunks tie only source loads two offsets old.
+        // AHEAD = 1: the chunks just loaded go there in the last NPAIRC k
+        // blocks, two per k block, tying the previous offset's source loads
+        // with NB - NPAIRC k blocks to arrive.  The loads are issued
+        // unconditionally (near the end they re-read the last operator): a
+        // branch around them would make the wait for a chunk cover every newer
+        // load.
         f4 ahead[2 * NPAIRC];
 #pragma unroll
         for (int ch = 0; ch < NCHUNK; ++ch)
-            if (EXACT || ch * CHUNK + 4 * tid < OPF) ahead[ch] = *reinterpret_cast<const f4 *>(ogn + ch * CHUNK);
+            if (EXACT || ch * CHUNK + 4 * tid < OPF) {
+                const f4 v = *reinterpret_cast<const f4 *>(ogn + ch * CHUNK);
+                if constexpr (AHEAD == 2) ahead[ch] = v;
+                else stage[ch] = v;
+            }
         __builtin_amdgcn_sched_barrier(0);
         f4 aq[2][NRBH];
 #pragma unroll
@@ -649,9 +661,13 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
             if (!TRI || kbs[i] > 0) aq[0][i] = *reinterpret_cast<const f4 *>(olc + (rbs[i] * NB) * 256);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
+            // chunks [c0, c1) of the operator in `stage` go out in k block b
+            const int c0 = AHEAD == 2 ? b * NCHUNK / NB : (b < NB - NPAIRC ? NCHUNK : 2 * (b - (NB - NPAIRC)));
+            const int c1 = AHEAD == 2 ? (b + 1) * NCHUNK / NB : (b < NB - NPAIRC ? NCHUNK : c0 + 2);
 #pragma unroll
-            for (int ch = b * NCHUNK / NB; ch < (b + 1) * NCHUNK / NB; ++ch)
-                if (EXACT || ch * CHUNK + 4 * tid < OPF) *reinterpret_cast<f4 *>(oln + ch * CHUNK) = stage[ch];
+            for (int ch = c0; ch < c1; ++ch)
+                if (ch < NCHUNK && (EXACT || ch * CHUNK + 4 * tid < OPF))
+                    *reinterpret_cast<f4 *>(oln + ch * CHUNK) = stage[ch];
             __builtin_amdgcn_sched_barrier(0);
             if (b + 1 < NB)
 #pragma unroll
@@ -670,8 +686,9 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
             load_b(b, spn);
             __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (AHEAD == 2)
 #pragma unroll
-        for (int ch = 0; ch < NCHUNK; ++ch) stage[ch] = ahead[ch];
+            for (int ch = 0; ch < NCHUNK; ++ch) stage[ch] = ahead[ch];
         __syncthreads();
     }
     if (t < 0) return;
