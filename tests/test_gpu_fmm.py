@@ -310,3 +310,17 @@ def test_low_degrees_and_largest_image_block(ctx, p, K):
     assert rel(u, uo) < 1e-10 and rel(J, Jo) < 1e-10
     um, _, Jm = _run(ctx, x, a, h, p, 1, K, precision="mixed")
     assert rel(um, u) < 1e-5 and rel(Jm, J) < 1e-4
+
+
+@pytest.mark.parametrize("p", [7, 9])
+def test_degrees_inside_the_operator_stationary_shapes(ctx, p):
+    """p = 7 and p = 9 run the operator-stationary M2L shapes of p = 6 and
+    p = 10 with more padding (p = 9: a row block of zeros, a part-empty last k
+    block): FP64 against the oracle 1e-10, mixed against FP64 1e-5 / 1e-4."""
+    x, a = W.random_field(16, 4.0, 120 + p)
+    h = L / 16
+    u, _, J = _run(ctx, x, a, h, p, 2, 3)
+    uo, Jo = OF.fmm(x, a, h, p, 2, periodic=3)
+    assert rel(u, uo) < 1e-10 and rel(J, Jo) < 1e-10
+    um, _, Jm = _run(ctx, x, a, h, p, 2, 3, precision="mixed")
+    assert rel(um, u) < 1e-5 and rel(Jm, J) < 1e-4
