@@ -688,7 +688,8 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
         }
         if constexpr (AHEAD == 2)
 #pragma unroll
-            for (int ch = 0; ch < NCHUNK; ++ch) stage[ch] = ahead[ch];
+            for (int ch = 0; ch < NCHUNK; ++ch)
+                if (EXACT || ch * CHUNK + 4 * tid < OPF) stage[ch] = ahead[ch];
         __syncthreads();
     }
     if (t < 0) return;
