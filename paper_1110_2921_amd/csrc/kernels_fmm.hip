@@ -56,10 +56,108 @@ __device__ __forceinline__ int group_count(int p, int mlo, int mhi) {
     return c;
 }
 
-template <typename T>
+// Contiguous m ranges of about C / G coefficients each, the smallest G >= 4
+// with at most 64 per range (ng = 0 if there is none).
+constexpr MGroups p2m_groups(int p) {
+    MGroups grp{};
+    const int C = (p + 1) * (p + 1);
+    for (int G = 4; G <= kP2mMaxGroups; ++G) {
+        grp.ng = G;
+        int m = 0, done = 0;
+        for (int g = 0; g < G; ++g) {
+            grp.lo[g] = m;
+            const int target = (C * (g + 1) + G - 1) / G;
+            while (m <= p && (g == G - 1 || done + (p + 1 - m) * (m > 0 ? 2 : 1) / 2 < target)) {
+                done += (p + 1 - m) * (m > 0 ? 2 : 1);
+                ++m;
+            }
+        }
+        grp.lo[G] = p + 1;
+        grp.maxn = 0;
+        for (int g = 0; g < G; ++g) {
+            int c = 0;
+            for (int mm = grp.lo[g]; mm < grp.lo[g + 1]; ++mm) c += (p + 1 - mm) * (mm > 0 ? 2 : 1);
+            grp.maxn = c > grp.maxn ? c : grp.maxn;
+        }
+        if (grp.maxn <= 64) return grp;
+    }
+    grp.ng = 0;
+    return grp;
+}
+
+// Regular harmonics of one particle, orders mlo .. mhi-1 and degrees m .. p, into
+// row (order m, then n, (re, -im) pairs for m > 0).  With PT > 0 the degree and
+// the range are the compile-time PT, MLO, MHI: the recurrence then unrolls and
+// its table reads become scalar loads at fixed offsets, issued together.
+// (the unroll requests cannot be met where the bounds are run-time values)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wpass-failed"
+template <typename T, int PT, int MLO, int MHI>
+__device__ __forceinline__ void p2m_row(T X, T Y, T Z, int p_rt, int mlo_rt, int mhi_rt, const T *__restrict__ c1,
+                                        const T *__restrict__ c2, const T *__restrict__ dg, T *row) {
+    const int p = PT > 0 ? PT : p_rt, mlo = PT > 0 ? MLO : mlo_rt, mhi = PT > 0 ? MHI : mhi_rt;
+    const T r2 = X * X + Y * Y + Z * Z;
+    // diagonal Rb_m^m = -(X + iY) diag[m] Rb_{m-1}^{m-1} up to the range start
+    T dre = T(1), dim = T(0);
+#pragma unroll
+    for (int m = 1; m <= mlo; ++m) {
+        const T sc = -dg[m];
+        const T nre = sc * (X * dre - Y * dim);
+        const T nim = sc * (X * dim + Y * dre);
+        dre = nre;
+        dim = nim;
+    }
+    int o = 0;
+#pragma unroll
+    for (int m = mlo; m < mhi; ++m) {
+        if (m > mlo) {
+            const T sc = -dg[m];
+            const T nre = sc * (X * dre - Y * dim);
+            const T nim = sc * (X * dim + Y * dre);
+            dre = nre;
+            dim = nim;
+        }
+        T are = dre, aim = dim, bre = T(0), bim = T(0);
+        row[o++] = are;
+        if (m > 0) row[o++] = -aim;
+#pragma unroll
+        for (int n = m + 1; n <= p; ++n) {
+            const int e = n * (n + 1) / 2 + m;
+            const T k1 = c1[e] * Z, k2 = c2[e] * r2;
+            const T cre = k1 * are - k2 * bre;
+            const T cim = k1 * aim - k2 * bim;
+            bre = are;
+            bim = aim;
+            are = cre;
+            aim = cim;
+            row[o++] = are;
+            if (m > 0) row[o++] = -aim;
+        }
+    }
+}
+
+#pragma clang diagnostic pop
+
+// p2m_row for range g of the compile-time partition of degree PT.
+template <typename T, int PT, int GI>
+__device__ __forceinline__ void p2m_row_fixed(int g, T X, T Y, T Z, const T *__restrict__ c1,
+                                              const T *__restrict__ c2, const T *__restrict__ dg, T *row) {
+    constexpr MGroups GP = p2m_groups(PT);
+    if constexpr (GI < GP.ng) {
+        if (g == GI) {
+            p2m_row<T, PT, GP.lo[GI], GP.lo[GI + 1]>(X, Y, Z, 0, 0, 0, c1, c2, dg, row);
+            return;
+        }
+        p2m_row_fixed<T, PT, GI + 1>(g, X, Y, Z, c1, c2, dg, row);
+    }
+}
+
+// PT > 0: the degree p is PT (the partition grp is p2m_groups(PT)).
+template <typename T, int PT>
 __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__restrict__ parts,
                                             const int32_t *__restrict__ start, int nleaf, int p, int kp,
                                             T inv_w, DevTables tab, MGroups grp, T *__restrict__ mout) {
+    static_assert(PT == 0 || p2m_groups(PT).ng > 0, "no partition of the orders for this degree");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = threadIdx.x;
     // XCD-aware: blockIdx mod 8 selects the XCD's leaf range; the 4 groups of a leaf follow
@@ -87,41 +185,8 @@ __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__re
             const auto q = parts[s0 + base + lane];
             T *row = rows + lane * stride;
             const T X = T(q.dx) * inv_w, Y = T(q.dy) * inv_w, Z = T(q.dz) * inv_w;
-            const T r2 = X * X + Y * Y + Z * Z;
-            // diagonal Rb_m^m = -(X + iY) diag[m] Rb_{m-1}^{m-1} up to the range start
-            T dre = T(1), dim = T(0);
-            for (int m = 1; m <= mlo; ++m) {
-                const T sc = -dg[m];
-                const T nre = sc * (X * dre - Y * dim);
-                const T nim = sc * (X * dim + Y * dre);
-                dre = nre;
-                dim = nim;
-            }
-            int o = 0;
-            for (int m = mlo; m < mhi; ++m) {
-                if (m > mlo) {
-                    const T sc = -dg[m];
-                    const T nre = sc * (X * dre - Y * dim);
-                    const T nim = sc * (X * dim + Y * dre);
-                    dre = nre;
-                    dim = nim;
-                }
-                T are = dre, aim = dim, bre = T(0), bim = T(0);
-                row[o++] = are;
-                if (m > 0) row[o++] = -aim;
-                for (int n = m + 1; n <= p; ++n) {
-                    const int e = n * (n + 1) / 2 + m;
-                    const T k1 = c1[e] * Z, k2 = c2[e] * r2;
-                    const T cre = k1 * are - k2 * bre;
-                    const T cim = k1 * aim - k2 * bim;
-                    bre = are;
-                    bim = aim;
-                    are = cre;
-                    aim = cim;
-                    row[o++] = are;
-                    if (m > 0) row[o++] = -aim;
-                }
-            }
+            if constexpr (PT > 0) p2m_row_fixed<T, PT, 0>(g, X, Y, Z, c1, c2, dg, row);
+            else p2m_row<T, 0, 0, 0>(X, Y, Z, p, mlo, mhi, c1, c2, dg, row);
             al[lane * 3 + 0] = q.ax;
             al[lane * 3 + 1] = q.ay;
             al[lane * 3 + 2] = q.az;
@@ -732,35 +797,18 @@ __global__ void __launch_bounds__(256) k_lattice(int C, int kp, const double *__
 template <typename T>
 hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t *start, int p, int kp,
                       double inv_w, const DevTables &tab, T *m_out) {
-    // contiguous m ranges of about C / G coefficients each, G >= 4 and at most 64 per range
-    MGroups grp;
-    const int C = (p + 1) * (p + 1);
-    auto count = [&](int mm) { return (p + 1 - mm) * (mm > 0 ? 2 : 1); };
-    bool ok = false;
-    for (int G = 4; G <= kP2mMaxGroups && !ok; ++G) {
-        grp.ng = G;
-        int m = 0, done = 0;
-        for (int g = 0; g < G; ++g) {
-            grp.lo[g] = m;
-            const int target = (C * (g + 1) + G - 1) / G;
-            while (m <= p && (g == G - 1 || done + count(m) / 2 < target)) {
-                done += count(m);
-                ++m;
-            }
-        }
-        grp.lo[G] = p + 1;
-        grp.maxn = 0;
-        for (int g = 0; g < G; ++g) {
-            int c = 0;
-            for (int mm = grp.lo[g]; mm < grp.lo[g + 1]; ++mm) c += count(mm);
-            grp.maxn = c > grp.maxn ? c : grp.maxn;
-        }
-        ok = grp.maxn <= 64;
-    }
-    if (!ok) return hipErrorInvalidValue;
+    const MGroups grp = p2m_groups(p);
+    if (grp.ng == 0) return hipErrorInvalidValue;
     const size_t smem = sizeof(T) * (size_t(64) * (grp.maxn + 1) + 64 * 3);
-    hipLaunchKernelGGL(k_p2m<T>, dim3(unsigned(nleaf) * grp.ng), dim3(64), smem, s,
-                       (const typename PartOf<T>::type *)parts, start, nleaf, p, kp, T(inv_w), tab, grp, m_out);
+    const auto *pp = (const typename PartOf<T>::type *)parts;
+    const dim3 grid(unsigned(nleaf) * grp.ng);
+    // the degrees of the workloads at compile time, any other at run time
+    switch (p) {
+    case 6: hipLaunchKernelGGL((k_p2m<T, 6>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out); break;
+    case 8: hipLaunchKernelGGL((k_p2m<T, 8>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out); break;
+    case 10: hipLaunchKernelGGL((k_p2m<T, 10>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out); break;
+    default: hipLaunchKernelGGL((k_p2m<T, 0>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out);
+    }
     return hipGetLastError();
 }
 
