@@ -739,6 +739,10 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
                 for (int i = 0; i < NRBH; ++i)
                     if (!TRI || b + 1 < kbs[i])
                         aq[(b + 1) & 1][i] = *reinterpret_cast<const f4 *>(olc + (rbs[i] * NB + b + 1) * 256);
+            // raised issue priority for the MFMA cluster: the SIMD's other wave,
+            // between its own clusters, then yields to it instead of
+            // interleaving its memory instructions into this one
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
@@ -747,6 +751,7 @@ __global__ void __launch_bounds__(kTrThreads) k_m2l_os(int level, int periodic, 
 #pragma unroll
                         for (int c = 0; c < 3; ++c)
                             acc[i][c] = Mfma<float>::op(aq[b & 1][i][s4], B[b][c][s4], acc[i][c]);
+            __builtin_amdgcn_s_setprio(0);
             __builtin_amdgcn_sched_barrier(0);
             load_b(b, spn);
             __builtin_amdgcn_sched_barrier(0);
