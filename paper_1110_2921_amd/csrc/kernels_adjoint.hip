@@ -21,14 +21,17 @@ using dev::PartOf;
 using dev::Tab;
 
 // L2P^T: V[b][s] = sum_i ubar_{i,b} c_s(X_i) (degree < p), lam_bar = su * T V.
-template <typename T>
+// PT > 0 fixes the degree at compile time (the harmonic recurrence may then
+// unroll with its table offsets folded); PT = 0 takes it from p_arg.
+template <typename T, int PT>
 __global__ void __launch_bounds__(64) k_l2p_adj(const typename PartOf<T>::type *__restrict__ parts,
                                                 const int32_t *__restrict__ start, const int32_t *__restrict__ perm,
-                                                int n, const double *__restrict__ ubar, int p, int kp, T inv_w,
+                                                int n, const double *__restrict__ ubar, int p_arg, int kp, T inv_w,
                                                 T su, DevTables tab, const int32_t *__restrict__ t_idx,
                                                 const T *__restrict__ t_w, int width, int chunk,
                                                 T *__restrict__ lbar) {
     extern __shared__ unsigned char smem_raw[];
+    const int p = PT > 0 ? PT : p_arg;
     const int nu = p * p, C = (p + 1) * (p + 1);
     T *cv = reinterpret_cast<T *>(smem_raw);   // [chunk][nu]
     T *ub = cv + size_t(chunk) * nu;           // [chunk][3]
@@ -219,8 +222,13 @@ hipError_t launch_l2p_adj(hipStream_t s, int nleaf, int n, const void *parts, co
     if (chunk < 1) chunk = 1;
     const size_t smem = sizeof(T) * (size_t(chunk) * (nu + 3) + 3 * size_t(nu));
     const double su = 1.0 / (12.566370614359172953850573533118 * w * w);
-    hipLaunchKernelGGL(k_l2p_adj<T>, dim3(nleaf), dim3(64), smem, s, (const typename PartOf<T>::type *)parts,
-                       start, perm, n, ubar, p, kp, T(inv_w), T(su), tab, t_idx, t_w, width, chunk, lbar);
+    const auto *pp = (const typename PartOf<T>::type *)parts;
+    switch (p) {   // the workloads' degrees at compile time, any other at run time
+    case 6: hipLaunchKernelGGL((k_l2p_adj<T, 6>), dim3(nleaf), dim3(64), smem, s, pp, start, perm, n, ubar, p, kp, T(inv_w), T(su), tab, t_idx, t_w, width, chunk, lbar); break;
+    case 8: hipLaunchKernelGGL((k_l2p_adj<T, 8>), dim3(nleaf), dim3(64), smem, s, pp, start, perm, n, ubar, p, kp, T(inv_w), T(su), tab, t_idx, t_w, width, chunk, lbar); break;
+    case 10: hipLaunchKernelGGL((k_l2p_adj<T, 10>), dim3(nleaf), dim3(64), smem, s, pp, start, perm, n, ubar, p, kp, T(inv_w), T(su), tab, t_idx, t_w, width, chunk, lbar); break;
+    default: hipLaunchKernelGGL((k_l2p_adj<T, 0>), dim3(nleaf), dim3(64), smem, s, pp, start, perm, n, ubar, p, kp, T(inv_w), T(su), tab, t_idx, t_w, width, chunk, lbar);
+    }
     return hipGetLastError();
 }
 
