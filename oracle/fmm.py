@@ -37,25 +37,35 @@ def _centres(keys, level, lo, box_len):
     return np.asarray(lo, np.float64) + (T.demorton(keys, level) + 0.5) * w
 
 
+def supercell_multipole(m0, p, box_len, k):
+    """Multipole, about its own centre, of the supercell of ring k >= 2: the
+    block of 3^(k-2) image boxes per side.  Ring 2's supercell is the root box
+    itself (``m0``); each further ring's is the M2M sum of 27 copies of the
+    previous one, centred at e 3^(j-3) L for e in [-1, 1]^3."""
+    block = np.array(list(itertools.product((-1, 0, 1), repeat=3)), np.float64)
+    msup = m0
+    for j in range(3, k + 1):
+        s_small = 3.0 ** (j - 3) * box_len
+        msup = sum(H.m2m_matrix(e * s_small, p) @ msup.T for e in block).T
+    return msup
+
+
 def lattice_local(m0, p, box_len, K):
     """Local expansion at the root centre of the images S_K minus S_1.
 
     ``m0``: root multipole, complex (ncomp, C).  Ring k (2 <= k <= K) is made
     of the 9^3 - 3^3 = 702 supercells of width s = 3^(k-2) L centred at d s,
-    d in [-4, 4]^3 minus [-1, 1]^3; a supercell's multipole is the M2M sum
-    of the 27 copies of the next smaller one.
+    d in [-4, 4]^3 minus [-1, 1]^3 (together exactly the boxes of S_k minus
+    S_(k-1)); a supercell's multipole is the M2M sum of the 27 copies of the
+    next smaller one.
     """
     out = np.zeros_like(m0)
     if K < 2:
         return out
     ring = np.array([d for d in itertools.product(range(-4, 5), repeat=3)
                      if max(abs(v) for v in d) > 1], np.float64)
-    block = np.array(list(itertools.product((-1, 0, 1), repeat=3)), np.float64)
-    msup = m0
     for k in range(2, K + 1):
-        if k >= 3:
-            s_small = 3.0 ** (k - 3) * box_len
-            msup = sum(H.m2m_matrix(e * s_small, p) @ msup.T for e in block).T
+        msup = supercell_multipole(m0, p, box_len, k)
         s = 3.0 ** (k - 2) * box_len
         mats = H.m2l_matrices(ring * s, p)
         for T_d in mats:

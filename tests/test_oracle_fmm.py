@@ -12,6 +12,7 @@
   must rotate with it to round-off.  A wrong sign, index or transposed
   operand in any translation breaks this.
 """
+import itertools
 import math
 
 import numpy as np
@@ -157,6 +158,58 @@ def test_level_zero_periodic_is_images_plus_lattice():
         u, J = F.fmm(x, a, sigma, p, 0, periodic=2)
         errs.append(np.linalg.norm(u - u2) / np.linalg.norm(u2 - u1))
     assert errs[1] < errs[0] / 4 and errs[2] < errs[1] / 4
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_supercell_multipole_is_the_image_block_multipole(k):
+    """Ring k of the lattice sum sees the block of 3^(k-2) image boxes per side
+    through one multipole about the block's centre, built from the root
+    multipole by M2M (27 copies per step).  Brute force: the multipole of every
+    particle copy x_j + n L, n in {-R..R}^3 with R = (3^(k-2) - 1)/2, about that
+    centre.  M2M is exact up to degree p, so the two agree to round-off; a wrong
+    supercell spacing or centring does not."""
+    x, a = W.random_particles(20, 27)
+    p = 8
+    c0 = np.full(3, L / 2)
+    m0 = H.p2m(x - c0, a, p)
+    R = (3 ** (k - 2) - 1) // 2
+    img = np.array(list(itertools.product(range(-R, R + 1), repeat=3)), np.float64)
+    copies = (x[None, :, :] - c0 + img[:, None, :] * L).reshape(-1, 3)
+    brute = H.p2m(copies, np.tile(a, (len(img), 1)), p)
+    msup = F.supercell_multipole(m0, p, L, k)
+    assert np.abs(msup - brute).max() < 1e-12 * np.abs(brute).max()
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_lattice_rings_beyond_s2_converge_to_image_sums(level):
+    """The rings k >= 3 of the lattice operator (the paper's 27^3 block is K = 3)
+    against the direct sum over the image boxes of S_K minus S_2 with the cutoff
+    dropped (rho >= 16 there): the difference FMM(K) - FMM(2) isolates them, and
+    so does model(K) - model(2).  Ring 3's supercells (3L wide, at >= 6L) bound
+    the error by (sqrt(3)/2 (3 + 1) / 6)^p = 0.58^p: it must fall at least 4x
+    every 4 degrees and reach 1e-4 at p = 12, for K = 3 and K = 4 alike.  The
+    whole periodic sum S_K at level 0/1 converges to the image-block model too."""
+    x, a = W.random_particles(30, 24)
+    sigma = 0.3
+    m1, m2, m3, m4 = (_model(x, a, sigma, level, K) for K in (1, 2, 3, 4))
+    errs = {3: [], 4: []}
+    errJ = {3: [], 4: []}
+    full = []
+    for p in (4, 8, 12):
+        u2, J2 = F.fmm(x, a, sigma, p, level, periodic=2)
+        for K, mk in ((3, m3), (4, m4)):
+            uk, Jk = F.fmm(x, a, sigma, p, level, periodic=K)
+            du, dJ = mk[0] - m2[0], mk[1] - m2[1]
+            errs[K].append(np.linalg.norm((uk - u2) - du) / np.linalg.norm(du))
+            errJ[K].append(np.linalg.norm((Jk - J2) - dJ) / np.linalg.norm(dJ))
+            if K == 3:
+                full.append(np.linalg.norm(uk - m3[0]) / np.linalg.norm(m3[0] - m1[0]))
+    for e in list(errs.values()) + list(errJ.values()) + [full]:
+        assert e[1] < e[0] / 4 and e[2] < e[1] / 4, e
+    for K in (3, 4):
+        assert errs[K][2] < 1e-4 and errJ[K][2] < 1e-4
+    # ring 4 adds to ring 3 (a K = 4 sum is not a K = 3 sum)
+    assert np.linalg.norm(m4[0] - m3[0]) > 1e-3 * np.linalg.norm(m3[0] - m2[0])
 
 
 @pytest.mark.parametrize("periodic,level", [(3, 2), (0, 2), (1, 1), (2, 0)])
