@@ -149,40 +149,61 @@ def measured_tree_bytes(workload, precision):
     return sum(ks[k]["hbm_bytes_per_launch"] * ks[k]["dispatches"] / evals for k in TREE_KERNELS if k in ks)
 
 
-def cpu_baseline(w, budget_s=30.0):
-    """The oracle FMM timed on the host on a 32^3 sample of the same recipe."""
+def cpu_baseline(w, x_full, a_full, targets):
+    """The oracle timed on the host: its FMM on a 32^3 sample of the same recipe,
+    and its direct sum (the exact regularised kernel over the 27 images S_1) at
+    the sampled particles `targets` of the full workload.  Returns the baseline
+    record and the direct-sum velocity and gradient at the targets, against
+    which the GPU's accuracy is stated."""
+    import resource
+
     import workloads as W
+    from oracle import direct as oracle_direct
     from oracle import fmm as oracle_fmm
+    from oracle import tree as oracle_tree
+
+    def cpu_seconds():
+        r = resource.getrusage(resource.RUSAGE_SELF)
+        return r.ru_utime + r.ru_stime
+
     ng = 32
     x, a = W.random_field(ng, w.k0, seed=w.seed)
     h = 2 * math.pi / ng
     level = 3                     # 64 particles per leaf, as in the full workload
     reps = []
+    c0 = cpu_seconds()
     for _ in range(3):            # median of three runs (about 5 s each on 16 cores)
         t0 = time.perf_counter()
         oracle_fmm.fmm(x, a, h, w.p, level, periodic=w.periodic)
         reps.append(time.perf_counter() - t0)
+    # the threads the oracle kept busy on average: its CPU seconds over its wall seconds
+    busy = (cpu_seconds() - c0) / sum(reps)
     t = sorted(reps)[1]
     n_sample = ng ** 3
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # the oracle's direct sum (C, OpenMP, FP64) on 2048 targets of the sample
-    from oracle import direct as oracle_direct
+    xw = oracle_tree.wrap(x_full, (0.0, 0.0, 0.0), w.box_len)
+    c0 = cpu_seconds()
     t0 = time.perf_counter()
-    oracle_direct.direct(x[:2048], x, a, h, 2 * math.pi, K=1)
+    ud, Jd = oracle_direct.direct(xw[targets], xw, a_full, w.sigma, w.box_len, K=1)
     td = time.perf_counter() - t0
+    busy_d = (cpu_seconds() - c0) / td
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": (n_sample / w.n) / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "cpu_model": model, "os_cpu_count": os.cpu_count(),
-            "direct_pairs_per_s": 2048 * n_sample * 27 / td,
-            "sample": f"oracle CPU FMM (NumPy + C/OpenMP, FP64) on N={ng}^3 particles of the same recipe "
-                      f"(k0={w.k0:g}, 64/leaf, p={w.p}, {3 ** w.periodic}^3 images), median of 3 runs {t:.1f} s, scaled by "
-                      f"{n_sample}/{w.n} (cost linear in N at fixed particles per leaf)",
-            "seconds": t}
+    rec = {"value": (n_sample / w.n) / t, "unit": "evals/s", "cores": round(busy, 1), "kind": "oracle",
+           "cores_what": "average busy threads of the oracle FMM (process CPU time over wall time): its P2P "
+                         "runs in C/OpenMP, the expansions in NumPy",
+           "threads_available": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+           "cpu_model": model, "os_cpu_count": os.cpu_count(),
+           "direct_pairs_per_s": len(targets) * w.n * 27 / td, "direct_cores": round(busy_d, 1),
+           "sample": f"oracle CPU FMM (NumPy + C/OpenMP, FP64) on N={ng}^3 particles of the same recipe "
+                     f"(k0={w.k0:g}, 64/leaf, p={w.p}, {3 ** w.periodic}^3 images), median of 3 runs {t:.1f} s, "
+                     f"scaled by {n_sample}/{w.n} (cost linear in N at fixed particles per leaf); direct sum "
+                     f"at {len(targets)} sampled particles of the full workload over S_1 ({td:.1f} s)",
+           "seconds": t}
+    return rec, ud, Jd
 
 
 def main():
@@ -195,6 +216,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the accuracy against the direct sum and the p = 14 timings")
     ap.add_argument("--no-rbf", action="store_true")
     ap.add_argument("--no-truncation", action="store_true")
     ap.add_argument("--graph", action="store_true",
@@ -223,7 +246,6 @@ def main():
     dev = torch.device("cuda:0")
     x = torch.from_numpy(np.ascontiguousarray(x_np.T)).to(dev)
     a = torch.from_numpy(np.ascontiguousarray(a_np.T)).to(dev)
-    del x_np
     n = w.n
     x0, a0 = x.clone(), a.clone()            # initial state, kept for the FP64 comparison
     u = torch.empty((3, n), dtype=torch.float64, device=dev)
@@ -386,6 +408,38 @@ def main():
                                 "enstrophy": float((e1[1] - e0[1]) / e0[1])}
         log(f"[bench] fp64 {t64 * 1e3:.1f} ms/eval; mixed vs fp64 rel-L2 u {eu:.2e} dalpha {ed:.2e}; "
             f"fp64 drift E {result['drift_fp64']['energy']:.3e}")
+
+    if not args.no_accuracy:
+        # accuracy against the exact sum (images S_1, the oracle's direct sum at 16 sampled
+        # particles, computed in the CPU-baseline leg) at the headline degree and at
+        # p = 14, where the FP64 error in u falls below 1e-6; both forms timed at p = 14
+        # in the headline configuration
+        targets = np.sort(np.random.default_rng(11).choice(n, 16, replace=False))
+        tt = torch.from_numpy(targets).to(dev)
+        acc_p = (w.p, 14)
+        got = {}
+        for pp in acc_p:
+            for prec in ("fp64", "mixed"):
+                ctx.eval(x0, a0, w.sigma, pp, w.level, periodic=1, box_len=w.box_len, precision=prec,
+                         want_dalpha=False, out=(u, None, J))
+                got[pp, prec] = (u[:, tt].cpu().numpy().T, J[:, tt].cpu().numpy().T)
+        t14 = {}
+        for prec in ("fp64", "mixed"):
+            ctx.eval(x0, a0, w.sigma, 14, w.level, precision=prec, out=(u, da, None), **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                ctx.eval(x0, a0, w.sigma, 14, w.level, precision=prec, out=(u, da, None), **kw)
+            torch.cuda.synchronize()
+            t14[prec] = (time.perf_counter() - t0) / 3
+        result["accuracy_vs_direct"] = {"targets": len(targets), "images": "S_1 (27 boxes)", "per_p": {}}
+        result["p14"] = {"fp64_ms": 1e3 * t14["fp64"], "mixed_ms": 1e3 * t14["mixed"],
+                         "mixed_speedup_vs_fp64": t14["fp64"] / t14["mixed"],
+                         "what": "one evaluation (u, dalpha/dt) at p = 14 in the headline configuration"}
+        log(f"[bench] p=14: fp64 {1e3 * t14['fp64']:.1f} ms, mixed {1e3 * t14['mixed']:.1f} ms per evaluation")
+        pending_accuracy = (targets, acc_p, got)
+    else:
+        pending_accuracy = None
 
     if not args.no_adjoint:
         # reverse pass: gradient of L = h^3/2 sum |u|^2 with respect to x and alpha (the
@@ -586,7 +640,20 @@ def main():
 
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(w)
+        tg = pending_accuracy[0] if pending_accuracy else np.zeros(0, np.int64)
+        result["cpu_baseline"], ud, Jd = cpu_baseline(w, x_np, a_np, tg)
+        if pending_accuracy:
+            _, acc_p, got = pending_accuracy
+            for pp in acc_p:
+                e = {}
+                for prec in ("fp64", "mixed"):
+                    ug, Jg = got[pp, prec]
+                    e[prec] = {"u": float(np.linalg.norm(ug - ud) / np.linalg.norm(ud)),
+                               "J": float(np.linalg.norm(Jg - Jd.reshape(-1, 9)) / np.linalg.norm(Jd))}
+                result["accuracy_vs_direct"]["per_p"][str(pp)] = e
+                log(f"[bench] p={pp} vs direct sum: fp64 u {e['fp64']['u']:.2e} J {e['fp64']['J']:.2e}; "
+                    f"mixed u {e['mixed']['u']:.2e} J {e['mixed']['J']:.2e}")
+            result["rel_l2_u_vs_direct"] = result["accuracy_vs_direct"]["per_p"][str(w.p)]["mixed"]["u"]
     print(json.dumps(result), flush=True)
 
 

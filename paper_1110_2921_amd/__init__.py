@@ -374,6 +374,12 @@ class FMM:
         return out.cpu().numpy()
 
 
+# keyword arguments of FMM.eval that velocity() passes on, and the subset the
+# adjoint takes (the stretching form does not enter u)
+_VELOCITY_KW = {"periodic", "box_lo", "box_len", "precision", "scheme", "check_domain", "stream", "truncation"}
+_ADJOINT_KW = {"periodic", "box_lo", "box_len", "precision", "stream", "truncation"}
+
+
 def _velocity_function():
     import torch
 
@@ -382,32 +388,45 @@ def _velocity_function():
 
         @staticmethod
         def forward(ctx, x, alpha, fmm, kw):
-            # the gradient output lets the backward pass reuse this evaluation's tree
+            # The SoA tensors the library reads are kept for the backward pass: while
+            # they are alive no other allocation can take their addresses, so the
+            # library's check that its last evaluation was this one (the x and alpha
+            # addresses among the arguments) cannot be fooled by a temporary copy
+            # of a later call landing at the same address.
+            xs = _soa(x, torch)
+            als = _soa(alpha, torch)
             need = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
-            u, _, J = fmm.eval(x, alpha, want_dalpha=False, want_grad=need, **kw)
-            ctx.save_for_backward(x, alpha)
+            # the gradient output lets the backward pass reuse this evaluation's tree
+            u, _, J = fmm.eval(xs, als, want_dalpha=False, want_grad=need, **kw)
+            ctx.save_for_backward(xs, als)
             ctx.fmm = fmm
             ctx.kw = kw
             ctx.J = J
-            ctx.versions = (x._version, alpha._version)
+            ctx.versions = (xs._version, als._version)
+            ctx.aos = (x.shape[0] != 3, alpha.shape[0] != 3)
             return u
 
         @staticmethod
         def backward(ctx, u_bar):
-            x, alpha = ctx.saved_tensors
-            kw = dict(ctx.kw)
-            kw.pop("scheme", None)
+            xs, als = ctx.saved_tensors
+            kw = {k: v for k, v in ctx.kw.items() if k in _ADJOINT_KW or k in ("sigma", "p", "level")}
             args = dict(want_x=ctx.needs_input_grad[0], want_alpha=ctx.needs_input_grad[1], **kw)
             u_bar = u_bar.contiguous()
-            if ctx.J is not None and ctx.versions == (x._version, alpha._version):
+            xb = ab = None
+            if ctx.J is not None and ctx.versions == (xs._version, als._version):
                 try:
-                    xb, ab = ctx.fmm.adjoint(x, alpha, u_bar, grad=ctx.J, **args)
-                    return xb, ab, None, None
+                    xb, ab = ctx.fmm.adjoint(xs, als, u_bar, grad=ctx.J, **args)
                 except _lib.VmError as e:
                     # the context evaluated something else since the forward pass
                     if e.status != _lib.VM_EINVAL:
                         raise
-            xb, ab = ctx.fmm.adjoint(x, alpha, u_bar, **args)
+            if xb is None and ab is None:
+                xb, ab = ctx.fmm.adjoint(xs, als, u_bar, **args)
+            # gradients in the layout of the inputs
+            if xb is not None and ctx.aos[0]:
+                xb = xb.t()
+            if ab is not None and ctx.aos[1]:
+                ab = ab.t()
             return xb, ab, None, None
 
     return VortexFMM
@@ -417,11 +436,18 @@ _VORTEX_FMM = None
 
 
 def velocity(x, alpha, fmm, sigma, p, level, **kw):
-    """Differentiable velocity (3, n) of particles x, alpha ((3, n) float64 CUDA tensors).
+    """Differentiable velocity (3, n) of particles x, alpha (float64 CUDA tensors,
+    (3, n) or (n, 3); gradients come back in the inputs' layout).
 
     Gradients with respect to x and alpha come from the discrete adjoint of the
-    same FMM (``vm_fmm_adjoint``); keyword arguments are those of ``FMM.eval``."""
+    same FMM (``vm_fmm_adjoint``, or ``vm_fmm_adjoint_reuse`` when the context's
+    last evaluation is still this one).  Keyword arguments: those of ``FMM.eval``
+    that describe the evaluation -- periodic, box_lo, box_len, precision,
+    scheme, check_domain, stream, truncation."""
     global _VORTEX_FMM
+    bad = set(kw) - _VELOCITY_KW
+    if bad:
+        raise TypeError("velocity() does not take " + ", ".join(sorted(bad)))
     if _VORTEX_FMM is None:
         _VORTEX_FMM = _velocity_function()
     kw = dict(kw, sigma=sigma, p=p, level=level)

@@ -287,3 +287,35 @@ def test_autograd_falls_back_when_the_context_moved_on(ctx):
     xb, ab = ctx.adjoint(_dev(x), _dev(a), (h ** 3 * u).detach(), h, CASE["p"], CASE["level"],
                          periodic=CASE["K"])
     assert torch.equal(gx, xb) and torch.equal(ga, ab)
+
+
+def test_autograd_with_row_major_inputs_and_an_eval_in_between(ctx):
+    """(n, 3) inputs are copied into SoA tensors for the library.  The forward
+    pass keeps those copies, so the temporaries of a later evaluation of the
+    same size cannot take their addresses and pass the library's reuse check:
+    the backward pass must recompute and give vm_fmm_adjoint's gradient bit for
+    bit, in the (n, 3) layout of the inputs.  Keyword arguments that only the
+    evaluation takes (check_domain) do not reach the adjoint."""
+    import torch
+    import paper_1110_2921_amd as vm
+    x, a, h = _case()
+    args = (h, CASE["p"], CASE["level"])
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda().requires_grad_(True)
+    at = torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
+    u = vm.velocity(xt, at, ctx, *args, periodic=CASE["K"], check_domain=True)
+    u2 = vm.velocity(xt.detach(), at.detach(), ctx, *args, periodic=CASE["K"])   # reuses nothing of u
+    ctx.eval(torch.from_numpy(np.ascontiguousarray(x + 0.01)).cuda(),
+             torch.from_numpy(np.ascontiguousarray(a[::-1])).cuda(), *args, periodic=CASE["K"])
+    loss = 0.5 * h ** 3 * (u * u).sum()
+    gx, ga = torch.autograd.grad(loss, (xt, at))
+    assert gx.shape == xt.shape and ga.shape == at.shape
+    xb, ab = ctx.adjoint(_dev(x), _dev(a), (h ** 3 * u).detach(), *args, periodic=CASE["K"])
+    assert torch.equal(gx, xb.t()) and torch.equal(ga, ab.t())
+    assert torch.equal(u2, u.detach())
+
+
+def test_velocity_rejects_output_keywords(ctx):
+    import paper_1110_2921_amd as vm
+    x, a, h = _case()
+    with pytest.raises(TypeError):
+        vm.velocity(_dev(x), _dev(a), ctx, h, CASE["p"], CASE["level"], want_grad=True)

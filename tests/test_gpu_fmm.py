@@ -1,12 +1,13 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances (relative L2 over all particles unless stated):
+Tolerances (relative L2 over all particles, and the worst particle's error
+over the largest reference magnitude, as ``_gates`` defines them):
 * tree arrays (keys, sorted order, leaf ranges): bit-exact;
-* FP64 FMM vs the oracle FMM of the same definition: 1e-10 (both are
-  round-off apart: same tree, lists, truncation and lattice construction);
+* FP64 FMM vs the oracle FMM of the same definition: 1e-10 in both measures
+  (round-off apart: same tree, lists, truncation and lattice construction);
 * no far field (one leaf, free space): FP64 vs the direct sum 1e-13;
-* mixed (FP32 near field + FP32 MFMA expansions) vs FP64: 1e-5 for u,
-  1e-4 for dalpha/dt and J;
+* mixed (FP32 near field + FP32 MFMA expansions) vs FP64: 1e-5 / 4e-5 for u,
+  1e-4 / 4e-4 for dalpha/dt and J;
 * compensated near-field sums: same-sign velocity terms summed over 16368
   sources, mixed vs the FP64 direct sum within 1e-6, where plain FP32
   accumulation in the same order (emulated on the CPU) is off by more than 2e-6.
@@ -20,6 +21,7 @@ import workloads as W
 from oracle import direct as D
 from oracle import fmm as OF
 from oracle import tree as T
+from _gates import FP64, MIXED_J, MIXED_U, close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -52,10 +54,6 @@ def _host(t):
     return t.cpu().numpy().T
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
-
-
 @pytest.mark.parametrize("periodic", [0, 1])
 @pytest.mark.parametrize("level", [1, 2, 3, 5])
 def test_tree_is_bit_exact(ctx, periodic, level):
@@ -81,9 +79,9 @@ def test_level0_free_space_is_direct_sum(ctx):
     sigma = 0.2
     u, da, J = _run(ctx, x, a, sigma, 4, 0, 0)
     u0, J0 = D.direct(x, x, a, sigma)
-    assert rel(u, u0) < 1e-13
-    assert rel(J, J0) < 1e-13
-    assert rel(da, D.stretching(J0, a)) < 1e-13
+    close(u, u0, (1e-13, 1e-13), "u vs u0")
+    close(J, J0, (1e-13, 1e-13), "J vs J0")
+    close(da, D.stretching(J0, a), (1e-13, 1e-13), "dalpha/dt vs direct")
 
 
 def test_taylor_green_free_space_matches_oracle(ctx):
@@ -91,9 +89,9 @@ def test_taylor_green_free_space_matches_oracle(ctx):
     x, a = W.make(w)
     u, da, J = _run(ctx, x, a, w.sigma, w.p, w.level, 0)
     uo, Jo = OF.fmm(x, a, w.sigma, w.p, w.level, periodic=0)
-    assert rel(u, uo) < 1e-10
-    assert rel(J, Jo) < 1e-10
-    assert rel(da, D.stretching(Jo, a)) < 1e-10
+    close(u, uo, FP64, "u vs uo")
+    close(J, Jo, FP64, "J vs Jo")
+    close(da, D.stretching(Jo, a), FP64, "dalpha/dt vs oracle")
     # and it is close to the exact direct sum (p = 6 truncation)
     ud, Jd = D.direct(x, x, a, w.sigma)
     assert rel(u, ud) < 1e-3
@@ -105,8 +103,8 @@ def test_periodic_fp64_matches_oracle(ctx, K):
     h = L / 16
     u, da, J = _run(ctx, x, a, h, 8, 2, K)
     uo, Jo = OF.fmm(x, a, h, 8, 2, periodic=K)
-    assert rel(u, uo) < 1e-10
-    assert rel(J, Jo) < 1e-10
+    close(u, uo, FP64, "u vs uo")
+    close(J, Jo, FP64, "J vs Jo")
 
 
 def test_rand32_periodic_matches_oracle(ctx):
@@ -114,13 +112,13 @@ def test_rand32_periodic_matches_oracle(ctx):
     x, a = W.make(w)
     u, da, J = _run(ctx, x, a, w.sigma, w.p, w.level, w.periodic)
     uo, Jo = OF.fmm(x, a, w.sigma, w.p, w.level, periodic=w.periodic)
-    assert rel(u, uo) < 1e-10
-    assert rel(J, Jo) < 1e-10
-    assert rel(da, D.stretching(Jo, a)) < 1e-10
+    close(u, uo, FP64, "u vs uo")
+    close(J, Jo, FP64, "J vs Jo")
+    close(da, D.stretching(Jo, a), FP64, "dalpha/dt vs oracle")
     um, dam, Jm = _run(ctx, x, a, w.sigma, w.p, w.level, w.periodic, precision="mixed")
-    assert rel(um, u) < 1e-5
-    assert rel(dam, da) < 1e-4
-    assert rel(Jm, J) < 1e-4
+    close(um, u, MIXED_U, "um vs u")
+    close(dam, da, MIXED_J, "dam vs da")
+    close(Jm, J, MIXED_J, "Jm vs J")
 
 
 # leaf populations around the kernel's block boundaries: empty, a few (lane groups
@@ -137,13 +135,13 @@ def test_uneven_leaf_populations(ctx, periodic):
     sigma, p = 0.15, 6
     u, da, J = _run(ctx, x, a, sigma, p, level, periodic)
     uo, Jo = OF.fmm(x, a, sigma, p, level, periodic=periodic)
-    assert rel(u, uo) < 1e-10
-    assert rel(J, Jo) < 1e-10
-    assert rel(da, D.stretching(Jo, a)) < 1e-10
+    close(u, uo, FP64, "u vs uo")
+    close(J, Jo, FP64, "J vs Jo")
+    close(da, D.stretching(Jo, a), FP64, "dalpha/dt vs oracle")
     um, dam, Jm = _run(ctx, x, a, sigma, p, level, periodic, precision="mixed")
-    assert rel(um, u) < 1e-5
-    assert rel(Jm, J) < 1e-4
-    assert rel(dam, da) < 1e-4
+    close(um, u, MIXED_U, "um vs u")
+    close(Jm, J, MIXED_J, "Jm vs J")
+    close(dam, da, MIXED_J, "dam vs da")
 
 
 def test_compensated_near_field_sums(ctx):
@@ -187,8 +185,10 @@ def test_largest_degree(ctx, periodic):
     """p = 18, the largest degree (single-buffered translation tiles, 7 P2M
     order ranges, the widest L2P tables): against the direct sum with the
     far-field model (g = 1 beyond adjacent leaves), to which the FMM converges
-    as p grows.  FP64 at p = 18 within 1e-6 of it and at least 10x closer than
-    at p = 12; mixed within 1e-5 (u) and 1e-4 (J) of FP64."""
+    as p grows.  FP64 at p = 18 within 3e-7 of it (measured 1.0e-7 on one
+    box: the model error of the farthest far pairs plus what is left of the
+    truncation) and at least 10x closer than at p = 12; mixed within the usual
+    gates of FP64."""
     x, a = W.random_particles(3000, 43)
     sigma, level = 0.15, 2
     tr = T.build(x, (0, 0, 0), L, level, periodic)
@@ -196,11 +196,12 @@ def test_largest_degree(ctx, periodic):
     ud, Jd = D.direct(tr["xw"], tr["xw"], a, sigma, L, K=periodic, cells_t=c, cells_s=c, level=level)
     u12, _, J12 = _run(ctx, x, a, sigma, 12, level, periodic)
     u, _, J = _run(ctx, x, a, sigma, 18, level, periodic)
-    assert rel(u, ud) < 1e-6 and rel(J, Jd) < 1e-6
+    print(f"[parity] p=18 vs model: u {rel(u, ud):.2e} J {rel(J, Jd):.2e}; p=12: u {rel(u12, ud):.2e}")
+    assert rel(u, ud) < 3e-7 and rel(J, Jd) < 3e-7
     assert rel(u, ud) < rel(u12, ud) / 10 and rel(J, Jd) < rel(J12, Jd) / 10
     um, _, Jm = _run(ctx, x, a, sigma, 18, level, periodic, precision="mixed")
-    assert rel(um, u) < 1e-5
-    assert rel(Jm, J) < 1e-4
+    close(um, u, MIXED_U, "um vs u")
+    close(Jm, J, MIXED_J, "Jm vs J")
 
 
 def test_transpose_scheme_conserves_vorticity(ctx):
@@ -255,10 +256,11 @@ def test_triangular_truncation_matches_oracle(ctx, p):
     u, da, J = ctx.eval(_dev(x), _dev(a), h, p, 2, **kw)
     uo, Jo = OF.fmm(x, a, h, p, 2, periodic=3, truncation="triangular")
     u, J = _host(u), _host(J).reshape(-1, 3, 3)
-    assert rel(u, uo) < 1e-10 and rel(J, Jo) < 1e-10
+    close(u, uo, FP64, "u vs uo")
+    close(J, Jo, FP64, "J vs Jo")
     um, _, Jm = ctx.eval(_dev(x), _dev(a), h, p, 2, precision="mixed", **kw)
-    assert rel(_host(um), u) < 1e-5
-    assert rel(_host(Jm).reshape(-1, 3, 3), J) < 1e-4
+    close(_host(um), u, MIXED_U, "um vs u")
+    close(_host(Jm).reshape(-1, 3, 3), J, MIXED_J, "Jm vs J")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -307,9 +309,11 @@ def test_low_degrees_and_largest_image_block(ctx, p, K):
     h = L / 8
     u, _, J = _run(ctx, x, a, h, p, 1, K)
     uo, Jo = OF.fmm(x, a, h, p, 1, periodic=K)
-    assert rel(u, uo) < 1e-10 and rel(J, Jo) < 1e-10
+    close(u, uo, FP64, "u vs uo")
+    close(J, Jo, FP64, "J vs Jo")
     um, _, Jm = _run(ctx, x, a, h, p, 1, K, precision="mixed")
-    assert rel(um, u) < 1e-5 and rel(Jm, J) < 1e-4
+    close(um, u, MIXED_U, "um vs u")
+    close(Jm, J, MIXED_J, "Jm vs J")
 
 
 @pytest.mark.parametrize("p", [7, 9])
@@ -321,6 +325,8 @@ def test_degrees_inside_the_operator_stationary_shapes(ctx, p):
     h = L / 16
     u, _, J = _run(ctx, x, a, h, p, 2, 3)
     uo, Jo = OF.fmm(x, a, h, p, 2, periodic=3)
-    assert rel(u, uo) < 1e-10 and rel(J, Jo) < 1e-10
+    close(u, uo, FP64, "u vs uo")
+    close(J, Jo, FP64, "J vs Jo")
     um, _, Jm = _run(ctx, x, a, h, p, 2, 3, precision="mixed")
-    assert rel(um, u) < 1e-5 and rel(Jm, J) < 1e-4
+    close(um, u, MIXED_U, "um vs u")
+    close(Jm, J, MIXED_J, "Jm vs J")

@@ -3,12 +3,15 @@ in the launch configuration the benchmark times, on sampled particles.
 
 The oracle evaluates the same FMM at 96 sampled particles (``oracle.fmm.fmm_at``:
 full upward pass, downward pass along the sampled leaves' ancestors, L2P and
-P2P at the samples).  Tolerances (relative L2 over the samples):
-  FP64 GPU vs oracle: 1e-10 for u and J;  mixed GPU vs oracle: 1e-5 for u, 1e-4 for J.
+P2P at the samples).  Tolerances (relative L2 over the samples and worst
+sample, as ``_gates`` defines them): FP64 GPU vs oracle 1e-10 / 1e-10 for u, J
+and dalpha/dt; mixed GPU vs oracle 1e-5 / 4e-5 for u, 1e-4 / 4e-4 for J.
 Properties over all N: the transpose stretching form conserves sum alpha to the
 FMM's accuracy, and a repeated evaluation is bitwise identical.  Against the
 exact regularised sum over the 27 images S_1 (oracle direct sum at 32 sampled
-particles) the FMM with p = 10 is within 1e-3 (the expansions' truncation).
+particles), gates from the measured degree sweep at 128^3 (p = 10: u 1.2e-5,
+J 3.6e-5; p = 14: u 5.0e-7): p = 10 within 3e-5 (u) and 1e-4 (J), p = 14
+within 1e-6 (u) in FP64 -- the accuracy the evaluation is asked to reach.
 """
 import numpy as np
 import pytest
@@ -17,6 +20,7 @@ import workloads as W
 from oracle import direct as D
 from oracle import fmm as OF
 from oracle import tree as T
+from _gates import FP64, MIXED_J, MIXED_U, close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -28,10 +32,6 @@ def ctx():
         pytest.skip("no GPU")
     import paper_1110_2921_amd as vm
     return vm.FMM(0)
-
-
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 @pytest.mark.timeout(900)
@@ -65,20 +65,22 @@ def test_full_size_sampled_parity(ctx, name):
     torch.cuda.empty_cache()
     uo, Jo = OF.fmm_at(x_np, a_np, w.sigma, w.p, w.level, t, periodic=w.periodic, box_len=w.box_len)
     u64, J64, d64 = out["fp64"]
-    assert rel(u64, uo) < 1e-10
-    assert rel(J64, Jo) < 1e-10
-    assert rel(d64, D.stretching(Jo, a_np[t])) < 1e-10
+    close(u64, uo, FP64, name + " u fp64 vs oracle")
+    close(J64, Jo, FP64, name + " J fp64 vs oracle")
+    close(d64, D.stretching(Jo, a_np[t]), FP64, name + " dalpha/dt fp64 vs oracle")
     um, Jm, _ = out["mixed"]
-    assert rel(um, uo) < 1e-5
-    assert rel(Jm, Jo) < 1e-4
+    close(um, uo, MIXED_U, name + " u mixed vs oracle")
+    close(Jm, Jo, MIXED_J, name + " J mixed vs oracle")
 
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("name", ["rand128_periodic", "rand256_periodic"])
 def test_full_size_against_direct_sum(ctx, name):
-    """FMM (p = 10, images S_1) against the exact regularised sum over S_1 at 32
-    sampled particles: the truncation error of the expansions plus the far-field
-    model (about 5e-7), stated as 1e-3 for u and J; mixed within 1e-5 of it."""
+    """FMM (images S_1) against the exact regularised sum over S_1 at 32 sampled
+    particles: the truncation error of the expansions plus the far-field model
+    (about 5e-7).  FP64 at p = 10 within 3e-5 (u) and 1e-4 (J); at p = 14 within
+    1e-6 (u) and 4e-6 (J); the mixed form within 1e-5 (u) and 1e-4 (J) of FP64's
+    error at either degree."""
     import torch
     w = W.WORKLOADS[name]
     x_np, a_np = W.make(w)
@@ -88,19 +90,23 @@ def test_full_size_against_direct_sum(ctx, name):
     t = np.sort(np.random.default_rng(11).choice(w.n, 32, replace=False))
     tt = torch.from_numpy(t).cuda()
     res = {}
-    for prec in ("fp64", "mixed"):
-        u, _, J = ctx.eval(x, a, w.sigma, w.p, w.level, periodic=1, box_len=w.box_len, precision=prec,
-                           want_grad=True, want_dalpha=False)
-        res[prec] = (u[:, tt].cpu().numpy().T, J[:, tt].cpu().numpy().T.reshape(-1, 3, 3))
-        del u, J
+    for p in (w.p, 14):
+        for prec in ("fp64", "mixed"):
+            u, _, J = ctx.eval(x, a, w.sigma, p, w.level, periodic=1, box_len=w.box_len, precision=prec,
+                               want_grad=True, want_dalpha=False)
+            res[p, prec] = (u[:, tt].cpu().numpy().T, J[:, tt].cpu().numpy().T.reshape(-1, 3, 3))
+            del u, J
     del x, a
     torch.cuda.empty_cache()
     ud, Jd = D.direct(xw[t], xw, a_np, w.sigma, w.box_len, K=1)
-    eu, ej = rel(res["fp64"][0], ud), rel(res["fp64"][1], Jd)
-    print(f"{name}: FMM p={w.p} vs direct sum (S_1): u {eu:.2e}  J {ej:.2e}")
-    assert eu < 1e-3 and ej < 1e-3
-    assert rel(res["mixed"][0], ud) < eu + 1e-5
-    assert rel(res["mixed"][1], Jd) < ej + 1e-4
+    gates = {w.p: (3e-5, 1e-4), 14: (1e-6, 4e-6)}
+    for p in (w.p, 14):
+        eu, ej = rel(res[p, "fp64"][0], ud), rel(res[p, "fp64"][1], Jd)
+        mu, mj = rel(res[p, "mixed"][0], ud), rel(res[p, "mixed"][1], Jd)
+        print(f"[parity] {name}: FMM p={p} vs direct sum (S_1): fp64 u {eu:.2e} J {ej:.2e}; "
+              f"mixed u {mu:.2e} J {mj:.2e}", flush=True)
+        assert eu < gates[p][0] and ej < gates[p][1]
+        assert mu < eu + 1e-5 and mj < ej + 1e-4
 
 
 @pytest.mark.timeout(900)
