@@ -183,6 +183,30 @@ def random_particles(n: int, seed: int, box_len: float = TWO_PI, lo=(0.0, 0.0, 0
     return x, a
 
 
+def clustered_particles(n: int, seed: int, nclusters: int = 8, background: float = 0.1,
+                        box_len: float = TWO_PI, lo=(0.0, 0.0, 0.0)):
+    """A non-uniform particle set for the adaptive tree: `nclusters` Gaussian
+    clusters at uniformly drawn centres, with standard deviations spread
+    log-uniformly over [box_len/64, box_len/8] and Dirichlet(1) shares of
+    (1 - background) n particles, plus background n uniform ones; positions
+    wrapped into the box [lo, lo + box_len)^3; N(0,1) strengths with zero sum."""
+    rng = np.random.default_rng(seed)
+    nb = int(round(background * n))
+    shares = rng.dirichlet(np.ones(nclusters))
+    counts = np.floor(shares * (n - nb)).astype(np.int64)
+    counts[: (n - nb) - int(counts.sum())] += 1
+    centres = rng.uniform(0.0, box_len, size=(nclusters, 3))
+    widths = box_len * np.exp(rng.uniform(np.log(1 / 64), np.log(1 / 8), size=nclusters))
+    xs = [rng.normal(centres[k], widths[k], size=(int(counts[k]), 3)) for k in range(nclusters)]
+    xs.append(rng.uniform(0.0, box_len, size=(nb, 3)))
+    x = np.mod(np.concatenate(xs, axis=0), box_len)
+    x = rng.permutation(x) + np.asarray(lo)
+    a = rng.standard_normal((n, 3))
+    if n > 1:
+        a -= a.mean(axis=0, keepdims=True)
+    return x, a
+
+
 def particles_with_leaf_counts(counts, level: int, seed: int, box_len: float = TWO_PI):
     """Particles placed uniformly inside the leaves of a uniform octree at
     `level`, counts[i] of them in the leaf with cell coordinates
