@@ -187,6 +187,25 @@ vm_status vm_diagnostics(vm_ctx *ctx, int64_t n, const double *u, const double *
                          double h3, double *out);
 
 /*
+ * vm_diagnostics for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, arguments, results (bit for bit) and errors, but the
+ * per-block partial sums live in a static device array of the library
+ * (3 x 1024 doubles = 24 KiB per device, held until the process ends) instead
+ * of the context's workspace, and the call allocates nothing -- no hipMalloc,
+ * hipFree or allocating library routine; its first call on a device looks up
+ * that device's copy of the array (hipGetSymbolAddress).  The partial-sum
+ * pass is grid-strided over at most 1024 blocks, so every n in [1, 2^31)
+ * fits; a launch needing more slots would return VM_EINVAL.  Every slot it
+ * reads is written by the same call first, so nothing needs clearing between
+ * calls.  All calls on one device share that array: two such calls that
+ * overlap in time on one device (different streams or contexts, or host
+ * threads) race and give wrong results; calls in one stream are ordered.
+ */
+vm_status vm_diagnostics_noalloc(vm_ctx *ctx, int64_t n, const double *u, const double *grad,
+                                 const double *alpha, double h3, double *out);
+
+/*
  * Gaussian smoothing sum over the neighbour list (Sec. 2.2, eqs. 3-4, and the
  * reinitialisation paragraph there): the vorticity the particles carry, at
  * the particles,

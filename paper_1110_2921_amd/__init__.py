@@ -196,6 +196,17 @@ class FMM:
                                              float(h3), ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def diagnostics_noalloc(self, u, grad, alpha, h3, out, stream=None):
+        """vm_diagnostics_noalloc: (E, Omega, Omega_p) written into `out` (a float64
+        CUDA tensor of 3 the caller owns); the library allocates nothing."""
+        n = u.shape[1]
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        self._check(self._lib.vm_diagnostics_noalloc(self._h, n, ctypes.c_void_p(u.data_ptr()),
+                                                     ctypes.c_void_p(grad.data_ptr() if grad is not None else 0),
+                                                     ctypes.c_void_p(alpha.data_ptr() if alpha is not None else 0),
+                                                     float(h3), ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def gauss_sum(self, x, gamma, sigma, level, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi,
                   precision="fp64", stream=None, out=None):
         """Gaussian smoothing sum over the neighbour list, (3, n) float64."""

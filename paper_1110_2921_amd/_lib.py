@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "VM_OK", -1: "VM_EINVAL", -2: "VM_ENOMEM", -3: "VM_EDEVICE", 
 
 # every symbol include/vmfmm.h declares
 EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_eval", "vm_fmm_eval_at",
-           "vm_fmm_adjoint", "vm_fmm_adjoint_reuse", "vm_rk2_step", "vm_diagnostics", "vm_gauss_sum", "vm_gauss_eval", "vm_rbf_solve",
+           "vm_fmm_adjoint", "vm_fmm_adjoint_reuse", "vm_rk2_step", "vm_diagnostics", "vm_diagnostics_noalloc", "vm_gauss_sum", "vm_gauss_eval", "vm_rbf_solve",
            "vm_reinit", "vm_run", "vm_energy_spectrum", "vm_tune_level",
            "vm_set_timing", "vm_get_timing", "vm_debug_tree", "vm_debug_expansions", "vm_debug_far", "vm_debug_offsets", "vm_debug_list",
            "vm_debug_operator")
@@ -78,6 +78,8 @@ def load():
     lib.vm_rk2_step.restype = ctypes.c_int
     lib.vm_diagnostics.argtypes = [vp, i64, dp, dp, dp, ctypes.c_double, dp]
     lib.vm_diagnostics.restype = ctypes.c_int
+    lib.vm_diagnostics_noalloc.argtypes = [vp, i64, dp, dp, dp, ctypes.c_double, dp]
+    lib.vm_diagnostics_noalloc.restype = ctypes.c_int
     lib.vm_gauss_sum.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(VmOpts), dp]
     lib.vm_gauss_sum.restype = ctypes.c_int
     lib.vm_gauss_eval.argtypes = [vp, i64, dp, dp, i64, dp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(VmOpts),

@@ -155,6 +155,10 @@ hipError_t launch_rk_stage2(hipStream_t s, int n, double *x, double *a, const do
 int diag_blocks(int n);
 hipError_t launch_diagnostics(hipStream_t s, int n, const double *u, const double *J, const double *a,
                               double h3, double *part, double *out);
+// Device address, on `device` (which must be current), of the static partial-sum
+// array of the allocation-free diagnostics; looked up once per device.
+hipError_t diag_scratch(int device, double **ptr);
+size_t diag_scratch_bytes();
 
 // rows of the translation-operator GEMM tile
 inline int pad16(int c) { return (c + 15) / 16 * 16; }

@@ -3,6 +3,8 @@
 // enstrophy reductions.  All bandwidth-bound, one thread per particle.
 #include "kernels.h"
 
+#include <mutex>
+
 namespace vmfmm {
 
 namespace {
@@ -43,6 +45,15 @@ __global__ void __launch_bounds__(256) k_rk_stage2(int n, double *__restrict__ x
 
 // Per-block partial sums of |u|^2, |curl u|^2, |alpha|^2 (fixed order).
 constexpr int kDiagThreads = 256;
+constexpr int kDiagMaxBlocks = 1024;
+
+// The partial sums of the allocation-free diagnostics entry point: one slot
+// of three doubles per block of the partial-sum pass, at most kDiagMaxBlocks
+// blocks, 24 KiB on every device the library runs on, held until the process
+// ends.  Host code never passes this name to a kernel (on the host it is only
+// a stand-in for the symbol): it passes the device address that
+// diag_scratch() looked up on the device concerned.
+static __device__ __align__(256) double scratch[3 * kDiagMaxBlocks];
 
 __global__ void __launch_bounds__(kDiagThreads) k_diag_partial(int n, const double *__restrict__ u,
                                                                const double *__restrict__ J,
@@ -106,7 +117,7 @@ hipError_t launch_rk_stage2(hipStream_t s, int n, double *x, double *a, const do
     return hipGetLastError();
 }
 
-int diag_blocks(int n) { return std::min(1024, std::max(1, blocks(n, kDiagThreads))); }
+int diag_blocks(int n) { return std::min(kDiagMaxBlocks, std::max(1, blocks(n, kDiagThreads))); }
 
 hipError_t launch_diagnostics(hipStream_t s, int n, const double *u, const double *J, const double *a,
                               double h3, double *part, double *out) {
@@ -115,5 +126,27 @@ hipError_t launch_diagnostics(hipStream_t s, int n, const double *u, const doubl
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, nblk, (const double *)part, h3, out);
     return hipGetLastError();
 }
+
+constexpr int kMaxDevices = 64;
+
+hipError_t diag_scratch(int device, double **ptr) {
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        // the caller has made `device` current; each device holds its own copy
+        // of the array at its own address
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<double *>(p);
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
+size_t diag_scratch_bytes() { return sizeof(double) * 3 * kDiagMaxBlocks; }
 
 }  // namespace vmfmm

@@ -1160,6 +1160,21 @@ vm_status vm_diagnostics(vm_ctx *ctx, int64_t n, const double *u, const double *
     return VM_OK;
 }
 
+vm_status vm_diagnostics_noalloc(vm_ctx *ctx, int64_t n, const double *u, const double *grad,
+                                 const double *alpha, double h3, double *out) {
+    if (!ctx) return VM_EINVAL;
+    if (!u || !out) return fail(ctx, VM_EINVAL, "u and out must be non-NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return fail(ctx, VM_EINVAL, "n out of range [1, 2^31)");
+    if (!(h3 > 0.0)) return fail(ctx, VM_EINVAL, "h3 must be positive");
+    if (size_t(3) * sizeof(double) * diag_blocks(int(n)) > diag_scratch_bytes())
+        return fail(ctx, VM_EINVAL, "partial sums exceed the static scratch array");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    double *part = nullptr;
+    VM_HIP(diag_scratch(ctx->device, &part), "hipGetSymbolAddress(scratch)");
+    VM_HIP(launch_diagnostics(ctx->stream, int(n), u, grad, alpha, h3, part, out), "diagnostics");
+    return VM_OK;
+}
+
 vm_status vm_gauss_sum(vm_ctx *ctx, int64_t n, const double *x, const double *gamma, double sigma, int level,
                        const vm_opts *opts, double *omega) {
     if (!ctx) return VM_EINVAL;
