@@ -127,6 +127,66 @@ vm_status vm_fmm_eval_at(vm_ctx *ctx, int64_t n, const double *x, const double *
                          double sigma, int p, int level, const vm_opts *opts, double *u, double *grad);
 
 /*
+ * Adaptive hybrid treecode-FMM (Sec. 3.2): the same velocity, gradient and
+ * stretching as vm_fmm_eval for particle sets that are far from uniform.
+ *   tree     the particles are keyed at max_level exactly as vm_fmm_eval keys
+ *            them at `level`; a cell is split when it holds more than ncrit
+ *            particles and lies above max_level, and only its non-empty
+ *            children exist, so leaves sit at any level and hold at most ncrit
+ *            particles except at max_level;
+ *   lists    a stack-based dual traversal from the root against itself (and,
+ *            periodic, its 26 images) pairs cells: two cells whose closed cubes
+ *            (the source shifted by its image) do not touch interact through
+ *            expansions -- M2L between cells of one level (cell-cell), M2P from
+ *            a finer source cell to the particles of a leaf and P2L from the
+ *            particles of a coarser leaf to a cell (cell-particle) -- touching
+ *            leaves exchange the exact regularised kernel (P2P), any other
+ *            touching pair is refined.  Every (target, source, image) triple is
+ *            covered once; on a uniform tree the lists are vm_fmm_eval's.
+ *   far field  the cutoff is dropped in all expansion interactions (the cells
+ *            are at least one width of the smaller one apart, so at leaves of
+ *            width >= 4 sigma as in vm_fmm_eval);
+ *   periodic images beyond the 27 of the tree by the same lattice operator.
+ * n, x, alpha, sigma, opts, u, dalpha_dt, grad as vm_fmm_eval; p in
+ * 1..VM_ADAPTIVE_MAX_P; ncrit >= 1; max_level 0..VM_MAX_LEVEL.  FP64 form and
+ * square truncation only (VM_EINVAL otherwise).  Unlike vm_fmm_eval the call
+ * synchronises the stream several times (the host sizes each level's cells and
+ * the lists) and cannot be captured into a graph.  The context keeps the
+ * tree, the lists and the expansions of the last call (vm_debug_adaptive).
+ */
+#define VM_ADAPTIVE_MAX_P 14   /* the cell-particle kernel holds (p+3)^2 harmonics per particle in LDS */
+vm_status vm_fmm_eval_adaptive(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                               int ncrit, int max_level, const vm_opts *opts, double *u, double *dalpha_dt,
+                               double *grad);
+
+/*
+ * Auto-tuned leaf size of the adaptive tree (Sec. 3.2: the number of particles
+ * per box at the deepest levels is chosen without user input): candidates
+ * ncrit = 8, 16, ..., 1024 in increasing order, each run once untimed and
+ * `reps` times timed (HIP events on the context's stream) with
+ * vm_fmm_eval_adaptive, until the time has risen twice in a row.
+ *   ncrit  out: the fastest candidate
+ *   ms     out or NULL: [VM_NCRIT_CANDIDATES] milliseconds per evaluation of
+ *          each candidate tried, -1 for the others
+ * Errors as vm_fmm_eval_adaptive; VM_EINVAL for reps outside 1..100.
+ */
+#define VM_NCRIT_CANDIDATES 8
+vm_status vm_tune_ncrit(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                        int max_level, const vm_opts *opts, int reps, int *ncrit, double *ms);
+
+/*
+ * Debug views of the last vm_fmm_eval_adaptive (synchronous copies into host
+ * memory `out`, or NULL to query *rows only):
+ *   what 0: cells, rows of 6 int32 (Morton key at the cell's level, level,
+ *           first sorted particle, particle count, parent cell or -1, leaf 0/1),
+ *           level-major, ascending key within a level;
+ *   what 1, 2, 3, 4: the P2P, M2L, M2P, P2L lists, rows of 3 int32 (target
+ *           cell, source cell, image shift code (sx+1) + 3 (sy+1) + 9 (sz+1));
+ *   what 5: the caller index of each sorted particle (n int32).
+ */
+vm_status vm_debug_adaptive(vm_ctx *ctx, int what, int32_t *out, int64_t *rows);
+
+/*
  * Discrete adjoint of vm_fmm_eval's velocity (the transposed FMM): for a
  * cotangent u_bar of u it returns
  *   alpha_bar = (du/dalpha)^T u_bar,   x_bar = (du/dx)^T u_bar
@@ -388,6 +448,9 @@ enum {
     VM_PH_P2P,        /* near field + combine + scatter to caller order */
     VM_PH_GAUSS,      /* Gaussian sums of vm_gauss_sum / vm_rbf_solve (with the strength packing) */
     VM_PH_KRYLOV,     /* vector work of vm_rbf_solve: dots, updates, gathers and scatters */
+    VM_PH_LISTS,      /* adaptive tree: cells, leaves and the dual traversal's lists */
+    VM_PH_P2L,        /* adaptive tree: particle-cell interactions */
+    VM_PH_M2P,        /* adaptive tree: cell-particle interactions */
     VM_NPHASE
 };
 vm_status vm_set_timing(vm_ctx *ctx, int enable);

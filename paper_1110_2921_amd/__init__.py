@@ -120,6 +120,58 @@ class FMM:
                                              ctypes.c_void_p(J.data_ptr() if J is not None else 0)))
         return u, J
 
+    def eval_adaptive(self, x, alpha, sigma, p, ncrit, max_level, periodic=0, box_lo=(0.0, 0.0, 0.0),
+                      box_len=2 * math.pi, scheme="classic", want_dalpha=True, want_grad=False,
+                      check_domain=False, stream=None):
+        """vm_fmm_eval_adaptive (FP64): (u, dalpha/dt or None, J or None), (3, n) / (9, n)."""
+        torch = self._torch
+        x = _soa(x, torch)
+        alpha = _soa(alpha, torch)
+        n = x.shape[1]
+        if alpha.shape[1] != n:
+            raise ValueError("x and alpha differ in length")
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        u = torch.empty((3, n), dtype=torch.float64, device=x.device)
+        da = torch.empty((3, n), dtype=torch.float64, device=x.device) if want_dalpha else None
+        J = torch.empty((9, n), dtype=torch.float64, device=x.device) if want_grad else None
+        opts = self._opts(periodic, box_lo, box_len, "fp64", scheme, check_domain)
+        self._check(self._lib.vm_fmm_eval_adaptive(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                                   ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p),
+                                                   int(ncrit), int(max_level), ctypes.byref(opts),
+                                                   ctypes.c_void_p(u.data_ptr()),
+                                                   ctypes.c_void_p(da.data_ptr() if da is not None else 0),
+                                                   ctypes.c_void_p(J.data_ptr() if J is not None else 0)))
+        return u, da, J
+
+    def tune_ncrit(self, x, alpha, sigma, p, max_level, periodic=0, box_lo=(0.0, 0.0, 0.0), box_len=2 * math.pi,
+                   reps=2, stream=None):
+        """vm_tune_ncrit: (fastest ncrit, {ncrit: ms per evaluation})."""
+        torch = self._torch
+        x = _soa(x, torch)
+        alpha = _soa(alpha, torch)
+        n = x.shape[1]
+        self._check(self._lib.vm_set_stream(self._h, ctypes.c_void_p(self._stream_ptr(stream))))
+        opts = self._opts(periodic, box_lo, box_len, "fp64", "classic", False)
+        best = ctypes.c_int()
+        ms = np.zeros(8, np.float64)
+        self._check(self._lib.vm_tune_ncrit(self._h, n, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(alpha.data_ptr()), float(sigma), int(p), int(max_level),
+                                            ctypes.byref(opts), int(reps), ctypes.byref(best),
+                                            ctypes.c_void_p(ms.ctypes.data)))
+        return best.value, {8 << i: float(v) for i, v in enumerate(ms) if v >= 0}
+
+    def debug_adaptive(self, what):
+        """vm_debug_adaptive: int64 array, (ncell, 6) cells, (m, 3) lists or (n,) permutation."""
+        names = {"cells": 0, "p2p": 1, "m2l": 2, "m2p": 3, "p2l": 4, "perm": 5}
+        w = names[what]
+        rows = ctypes.c_int64()
+        self._check(self._lib.vm_debug_adaptive(self._h, w, None, ctypes.byref(rows)))
+        width = 6 if w == 0 else (1 if w == 5 else 3)
+        out = np.zeros(max(rows.value, 1) * width, np.int32)
+        self._check(self._lib.vm_debug_adaptive(self._h, w, ctypes.c_void_p(out.ctypes.data), ctypes.byref(rows)))
+        out = out[:rows.value * width].astype(np.int64)
+        return out if w == 5 else out.reshape(-1, width)
+
     def adjoint(self, x, alpha, u_bar, sigma, p, level, periodic=0, box_lo=(0.0, 0.0, 0.0),
                 box_len=2 * math.pi, precision="fp64", want_x=True, want_alpha=True, stream=None,
                 truncation="square", grad=None):

@@ -11,16 +11,16 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvmfmm.so")
 
-PHASES = ("tree", "p2m", "m2m", "lattice", "l2l", "m2l", "l2p", "p2p", "gauss", "krylov")
+PHASES = ("tree", "p2m", "m2m", "lattice", "l2l", "m2l", "l2p", "p2p", "gauss", "krylov", "lists", "p2l", "m2p")
 
 VM_OK, VM_EINVAL, VM_ENOMEM, VM_EDEVICE, VM_EDOMAIN = 0, -1, -2, -3, -4
 STATUS_NAMES = {0: "VM_OK", -1: "VM_EINVAL", -2: "VM_ENOMEM", -3: "VM_EDEVICE", -4: "VM_EDOMAIN"}
 
 # every symbol include/vmfmm.h declares
-EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_eval", "vm_fmm_eval_at",
+EXPORTS = ("vm_create", "vm_destroy", "vm_set_stream", "vm_last_error", "vm_fmm_eval", "vm_fmm_eval_at", "vm_fmm_eval_adaptive", "vm_tune_ncrit",
            "vm_fmm_adjoint", "vm_fmm_adjoint_reuse", "vm_rk2_step", "vm_diagnostics", "vm_diagnostics_noalloc", "vm_gauss_sum", "vm_gauss_eval", "vm_rbf_solve",
            "vm_reinit", "vm_run", "vm_energy_spectrum", "vm_tune_level",
-           "vm_set_timing", "vm_get_timing", "vm_debug_tree", "vm_debug_expansions", "vm_debug_far", "vm_debug_offsets", "vm_debug_list",
+           "vm_set_timing", "vm_get_timing", "vm_debug_tree", "vm_debug_expansions", "vm_debug_far", "vm_debug_offsets", "vm_debug_list", "vm_debug_adaptive",
            "vm_debug_operator")
 
 
@@ -70,6 +70,14 @@ def load():
     lib.vm_fmm_eval_at.argtypes = [vp, i64, dp, dp, i64, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(VmOpts), dp, dp]
     lib.vm_fmm_eval_at.restype = ctypes.c_int
+    lib.vm_fmm_eval_adaptive.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(VmOpts), dp, dp, dp]
+    lib.vm_fmm_eval_adaptive.restype = ctypes.c_int
+    lib.vm_tune_ncrit.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(VmOpts), ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
+    lib.vm_tune_ncrit.restype = ctypes.c_int
+    lib.vm_debug_adaptive.argtypes = [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.vm_debug_adaptive.restype = ctypes.c_int
     lib.vm_fmm_adjoint.argtypes = [vp, i64, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(VmOpts), dp, dp, dp]
     lib.vm_fmm_adjoint.restype = ctypes.c_int

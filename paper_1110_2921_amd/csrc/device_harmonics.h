@@ -55,5 +55,47 @@ __device__ __forceinline__ void for_each_harmonic(T X, T Y, T Z, int deg, const 
     }
 }
 
+// Balanced irregular solid harmonics Ib_n^m(X) for n <= deg, m <= n, by the
+// recurrence the regular ones use, divided by r^2 at each step:
+//   Ib_0^0 = 1/r,  Ib_m^m = -(X + iY) diag[m] Ib_{m-1}^{m-1} / r^2,
+//   Ib_n^m = (c1 Z Ib_{n-1}^m - c2 Ib_{n-2}^m) / r^2   (n > m),
+// with the regular harmonics' constants (c1, c2, diag of a table of degree
+// >= deg).  Written packed, [Ib_n^0, Re Ib_n^m, sgn Im Ib_n^m] at
+// n^2, n^2 + 2m - 1, n^2 + 2m, with sgn = +1 or -1 (the conjugate).
+template <typename T>
+__device__ __forceinline__ void irregular_packed(T X, T Y, T Z, int deg, const T *__restrict__ c1,
+                                                 const T *__restrict__ c2, const T *__restrict__ dg, T sgn,
+                                                 T *__restrict__ out, int stride) {
+    const T r2 = X * X + Y * Y + Z * Z;
+    const T ir2 = T(1) / r2;
+    T dre = sqrt(ir2), dim = T(0);
+    for (int m = 0; m <= deg; ++m) {
+        if (m > 0) {
+            const T s = -dg[m] * ir2;
+            const T nre = s * (X * dre - Y * dim);
+            const T nim = s * (X * dim + Y * dre);
+            dre = nre;
+            dim = nim;
+        }
+        T are = dre, aim = dim, bre = T(0), bim = T(0);
+        for (int n = m; n <= deg; ++n) {
+            if (n > m) {
+                const int e = n * (n + 1) / 2 + m;
+                const T k1 = c1[e] * Z, k2 = c2[e];
+                const T cre = (k1 * are - k2 * bre) * ir2;
+                const T cim = (k1 * aim - k2 * bim) * ir2;
+                bre = are; bim = aim;
+                are = cre; aim = cim;
+            }
+            if (m == 0) {
+                out[(n * n) * stride] = are;
+            } else {
+                out[(n * n + 2 * m - 1) * stride] = are;
+                out[(n * n + 2 * m) * stride] = sgn * aim;
+            }
+        }
+    }
+}
+
 }  // namespace dev
 }  // namespace vmfmm

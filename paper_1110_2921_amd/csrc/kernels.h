@@ -35,6 +35,10 @@ hipError_t launch_permute(hipStream_t s, int n, const double *x, const double *a
                           const int32_t *perm, const uint32_t *keys, const TreeGeom &g,
                           Part64 *p64, Part32 *p32);
 hipError_t launch_iota(hipStream_t s, int n, int32_t *idx, uint32_t *keys);
+// In-place exclusive prefix sum of data[0..total); tile_sums holds at least
+// scan_tile_sums(total) words of scratch.
+hipError_t launch_exclusive_scan(hipStream_t s, int total, uint32_t *data, uint32_t *tile_sums);
+inline int scan_tile_sums(int total) { return (total + 4095) / 4096 + 1; }
 
 // --- expansions (kernels_fmm.hip) -------------------------------------------
 struct DevTables {
@@ -48,14 +52,25 @@ struct DevTables {
     int l2p_width, nu, ng;
 };
 
+// Leaves of an adaptive tree in particle order: leaf i holds the sorted
+// particles start[i] .. start[i+1]-1, sits at tree level lev[i] (its width
+// box_len 2^-lev) and keeps its expansions in cell slot cell[i].  The uniform
+// tree passes none (cell == nullptr): leaf i is then cell i at one width.
+struct LeafMap {
+    const int32_t *cell = nullptr;
+    const int32_t *lev = nullptr;
+    double box_len = 0.0, inv_len = 0.0;
+};
+
 template <typename T>
 hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t *start,
-                      int p, int kp, double inv_w, const DevTables &tab, T *m_out);
+                      int p, int kp, double inv_w, const DevTables &tab, T *m_out,
+                      const LeafMap &lm = LeafMap());
 
 template <typename T>
 hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start,
                       int p, int kp, double inv_w, double w, const DevTables &tab,
-                      const T *l_leaf, double *far);
+                      const T *l_leaf, double *far, const LeafMap &lm = LeafMap());
 
 // Generic translation GEMM on MFMA: mode 0 = M2L, 1 = L2L, 2 = M2M.
 // `part` (part_elems elements of T, may be null) is scratch for M2L launches
@@ -76,6 +91,27 @@ inline size_t tr_zero_elems(int kp) { return size_t(3) * kp + tr_slack_elems(kp)
 template <typename T>
 hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, const T *m0, T *l0);
 
+// The translation GEMMs on an adaptive tree's cells (same MFMA kernel, the
+// targets and sources from tables instead of a dense level):
+//   M2L: cells tcell[oct_base[o] ..] of octant o (8 groups, key order), source
+//        of pair i of target t in stab[(t - cell0) 189 + i] (-1: none), pair i
+//        the i-th operator of the octant's list;
+//   L2L: the same octant groups, source the parent parent[t];
+//   M2M: cells tcell[0 .. ntarget) in any order, pairs the 8 children
+//        child[8 t + o] (-1: none); targets without children are skipped.
+struct AdaptTr {
+    const int32_t *tcell = nullptr;
+    int oct_base[8] = {0, 0, 0, 0, 0, 0, 0, 0};       // M2L / L2L: group o is tcell[oct_base[o] ..]
+    int oct_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};          //   of oct_n[o] cells
+    int tile_start[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  //   first workgroup of each group
+    int ntarget = 0;                                   // M2M: tcell[0 .. ntarget)
+    int cell0 = 0;                                     // M2L: first cell of the stab rows
+    const int32_t *stab = nullptr, *parent = nullptr, *child = nullptr;
+};
+template <typename T>
+hipError_t launch_translate_adaptive(hipStream_t s, int mode, int p, int kp, const T *ops, const int16_t *oct_lists,
+                                     const T *src, T *dst, int accumulate, const AdaptTr &ad);
+
 // --- near field (kernels_p2p.hip) ---------------------------------------------
 struct P2PArgs {
     int n, nleaf, level, periodic, scheme, have_far;   // n: number of targets
@@ -90,6 +126,17 @@ struct P2PArgs {
 };
 hipError_t launch_p2p64(hipStream_t s, const P2PArgs &a, const Part64 *parts);
 hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts);
+
+// Near field of an adaptive tree: target leaf lcell[i] (particles lstart[i] ..
+// lstart[i+1]-1) against the source leaves of its P2P list, entries
+// off[c] .. off[c] + cnt[c] - 1 of (src, code) with image shift codes; cells'
+// particle ranges, keys and levels from the tree.  Same combine and output as
+// launch_p2p64 (a.n, a.perm, a.alpha, a.far, a.u, a.dalpha, a.grad, a.scheme,
+// a.have_far, a.sigma are used).
+struct AdTreeView;
+hipError_t launch_p2p64_list(hipStream_t s, const P2PArgs &a, int nleaf, const int32_t *lcell, const int32_t *lstart,
+                             const AdTreeView &t, const uint32_t *off, const uint32_t *cnt, const int32_t *src,
+                             const int8_t *code, const Part64 *parts);
 
 // --- RBF interpolation (kernels_rbf.hip) --------------------------------------------
 struct GaussArgs {
@@ -159,6 +206,63 @@ hipError_t launch_diagnostics(hipStream_t s, int n, const double *u, const doubl
 // array of the allocation-free diagnostics; looked up once per device.
 hipError_t diag_scratch(int device, double **ptr);
 size_t diag_scratch_bytes();
+
+// --- adaptive tree (kernels_adaptive.hip) ------------------------------------------
+// Cells level-major, ascending key inside a level; a cell is split when it
+// holds more than ncrit particles above max_level (then it has >= 1 child).
+struct AdTreeView {
+    const uint32_t *key;
+    const int32_t *level, *start, *count, *parent, *child;   // child: [cell][8], -1 absent
+    int ncrit, max_level, periodic;
+    double lo[3], box_len, inv_len;
+};
+// Interaction lists: partners (unresolved touching pairs a cell hands to its
+// children), the M2L table, and P2P / M2P / P2L lists in CSR form.
+struct AdLists {
+    int32_t *part;            // [cell][27] partner cell
+    int8_t *pcode;            // [cell][27] partner image shift code
+    int32_t *npart;           // [cell]
+    int32_t *vtab;            // [cell][189]: M2L source per slot of the cell's octant list, -1 none
+    const int16_t *vslot;     // [8][343] slot of offset d in octant o's M2L list (-1: not in it)
+    uint32_t *cnt;            // [3][ncell] counts of the P2P, M2P, P2L lists (counting pass)
+    const uint32_t *off;      // [3][ncell] exclusive offsets into the payload (filling pass)
+    int32_t *src[3];          // list payloads (one buffer): source cell
+    int8_t *code[3];          //   and its image shift code (sx+1) + 3 (sy+1) + 9 (sz+1)
+    int *err;                 // set on a partner overflow or an M2L offset outside the list
+};
+hipError_t launch_ad_root(hipStream_t s, const AdTreeView &t, int n);
+// children of the cells [off, off + ncl) of one level; writes the next level's
+// cells from off + ncl on, and their number to *nnext
+hipError_t launch_ad_level(hipStream_t s, const AdTreeView &t, int off, int ncl, const uint32_t *fine_keys,
+                           int32_t *slot_start, int32_t *slot_count, uint32_t *rank, uint32_t *tile_sums,
+                           int *nnext);
+// marks the cells [off, off + ncl) of the last level as childless
+hipError_t launch_ad_no_children(hipStream_t s, const AdTreeView &t, int off, int ncl);
+// leaves in particle order: lcell, lstart (nleaf + 1), llev; *nleaf_out
+hipError_t launch_ad_leaves(hipStream_t s, const AdTreeView &t, int ncell, int n, int32_t *leaf_at, uint32_t *rank,
+                            uint32_t *tile_sums, int32_t *lcell, int32_t *lstart, int32_t *llev, int *nleaf_out);
+// sorted FP64 records relative to each leaf's centre
+hipError_t launch_ad_permute(hipStream_t s, const AdTreeView &t, int n, const double *x, const double *alpha,
+                             const int32_t *perm, int nleaf, const int32_t *lcell, Part64 *parts);
+// dual traversal of the cells [off, off + ncl) of level l: pass 0 counts the
+// list entries and records the partners, pass 1 fills the lists (entries of
+// list k of cell c at off[k ncell + c] ..) and the M2L table (row c - vcell0)
+hipError_t launch_ad_traverse(hipStream_t s, const AdTreeView &t, const AdLists &ls, int l, int off, int ncl,
+                              int pass, int vcell0, int ncell);
+// octant groups of the cells [off, off + ncl): group o (key order) in
+// tcell[o ncl ..], its size in oct_count[o] (device)
+hipError_t launch_ad_octants(hipStream_t s, const AdTreeView &t, int off, int ncl, int32_t *tcell, uint32_t *rank,
+                             uint32_t *tile_sums, int *oct_count);
+// P2L: local expansions of the cells [off, off + ncl) (holding L2L and M2L)
+// += the particles of the source leaves of their P2L lists
+hipError_t launch_ad_p2l(hipStream_t s, const AdTreeView &t, const AdLists &ls, int off, int ncl, int ncell, int p,
+                         int kp, const DevTables &tab, const Part64 *parts, double *L);
+// M2P: far[12][n] of the particles of the leaves += the derivatives of the
+// source cells' multipoles (m2p_table layout; tab's recurrence of degree >= p + 2)
+hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nleaf, const int32_t *lcell,
+                         const int32_t *lstart, int n, int ncell, int p, int kp, int nrow, int nharm,
+                         const DevTables &tab, const int32_t *rowptr, const int32_t *col, const int32_t *harm,
+                         const double *w, const double *G, const Part64 *parts, const double *M, double *far);
 
 // rows of the translation-operator GEMM tile
 inline int pad16(int c) { return (c + 15) / 16 * 16; }

@@ -1,0 +1,569 @@
+// Adaptive tree of the hybrid treecode-FMM (Sec. 3.2): construction level by
+// level from the particles sorted at the finest level, the stack-based dual
+// traversal that turns touching cell pairs into P2P, M2L (cell-cell), M2P and
+// P2L (cell-particle) interactions, and the two cell-particle kernels.
+//
+// Cells are numbered level by level, ascending key inside a level.  A cell is
+// split when it holds more than ncrit particles above max_level; only its
+// non-empty children exist.  Two cells interact through expansions when their
+// closed cubes (the source shifted by its image) do not touch, an integer test
+// on the finest grid.
+//
+// Traversal: a cell's partners are the touching (cell, image) pairs it hands to
+// its children unresolved: same-level cells and coarser leaves, at most the 27
+// neighbour positions of the cell.  A cell's candidates are its parent's
+// partners, split ones replaced by their children (the root: itself and, when
+// periodic, its 26 images).  A candidate that does not touch the cell is an
+// M2L source (same level) or a P2L source (a coarser leaf); a touching one is
+// a P2P source when both are leaves, a partner when the cell is split, and
+// when only the candidate is split its subtree is walked with an explicit
+// stack: cells that do not touch the leaf are M2P sources, touching leaves
+// P2P sources, touching split cells are opened.  Each (target particle,
+// source particle, image) triple is then covered by exactly one interaction.
+#include <cstdio>
+
+#include "device_harmonics.h"
+#include "kernels.h"
+
+namespace vmfmm {
+
+namespace {
+
+using dev::irregular_packed;
+
+__device__ __forceinline__ int ad_coord(uint32_t k, int d, int level) {
+    int c = 0;
+    for (int b = 0; b < level; ++b) c |= int((k >> (3 * b + d)) & 1u) << b;
+    return c;
+}
+
+__device__ __forceinline__ bool ad_leaf(const AdTreeView &t, int c) {
+    return t.count[c] <= t.ncrit || t.level[c] >= t.max_level;
+}
+
+// image shift code (sx+1) + 3 (sy+1) + 9 (sz+1) -> component d
+__device__ __forceinline__ int shift_of(int code, int d) {
+    return d == 0 ? code % 3 - 1 : (d == 1 ? (code / 3) % 3 - 1 : code / 9 - 1);
+}
+
+// Do the closed cubes of a and of b shifted by image `code` touch?
+__device__ __forceinline__ bool touching(const AdTreeView &t, int a, int b, int code) {
+    const int la = t.level[a], lb = t.level[b], M = t.max_level;
+    const int na = 1 << (M - la), nb = 1 << (M - lb);
+    for (int d = 0; d < 3; ++d) {
+        const int ca = ad_coord(t.key[a], d, la) << (M - la);
+        const int cb = (ad_coord(t.key[b], d, lb) << (M - lb)) + shift_of(code, d) * (1 << M);
+        if (ca > cb + nb || cb > ca + na) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void centre(const AdTreeView &t, int c, double out[3]) {
+    const int l = t.level[c];
+    const double w = ldexp(t.box_len, -l);
+    for (int d = 0; d < 3; ++d) out[d] = t.lo[d] + (double(ad_coord(t.key[c], d, l)) + 0.5) * w;
+}
+
+// ------------------------------------------------------------- construction ----
+__global__ void k_ad_root(AdTreeView t, int n) {
+    if (threadIdx.x != 0) return;
+    int32_t *child = const_cast<int32_t *>(t.child);
+    const_cast<uint32_t *>(t.key)[0] = 0u;
+    const_cast<int32_t *>(t.level)[0] = 0;
+    const_cast<int32_t *>(t.start)[0] = 0;
+    const_cast<int32_t *>(t.count)[0] = n;
+    const_cast<int32_t *>(t.parent)[0] = -1;
+    for (int o = 0; o < 8; ++o) child[o] = -1;
+}
+
+// slot 8 (c - off) + o: particle range of child o of cell c (empty unless c is split)
+__global__ void __launch_bounds__(256) k_ad_children(AdTreeView t, int off, int ncl, const uint32_t *__restrict__ fine,
+                                                     int32_t *__restrict__ sstart, int32_t *__restrict__ scount,
+                                                     uint32_t *__restrict__ flag) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= 8 * ncl) return;
+    const int c = off + slot / 8, o = slot % 8;
+    int s0 = 0, cnt = 0;
+    const int l = t.level[c];
+    if (!ad_leaf(t, c)) {
+        const int shift = 3 * (t.max_level - l - 1);
+        const uint32_t want = (t.key[c] << 3) | uint32_t(o);
+        const int a = t.start[c], e = a + t.count[c];
+        // first position with prefix >= want, then first with prefix > want
+        int lo = a, hi = e;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((fine[mid] >> shift) < want) lo = mid + 1;
+            else hi = mid;
+        }
+        int lo2 = lo, hi2 = e;
+        while (lo2 < hi2) {
+            const int mid = (lo2 + hi2) >> 1;
+            if ((fine[mid] >> shift) <= want) lo2 = mid + 1;
+            else hi2 = mid;
+        }
+        s0 = lo;
+        cnt = lo2 - lo;
+    }
+    sstart[slot] = s0;
+    scount[slot] = cnt;
+    flag[slot] = cnt > 0 ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_ad_emit(AdTreeView t, int off, int ncl, const int32_t *__restrict__ sstart,
+                                                 const int32_t *__restrict__ scount, const uint32_t *__restrict__ rank,
+                                                 int *__restrict__ nnext) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= 8 * ncl) return;
+    const int c = off + slot / 8, o = slot % 8;
+    const int next0 = off + ncl;
+    if (slot == 8 * ncl - 1) *nnext = int(rank[slot]) + (scount[slot] > 0 ? 1 : 0);
+    int32_t *child = const_cast<int32_t *>(t.child);
+    if (scount[slot] == 0) {
+        child[8 * c + o] = -1;
+        return;
+    }
+    const int idx = next0 + int(rank[slot]);
+    const_cast<uint32_t *>(t.key)[idx] = (t.key[c] << 3) | uint32_t(o);
+    const_cast<int32_t *>(t.level)[idx] = t.level[c] + 1;
+    const_cast<int32_t *>(t.start)[idx] = sstart[slot];
+    const_cast<int32_t *>(t.count)[idx] = scount[slot];
+    const_cast<int32_t *>(t.parent)[idx] = c;
+    child[8 * c + o] = idx;
+}
+
+// the children of the last level's cells do not exist
+__global__ void __launch_bounds__(256) k_ad_no_children(AdTreeView t, int off, int ncl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 8 * ncl) return;
+    const_cast<int32_t *>(t.child)[8 * off + i] = -1;
+}
+
+// ------------------------------------------------------------------ leaves ----
+__global__ void __launch_bounds__(256) k_ad_leaf_mark(AdTreeView t, int ncell, int32_t *__restrict__ leaf_at) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell || !ad_leaf(t, c)) return;
+    leaf_at[t.start[c]] = c;
+}
+
+__global__ void __launch_bounds__(256) k_ad_leaf_flag(int n, const int32_t *__restrict__ leaf_at,
+                                                      uint32_t *__restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = leaf_at[i] >= 0 ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_ad_leaf_compact(AdTreeView t, int n, const int32_t *__restrict__ leaf_at,
+                                                         const uint32_t *__restrict__ rank, int32_t *__restrict__ lcell,
+                                                         int32_t *__restrict__ lstart, int32_t *__restrict__ llev,
+                                                         int *__restrict__ nleaf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = leaf_at[i];
+    if (i == n - 1) {
+        const int tot = int(rank[i]) + (c >= 0 ? 1 : 0);
+        *nleaf = tot;
+        lstart[tot] = n;
+    }
+    if (c < 0) return;
+    const int r = int(rank[i]);
+    lcell[r] = c;
+    lstart[r] = i;
+    llev[r] = t.level[c];
+}
+
+__device__ __forceinline__ double wrap1(double x, double lo, double len, double inv_len) {
+#pragma clang fp contract(off)
+    const double s = floor((x - lo) * inv_len);
+    const double tt = s * len;
+    return x - tt;
+}
+
+// one workgroup per leaf: records of its particles relative to its centre
+__global__ void __launch_bounds__(64) k_ad_permute(AdTreeView t, int n, const double *__restrict__ x,
+                                                   const double *__restrict__ alpha, const int32_t *__restrict__ perm,
+                                                   const int32_t *__restrict__ lcell, Part64 *__restrict__ parts) {
+    const int c = lcell[blockIdx.x];
+    double ctr[3];
+    centre(t, c, ctr);
+    const int s0 = t.start[c], cnt = t.count[c];
+    for (int k = threadIdx.x; k < cnt; k += 64) {
+        const int i = s0 + k, j = perm[i];
+        double dl[3], al[3];
+        for (int d = 0; d < 3; ++d) {
+            double xv = x[size_t(d) * n + j];
+            if (t.periodic) xv = wrap1(xv, t.lo[d], t.box_len, t.inv_len);
+            dl[d] = xv - ctr[d];
+            al[d] = alpha[size_t(d) * n + j];
+        }
+        Part64 r;
+        r.dx = dl[0]; r.dy = dl[1]; r.dz = dl[2];
+        r.ax = al[0]; r.ay = al[1]; r.az = al[2];
+        r.pad0 = 0.0; r.pad1 = 0.0;
+        parts[i] = r;
+    }
+}
+
+// --------------------------------------------------------------- traversal ----
+constexpr int kAdStack = 128;
+constexpr int kM2LSlots = 189;
+
+__device__ __forceinline__ void put(const AdLists &ls, int pass, int ncell, int k, int a, uint32_t &cnt, int b,
+                                    int code) {
+    if (pass == 1) {
+        const size_t pos = size_t(ls.off[size_t(k) * ncell + a]) + cnt;
+        ls.src[k][pos] = b;
+        ls.code[k][pos] = int8_t(code);
+    }
+    ++cnt;
+}
+
+__global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, int l, int off, int ncl, int pass,
+                                                    int vcell0, int ncell) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    const int a = off + i;
+    const bool leaf_a = ad_leaf(t, a);
+    const int oct = int(t.key[a] & 7u);
+    int ca[3];
+    for (int d = 0; d < 3; ++d) ca[d] = ad_coord(t.key[a], d, l);
+    uint32_t cnt[3] = {0u, 0u, 0u};
+    int np = 0;
+    int stack[kAdStack];
+    bool bad = false;
+
+    auto classify = [&](int b, int code) {
+        const int lb = t.level[b];
+        if (!touching(t, a, b, code)) {
+            if (lb == l) {
+                if (pass == 1) {
+                    int idx = 0, mul = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        const int dd = ad_coord(t.key[b], d, l) + shift_of(code, d) * (1 << l) - ca[d];
+                        if (dd < -3 || dd > 3) bad = true;
+                        idx += (dd + 3) * mul;
+                        mul *= 7;
+                    }
+                    const int slot = bad ? -1 : ls.vslot[oct * 343 + idx];
+                    if (slot < 0) bad = true;
+                    else ls.vtab[size_t(a - vcell0) * kM2LSlots + slot] = b;
+                }
+            } else {
+                put(ls, pass, ncell, 2, a, cnt[2], b, code);      // P2L: b is a coarser leaf
+            }
+            return;
+        }
+        const bool leaf_b = ad_leaf(t, b);
+        if (leaf_a && leaf_b) {
+            put(ls, pass, ncell, 0, a, cnt[0], b, code);
+        } else if (leaf_a) {
+            // walk b's subtree: cells apart from a are M2P sources
+            int sp = 0;
+            for (int o = 0; o < 8; ++o) {
+                const int e = t.child[8 * b + o];
+                if (e >= 0) {
+                    if (sp < kAdStack) stack[sp++] = e;
+                    else bad = true;
+                }
+            }
+            while (sp > 0) {
+                const int e = stack[--sp];
+                if (!touching(t, a, e, code)) {
+                    put(ls, pass, ncell, 1, a, cnt[1], e, code);
+                } else if (ad_leaf(t, e)) {
+                    put(ls, pass, ncell, 0, a, cnt[0], e, code);
+                } else {
+                    for (int o = 0; o < 8; ++o) {
+                        const int f = t.child[8 * e + o];
+                        if (f >= 0) {
+                            if (sp < kAdStack) stack[sp++] = f;
+                            else bad = true;
+                        }
+                    }
+                }
+            }
+        } else {
+            // a is split: the pair goes to a's children
+            if (pass == 0) {
+                if (np < 27) {
+                    ls.part[size_t(a) * 27 + np] = b;
+                    ls.pcode[size_t(a) * 27 + np] = int8_t(code);
+                } else {
+                    bad = true;
+                }
+            }
+            ++np;
+        }
+    };
+
+    if (l == 0) {
+        if (t.periodic) {
+            for (int code = 0; code < 27; ++code) classify(0, code);
+        } else {
+            classify(0, 13);
+        }
+    } else {
+        const int P = t.parent[a];
+        const int npp = ls.npart[P];
+        for (int k = 0; k < npp; ++k) {
+            const int B = ls.part[size_t(P) * 27 + k], code = ls.pcode[size_t(P) * 27 + k];
+            if (ad_leaf(t, B)) {
+                classify(B, code);
+            } else {
+                for (int o = 0; o < 8; ++o) {
+                    const int b = t.child[8 * B + o];
+                    if (b >= 0) classify(b, code);
+                }
+            }
+        }
+    }
+    if (pass == 0) {
+        ls.npart[a] = np < 27 ? np : 27;
+        for (int k = 0; k < 3; ++k) ls.cnt[size_t(k) * ncell + a] = cnt[k];
+    }
+    if (bad) atomicExch(ls.err, 1);
+}
+
+// octant groups of one level: counts, then stable placement by prefix within each octant
+__global__ void __launch_bounds__(256) k_ad_oct_flags(AdTreeView t, int off, int ncl, int o, uint32_t *__restrict__ f) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncl) f[i] = int(t.key[off + i] & 7u) == o ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_ad_oct_place(AdTreeView t, int off, int ncl, int o,
+                                                      const uint32_t *__restrict__ rank, int32_t *__restrict__ out,
+                                                      int *__restrict__ count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    const bool mine = int(t.key[off + i] & 7u) == o;
+    if (i == ncl - 1) *count = int(rank[i]) + (mine ? 1 : 0);
+    if (mine) out[rank[i]] = off + i;
+}
+
+// ------------------------------------------------------------ cell-particle ----
+// P2L: one workgroup per target cell with a P2L list.  Lane j takes the
+// conjugated irregular harmonics of source particle j (relative to the target
+// centre, in target widths) into its LDS row; lanes then sum the rows per
+// coefficient, weighted by the particles' strengths, and add the result to the
+// cell's local expansion (which already holds L2L and M2L).
+__global__ void __launch_bounds__(64) k_ad_p2l(AdTreeView t, AdLists ls, int off, int ncl, int ncell, int p, int kp,
+                                               DevTables tab, const Part64 *__restrict__ parts,
+                                               double *__restrict__ L) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int a = off + blockIdx.x;
+    const uint32_t e0 = ls.off[size_t(2) * ncell + a];
+    const uint32_t e1 = e0 + ls.cnt[size_t(2) * ncell + a];
+    if (e1 == e0) return;
+    const int C = (p + 1) * (p + 1), lane = threadIdx.x;
+    const int stride = C + 1;
+    double *rows = reinterpret_cast<double *>(smem_raw);   // [64][C + 1]
+    double *al = rows + 64 * stride;                       // [64][3]
+    double ca[3];
+    centre(t, a, ca);
+    const double inv_w = ldexp(t.inv_len, t.level[a]);
+    constexpr int kMaxC = 4;   // coefficients per lane: C <= 256 (p <= 15)
+    double acc[kMaxC][3];
+    for (int q = 0; q < kMaxC; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+    for (uint32_t e = e0; e < e1; ++e) {
+        const int b = ls.src[2][e], code = ls.code[2][e];
+        double cb[3];
+        centre(t, b, cb);
+        // source position relative to the target centre: delta_j + (c_b + s L - c_a)
+        double sh[3];
+        for (int d = 0; d < 3; ++d) sh[d] = cb[d] + shift_of(code, d) * t.box_len - ca[d];
+        const int s0 = t.start[b], cnt = t.count[b];
+        for (int base = 0; base < cnt; base += 64) {
+            const int nj = min(64, cnt - base);
+            if (lane < nj) {
+                const Part64 q = parts[s0 + base + lane];
+                const double X = (q.dx + sh[0]) * inv_w, Y = (q.dy + sh[1]) * inv_w, Z = (q.dz + sh[2]) * inv_w;
+                irregular_packed<double>(X, Y, Z, p, tab.c1_64, tab.c2_64, tab.diag_64, -1.0, rows + lane * stride, 1);
+                al[lane * 3 + 0] = q.ax;
+                al[lane * 3 + 1] = q.ay;
+                al[lane * 3 + 2] = q.az;
+            }
+            __syncthreads();
+            for (int q = 0; q < kMaxC; ++q) {
+                const int cidx = lane + 64 * q;
+                if (cidx >= C) break;
+                for (int j = 0; j < nj; ++j) {
+                    const double v = rows[j * stride + cidx];
+                    acc[q][0] += al[j * 3 + 0] * v;
+                    acc[q][1] += al[j * 3 + 1] * v;
+                    acc[q][2] += al[j * 3 + 2] * v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = 0; q < kMaxC; ++q) {
+        const int cidx = lane + 64 * q;
+        if (cidx >= C) break;
+        for (int k = 0; k < 3; ++k) L[(size_t(a) * 3 + k) * kp + cidx] += acc[q][k];
+    }
+}
+
+// M2P: one workgroup per target leaf with an M2P list, one particle per lane.
+// For each source cell the lane writes the balanced irregular harmonics of its
+// particle's offset from the source centre (degree p + 2) into its LDS column,
+// forms the degree <= 2 local expansion about the particle from the table
+// (rows x (col, harm, weight)), and the table's evaluation matrix G turns
+// those coefficients into u and J at the particle, added to far[12][n].
+constexpr int kM2PMaxRow = 9;
+
+__global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, int nleaf, const int32_t *__restrict__ lcell,
+                                               const int32_t *__restrict__ lstart, int n, int ncell, int p, int kp,
+                                               int nrow, int nharm, DevTables tab, const int32_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const int32_t *__restrict__ harm,
+                                               const double *__restrict__ wt, const double *__restrict__ G,
+                                               const Part64 *__restrict__ parts, const double *__restrict__ M,
+                                               double *__restrict__ far) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int a = lcell[blockIdx.x];
+    const uint32_t e0 = ls.off[size_t(1) * ncell + a];
+    const uint32_t e1 = e0 + ls.cnt[size_t(1) * ncell + a];
+    if (e1 == e0) return;
+    const int lane = threadIdx.x;
+    double *hs = reinterpret_cast<double *>(smem_raw);     // [nharm][64]
+    double *mb = hs + size_t(nharm) * 64;                   // [3][kp]
+    double ca[3];
+    centre(t, a, ca);
+    const int s0 = lstart[blockIdx.x], cnt = lstart[blockIdx.x + 1] - s0;
+    for (int base = 0; base < cnt; base += 64) {
+        const bool valid = base + lane < cnt;
+        const Part64 me = parts[s0 + base + (valid ? lane : 0)];
+        double out[12];
+        for (int o = 0; o < 12; ++o) out[o] = 0.0;
+        for (uint32_t e = e0; e < e1; ++e) {
+            const int b = ls.src[1][e], code = ls.code[1][e];
+            double cb[3];
+            centre(t, b, cb);
+            const int lb = t.level[b];
+            const double inv_w = ldexp(t.inv_len, lb), w = ldexp(t.box_len, -lb);
+            __syncthreads();
+            for (int k = lane; k < 3 * kp; k += 64) mb[k] = M[size_t(b) * 3 * kp + k];
+            // particle relative to the source centre: delta_i + (c_a - c_b - s L)
+            const double X = (me.dx + (ca[0] - cb[0] - shift_of(code, 0) * t.box_len)) * inv_w;
+            const double Y = (me.dy + (ca[1] - cb[1] - shift_of(code, 1) * t.box_len)) * inv_w;
+            const double Z = (me.dz + (ca[2] - cb[2] - shift_of(code, 2) * t.box_len)) * inv_w;
+            irregular_packed<double>(X, Y, Z, p + 2, tab.c1_64, tab.c2_64, tab.diag_64, 1.0, hs + lane, 64);
+            __syncthreads();
+            double loc[3][kM2PMaxRow];
+            for (int r = 0; r < kM2PMaxRow; ++r) loc[0][r] = loc[1][r] = loc[2][r] = 0.0;
+#pragma unroll
+            for (int r = 0; r < kM2PMaxRow; ++r) {
+                if (r >= nrow) break;
+                double s0v = 0.0, s1v = 0.0, s2v = 0.0;
+                for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+                    const double hv = wt[k] * hs[harm[k] * 64 + lane];
+                    const int c = col[k];
+                    s0v += hv * mb[c];
+                    s1v += hv * mb[kp + c];
+                    s2v += hv * mb[2 * kp + c];
+                }
+                loc[0][r] = s0v;
+                loc[1][r] = s1v;
+                loc[2][r] = s2v;
+            }
+            const double su = 0.079577471545947667884 * inv_w * inv_w, sj = su * inv_w;
+            (void)w;
+            for (int o = 0; o < 12; ++o) {
+                double v = 0.0;
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int r = 0; r < kM2PMaxRow; ++r)
+                        if (r < nrow) v += G[size_t(o) * 3 * nrow + k * nrow + r] * loc[k][r];
+                out[o] += v * (o < 3 ? su : sj);
+            }
+        }
+        if (valid) {
+            const size_t gi = size_t(s0) + base + lane;
+            for (int o = 0; o < 12; ++o) far[size_t(o) * n + gi] += out[o];
+        }
+    }
+}
+
+inline int blocks(int n, int t) { return (n + t - 1) / t; }
+
+}  // namespace
+
+hipError_t launch_ad_root(hipStream_t s, const AdTreeView &t, int n) {
+    hipLaunchKernelGGL(k_ad_root, dim3(1), dim3(64), 0, s, t, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_level(hipStream_t s, const AdTreeView &t, int off, int ncl, const uint32_t *fine,
+                           int32_t *sstart, int32_t *scount, uint32_t *rank, uint32_t *tile_sums, int *nnext) {
+    const int slots = 8 * ncl;
+    hipLaunchKernelGGL(k_ad_children, dim3(blocks(slots, 256)), dim3(256), 0, s, t, off, ncl, fine, sstart, scount,
+                       rank);
+    hipError_t e = launch_exclusive_scan(s, slots, rank, tile_sums);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ad_emit, dim3(blocks(slots, 256)), dim3(256), 0, s, t, off, ncl,
+                       (const int32_t *)sstart, (const int32_t *)scount, (const uint32_t *)rank, nnext);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_no_children(hipStream_t s, const AdTreeView &t, int off, int ncl) {
+    hipLaunchKernelGGL(k_ad_no_children, dim3(blocks(8 * ncl, 256)), dim3(256), 0, s, t, off, ncl);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_leaves(hipStream_t s, const AdTreeView &t, int ncell, int n, int32_t *leaf_at, uint32_t *rank,
+                            uint32_t *tile_sums, int32_t *lcell, int32_t *lstart, int32_t *llev, int *nleaf_out) {
+    hipError_t e = hipMemsetAsync(leaf_at, 0xff, sizeof(int32_t) * size_t(n), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ad_leaf_mark, dim3(blocks(ncell, 256)), dim3(256), 0, s, t, ncell, leaf_at);
+    hipLaunchKernelGGL(k_ad_leaf_flag, dim3(blocks(n, 256)), dim3(256), 0, s, n, (const int32_t *)leaf_at, rank);
+    e = launch_exclusive_scan(s, n, rank, tile_sums);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ad_leaf_compact, dim3(blocks(n, 256)), dim3(256), 0, s, t, n, (const int32_t *)leaf_at,
+                       (const uint32_t *)rank, lcell, lstart, llev, nleaf_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_permute(hipStream_t s, const AdTreeView &t, int n, const double *x, const double *alpha,
+                             const int32_t *perm, int nleaf, const int32_t *lcell, Part64 *parts) {
+    hipLaunchKernelGGL(k_ad_permute, dim3(nleaf), dim3(64), 0, s, t, n, x, alpha, perm, lcell, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_traverse(hipStream_t s, const AdTreeView &t, const AdLists &ls, int l, int off, int ncl,
+                              int pass, int vcell0, int ncell) {
+    hipLaunchKernelGGL(k_ad_traverse, dim3(blocks(ncl, 64)), dim3(64), 0, s, t, ls, l, off, ncl, pass, vcell0, ncell);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_octants(hipStream_t s, const AdTreeView &t, int off, int ncl, int32_t *tcell, uint32_t *rank,
+                             uint32_t *tile_sums, int *oct_count) {
+    // octant o's cells land after those of octants < o; their offsets are
+    // prefix sums of oct_count, known only on the host, so each group is
+    // written into its own stretch of ncl entries: tcell[o ncl ...]
+    for (int o = 0; o < 8; ++o) {
+        hipLaunchKernelGGL(k_ad_oct_flags, dim3(blocks(ncl, 256)), dim3(256), 0, s, t, off, ncl, o, rank);
+        hipError_t e = launch_exclusive_scan(s, ncl, rank, tile_sums);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_ad_oct_place, dim3(blocks(ncl, 256)), dim3(256), 0, s, t, off, ncl, o,
+                           (const uint32_t *)rank, tcell + size_t(o) * ncl, oct_count + o);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_p2l(hipStream_t s, const AdTreeView &t, const AdLists &ls, int off, int ncl, int ncell, int p,
+                         int kp, const DevTables &tab, const Part64 *parts, double *L) {
+    const int C = (p + 1) * (p + 1);
+    const size_t smem = sizeof(double) * (size_t(64) * (C + 1) + 64 * 3);
+    hipLaunchKernelGGL(k_ad_p2l, dim3(ncl), dim3(64), smem, s, t, ls, off, ncl, ncell, p, kp, tab, parts, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nleaf, const int32_t *lcell,
+                         const int32_t *lstart, int n, int ncell, int p, int kp, int nrow, int nharm,
+                         const DevTables &tab, const int32_t *rowptr, const int32_t *col, const int32_t *harm,
+                         const double *w, const double *G, const Part64 *parts, const double *M, double *far) {
+    const size_t smem = sizeof(double) * (size_t(nharm) * 64 + size_t(3) * kp);
+    hipLaunchKernelGGL(k_ad_m2p, dim3(nleaf), dim3(64), smem, s, t, ls, nleaf, lcell, lstart, n, ncell, p, kp, nrow,
+                       nharm, tab, rowptr, col, harm, w, G, parts, M, far);
+    return hipGetLastError();
+}
+
+}  // namespace vmfmm

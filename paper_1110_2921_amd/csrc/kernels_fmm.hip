@@ -156,7 +156,8 @@ __device__ __forceinline__ void p2m_row_fixed(int g, T X, T Y, T Z, const T *__r
 template <typename T, int PT>
 __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__restrict__ parts,
                                             const int32_t *__restrict__ start, int nleaf, int p, int kp,
-                                            T inv_w, DevTables tab, MGroups grp, T *__restrict__ mout) {
+                                            T inv_w, DevTables tab, MGroups grp, T *__restrict__ mout,
+                                            LeafMap lm) {
     static_assert(PT == 0 || p2m_groups(PT).ng > 0, "no partition of the orders for this degree");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = threadIdx.x;
@@ -170,6 +171,11 @@ __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__re
     } else {
         g = b % G;
         leaf = b / G;
+    }
+    size_t mcell = size_t(leaf);
+    if (lm.cell) {               // adaptive tree: the leaf's own width and cell slot
+        inv_w = T(ldexp(lm.inv_len, lm.lev[leaf]));
+        mcell = size_t(lm.cell[leaf]);
     }
     const int mlo = grp.lo[g], mhi = grp.lo[g + 1];
     const int ng = group_count(p, mlo, mhi);
@@ -216,7 +222,7 @@ __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__re
         }
     }
     const int sidx = m == 0 ? n * n : n * n + 2 * m - 1 + part;
-    T *dst = mout + size_t(leaf) * 3 * kp;
+    T *dst = mout + mcell * 3 * kp;
     for (int c = 0; c < 3; ++c) dst[c * kp + sidx] = acc[c];
 }
 
@@ -228,7 +234,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__restrict__ parts,
                                             const int32_t *__restrict__ start, int n, int p, int kp,
                                             T inv_w, double su, double sj, DevTables tab,
-                                            const T *__restrict__ lleaf, double *__restrict__ far) {
+                                            const T *__restrict__ lleaf, double *__restrict__ far, LeafMap lm) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int C = (p + 1) * (p + 1);
     const int nu = tab.nu, ng = tab.ng, width = tab.l2p_width;
@@ -237,7 +243,15 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
     const int leaf = blockIdx.x, lane = threadIdx.x;
     const int s0 = start[leaf], cnt = start[leaf + 1] - s0;
     if (cnt == 0) return;
-    const T *src = lleaf + size_t(leaf) * 3 * kp;
+    size_t lcell = size_t(leaf);
+    if (lm.cell) {               // adaptive tree: the leaf's own width and cell slot
+        const double w = ldexp(lm.box_len, -lm.lev[leaf]);
+        inv_w = T(ldexp(lm.inv_len, lm.lev[leaf]));
+        su = 1.0 / (12.566370614359172953850573533118 * w * w);
+        sj = 1.0 / (12.566370614359172953850573533118 * w * w * w);
+        lcell = size_t(lm.cell[leaf]);
+    }
+    const T *src = lleaf + lcell * 3 * kp;
     for (int i = lane; i < 3 * C; i += 64) lam[i] = src[(i / C) * kp + (i % C)];
     __syncthreads();
     const T *tw = Tab<T>::w(tab);
@@ -363,7 +377,8 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
                                                           const int16_t *__restrict__ oct_lists,
                                                           const int8_t *__restrict__ offsets,
                                                           const T *__restrict__ src, T *__restrict__ dst,
-                                                          int accumulate, int nsplit, T *__restrict__ part) {
+                                                          int accumulate, int nsplit, T *__restrict__ part,
+                                                          AdaptTr ad) {
     using V = typename Mfma<T>::v4;
     constexpr int TTN = 16 * NT;
     constexpr int NCB = 3 * NT;                          // column blocks: (group, component)
@@ -382,9 +397,16 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
 
     int octant = 0, tile = blockIdx.x, npair = 1, pr0 = 0;
     int64_t ncell_t;
+    const bool adaptive = ad.tcell != nullptr;   // cells and sources from tables (adaptive tree)
     if (mode == 2) {                  // M2M: targets are the parents at `level`
-        ncell_t = int64_t(1) << (3 * level);
+        ncell_t = adaptive ? ad.ntarget : int64_t(1) << (3 * level);
         npair = 8;
+    } else if (adaptive) {            // octant groups of one level, tile_start[o] .. workgroups each
+        octant = 0;
+        while (octant < 7 && int(blockIdx.x) >= ad.tile_start[octant + 1]) ++octant;
+        tile = int(blockIdx.x) - ad.tile_start[octant];
+        ncell_t = ad.oct_n[octant];
+        if (mode == 0) npair = 189;
     } else {                          // M2L / L2L: targets at `level`, grouped by octant
         octant = blockIdx.x & 7;
         tile = blockIdx.x >> 3;
@@ -397,7 +419,16 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
     if (tid < TTN) {
         const int64_t slot = int64_t(tile) * TTN + tid;
         int32_t k = -1;
-        if (slot < ncell_t) k = mode == 2 ? int32_t(slot) : int32_t((slot << 3) | octant);
+        if (adaptive) {
+            if (slot < ncell_t) k = mode == 2 ? ad.tcell[slot] : ad.tcell[ad.oct_base[octant] + slot];
+            if (mode == 2 && k >= 0) {
+                bool any = false;
+                for (int o = 0; o < 8; ++o) any = any || ad.child[8 * size_t(k) + o] >= 0;
+                if (!any) k = -1;     // a leaf: its multipole is its own P2M
+            }
+        } else if (slot < ncell_t) {
+            k = mode == 2 ? int32_t(slot) : int32_t((slot << 3) | octant);
+        }
         tkey[tid] = k;
     }
     // the K padding of the staging buffers stays zero
@@ -413,6 +444,11 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
     auto source_key = [&](int i) -> int32_t {
         const int32_t t = tkey[tid];
         if (t < 0) return -1;
+        if (adaptive) {
+            if (mode == 0) return ad.stab[size_t(t - ad.cell0) * 189 + pr0 + i];
+            if (mode == 1) return ad.parent[t];
+            return ad.child[8 * size_t(t) + i];
+        }
         if (mode == 0) {
             const int op = op_of(i);
             int c[3];
@@ -801,7 +837,7 @@ __global__ void __launch_bounds__(256) k_lattice(int C, int kp, const double *__
 
 template <typename T>
 hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t *start, int p, int kp,
-                      double inv_w, const DevTables &tab, T *m_out) {
+                      double inv_w, const DevTables &tab, T *m_out, const LeafMap &lm) {
     const MGroups grp = p2m_groups(p);
     if (grp.ng == 0) return hipErrorInvalidValue;
     const size_t smem = sizeof(T) * (size_t(64) * (grp.maxn + 1) + 64 * 3);
@@ -809,23 +845,24 @@ hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t
     const dim3 grid(unsigned(nleaf) * grp.ng);
     // the degrees of the workloads at compile time, any other at run time
     switch (p) {
-    case 6: hipLaunchKernelGGL((k_p2m<T, 6>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out); break;
-    case 8: hipLaunchKernelGGL((k_p2m<T, 8>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out); break;
-    case 10: hipLaunchKernelGGL((k_p2m<T, 10>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out); break;
-    default: hipLaunchKernelGGL((k_p2m<T, 0>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out);
+    case 6: hipLaunchKernelGGL((k_p2m<T, 6>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm); break;
+    case 8: hipLaunchKernelGGL((k_p2m<T, 8>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm); break;
+    case 10: hipLaunchKernelGGL((k_p2m<T, 10>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm); break;
+    default: hipLaunchKernelGGL((k_p2m<T, 0>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm);
     }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start, int p,
-                      int kp, double inv_w, double w, const DevTables &tab, const T *l_leaf, double *far) {
+                      int kp, double inv_w, double w, const DevTables &tab, const T *l_leaf, double *far,
+                      const LeafMap &lm) {
     const int C = (p + 1) * (p + 1);
     const size_t smem = sizeof(T) * (3 * size_t(C) + 12 * size_t(tab.nu) + 12);
     const double four_pi = 12.566370614359172953850573533118;
     hipLaunchKernelGGL(k_l2p<T>, dim3(nleaf), dim3(64), smem, s, (const typename PartOf<T>::type *)parts,
                        start, n, p, kp, T(inv_w), 1.0 / (four_pi * w * w), 1.0 / (four_pi * w * w * w), tab,
-                       l_leaf, far);
+                       l_leaf, far, lm);
     return hipGetLastError();
 }
 
@@ -849,33 +886,33 @@ TrShape translate_shape(int kp) {
 template <typename T, int NT, int PF, int NR>
 void launch_translate_k(hipStream_t s, int mode, dim3 grid, size_t smem, int level, int periodic, int C, int kp,
                         int nrb, const T *ops, const int16_t *oct_lists, const int8_t *offsets, const T *src, T *dst,
-                        int accumulate, int nsplit, T *part) {
+                        int accumulate, int nsplit, T *part, const AdaptTr &ad) {
     const int nks = tr_nks(C);
     if (mode == 0)
         hipLaunchKernelGGL((k_translate<T, NR, NT, 0, PF>), grid, dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, part);
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, nsplit, part, ad);
     else if (mode == 1)
         hipLaunchKernelGGL((k_translate<T, NR, NT, 1, PF>), grid, dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, 1, (T *)nullptr);
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, 1, (T *)nullptr, ad);
     else
         hipLaunchKernelGGL((k_translate<T, NR, NT, 2, PF>), grid, dim3(kTrThreads), smem, s, level, periodic,
-                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, 1, (T *)nullptr);
+                           C, kp, nrb, nks, ops, oct_lists, offsets, src, dst, accumulate, 1, (T *)nullptr, ad);
 }
 
 template <typename T, int NT, int PF>
 hipError_t launch_translate_rows(hipStream_t s, int mode, int nrbw, dim3 grid, size_t smem, int level,
                                  int periodic, int C, int kp, int nrb, const T *ops, const int16_t *oct_lists,
                                  const int8_t *offsets, const T *src, T *dst, int accumulate, int nsplit,
-                                 T *part) {
+                                 T *part, const AdaptTr &ad = AdaptTr()) {
     switch (nrbw) {
         case 1: launch_translate_k<T, NT, PF, 1>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                                 offsets, src, dst, accumulate, nsplit, part); break;
+                                                 offsets, src, dst, accumulate, nsplit, part, ad); break;
         case 2: launch_translate_k<T, NT, PF, 2>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                                 offsets, src, dst, accumulate, nsplit, part); break;
+                                                 offsets, src, dst, accumulate, nsplit, part, ad); break;
         case 3: launch_translate_k<T, NT, PF, 3>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                                 offsets, src, dst, accumulate, nsplit, part); break;
+                                                 offsets, src, dst, accumulate, nsplit, part, ad); break;
         case 4: launch_translate_k<T, NT, PF, 4>(s, mode, grid, smem, level, periodic, C, kp, nrb, ops, oct_lists,
-                                                 offsets, src, dst, accumulate, nsplit, part); break;
+                                                 offsets, src, dst, accumulate, nsplit, part, ad); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -992,6 +1029,34 @@ hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, in
 }
 
 template <typename T>
+hipError_t launch_translate_adaptive(hipStream_t s, int mode, int p, int kp, const T *ops, const int16_t *oct_lists,
+                                     const T *src, T *dst, int accumulate, const AdaptTr &ad) {
+    const int C = (p + 1) * (p + 1);
+    const int nrb = tr_nrb(C);
+    const int nrbw = nrb / kTrWaves;
+    const TrShape sh = translate_shape<T>(kp);
+    const int ttn = 16 * sh.nt;
+    AdaptTr a = ad;
+    int grid;
+    if (mode == 2) {
+        grid = (a.ntarget + ttn - 1) / ttn;
+    } else {
+        a.tile_start[0] = 0;
+        for (int o = 0; o < 8; ++o) a.tile_start[o + 1] = a.tile_start[o] + (a.oct_n[o] + ttn - 1) / ttn;
+        grid = a.tile_start[8];
+    }
+    if (grid == 0) return hipSuccess;
+    const size_t smem = sizeof(T) * size_t(ttn) * 3 * tr_row_stride<T>(tr_nks(C)) * (sh.pf > 0 ? 2 : 1);
+    constexpr int NTP = sizeof(T) == 4 ? 2 : 1;
+    const dim3 g3(grid, 1);
+    if (sh.pf > 0)
+        return launch_translate_rows<T, NTP, 24>(s, mode, nrbw, g3, smem, 0, 0, C, kp, nrb, ops, oct_lists, nullptr,
+                                                 src, dst, accumulate, 1, nullptr, a);
+    return launch_translate_rows<T, 1, 0>(s, mode, nrbw, g3, smem, 0, 0, C, kp, nrb, ops, oct_lists, nullptr, src,
+                                          dst, accumulate, 1, nullptr, a);
+}
+
+template <typename T>
 hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, const T *m0, T *l0) {
     const int C = (p + 1) * (p + 1);
     hipLaunchKernelGGL(k_lattice<T>, dim3(1), dim3(256), 0, s, C, kp, tlat, m0, l0);
@@ -1000,13 +1065,16 @@ hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, cons
 
 #define VM_INST(T)                                                                                          \
     template hipError_t launch_p2m<T>(hipStream_t, int, const void *, const int32_t *, int, int, double,    \
-                                      const DevTables &, T *);                                              \
+                                      const DevTables &, T *, const LeafMap &);                             \
     template hipError_t launch_l2p<T>(hipStream_t, int, int, const void *, const int32_t *, int, int,       \
-                                      double, double, const DevTables &, const T *, double *);              \
+                                      double, double, const DevTables &, const T *, double *,               \
+                                      const LeafMap &);                                                     \
     template hipError_t launch_translate<T>(hipStream_t, int, int, int, int, int, const T *,                \
                                             const int16_t *, const int8_t *, const T *, T *, int, T *,      \
                                             size_t, const T *, int);                                        \
-    template hipError_t launch_lattice<T>(hipStream_t, int, int, const double *, const T *, T *);
+    template hipError_t launch_lattice<T>(hipStream_t, int, int, const double *, const T *, T *);          \
+    template hipError_t launch_translate_adaptive<T>(hipStream_t, int, int, int, const T *, const int16_t *,  \
+                                                     const T *, T *, int, const AdaptTr &);
 VM_INST(double)
 VM_INST(float)
 #undef VM_INST

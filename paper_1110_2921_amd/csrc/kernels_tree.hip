@@ -296,6 +296,15 @@ hipError_t launch_radix_pass(hipStream_t s, int n, int shift, int bits, const ui
     return hipGetLastError();
 }
 
+hipError_t launch_exclusive_scan(hipStream_t s, int total, uint32_t *data, uint32_t *tile_sums) {
+    if (total <= 0) return hipSuccess;
+    const int ntiles = (total + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanThreads), 0, s, total, data, tile_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, ntiles, tile_sums);
+    hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kScanThreads), 0, s, total, data, (const uint32_t *)tile_sums);
+    return hipGetLastError();
+}
+
 hipError_t launch_ranges(hipStream_t s, int n, int nleaf, const uint32_t *keys, int32_t *start) {
     hipLaunchKernelGGL(k_ranges, dim3(blocks(n, 256)), dim3(256), 0, s, n, nleaf, keys, start);
     return hipGetLastError();

@@ -397,6 +397,63 @@ AdjTables adj_tables(int p) {
     return t;
 }
 
+M2PTable m2p_table(int p) {
+    M2PTable t;
+    t.p = p;
+    const int kt = std::min(2, p), nrow = ncoef(kt), C = ncoef(p), deg = p + 2;
+    t.nrow = nrow;
+    t.nharm = ncoef(deg);
+    // the map (Mb, H) -> loc is bilinear: the real M2L matrix of a unit
+    // harmonic vector (one packed real of H set to 1) holds the weights of that
+    // harmonic real, for every (row, col)
+    std::vector<std::vector<std::pair<int, int>>> ent(nrow);   // (col, harm) per row
+    std::vector<std::vector<double>> wts(nrow);
+    std::vector<double> m(size_t(nrow) * C);
+    for (int j = 0; j < t.nharm; ++j) {
+        Harm H{deg, std::vector<cplx>((deg + 1) * (deg + 2) / 2, cplx(0.0, 0.0))};
+        const int N = int(std::sqrt(double(j) + 0.5)), r = j - N * N;
+        const int mu = (r + 1) / 2;
+        H.v[N * (N + 1) / 2 + mu] = (r == 0 || (r & 1)) ? cplx(1.0, 0.0) : cplx(0.0, 1.0);
+        real_matrix(kt, p, [&](int k, int l, int n, int mm) -> cplx {
+            const double sgn = ((k + l) & 1) ? -1.0 : 1.0;
+            return sgn * norm_nm(n + k, mm - l) / (norm_nm(k, l) * norm_nm(n, mm)) * H(n + k, mm - l);
+        }, m.data());
+        for (int row = 0; row < nrow; ++row)
+            for (int c = 0; c < C; ++c) {
+                const double v = m[size_t(row) * C + c];
+                if (v != 0.0) {
+                    ent[row].push_back({c, j});
+                    wts[row].push_back(v);
+                }
+            }
+    }
+    t.rowptr.assign(1, 0);
+    for (int row = 0; row < nrow; ++row) {
+        for (size_t e = 0; e < ent[row].size(); ++e) {
+            t.col.push_back(ent[row][e].first);
+            t.harm.push_back(ent[row][e].second);
+            t.w.push_back(wts[row][e]);
+        }
+        t.rowptr.push_back(int32_t(t.col.size()));
+    }
+    // slot 0 of the far-field evaluation tables: u and J at the expansion centre
+    t.G.assign(size_t(12) * 3 * nrow, 0.0);
+    const L2PTable l = l2p_table(p);
+    auto take = [&](int o, int r) {
+        for (int e = 0; e < l.width; ++e) {
+            const double wv = l.w[size_t(r) * l.width + e];
+            if (wv == 0.0) continue;
+            const int j = l.idx[size_t(r) * l.width + e], comp = j / C, coef = j % C;
+            if (coef >= nrow) throw std::logic_error("M2P: evaluation row beyond degree 2");
+            t.G[size_t(o) * 3 * nrow + comp * nrow + coef] += wv;
+        }
+    };
+    for (int b = 0; b < 3; ++b) take(b, b * l.nu);
+    if (l.ng > 0)
+        for (int k = 0; k < 9; ++k) take(3 + k, 3 * l.nu + k * l.ng);
+    return t;
+}
+
 RecTable rec_table(int p) {
     RecTable t;
     const int n_ent = (p + 1) * (p + 2) / 2;

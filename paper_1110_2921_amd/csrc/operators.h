@@ -70,6 +70,23 @@ struct AdjTables {
 };
 AdjTables adj_tables(int p);
 
+// Cell-particle evaluation (M2P): the first and second derivatives at a point
+// x of the multipole potential of a cell of width w, through the local
+// expansion about x of degree <= 2 that the M2L theorem gives (target width
+// w), from the balanced irregular harmonics H of X = (x - centre) / w, degree
+// <= p + 2, packed [Ib_n^0, Re Ib_n^m, Im Ib_n^m]:
+//   loc[k][r] = sum over the entries e of row r: w[e] Mb[k][col[e]] H[harm[e]],
+// rows r < nrow = (min(2, p) + 1)^2 the packed local coefficients, then
+//   out[o] = sum_q G[o][q] loc[q],  q = nrow k + r,
+// u_b = out[b] / (4 pi w^2), J[a][b] = out[3 + 3a + b] / (4 pi w^3).
+struct M2PTable {
+    int p = 0, nrow = 0, nharm = 0;
+    std::vector<int32_t> rowptr, col, harm;   // rowptr: nrow + 1 entry offsets
+    std::vector<double> w;
+    std::vector<double> G;                    // 12 x (3 nrow)
+};
+M2PTable m2p_table(int p);
+
 // Recurrence constants for the balanced regular harmonics, index n(n+1)/2 + m:
 //   Rb_m^m   = -(X + iY) diag[m] Rb_{m-1}^{m-1},  diag[m] = sqrt((2m-1)/(2m))
 //   Rb_n^m   = c1 Z Rb_{n-1}^m - c2 r^2 Rb_{n-2}^m  (n > m)

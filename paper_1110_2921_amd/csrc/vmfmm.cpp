@@ -149,6 +149,24 @@ struct vm_ctx {
     std::vector<hipEvent_t> events;              // pool, two per timed launch
     std::vector<std::pair<int, int>> timed;      // (phase, first event index)
 
+    // adaptive tree of vm_fmm_eval_adaptive: cells, leaves, lists and
+    // expansions of the last call (kept for the debug views), construction
+    // scratch and the tables of the cell-particle kernels
+    struct Adaptive {
+        DevBuf key, level, start, count, parent, child;        // cells
+        DevBuf sstart, scount, rank, tsum, ints;                // construction scratch, device counters
+        DevBuf leaf_at, lcell, lstart, llev, iota;              // leaves in particle order
+        DevBuf part, pcode, npart, vtab, cnt, off, src, code;   // traversal
+        DevBuf tcell, M, L, parts;
+        DevBuf rec_c1, rec_c2, rec_dg;                          // recurrence of degree p + 2
+        DevBuf m2p_rowptr, m2p_col, m2p_harm, m2p_w, m2p_G, vslot;
+        int rec_p = -1, m2p_p = -1, m2p_nrow = 0, m2p_nharm = 0;
+        size_t cell_cap = 0;
+        bool valid = false;
+        int n = 0, ncell = 0, nleaf = 0, max_level = 0, ncrit = 0, periodic = 0;
+        std::vector<int> level_off;                             // first cell of each level, then the end
+    } ad;
+
     // operator caches
     std::map<int, std::unique_ptr<OpSet>> ops;
     std::map<std::pair<int, int>, std::unique_ptr<DevBuf>> lattice;
@@ -190,21 +208,20 @@ struct Timed {
         ctx->timed.push_back({phase, ev});
         (void)hipEventRecord(ctx->events[ev], ctx->stream);
     }
-    ~Timed() {
+    void stop() {
         if (ev >= 0) (void)hipEventRecord(ctx->events[ev + 1], ctx->stream);
+        ev = -1;
     }
+    ~Timed() { stop(); }
 };
 
-vm_status ensure_tables(vm_ctx *ctx) {
-    if (ctx->tables_ready) return VM_OK;
+// Device order of each octant's 189 offsets: grouped by the parity of d
+// (the parity class of the source cells), (dz, dy, dx) order inside a
+// group.  Consecutive offsets then read source cells one parent apart,
+// which the workgroups of an XCD share in L2; the plain (dz, dy, dx) order
+// alternates between disjoint parity classes.
+std::vector<int16_t> device_octant_lists() {
     const OffsetTable &t = offset_table();
-    std::vector<int8_t> offs(316 * 3);
-    std::memcpy(offs.data(), t.d, sizeof(t.d));
-    // Device order of each octant's 189 offsets: grouped by the parity of d
-    // (the parity class of the source cells), (dz, dy, dx) order inside a
-    // group.  Consecutive offsets then read source cells one parent apart,
-    // which the workgroups of an XCD share in L2; the plain (dz, dy, dx) order
-    // alternates between disjoint parity classes.
     std::vector<int16_t> lists(8 * 189);
     for (int o = 0; o < 8; ++o) {
         int16_t *l = lists.data() + o * 189;
@@ -212,6 +229,15 @@ vm_status ensure_tables(vm_ctx *ctx) {
         auto cls = [&](int16_t i) { return (t.d[i][0] & 1) | ((t.d[i][1] & 1) << 1) | ((t.d[i][2] & 1) << 2); };
         std::stable_sort(l, l + 189, [&](int16_t a, int16_t b) { return cls(a) < cls(b); });
     }
+    return lists;
+}
+
+vm_status ensure_tables(vm_ctx *ctx) {
+    if (ctx->tables_ready) return VM_OK;
+    const OffsetTable &t = offset_table();
+    std::vector<int8_t> offs(316 * 3);
+    std::memcpy(offs.data(), t.d, sizeof(t.d));
+    const std::vector<int16_t> lists = device_octant_lists();
     VM_HIP(upload(ctx->offsets, offs), "upload offsets");
     VM_HIP(upload(ctx->octlists, lists), "upload octant lists");
     ctx->tables_ready = true;
@@ -457,6 +483,39 @@ vm_status check_flag(vm_ctx *ctx, const vm_opts *opts) {
     return VM_OK;
 }
 
+// Morton keys of the particles at `level` and their stable LSD radix sort
+// (Sec. 3.1 tree): on return `kin` holds the sorted keys and `vin` the caller
+// index of each sorted particle (both in b's key / value buffers, which must
+// hold ni entries, with ctx->hist sized for ni).  clear_flag must have run.
+vm_status sort_particles(vm_ctx *ctx, const TreeBufs &b, int ni, const double *x, int level, const vm_opts *opts,
+                         TreeGeom &g, uint32_t *&kin, int32_t *&vin) {
+    hipStream_t s = ctx->stream;
+    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
+    g.box_len = opts->box_len;
+    g.inv_len = 1.0 / opts->box_len;
+    g.inv_w = std::ldexp(g.inv_len, level);
+    g.w = std::ldexp(opts->box_len, -level);
+    g.level = level;
+    g.periodic = opts->periodic > 0;
+    kin = b.keys_a->as<uint32_t>();
+    vin = b.vals_a->as<int32_t>();
+    uint32_t *kout = b.keys_b->as<uint32_t>();
+    int32_t *vout = b.vals_b->as<int32_t>();
+    VM_HIP(launch_keys(s, ni, x, g, opts->check_domain, kin, vin, ctx->flag.as<int>()), "keys");
+    const int total_bits = 3 * level;
+    if (total_bits > 0) {
+        const int npass = (total_bits + 7) / 8;
+        const int bits = (total_bits + npass - 1) / npass;
+        for (int shift = 0; shift < total_bits; shift += bits) {
+            const int nb = std::min(bits, total_bits - shift);
+            VM_HIP(launch_radix_pass(s, ni, shift, nb, kin, vin, kout, vout, ctx->hist.as<uint32_t>()), "radix sort");
+            std::swap(kin, kout);
+            std::swap(vin, vout);
+        }
+    }
+    return VM_OK;
+}
+
 // Tree of the particles (Sec. 3.1): Morton keys, stable LSD radix sort, leaf
 // ranges and the sorted particle records (positions relative to their leaf
 // centres, `alpha` in the strength fields), in the precision of opts, in the
@@ -481,30 +540,11 @@ vm_status build_tree(vm_ctx *ctx, const TreeBufs &b, int ni, const double *x, co
     if (mixed) VM_HIP(b.p32->reserve(sizeof(Part32) * n), "alloc particles");
     else VM_HIP(b.p64->reserve(sizeof(Part64) * n), "alloc particles");
 
-    for (int d = 0; d < 3; ++d) g.lo[d] = opts->box_lo[d];
-    g.box_len = opts->box_len;
-    g.inv_len = 1.0 / opts->box_len;
-    g.inv_w = std::ldexp(g.inv_len, level);
-    g.w = std::ldexp(opts->box_len, -level);
-    g.level = level;
-    g.periodic = opts->periodic > 0;
-
     int32_t *start = b.start->as<int32_t>();
-    uint32_t *kin = b.keys_a->as<uint32_t>(), *kout = b.keys_b->as<uint32_t>();
-    int32_t *vin = b.vals_a->as<int32_t>(), *vout = b.vals_b->as<int32_t>();
+    uint32_t *kin = nullptr;
+    int32_t *vin = nullptr;
     Timed tm(ctx, VM_PH_TREE);
-    VM_HIP(launch_keys(s, ni, x, g, opts->check_domain, kin, vin, ctx->flag.as<int>()), "keys");
-    const int total_bits = 3 * level;
-    if (total_bits > 0) {
-        const int npass = (total_bits + 7) / 8;
-        const int bits = (total_bits + npass - 1) / npass;
-        for (int shift = 0; shift < total_bits; shift += bits) {
-            const int nb = std::min(bits, total_bits - shift);
-            VM_HIP(launch_radix_pass(s, ni, shift, nb, kin, vin, kout, vout, ctx->hist.as<uint32_t>()), "radix sort");
-            std::swap(kin, kout);
-            std::swap(vin, vout);
-        }
-    }
+    if (vm_status st = sort_particles(ctx, b, ni, x, level, opts, g, kin, vin); st != VM_OK) return st;
     VM_HIP(launch_ranges(s, ni, int(nleaf), kin, start), "leaf ranges");
     VM_HIP(launch_permute(s, ni, x, alpha, vin, kin, g, mixed ? nullptr : b.p64->as<Part64>(),
                           mixed ? b.p32->as<Part32>() : nullptr), "permute");
@@ -835,6 +875,347 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     return check_flag(ctx, opts);
 }
 
+// ------------------------------------------------------------- adaptive tree ----
+
+// Grows b to at least `want` bytes keeping its first `keep` bytes.
+vm_status grow_keep(vm_ctx *ctx, DevBuf &b, size_t want, size_t keep) {
+    if (want <= b.bytes && b.ptr) return VM_OK;
+    void *np = nullptr;
+    VM_HIP(hipMalloc(&np, want), "alloc adaptive tree");
+    if (keep && b.ptr)
+        VM_HIP(hipMemcpyAsync(np, b.ptr, std::min(keep, b.bytes), hipMemcpyDeviceToDevice, ctx->stream),
+               "copy adaptive tree");
+    VM_HIP(hipStreamSynchronize(ctx->stream), "synchronize");
+    b.release();
+    b.ptr = np;
+    b.bytes = want;
+    return VM_OK;
+}
+
+vm_status read_ints(vm_ctx *ctx, const void *dev, int *host, int count) {
+    VM_HIP(hipMemcpyAsync(host, dev, sizeof(int) * size_t(count), hipMemcpyDeviceToHost, ctx->stream), "read counts");
+    VM_HIP(hipStreamSynchronize(ctx->stream), "synchronize");
+    return VM_OK;
+}
+
+// Cell arrays of capacity `cap` (the first `keep` cells kept).
+vm_status ad_cells(vm_ctx *ctx, size_t cap, size_t keep) {
+    auto &A = ctx->ad;
+    if (cap <= A.cell_cap) return VM_OK;
+    DevBuf *b4[] = {&A.key, &A.level, &A.start, &A.count, &A.parent};
+    for (DevBuf *b : b4)
+        if (vm_status st = grow_keep(ctx, *b, cap * 4, keep * 4); st != VM_OK) return st;
+    if (vm_status st = grow_keep(ctx, A.child, cap * 32, keep * 32); st != VM_OK) return st;
+    A.cell_cap = cap;
+    return VM_OK;
+}
+
+AdTreeView ad_view(vm_ctx *ctx, const vm_opts *opts, int ncrit, int max_level) {
+    auto &A = ctx->ad;
+    AdTreeView t;
+    t.key = A.key.as<uint32_t>();
+    t.level = A.level.as<int32_t>();
+    t.start = A.start.as<int32_t>();
+    t.count = A.count.as<int32_t>();
+    t.parent = A.parent.as<int32_t>();
+    t.child = A.child.as<int32_t>();
+    t.ncrit = ncrit;
+    t.max_level = max_level;
+    t.periodic = opts->periodic > 0;
+    for (int d = 0; d < 3; ++d) t.lo[d] = opts->box_lo[d];
+    t.box_len = opts->box_len;
+    t.inv_len = 1.0 / opts->box_len;
+    return t;
+}
+
+// Tables of the cell-particle kernels for degree p (recurrence of degree
+// p + 2, the M2P table) and the slot of each M2L offset in its octant's list.
+vm_status ensure_ad_tables(vm_ctx *ctx, int p) {
+    auto &A = ctx->ad;
+    if (A.rec_p != p) {
+        const RecTable r = rec_table(p + 2);
+        VM_HIP(upload(A.rec_c1, r.c1), "upload recurrence");
+        VM_HIP(upload(A.rec_c2, r.c2), "upload recurrence");
+        VM_HIP(upload(A.rec_dg, r.diag), "upload recurrence");
+        A.rec_p = p;
+    }
+    if (A.m2p_p != p) {
+        const M2PTable m = m2p_table(p);
+        VM_HIP(upload(A.m2p_rowptr, m.rowptr), "upload M2P table");
+        VM_HIP(upload(A.m2p_col, m.col), "upload M2P table");
+        VM_HIP(upload(A.m2p_harm, m.harm), "upload M2P table");
+        VM_HIP(upload(A.m2p_w, m.w), "upload M2P table");
+        VM_HIP(upload(A.m2p_G, m.G), "upload M2P table");
+        A.m2p_nrow = m.nrow;
+        A.m2p_nharm = m.nharm;
+        A.m2p_p = p;
+    }
+    if (A.vslot.bytes == 0) {
+        const OffsetTable &t = offset_table();
+        const std::vector<int16_t> lists = device_octant_lists();
+        std::vector<int16_t> vs(8 * 343, int16_t(-1));
+        for (int o = 0; o < 8; ++o)
+            for (int i = 0; i < 189; ++i) {
+                const int8_t *d = t.d[lists[o * 189 + i]];
+                vs[o * 343 + (d[0] + 3) + 7 * (d[1] + 3) + 49 * (d[2] + 3)] = int16_t(i);
+            }
+        VM_HIP(upload(A.vslot, vs), "upload M2L slots");
+    }
+    return VM_OK;
+}
+
+// Adaptive hybrid treecode-FMM (Sec. 3.2), FP64: tree from the particles
+// sorted at max_level, dual traversal into P2P / M2L / M2P / P2L lists, then
+// P2M, M2M, lattice, L2L + M2L + P2L per level, L2P + M2P, P2P.
+vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double *alpha, double sigma, int p,
+                        int ncrit, int max_level, const vm_opts *opts, double *u, double *dalpha_dt, double *grad) {
+    hipStream_t s = ctx->stream;
+    auto &A = ctx->ad;
+    const int n = int(n64);
+    const int K = opts->periodic;
+    if (vm_status st = ensure_tables(ctx); st != VM_OK) return st;
+    OpSet *ops = nullptr;
+    if (vm_status st = ensure_ops(ctx, p, &ops); st != VM_OK) return st;
+    const double *tlat = nullptr;
+    if (K >= 2)
+        if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
+    if (vm_status st = ensure_ad_tables(ctx, p); st != VM_OK) return st;
+    const int C = ncoef(p), kp = coef_stride(C);
+    A.valid = false;
+    ++ctx->tree_gen;
+    ctx->last_eval.valid = false;
+    ctx->last_level = -1;   // the uniform debug views no longer describe the buffers
+    ctx->last_p = -1;
+
+    // --- particles sorted at the finest level ---------------------------------
+    const TreeBufs b = source_bufs(ctx);
+    const int nblk = (n + kRadixTile - 1) / kRadixTile;
+    VM_HIP(b.keys_a->reserve(sizeof(uint32_t) * size_t(n)), "alloc keys");
+    VM_HIP(b.keys_b->reserve(sizeof(uint32_t) * size_t(n)), "alloc keys");
+    VM_HIP(b.vals_a->reserve(sizeof(int32_t) * size_t(n)), "alloc perm");
+    VM_HIP(b.vals_b->reserve(sizeof(int32_t) * size_t(n)), "alloc perm");
+    VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * (size_t(nblk) * 256 + size_t(nblk) * 256 / 4096 + 256)),
+           "alloc histogram");
+    VM_HIP(A.ints.reserve(sizeof(int) * 32), "alloc counters");
+    int *dints = A.ints.as<int>();
+    if (vm_status st = clear_flag(ctx, opts); st != VM_OK) return st;
+    TreeGeom g;
+    uint32_t *kin = nullptr;
+    int32_t *vin = nullptr;
+    {
+        Timed tm(ctx, VM_PH_TREE);
+        if (vm_status st = sort_particles(ctx, b, n, x, max_level, opts, g, kin, vin); st != VM_OK) return st;
+    }
+
+    // --- cells, level by level (the host learns each level's size) -------------
+    Timed tm_lists(ctx, VM_PH_LISTS);
+    if (vm_status st = ad_cells(ctx, std::max<size_t>(1024, size_t(n) / size_t(std::max(ncrit, 1)) * 2 + 64), 0);
+        st != VM_OK)
+        return st;
+    AdTreeView t = ad_view(ctx, opts, ncrit, max_level);
+    VM_HIP(launch_ad_root(s, t, n), "adaptive root");
+    std::vector<int> lo{0, 1};
+    int off = 0, ncl = 1;
+    for (int l = 0; l < max_level && ncl > 0; ++l) {
+        const size_t need = size_t(off) + ncl + 8 * size_t(ncl);
+        if (need > A.cell_cap) {
+            if (vm_status st = ad_cells(ctx, std::max(need, 2 * A.cell_cap), size_t(off) + ncl); st != VM_OK) return st;
+            t = ad_view(ctx, opts, ncrit, max_level);
+        }
+        const int slots = 8 * ncl;
+        VM_HIP(A.sstart.reserve(sizeof(int32_t) * slots), "alloc slots");
+        VM_HIP(A.scount.reserve(sizeof(int32_t) * slots), "alloc slots");
+        VM_HIP(A.rank.reserve(sizeof(uint32_t) * std::max(slots, n)), "alloc ranks");
+        VM_HIP(A.tsum.reserve(sizeof(uint32_t) * scan_tile_sums(std::max(slots, 3 * n + 3))), "alloc scan sums");
+        VM_HIP(launch_ad_level(s, t, off, ncl, kin, A.sstart.as<int32_t>(), A.scount.as<int32_t>(),
+                               A.rank.as<uint32_t>(), A.tsum.as<uint32_t>(), dints), "adaptive level");
+        int nn = 0;
+        if (vm_status st = read_ints(ctx, dints, &nn, 1); st != VM_OK) return st;
+        off += ncl;
+        ncl = nn;
+        if (ncl > 0) lo.push_back(off + ncl);
+    }
+    if (ncl > 0) VM_HIP(launch_ad_no_children(s, t, off, ncl), "adaptive last level");
+    const int ncell = lo.back();
+    const int nlev = int(lo.size()) - 1;
+
+    // --- leaves in particle order and the sorted records -----------------------
+    VM_HIP(A.leaf_at.reserve(sizeof(int32_t) * size_t(n)), "alloc leaves");
+    VM_HIP(A.rank.reserve(sizeof(uint32_t) * size_t(std::max(n, 3 * ncell))), "alloc ranks");
+    VM_HIP(A.tsum.reserve(sizeof(uint32_t) * scan_tile_sums(std::max(n, 3 * ncell))), "alloc scan sums");
+    VM_HIP(A.lcell.reserve(sizeof(int32_t) * size_t(ncell)), "alloc leaves");
+    VM_HIP(A.lstart.reserve(sizeof(int32_t) * (size_t(ncell) + 1)), "alloc leaves");
+    VM_HIP(A.llev.reserve(sizeof(int32_t) * size_t(ncell)), "alloc leaves");
+    VM_HIP(launch_ad_leaves(s, t, ncell, n, A.leaf_at.as<int32_t>(), A.rank.as<uint32_t>(), A.tsum.as<uint32_t>(),
+                            A.lcell.as<int32_t>(), A.lstart.as<int32_t>(), A.llev.as<int32_t>(), dints + 1),
+           "adaptive leaves");
+    int nleaf = 0;
+    if (vm_status st = read_ints(ctx, dints + 1, &nleaf, 1); st != VM_OK) return st;
+    VM_HIP(A.parts.reserve(sizeof(Part64) * size_t(n)), "alloc particles");
+    Part64 *parts = A.parts.as<Part64>();
+    VM_HIP(launch_ad_permute(s, t, n, x, alpha, vin, nleaf, A.lcell.as<int32_t>(), parts), "adaptive permute");
+
+    // --- dual traversal: counting pass (partners), offsets, filling pass --------
+    VM_HIP(A.part.reserve(sizeof(int32_t) * 27 * size_t(ncell)), "alloc partners");
+    VM_HIP(A.pcode.reserve(27 * size_t(ncell)), "alloc partners");
+    VM_HIP(A.npart.reserve(sizeof(int32_t) * size_t(ncell)), "alloc partners");
+    VM_HIP(A.cnt.reserve(sizeof(uint32_t) * 3 * size_t(ncell)), "alloc list counts");
+    VM_HIP(A.off.reserve(sizeof(uint32_t) * 3 * size_t(ncell)), "alloc list offsets");
+    VM_HIP(A.vtab.reserve(sizeof(int32_t) * 189 * size_t(ncell)), "alloc M2L table");
+    VM_HIP(hipMemsetAsync(dints + 2, 0, sizeof(int), s), "clear error flag");
+    AdLists ls{};
+    ls.part = A.part.as<int32_t>();
+    ls.pcode = A.pcode.as<int8_t>();
+    ls.npart = A.npart.as<int32_t>();
+    ls.vtab = A.vtab.as<int32_t>();
+    ls.vslot = A.vslot.as<int16_t>();
+    ls.cnt = A.cnt.as<uint32_t>();
+    ls.off = A.off.as<uint32_t>();
+    ls.err = dints + 2;
+    for (int l = 0; l < nlev; ++l)
+        VM_HIP(launch_ad_traverse(s, t, ls, l, lo[l], lo[l + 1] - lo[l], 0, 0, ncell), "adaptive traversal");
+    VM_HIP(hipMemcpyAsync(A.off.ptr, A.cnt.ptr, sizeof(uint32_t) * 3 * size_t(ncell), hipMemcpyDeviceToDevice, s),
+           "copy list counts");
+    VM_HIP(launch_exclusive_scan(s, 3 * ncell, A.off.as<uint32_t>(), A.tsum.as<uint32_t>()), "list offsets");
+    uint32_t tail[2] = {0, 0};
+    VM_HIP(hipMemcpyAsync(&tail[0], A.off.as<uint32_t>() + 3 * size_t(ncell) - 1, 4, hipMemcpyDeviceToHost, s),
+           "read list size");
+    VM_HIP(hipMemcpyAsync(&tail[1], A.cnt.as<uint32_t>() + 3 * size_t(ncell) - 1, 4, hipMemcpyDeviceToHost, s),
+           "read list size");
+    VM_HIP(hipStreamSynchronize(s), "synchronize");
+    const size_t nentry = size_t(tail[0]) + tail[1];
+    VM_HIP(A.src.reserve(sizeof(int32_t) * std::max<size_t>(nentry, 1)), "alloc lists");
+    VM_HIP(A.code.reserve(std::max<size_t>(nentry, 1)), "alloc lists");
+    for (int k = 0; k < 3; ++k) {
+        ls.src[k] = A.src.as<int32_t>();
+        ls.code[k] = A.code.as<int8_t>();
+    }
+    VM_HIP(hipMemsetAsync(A.vtab.ptr, 0xff, sizeof(int32_t) * 189 * size_t(ncell), s), "clear M2L table");
+    for (int l = 0; l < nlev; ++l)
+        VM_HIP(launch_ad_traverse(s, t, ls, l, lo[l], lo[l + 1] - lo[l], 1, 0, ncell), "adaptive traversal");
+    int err = 0;
+    if (vm_status st = read_ints(ctx, dints + 2, &err, 1); st != VM_OK) return st;
+    if (err) return fail(ctx, VM_EDEVICE, "adaptive traversal: partner or stack overflow, or an M2L offset outside its list");
+    tm_lists.stop();
+
+    // --- expansions -------------------------------------------------------------
+    const size_t cbytes = (size_t(ncell) * 3 * kp + tr_slack_elems(kp)) * sizeof(double);
+    VM_HIP(A.M.reserve(cbytes), "alloc multipoles");
+    VM_HIP(A.L.reserve(cbytes), "alloc locals");
+    VM_HIP(hipMemsetAsync(A.M.ptr, 0, cbytes, s), "clear multipoles");
+    VM_HIP(hipMemsetAsync(A.L.ptr, 0, cbytes, s), "clear locals");
+    VM_HIP(ctx->far.reserve(sizeof(double) * 12 * size_t(n)), "alloc far field");
+    VM_HIP(A.iota.reserve(sizeof(int32_t) * size_t(ncell)), "alloc cell list");
+    VM_HIP(A.tcell.reserve(sizeof(int32_t) * 8 * size_t(ncell)), "alloc octant groups");
+    VM_HIP(launch_iota(s, ncell, A.iota.as<int32_t>(), A.rank.as<uint32_t>()), "cell list");
+    double *M = A.M.as<double>(), *L = A.L.as<double>();
+    DevTables tab;
+    tab.c1_64 = ops->c1_64.as<double>(); tab.c2_64 = ops->c2_64.as<double>(); tab.diag_64 = ops->dg_64.as<double>();
+    tab.c1_32 = ops->c1_32.as<float>(); tab.c2_32 = ops->c2_32.as<float>(); tab.diag_32 = ops->dg_32.as<float>();
+    tab.l2p_idx = ops->l2p_idx.as<int32_t>();
+    tab.l2p_w64 = ops->l2p_w64.as<double>();
+    tab.l2p_w32 = ops->l2p_w32.as<float>();
+    tab.l2p_width = ops->width;
+    tab.nu = ops->nu;
+    tab.ng = ops->ng;
+    DevTables tabI = tab;   // recurrence of degree p + 2 for the irregular harmonics
+    tabI.c1_64 = A.rec_c1.as<double>();
+    tabI.c2_64 = A.rec_c2.as<double>();
+    tabI.diag_64 = A.rec_dg.as<double>();
+    LeafMap lm;
+    lm.cell = A.lcell.as<int32_t>();
+    lm.lev = A.llev.as<int32_t>();
+    lm.box_len = opts->box_len;
+    lm.inv_len = 1.0 / opts->box_len;
+    const int32_t *lcell = A.lcell.as<int32_t>(), *lstart = A.lstart.as<int32_t>();
+    const int16_t *lists = ctx->octlists.as<int16_t>();
+    {
+        Timed tm(ctx, VM_PH_P2M);
+        VM_HIP(launch_p2m<double>(s, nleaf, parts, lstart, p, kp, 0.0, tab, M, lm), "adaptive P2M");
+    }
+    for (int l = nlev - 2; l >= 0; --l) {
+        AdaptTr ad;
+        ad.tcell = A.iota.as<int32_t>() + lo[l];
+        ad.ntarget = lo[l + 1] - lo[l];
+        ad.child = t.child;
+        Timed tm(ctx, VM_PH_M2M);
+        VM_HIP(launch_translate_adaptive<double>(s, 2, p, kp, ops->m2m64.as<double>(), lists, M, M, 0, ad),
+               "adaptive M2M");
+    }
+    if (K >= 2) {
+        Timed tm(ctx, VM_PH_LATTICE);
+        VM_HIP(launch_lattice<double>(s, p, kp, tlat, M, L), "lattice");
+    }
+    for (int l = 1; l < nlev; ++l) {
+        const int nl = lo[l + 1] - lo[l];
+        VM_HIP(launch_ad_octants(s, t, lo[l], nl, A.tcell.as<int32_t>(), A.rank.as<uint32_t>(), A.tsum.as<uint32_t>(),
+                                 dints + 8), "octant groups");
+        int oc[8];
+        if (vm_status st = read_ints(ctx, dints + 8, oc, 8); st != VM_OK) return st;
+        AdaptTr ad;
+        ad.tcell = A.tcell.as<int32_t>();
+        for (int o = 0; o < 8; ++o) {
+            ad.oct_base[o] = o * nl;
+            ad.oct_n[o] = oc[o];
+        }
+        ad.parent = t.parent;
+        ad.stab = A.vtab.as<int32_t>();
+        ad.cell0 = 0;
+        {
+            Timed tm(ctx, VM_PH_L2L);
+            VM_HIP(launch_translate_adaptive<double>(s, 1, p, kp, ops->l2l64.as<double>(), lists, L, L, 1, ad),
+                   "adaptive L2L");
+        }
+        {
+            Timed tm(ctx, VM_PH_M2L);
+            VM_HIP(launch_translate_adaptive<double>(s, 0, p, kp, ops->m2l64.as<double>(), lists, M, L, 1, ad),
+                   "adaptive M2L");
+        }
+        Timed tm(ctx, VM_PH_P2L);
+        VM_HIP(launch_ad_p2l(s, t, ls, lo[l], nl, ncell, p, kp, tabI, parts, L), "adaptive P2L");
+    }
+    {
+        Timed tm(ctx, VM_PH_L2P);
+        VM_HIP(launch_l2p<double>(s, nleaf, n, parts, lstart, p, kp, 0.0, 1.0, tab, L, ctx->far.as<double>(), lm),
+               "adaptive L2P");
+    }
+    {
+        Timed tm(ctx, VM_PH_M2P);
+        VM_HIP(launch_ad_m2p(s, t, ls, nleaf, lcell, lstart, n, ncell, p, kp, A.m2p_nrow, A.m2p_nharm, tabI,
+                             A.m2p_rowptr.as<int32_t>(), A.m2p_col.as<int32_t>(), A.m2p_harm.as<int32_t>(),
+                             A.m2p_w.as<double>(), A.m2p_G.as<double>(), parts, M, ctx->far.as<double>()),
+               "adaptive M2P");
+    }
+    P2PArgs a{};
+    a.n = n;
+    a.scheme = opts->scheme;
+    a.have_far = 1;
+    a.sigma = sigma;
+    a.perm = vin;
+    a.alpha = alpha;
+    a.far = ctx->far.as<double>();
+    a.u = u;
+    a.dalpha = dalpha_dt;
+    a.grad = grad;
+    {
+        Timed tm(ctx, VM_PH_P2P);
+        VM_HIP(launch_p2p64_list(s, a, nleaf, lcell, lstart, t, A.off.as<uint32_t>(), A.cnt.as<uint32_t>(),
+                                 A.src.as<int32_t>(), A.code.as<int8_t>(), parts),
+               "adaptive P2P");
+    }
+    A.valid = true;
+    A.n = n;
+    A.ncell = ncell;
+    A.nleaf = nleaf;
+    A.max_level = max_level;
+    A.ncrit = ncrit;
+    A.periodic = K > 0;
+    A.level_off = lo;
+    ctx->last_keys = kin;
+    ctx->last_perm = vin;
+    return check_flag(ctx, opts);
+}
+
 // Solution of the (j+1) x (j+1) upper triangular system R y = g of one
 // component's rotated Hessenberg matrix (column-major, leading dimension ld).
 void back_substitute(const std::vector<double> &R, int ld, const std::vector<double> &g, int cols, double *y) {
@@ -906,6 +1287,23 @@ vm_status vm_fmm_eval_at(vm_ctx *ctx, int64_t n, const double *x, const double *
     if (p < 1 || p > VM_MAX_P) return fail(ctx, VM_EINVAL, "p out of range [1, VM_MAX_P = 18]");
     VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
     return fmm_impl(ctx, n, x, alpha, m, y, sigma, p, level, opts, u, nullptr, grad);
+}
+
+vm_status vm_fmm_eval_adaptive(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                               int ncrit, int max_level, const vm_opts *opts, double *u, double *dalpha_dt,
+                               double *grad) {
+    if (!ctx) return VM_EINVAL;
+    if (vm_status st = check_common(ctx, n, sigma, max_level, opts); st != VM_OK) return st;
+    if (p < 1 || p > VM_ADAPTIVE_MAX_P) return fail(ctx, VM_EINVAL, "p out of range [1, 14] for the adaptive tree");
+    if (ncrit < 1) return fail(ctx, VM_EINVAL, "ncrit must be positive");
+    if (opts->precision != VM_FP64) return fail(ctx, VM_EINVAL, "the adaptive tree computes in FP64 only");
+    if (opts->truncation != VM_SQUARE) return fail(ctx, VM_EINVAL, "the adaptive tree takes the square truncation only");
+    if (opts->scheme != VM_CLASSIC && opts->scheme != VM_TRANSPOSE) return fail(ctx, VM_EINVAL, "unknown scheme");
+    if (!x || !alpha || !u) return fail(ctx, VM_EINVAL, "x, alpha and u must be non-NULL");
+    if (misaligned(x) || misaligned(alpha) || misaligned(u) || misaligned(dalpha_dt) || misaligned(grad))
+        return fail(ctx, VM_EINVAL, "arrays must be 8-byte aligned");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    return adaptive_impl(ctx, n, x, alpha, sigma, p, ncrit, max_level, opts, u, dalpha_dt, grad);
 }
 
 }  // extern "C"
@@ -1522,6 +1920,149 @@ vm_status vm_tune_level(vm_ctx *ctx, int64_t n, const double *x, const double *a
     (void)hipEventDestroy(e1);
     if (st != VM_OK) return st;
     *level = arg;
+    return VM_OK;
+}
+
+vm_status vm_tune_ncrit(vm_ctx *ctx, int64_t n, const double *x, const double *alpha, double sigma, int p,
+                        int max_level, const vm_opts *opts, int reps, int *ncrit, double *ms) {
+    if (!ctx) return VM_EINVAL;
+    if (!ncrit) return fail(ctx, VM_EINVAL, "ncrit must be non-NULL");
+    if (vm_status st = check_common(ctx, n, sigma, max_level, opts); st != VM_OK) return st;
+    if (reps < 1 || reps > 100) return fail(ctx, VM_EINVAL, "reps out of range [1, 100]");
+    if (ms)
+        for (int i = 0; i < VM_NCRIT_CANDIDATES; ++i) ms[i] = -1.0;
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t bytes = sizeof(double) * 3 * size_t(n);
+    VM_HIP(ctx->rk_u.reserve(bytes), "alloc tuning");
+    VM_HIP(ctx->rk_s.reserve(bytes), "alloc tuning");
+    hipEvent_t e0, e1;
+    VM_HIP(hipEventCreate(&e0), "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, VM_EDEVICE, "event");
+    }
+    // leaf sizes 8, 16, ..., 1024 in increasing order while the time falls: a
+    // larger bound trades expansion work (fewer, coarser cells) for near-field
+    // pairs, so the time has one valley
+    double best = -1.0, prev = -1.0;
+    int arg = 8, rises = 0;
+    vm_status st = VM_OK;
+    for (int i = 0; i < VM_NCRIT_CANDIDATES; ++i) {
+        const int nc = 8 << i;
+        auto run = [&]() {
+            return vm_fmm_eval_adaptive(ctx, n, x, alpha, sigma, p, nc, max_level, opts, ctx->rk_u.as<double>(),
+                                        ctx->rk_s.as<double>(), nullptr);
+        };
+        st = run();   // untimed: workspace
+        if (st != VM_OK) break;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = fail(ctx, VM_EDEVICE, "event"); break; }
+        for (int r = 0; r < reps && st == VM_OK; ++r) st = run();
+        if (st != VM_OK) break;
+        float tms = 0.0f;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&tms, e0, e1) != hipSuccess) {
+            st = fail(ctx, VM_EDEVICE, "event timing");
+            break;
+        }
+        const double avg = double(tms) / reps;
+        if (ms) ms[i] = avg;
+        if (best < 0.0 || avg < best) {
+            best = avg;
+            arg = nc;
+        }
+        rises = (prev >= 0.0 && avg > prev) ? rises + 1 : 0;
+        if (rises == 2) break;
+        prev = avg;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != VM_OK) return st;
+    *ncrit = arg;
+    return VM_OK;
+}
+
+vm_status vm_debug_adaptive(vm_ctx *ctx, int what, int32_t *out, int64_t *rows) {
+    if (!ctx || !rows) return VM_EINVAL;
+    auto &A = ctx->ad;
+    if (!A.valid) return fail(ctx, VM_EINVAL, "no adaptive evaluation yet");
+    if (what < 0 || what > 5) return fail(ctx, VM_EINVAL, "what out of range [0, 5]");
+    hipStream_t s = ctx->stream;
+    const int nc = A.ncell;
+    auto fetch = [&](const DevBuf &b, size_t count, auto *host) -> vm_status {
+        VM_HIP(hipMemcpyAsync(host, b.ptr, count * sizeof(*host), hipMemcpyDeviceToHost, s), "copy debug view");
+        return VM_OK;
+    };
+    if (what == 5) {
+        *rows = A.n;
+        if (!out) return VM_OK;
+        VM_HIP(hipMemcpyAsync(out, ctx->last_perm, sizeof(int32_t) * size_t(A.n), hipMemcpyDeviceToHost, s),
+               "copy debug view");
+        VM_HIP(hipStreamSynchronize(s), "synchronize");
+        return VM_OK;
+    }
+    std::vector<uint32_t> key(nc);
+    std::vector<int32_t> lev(nc), st(nc), cnt(nc), par(nc);
+    vm_status r = VM_OK;
+    if ((r = fetch(A.key, nc, key.data())) != VM_OK || (r = fetch(A.level, nc, lev.data())) != VM_OK ||
+        (r = fetch(A.start, nc, st.data())) != VM_OK || (r = fetch(A.count, nc, cnt.data())) != VM_OK ||
+        (r = fetch(A.parent, nc, par.data())) != VM_OK)
+        return r;
+    std::vector<int32_t> rowsv;
+    if (what == 0) {
+        VM_HIP(hipStreamSynchronize(s), "synchronize");
+        for (int c = 0; c < nc; ++c) {
+            const int leaf = cnt[c] <= A.ncrit || lev[c] >= A.max_level;
+            const int32_t row[6] = {int32_t(key[c]), lev[c], st[c], cnt[c], par[c], leaf};
+            rowsv.insert(rowsv.end(), row, row + 6);
+        }
+    } else if (what == 2) {
+        std::vector<int32_t> vt(size_t(nc) * 189);
+        if ((r = fetch(A.vtab, vt.size(), vt.data())) != VM_OK) return r;
+        VM_HIP(hipStreamSynchronize(s), "synchronize");
+        const OffsetTable &t = offset_table();
+        const std::vector<int16_t> lists = device_octant_lists();
+        for (int c = 0; c < nc; ++c)
+            for (int i = 0; i < 189; ++i) {
+                const int b = vt[size_t(c) * 189 + i];
+                if (b < 0) continue;
+                const int l = lev[c], o = int(key[c] & 7u), side = 1 << l;
+                const int8_t *d = t.d[lists[o * 189 + i]];
+                int code = 0, mul = 1;
+                for (int k = 0; k < 3; ++k) {
+                    int cc = 0;
+                    for (int bit = 0; bit < l; ++bit) cc |= int((key[c] >> (3 * bit + k)) & 1u) << bit;
+                    const int pos = cc + d[k];
+                    const int sh = pos < 0 ? -1 : (pos >= side ? 1 : 0);
+                    code += (sh + 1) * mul;
+                    mul *= 3;
+                }
+                const int32_t row[3] = {c, b, code};
+                rowsv.insert(rowsv.end(), row, row + 3);
+            }
+    } else {
+        const int k = what == 1 ? 0 : (what == 3 ? 1 : 2);   // P2P, M2P, P2L
+        std::vector<uint32_t> lc(3 * size_t(nc)), lo(3 * size_t(nc));
+        if ((r = fetch(A.cnt, lc.size(), lc.data())) != VM_OK || (r = fetch(A.off, lo.size(), lo.data())) != VM_OK)
+            return r;
+        VM_HIP(hipStreamSynchronize(s), "synchronize");
+        const size_t total = size_t(lo.back()) + lc.back();
+        std::vector<int32_t> src(total);
+        std::vector<int8_t> code(total);
+        if (total) {
+            if ((r = fetch(A.src, total, src.data())) != VM_OK || (r = fetch(A.code, total, code.data())) != VM_OK)
+                return r;
+            VM_HIP(hipStreamSynchronize(s), "synchronize");
+        }
+        for (int c = 0; c < nc; ++c)
+            for (uint32_t e = 0; e < lc[size_t(k) * nc + c]; ++e) {
+                const size_t pos = size_t(lo[size_t(k) * nc + c]) + e;
+                const int32_t row[3] = {c, src[pos], code[pos]};
+                rowsv.insert(rowsv.end(), row, row + 3);
+            }
+    }
+    const int width = what == 0 ? 6 : 3;
+    *rows = int64_t(rowsv.size() / width);
+    if (out) std::memcpy(out, rowsv.data(), rowsv.size() * sizeof(int32_t));
     return VM_OK;
 }
 

@@ -1,0 +1,156 @@
+"""GPU checks of the adaptive hybrid treecode-FMM (vm_fmm_eval_adaptive).
+
+Gates:
+* cells (key, level, particle range, parent, leaf), the sorted order and the
+  four interaction lists (P2P, M2L, M2P, P2L as (target, source, image)
+  triples): bit-exact against the oracle's tree and dual traversal;
+* u, J and dalpha/dt against the oracle's adaptive FMM (same tree, lists and
+  truncation, FP64): 1e-10 relative L2 and 1e-10 of the largest reference
+  magnitude per particle (round-off apart);
+* on a uniform tree: equal to vm_fmm_eval at the same level to 1e-12 (the
+  same operators, other accumulation order);
+* degenerate trees: one leaf holding every particle (n <= ncrit: the exact
+  sum over the images), a single particle, particles piled into one finest
+  cell beyond ncrit.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1110_2921_amd as vm
+import workloads as W
+from oracle import adaptive as A
+from oracle import direct as D
+from oracle import fmm as OF
+from _gates import FP64, close, rel
+
+pytestmark = pytest.mark.gpu
+
+L = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = vm.FMM(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64).T)).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy().T
+
+
+def _run(ctx, x, a, sigma, p, ncrit, ml, periodic, scheme="classic"):
+    u, da, J = ctx.eval_adaptive(_dev(x), _dev(a), sigma, p, ncrit, ml, periodic=periodic, scheme=scheme,
+                                 want_grad=True)
+    torch.cuda.synchronize()
+    return _host(u), _host(da), _host(J).reshape(-1, 3, 3)
+
+
+CASES = [  # (n, seed, ncrit, max_level, periodic, p)
+    (1500, 3, 24, 5, 0, 5),
+    (1200, 8, 16, 4, 1, 6),
+    (900, 12, 20, 4, 3, 5),
+]
+
+
+@pytest.mark.parametrize("n,seed,ncrit,ml,periodic,p", CASES)
+def test_tree_and_lists_bit_exact(ctx, n, seed, ncrit, ml, periodic, p):
+    x, a = W.clustered_particles(n, seed)
+    print(f"[adaptive] lists n={n} seed={seed} ncrit={ncrit} ml={ml} K={periodic}", flush=True)
+    _run(ctx, x, a, L / 64, p, ncrit, ml, periodic)
+    tr = A.build_tree(x, (0, 0, 0), L, ncrit, ml, periodic)
+    ls = A.lists(tr)
+    cells = ctx.debug_adaptive("cells")
+    want = np.stack([tr["key"], tr["level"], tr["start"], tr["count"], tr["parent"], tr["leaf"].astype(np.int64)], 1)
+    assert cells.shape == want.shape and np.array_equal(cells, want)
+    assert np.array_equal(ctx.debug_adaptive("perm"), tr["perm"])
+    for name in ("p2p", "m2l", "m2p", "p2l"):
+        got = ctx.debug_adaptive(name)
+        got = got[np.lexsort((got[:, 2], got[:, 1], got[:, 0]))] if len(got) else got.reshape(0, 3)
+        assert got.shape == ls[name].shape and np.array_equal(got, ls[name]), name
+    assert len(ls["m2p"]) and len(ls["p2l"]) and len(ls["m2l"])
+
+
+@pytest.mark.parametrize("n,seed,ncrit,ml,periodic,p", CASES)
+def test_matches_oracle(ctx, n, seed, ncrit, ml, periodic, p):
+    x, a = W.clustered_particles(n, seed)
+    sigma = L / 64
+    print(f"[adaptive] parity n={n} seed={seed} ncrit={ncrit} ml={ml} K={periodic} p={p}", flush=True)
+    u, da, J = _run(ctx, x, a, sigma, p, ncrit, ml, periodic)
+    uo, Jo = A.fmm(x, a, sigma, p, ncrit, ml, periodic=periodic)
+    print(f"[parity] u {rel(u, uo):.2e} J {rel(J, Jo):.2e}", flush=True)
+    close(u, uo, FP64, "u")
+    close(J, Jo, FP64, "J")
+    close(da, D.stretching(Jo, a, "classic"), FP64, "dalpha")
+
+
+def test_uniform_tree_equals_uniform_fmm(ctx):
+    ml = 3
+    x, a = W.particles_with_leaf_counts([9] * 512, ml, 21)
+    sigma, p = L / 32, 8
+    for periodic in (0, 3):
+        u, da, J = _run(ctx, x, a, sigma, p, 8, ml, periodic)
+        uu, dau, Ju = ctx.eval(_dev(x), _dev(a), sigma, p, ml, periodic=periodic, want_grad=True)
+        torch.cuda.synchronize()
+        uu, dau, Ju = _host(uu), _host(dau), _host(Ju).reshape(-1, 3, 3)
+        assert len(ctx.debug_adaptive("m2p")) == 0 and len(ctx.debug_adaptive("p2l")) == 0
+        assert rel(u, uu) < 1e-12 and rel(J, Ju) < 1e-12 and rel(da, dau) < 1e-12, periodic
+
+
+@pytest.mark.parametrize("periodic", [0, 1])
+def test_one_leaf_is_the_direct_sum(ctx, periodic):
+    x, a = W.clustered_particles(200, 4)
+    sigma = 0.2
+    u, _, J = _run(ctx, x, a, sigma, 6, 256, 4, periodic)
+    xw = A.T.wrap(x, (0, 0, 0), L) if periodic else x
+    ud, Jd = D.direct(xw, xw, a, sigma, L, K=periodic)
+    assert len(ctx.debug_adaptive("cells")) == 1
+    close(u, ud, (1e-13, 1e-13), "u")
+    close(J, Jd, (1e-13, 1e-13), "J")
+
+
+def test_single_particle_and_piled_cell(ctx):
+    # one particle: only its self term (zero velocity)
+    u, _, J = _run(ctx, np.array([[1.0, 2.0, 3.0]]), np.array([[0.3, -0.2, 0.5]]), 0.1, 4, 8, 3, 0)
+    assert np.all(u == 0.0)
+    # 300 particles inside one finest cell plus a scattered rest: the pile stays one leaf at max_level
+    rng = np.random.default_rng(9)
+    ml = 4
+    w = L / (1 << ml)
+    pile = (np.array([5, 9, 2]) + rng.uniform(0.2, 0.8, (300, 3))) * w
+    rest, _ = W.random_particles(400, 10)
+    x = np.concatenate([pile, rest])
+    a = rng.standard_normal(x.shape)
+    sigma, p = w / 4, 5
+    u, _, J = _run(ctx, x, a, sigma, p, 16, ml, 0)
+    cells = ctx.debug_adaptive("cells")
+    leaves = cells[cells[:, 5] == 1]
+    big = leaves[leaves[:, 3].argmax()]
+    assert big[3] >= 300 and big[1] == ml
+    uo, Jo = A.fmm(x, a, sigma, p, 16, ml, periodic=0)
+    close(u, uo, FP64, "u")
+    close(J, Jo, FP64, "J")
+
+
+def test_tune_ncrit(ctx):
+    x, a = W.clustered_particles(60000, 31)
+    best, ms = ctx.tune_ncrit(_dev(x), _dev(a), L / 128, 6, 6, reps=1)
+    print(f"[adaptive] tuned ncrit {best}: {ms}", flush=True)
+    assert best in ms and ms[best] == min(ms.values()) and len(ms) >= 3
+
+
+def test_rejects_unsupported_forms(ctx):
+    x, a = W.clustered_particles(100, 1)
+    with pytest.raises(vm._lib.VmError):
+        ctx.eval_adaptive(_dev(x), _dev(a), 0.1, 15, 16, 4)          # p beyond the adaptive limit
+    with pytest.raises(vm._lib.VmError):
+        ctx.eval_adaptive(_dev(x), _dev(a), 0.1, 6, 0, 4)            # ncrit < 1
