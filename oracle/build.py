@@ -18,5 +18,18 @@ def build() -> str:
     return out
 
 
+def build_asan() -> str:
+    """The direct sum and its driver (``asan_check.c``) built with AddressSanitizer
+    and UndefinedBehaviorSanitizer into the executable ``_direct_asan``."""
+    out = os.path.join(_HERE, "_direct_asan")
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-ffp-contract=off", "-fopenmp", "-std=c99", "-o", tmp,
+           os.path.join(_HERE, "direct.c"), os.path.join(_HERE, "asan_check.c"), "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build())

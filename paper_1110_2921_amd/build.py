@@ -60,5 +60,33 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+def build_host_check() -> str:
+    """The host layer (the C ABI driver and the operator generation) built with
+    AddressSanitizer, linked with the kernels' objects of the last build() and
+    the driver csrc/host_check.cpp, into the executable _build/host_check."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    san = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+    objs, procs = [], []
+    for src in ("operators.cpp", "vmfmm.cpp", "host_check.cpp"):
+        obj = os.path.join(BUILD_DIR, src + ".asan.o")
+        objs.append(obj)
+        cmd = [HIPCC, "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"),
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + san + \
+              ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError("hipcc failed for " + src + ":\n" + out.decode(errors="replace"))
+    kernels = [os.path.join(BUILD_DIR, s + ".o") for s in SOURCES if s.endswith(".hip")]
+    if not all(os.path.exists(k) for k in kernels):
+        build()
+    exe = os.path.join(BUILD_DIR, "host_check")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address", "-o", exe] + objs + kernels + \
+          ["-L/opt/rocm/lib", "-lhipfft"]
+    subprocess.run(cmd, check=True)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
