@@ -45,7 +45,7 @@ struct DevTables {
     // recurrence constants for balanced regular harmonics (index n(n+1)/2 + m)
     const double *c1_64, *c2_64, *diag_64;
     const float *c1_32, *c2_32, *diag_32;
-    // L2P sparse table: rows (3 nu + 9 ng) x width
+    // L2P sparse table: rows (3 nu + 9 ng) x width, stored entry-major [width][rows]
     const int32_t *l2p_idx;
     const double *l2p_w64;
     const float *l2p_w32;

@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
     __syncthreads();
     for (int r = lane; r < rows; r += 64) {
         T s = T(0);
-        for (int e = 0; e < width; ++e) s += tw[size_t(r) * width + e] * lam[tab.l2p_idx[size_t(r) * width + e]];
+        for (int e = 0; e < width; ++e) s += tw[size_t(e) * rows + r] * lam[tab.l2p_idx[size_t(e) * rows + r]];
         int slot, comp;
         if (r < 3 * nu) {
             comp = r / nu;

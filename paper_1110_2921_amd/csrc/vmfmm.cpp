@@ -296,10 +296,20 @@ vm_status ensure_ops(vm_ctx *ctx, int p, OpSet **out) {
         VM_HIP(upload(set->dg_32, fd), "upload rec");
     }
     {
+        // entry-major on the device ([entry][row]): the L2P kernel's lanes take
+        // consecutive rows, so each entry's loads are coalesced
         const L2PTable l = l2p_table(p);
-        std::vector<float> w32(l.w.begin(), l.w.end());
-        VM_HIP(upload(set->l2p_idx, l.idx), "upload L2P table");
-        VM_HIP(upload(set->l2p_w64, l.w), "upload L2P table");
+        const int rows = 3 * l.nu + 9 * l.ng;
+        std::vector<int32_t> idx(l.idx.size());
+        std::vector<double> w64(l.w.size());
+        for (int r = 0; r < rows; ++r)
+            for (int e = 0; e < l.width; ++e) {
+                idx[size_t(e) * rows + r] = l.idx[size_t(r) * l.width + e];
+                w64[size_t(e) * rows + r] = l.w[size_t(r) * l.width + e];
+            }
+        std::vector<float> w32(w64.begin(), w64.end());
+        VM_HIP(upload(set->l2p_idx, idx), "upload L2P table");
+        VM_HIP(upload(set->l2p_w64, w64), "upload L2P table");
         VM_HIP(upload(set->l2p_w32, w32), "upload L2P table");
         set->width = l.width;
         set->nu = l.nu;
