@@ -127,16 +127,18 @@ struct P2PArgs {
 hipError_t launch_p2p64(hipStream_t s, const P2PArgs &a, const Part64 *parts);
 hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts);
 
-// Near field of an adaptive tree: target leaf lcell[i] (particles lstart[i] ..
-// lstart[i+1]-1) against the source leaves of its P2P list, entries
-// off[c] .. off[c] + cnt[c] - 1 of (src, code) with image shift codes; cells'
-// particle ranges, keys and levels from the tree.  Same combine and output as
-// launch_p2p64 (a.n, a.perm, a.alpha, a.far, a.u, a.dalpha, a.grad, a.scheme,
-// a.have_far, a.sigma are used).
+// Near field of an adaptive tree: work item w is the target block items[w] =
+// (leaf i in particle order, first target of the block in the leaf; blocks
+// of 64); leaf i is cell lcell[i] with particles lstart[i] .. lstart[i+1]-1,
+// its sources the leaves of its P2P list, entries off[c] .. off[c] + cnt[c] - 1
+// of (src, code) with image shift codes; cells' particle ranges, keys and
+// levels from the tree.  Same combine and output as launch_p2p64 (a.n,
+// a.perm, a.alpha, a.far, a.u, a.dalpha, a.grad, a.scheme, a.have_far,
+// a.sigma are used).
 struct AdTreeView;
-hipError_t launch_p2p64_list(hipStream_t s, const P2PArgs &a, int nleaf, const int32_t *lcell, const int32_t *lstart,
-                             const AdTreeView &t, const uint32_t *off, const uint32_t *cnt, const int32_t *src,
-                             const int8_t *code, const Part64 *parts);
+hipError_t launch_p2p64_list(hipStream_t s, const P2PArgs &a, int nitem, const int2 *items, const int32_t *lcell,
+                             const int32_t *lstart, const AdTreeView &t, const uint32_t *off, const uint32_t *cnt,
+                             const int32_t *src, const int8_t *code, const Part64 *parts);
 
 // --- RBF interpolation (kernels_rbf.hip) --------------------------------------------
 struct GaussArgs {
@@ -241,6 +243,10 @@ hipError_t launch_ad_no_children(hipStream_t s, const AdTreeView &t, int off, in
 // leaves in particle order: lcell, lstart (nleaf + 1), llev; *nleaf_out
 hipError_t launch_ad_leaves(hipStream_t s, const AdTreeView &t, int ncell, int n, int32_t *leaf_at, uint32_t *rank,
                             uint32_t *tile_sums, int32_t *lcell, int32_t *lstart, int32_t *llev, int *nleaf_out);
+// target blocks of 64 of the leaves (particle order): items (leaf, first
+// target), their number in *nitem_out; rank / tile_sums scratch of nleaf words
+hipError_t launch_ad_blocks(hipStream_t s, int nleaf, const int32_t *lstart, uint32_t *rank, uint32_t *tile_sums,
+                            int2 *items, int *nitem_out);
 // sorted FP64 records relative to each leaf's centre
 hipError_t launch_ad_permute(hipStream_t s, const AdTreeView &t, int n, const double *x, const double *alpha,
                              const int32_t *perm, int nleaf, const int32_t *lcell, Part64 *parts);
@@ -257,10 +263,11 @@ hipError_t launch_ad_octants(hipStream_t s, const AdTreeView &t, int off, int nc
 // += the particles of the source leaves of their P2L lists
 hipError_t launch_ad_p2l(hipStream_t s, const AdTreeView &t, const AdLists &ls, int off, int ncl, int ncell, int p,
                          int kp, const DevTables &tab, const Part64 *parts, double *L);
-// M2P: far[12][n] of the particles of the leaves += the derivatives of the
-// source cells' multipoles (m2p_table layout; tab's recurrence of degree >= p + 2)
-hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nleaf, const int32_t *lcell,
-                         const int32_t *lstart, int n, int ncell, int p, int kp, int nrow, int nharm,
+// M2P: far[12][n] of the particles of the target blocks `items` += the
+// derivatives of the source cells' multipoles (m2p_table layout; tab's
+// recurrence of degree >= p + 2)
+hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nitem, const int2 *items,
+                         const int32_t *lcell, const int32_t *lstart, int n, int ncell, int p, int kp, int nrow, int nharm,
                          const DevTables &tab, const int32_t *rowptr, const int32_t *col, const int32_t *harm,
                          const double *w, const double *G, const Part64 *parts, const double *M, double *far);
 

@@ -410,7 +410,8 @@ __global__ void __launch_bounds__(64) k_ad_p2l(AdTreeView t, AdLists ls, int off
 // those coefficients into u and J at the particle, added to far[12][n].
 constexpr int kM2PMaxRow = 9;
 
-__global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, int nleaf, const int32_t *__restrict__ lcell,
+__global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const int2 *__restrict__ items,
+                                               const int32_t *__restrict__ lcell,
                                                const int32_t *__restrict__ lstart, int n, int ncell, int p, int kp,
                                                int nrow, int nharm, DevTables tab, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col, const int32_t *__restrict__ harm,
@@ -418,7 +419,8 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, int nle
                                                const Part64 *__restrict__ parts, const double *__restrict__ M,
                                                double *__restrict__ far) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int a = lcell[blockIdx.x];
+    const int2 it = items[blockIdx.x];
+    const int a = lcell[it.x];
     const uint32_t e0 = ls.off[size_t(1) * ncell + a];
     const uint32_t e1 = e0 + ls.cnt[size_t(1) * ncell + a];
     if (e1 == e0) return;
@@ -427,8 +429,9 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, int nle
     double *mb = hs + size_t(nharm) * 64;                   // [3][kp]
     double ca[3];
     centre(t, a, ca);
-    const int s0 = lstart[blockIdx.x], cnt = lstart[blockIdx.x + 1] - s0;
-    for (int base = 0; base < cnt; base += 64) {
+    const int s0 = lstart[it.x], cnt = lstart[it.x + 1] - s0;
+    {
+        const int base = it.y;
         const bool valid = base + lane < cnt;
         const Part64 me = parts[s0 + base + (valid ? lane : 0)];
         double out[12];
@@ -480,6 +483,23 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, int nle
             for (int o = 0; o < 12; ++o) far[size_t(o) * n + gi] += out[o];
         }
     }
+}
+
+// target blocks of 64 per leaf, then the (leaf, first target) items
+__global__ void __launch_bounds__(256) k_ad_block_count(int nleaf, const int32_t *__restrict__ lstart,
+                                                        uint32_t *__restrict__ nb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nleaf) nb[i] = uint32_t((lstart[i + 1] - lstart[i] + 63) / 64);
+}
+
+__global__ void __launch_bounds__(256) k_ad_block_fill(int nleaf, const int32_t *__restrict__ lstart,
+                                                       const uint32_t *__restrict__ boff, int2 *__restrict__ items,
+                                                       int *__restrict__ nitem) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    const int nb = (lstart[i + 1] - lstart[i] + 63) / 64;
+    if (i == nleaf - 1) *nitem = int(boff[i]) + nb;
+    for (int b = 0; b < nb; ++b) items[boff[i] + b] = make_int2(i, 64 * b);
 }
 
 inline int blocks(int n, int t) { return (n + t - 1) / t; }
@@ -556,13 +576,25 @@ hipError_t launch_ad_p2l(hipStream_t s, const AdTreeView &t, const AdLists &ls, 
     return hipGetLastError();
 }
 
-hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nleaf, const int32_t *lcell,
-                         const int32_t *lstart, int n, int ncell, int p, int kp, int nrow, int nharm,
-                         const DevTables &tab, const int32_t *rowptr, const int32_t *col, const int32_t *harm,
-                         const double *w, const double *G, const Part64 *parts, const double *M, double *far) {
+hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nitem, const int2 *items,
+                         const int32_t *lcell, const int32_t *lstart, int n, int ncell, int p, int kp, int nrow,
+                         int nharm, const DevTables &tab, const int32_t *rowptr, const int32_t *col,
+                         const int32_t *harm, const double *w, const double *G, const Part64 *parts, const double *M,
+                         double *far) {
+    if (nitem == 0) return hipSuccess;
     const size_t smem = sizeof(double) * (size_t(nharm) * 64 + size_t(3) * kp);
-    hipLaunchKernelGGL(k_ad_m2p, dim3(nleaf), dim3(64), smem, s, t, ls, nleaf, lcell, lstart, n, ncell, p, kp, nrow,
+    hipLaunchKernelGGL(k_ad_m2p, dim3(nitem), dim3(64), smem, s, t, ls, items, lcell, lstart, n, ncell, p, kp, nrow,
                        nharm, tab, rowptr, col, harm, w, G, parts, M, far);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_blocks(hipStream_t s, int nleaf, const int32_t *lstart, uint32_t *rank, uint32_t *tile_sums,
+                            int2 *items, int *nitem_out) {
+    hipLaunchKernelGGL(k_ad_block_count, dim3(blocks(nleaf, 256)), dim3(256), 0, s, nleaf, lstart, rank);
+    hipError_t e = launch_exclusive_scan(s, nleaf, rank, tile_sums);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ad_block_fill, dim3(blocks(nleaf, 256)), dim3(256), 0, s, nleaf, lstart,
+                       (const uint32_t *)rank, items, nitem_out);
     return hipGetLastError();
 }
 

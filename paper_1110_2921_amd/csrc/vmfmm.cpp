@@ -155,7 +155,7 @@ struct vm_ctx {
     struct Adaptive {
         DevBuf key, level, start, count, parent, child;        // cells
         DevBuf sstart, scount, rank, tsum, ints;                // construction scratch, device counters
-        DevBuf leaf_at, lcell, lstart, llev, iota;              // leaves in particle order
+        DevBuf leaf_at, lcell, lstart, llev, iota, items;       // leaves in particle order, target blocks
         DevBuf part, pcode, npart, vtab, cnt, off, src, code;   // traversal
         DevBuf tcell, M, L, parts;
         DevBuf rec_c1, rec_c2, rec_dg;                          // recurrence of degree p + 2
@@ -1061,6 +1061,12 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
            "adaptive leaves");
     int nleaf = 0;
     if (vm_status st = read_ints(ctx, dints + 1, &nleaf, 1); st != VM_OK) return st;
+    // target blocks of 64 (the near field and M2P work items)
+    VM_HIP(A.items.reserve(sizeof(int2) * (size_t(nleaf) + size_t(n) / 64 + 1)), "alloc work items");
+    VM_HIP(launch_ad_blocks(s, nleaf, A.lstart.as<int32_t>(), A.rank.as<uint32_t>(), A.tsum.as<uint32_t>(),
+                            A.items.as<int2>(), dints + 3), "adaptive work items");
+    int nitem = 0;
+    if (vm_status st = read_ints(ctx, dints + 3, &nitem, 1); st != VM_OK) return st;
     VM_HIP(A.parts.reserve(sizeof(Part64) * size_t(n)), "alloc particles");
     Part64 *parts = A.parts.as<Part64>();
     VM_HIP(launch_ad_permute(s, t, n, x, alpha, vin, nleaf, A.lcell.as<int32_t>(), parts), "adaptive permute");
@@ -1191,7 +1197,8 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     }
     {
         Timed tm(ctx, VM_PH_M2P);
-        VM_HIP(launch_ad_m2p(s, t, ls, nleaf, lcell, lstart, n, ncell, p, kp, A.m2p_nrow, A.m2p_nharm, tabI,
+        VM_HIP(launch_ad_m2p(s, t, ls, nitem, A.items.as<int2>(), lcell, lstart, n, ncell, p, kp, A.m2p_nrow,
+                             A.m2p_nharm, tabI,
                              A.m2p_rowptr.as<int32_t>(), A.m2p_col.as<int32_t>(), A.m2p_harm.as<int32_t>(),
                              A.m2p_w.as<double>(), A.m2p_G.as<double>(), parts, M, ctx->far.as<double>()),
                "adaptive M2P");
@@ -1209,8 +1216,8 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     a.grad = grad;
     {
         Timed tm(ctx, VM_PH_P2P);
-        VM_HIP(launch_p2p64_list(s, a, nleaf, lcell, lstart, t, A.off.as<uint32_t>(), A.cnt.as<uint32_t>(),
-                                 A.src.as<int32_t>(), A.code.as<int8_t>(), parts),
+        VM_HIP(launch_p2p64_list(s, a, nitem, A.items.as<int2>(), lcell, lstart, t, A.off.as<uint32_t>(),
+                                 A.cnt.as<uint32_t>(), A.src.as<int32_t>(), A.code.as<int8_t>(), parts),
                "adaptive P2P");
     }
     A.valid = true;
