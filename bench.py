@@ -36,7 +36,7 @@ PEAKS = {  # MI355X published peaks
     "valu_f64_tflops": 78.6,
 }
 # Algorithmic work per unit, FMA = 2 flop:
-P2P_FLOP_PER_PAIR = {"mixed": 86.0, "fp64": 69.0}   # counted from the pair kernels
+P2P_FLOP_PER_PAIR = {"mixed": 78.0, "fp64": 69.0}   # counted from the pair kernels
 # Gaussian sum: r = t - s (3), |r|^2 (5), scale (1), exp2 (1), three strength FMAs (6)
 GAUSS_FLOP_PER_PAIR = 16.0
 
@@ -132,11 +132,18 @@ def _traffic_summary(workload, precision):
     return d if d.get("sources_sha256") == sources_sha256() else None
 
 
-def measured_traffic(workload, precision, kernel):
-    """HBM bytes per launch of `kernel` (see _traffic_summary), or None."""
+def measured_traffic(workload, precision, kernel, launches_per_eval=None):
+    """HBM bytes per launch of `kernel` (see _traffic_summary), or None.  With
+    `launches_per_eval`, the kernel's bytes per evaluation divided by its
+    launches per evaluation (the profile then comes from an evaluations-only
+    run, so every dispatch of the kernel belongs to an evaluation)."""
     d = _traffic_summary(workload, precision)
     k = None if d is None else d.get("kernels", {}).get(kernel)
-    return None if k is None else k["hbm_bytes_per_launch"]
+    if k is None:
+        return None
+    if launches_per_eval and k.get("hbm_bytes_per_evaluation"):
+        return k["hbm_bytes_per_evaluation"] / launches_per_eval
+    return k["hbm_bytes_per_launch"]
 
 
 def measured_tree_bytes(workload, precision):
@@ -147,6 +154,13 @@ def measured_tree_bytes(workload, precision):
     ks = d["kernels"]
     evals = ks["k_keys"]["dispatches"]          # one key pass per evaluation
     return sum(ks[k]["hbm_bytes_per_launch"] * ks[k]["dispatches"] / evals for k in TREE_KERNELS if k in ks)
+
+
+def direct_at(x, a, sigma, box_len, targets):
+    """CPU leg: the oracle's exact free-space sum at the sampled particles."""
+    from oracle import direct as oracle_direct
+
+    return oracle_direct.direct(x[targets], x, a, sigma, box_len, K=0)
 
 
 def cpu_baseline(w, x_full, a_full, targets):
@@ -227,7 +241,15 @@ def main():
                     help="steps of the paper's time loop to time (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="one 1 GiB device-to-device copy (known bytes) for counter calibration")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the adaptive-tree comparison on clustered particles")
+    ap.add_argument("--evals-only", action="store_true",
+                    help="time the Heun steps only (no other sections): the run the profiles are taken from")
     args = ap.parse_args()
+    if args.evals_only:
+        args.no_cpu_baseline = args.no_fp64_check = args.no_adjoint = args.no_accuracy = True
+        args.no_rbf = args.no_truncation = args.no_adaptive = True
+        args.loop_steps = 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -320,7 +342,7 @@ def main():
     esz = 4 if f32 else 8
     m2l_kernel = "k_m2l_os<4,8,false>" if (f32 and w.p in (9, 10)) else ("k_translate<double,1,1,0,24>"
                                                                        if not f32 else "k_m2l_os")
-    m2l_traffic = measured_traffic(w.name, args.precision, m2l_kernel)
+    m2l_traffic = measured_traffic(w.name, args.precision, m2l_kernel, m2l_launch)
     # algorithmic bytes of the M2L phase: read M, read and write L at every level, the operators once
     cells = sum(8 ** l for l in range(1 if w.periodic else 2, w.level + 1))
     m2l_alg_bytes = (cells * 3 * C * esz * 3 + 316 * C * C * esz) / m2l_launch
@@ -334,7 +356,7 @@ def main():
     roof_p2p = {"bound": "alu", "kernel": p2p_kernel,
                 "achieved": p2p_flop / (p2p_ms * 1e-3) / 1e12,
                 "peak": PEAKS["valu_f32_tflops" if f32 else "valu_f64_tflops"], "unit": "TFLOP/s",
-                "traffic": measured_traffic(w.name, args.precision, p2p_kernel), "traffic_unit": "bytes per launch",
+                "traffic": measured_traffic(w.name, args.precision, p2p_kernel, 1), "traffic_unit": "bytes per launch",
                 "algorithmic_bytes_per_launch": n * (32 if f32 else 64) + n * 8 * (12 + 3 + 3 + 9 + 3) + n * 4}
     roof_p2p["frac"] = roof_p2p["achieved"] / roof_p2p["peak"]
     dominant = roof_p2p if p2p_ms >= m2l_ms else roof_m2l
@@ -638,6 +660,60 @@ def main():
         log(f"[bench] 32^3 evaluation: eager {1e3 * te:.3f} ms, graph replay {1e3 * tg:.3f} ms")
         del graph, xs, as_, us, das
 
+    pending_adaptive = None
+    if not args.no_adaptive:
+        # clustered particles (Gaussian clusters and a uniform tenth, free space):
+        # the adaptive hybrid tree with its tuned leaf size against the uniform
+        # tree at its tuned level, both FP64 at p = 10; the accuracy of both
+        # against the exact sum at sampled particles comes with the CPU leg
+        na, pa = 1 << 19, 10
+        xa_np, aa_np = W.clustered_particles(na, seed=41)
+        sg = w.box_len / 1024
+        max_level = 8                 # leaves at least 4 sigma wide
+        xa = torch.from_numpy(np.ascontiguousarray(xa_np.T)).to(dev)
+        aa = torch.from_numpy(np.ascontiguousarray(aa_np.T)).to(dev)
+        # the uniform tree at its finest admissible level (leaves >= 4 sigma, no more
+        # leaves than particles); coarser levels put thousands of clustered particles
+        # in one leaf, whose near field one wave then runs alone for seconds
+        lv = 0
+        while lv < 10 and w.box_len / 2 ** (lv + 1) >= 4 * sg and 8 ** (lv + 1) <= na:
+            lv += 1
+        log(f"[bench] clustered {na}: uniform tree at level {lv}, tuning the adaptive leaf size")
+        nc, nms = ctx.tune_ncrit(xa, aa, sg, pa, max_level, periodic=0, box_len=w.box_len, reps=1)
+        log(f"[bench] adaptive ncrit {nc}: " + ", ".join(f"{k}: {v:.1f} ms" for k, v in sorted(nms.items())))
+        reps = 3
+        timings = {}
+        for name, fn in (("uniform", lambda: ctx.eval(xa, aa, sg, pa, lv, box_len=w.box_len, precision="fp64",
+                                                      want_grad=True)),
+                         ("adaptive", lambda: ctx.eval_adaptive(xa, aa, sg, pa, nc, max_level, box_len=w.box_len,
+                                                                want_grad=True))):
+            out = fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out = fn()
+            torch.cuda.synchronize()
+            timings[name] = ((time.perf_counter() - t0) / reps, out)
+            log(f"[bench] clustered {name}: {1e3 * timings[name][0]:.1f} ms per evaluation")
+        cells = ctx.debug_adaptive("cells")
+        lists = {k: int(len(ctx.debug_adaptive(k))) for k in ("p2p", "m2l", "m2p", "p2l")}
+        tga = np.sort(np.random.default_rng(12).choice(na, 16, replace=False))
+        got_a = {k: (v[1][0][:, tga].cpu().numpy().T, v[1][2][:, tga].cpu().numpy().T) for k, v in timings.items()}
+        result["adaptive"] = {
+            "workload": f"{na} particles in 8 Gaussian clusters (std 1/64 .. 1/8 of the box) and a uniform tenth, "
+                        f"free space, sigma = box/1024, p = {pa}, FP64, u + J + dalpha/dt",
+            "uniform": {"level": lv, "ms": 1e3 * timings["uniform"][0],
+                        "what": "finest level with leaves at least 4 sigma wide and no more leaves than particles"},
+            "adaptive": {"ncrit": nc, "max_level": max_level, "ms": 1e3 * timings["adaptive"][0],
+                         "tuning_ms_per_ncrit": {str(k): v for k, v in sorted(nms.items())},
+                         "cells": int(len(cells)), "leaves": int(cells[:, 5].sum()),
+                         "deepest_leaf_level": int(cells[cells[:, 5] == 1, 1].max()), "lists": lists},
+            "speedup_vs_uniform": timings["uniform"][0] / timings["adaptive"][0]}
+        log(f"[bench] clustered {na}: uniform level {lv} {1e3 * timings['uniform'][0]:.1f} ms, adaptive ncrit {nc} "
+            f"{1e3 * timings['adaptive'][0]:.1f} ms ({len(cells)} cells)")
+        pending_adaptive = (xa_np, aa_np, sg, tga, got_a)
+        del xa, aa, timings
+
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         tg = pending_accuracy[0] if pending_accuracy else np.zeros(0, np.int64)
@@ -654,6 +730,14 @@ def main():
                 log(f"[bench] p={pp} vs direct sum: fp64 u {e['fp64']['u']:.2e} J {e['fp64']['J']:.2e}; "
                     f"mixed u {e['mixed']['u']:.2e} J {e['mixed']['J']:.2e}")
             result["rel_l2_u_vs_direct"] = result["accuracy_vs_direct"]["per_p"][str(w.p)]["mixed"]["u"]
+        if pending_adaptive:
+            xa_np, aa_np, sg, tga, got_a = pending_adaptive
+            ud_a, Jd_a = direct_at(xa_np, aa_np, sg, w.box_len, tga)
+            for k, (ug, Jg) in got_a.items():
+                result["adaptive"][k]["rel_l2_vs_direct"] = {
+                    "u": float(np.linalg.norm(ug - ud_a) / np.linalg.norm(ud_a)),
+                    "J": float(np.linalg.norm(Jg - Jd_a.reshape(-1, 9)) / np.linalg.norm(Jd_a)),
+                    "targets": len(tga)}
     print(json.dumps(result), flush=True)
 
 

@@ -37,7 +37,7 @@ CALIBRATION_BYTES = 1 << 30
 # the sources the measured kernels (tree, expansions, translations, near field,
 # Gaussian sums) and their launch configurations are built from
 MEASURED_SOURCES = ("kernels.h", "device_harmonics.h", "kernels_tree.hip", "kernels_fmm.hip", "kernels_p2p.hip",
-                    "kernels_rbf.hip", "operators.h", "operators.cpp")
+                    "kernels_rbf.hip", "kernels_adaptive.hip", "operators.h", "operators.cpp", "vmfmm.cpp")
 
 
 def sources_sha256() -> str:
@@ -88,8 +88,11 @@ def trace_summary(d: str, command: str | None) -> str:
 
 
 def _counters(d: str, counter: str):
+    """Per kernel name and per (name, grid size) launch shape: the counter's
+    value of every dispatch; plus the values of the copy kernels."""
     rows = list(csv.DictReader(open(_one(d, "*counter_collection.csv"))))
     per = collections.defaultdict(list)
+    shape = collections.defaultdict(list)
     copies = []
     for r in rows:
         if r["Counter_Name"] != counter:
@@ -97,14 +100,21 @@ def _counters(d: str, counter: str):
         v = float(r["Counter_Value"])
         n = short_name(r["Kernel_Name"])
         per[n].append(v)
+        shape[(n, int(r["Grid_Size"]))].append(v)
         if "copyBuffer" in r["Kernel_Name"]:
             copies.append(v)
-    return per, copies
+    return per, shape, copies
 
 
 def traffic_summary(fetch_dir: str, write_dir: str, workload: str, command: str | None) -> dict:
-    fetch, fcopies = _counters(fetch_dir, "FETCH_SIZE")
-    write, wcopies = _counters(write_dir, "WRITE_SIZE")
+    """Calibrated HBM bytes of each kernel: per dispatch averaged over all its
+    dispatches, per evaluation (all its dispatches over the number of
+    evaluations, counted by the key kernel, which runs once per evaluation:
+    meaningful when the profiled command runs evaluations only) and per
+    launch shape (grid size), so that one level's launch of a kernel that runs
+    at every level can be read on its own."""
+    fetch, fshape, fcopies = _counters(fetch_dir, "FETCH_SIZE")
+    write, wshape, wcopies = _counters(write_dir, "WRITE_SIZE")
     if not wcopies:
         raise SystemExit("no copy kernel in the run: profile a command with --copy-calibration")
     # the calibration copy is the copy that writes the most
@@ -114,6 +124,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, workload: str, command: str 
     known_kib = CALIBRATION_BYTES / 1024.0
     ff, wf = known_kib / f_kib, known_kib / w_kib
     kernels = {}
+    evals = len(fetch.get("k_keys", []))
     for name in sorted(set(fetch) | set(write)):
         if not name.startswith(("k_m2l_os", "k_translate", "k_p2p", "k_split_reduce", "k_permute",
                                 "k_radix", "k_keys", "k_iota", "k_scan", "k_ranges", "k_p2m", "k_l2p",
@@ -123,9 +134,19 @@ def traffic_summary(fetch_dir: str, write_dir: str, workload: str, command: str 
         if not fv or not wv:
             continue
         fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
+        shapes = []
+        for (nm, grid) in sorted(k for k in fshape if k[0] == name):
+            a, b = fshape[(nm, grid)], wshape.get((nm, grid), [])
+            if not b:
+                continue
+            shapes.append({"grid_size": grid, "dispatches": len(a),
+                           "hbm_bytes_per_dispatch": 1024.0 * (sum(a) / len(a) * ff + sum(b) / len(b) * wf)})
         kernels[name] = {"dispatches": len(fv), "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
-                         "hbm_bytes_per_launch": 1024.0 * (fk * ff + wk * wf)}
-    return {"workload": workload, "command": command,
+                         "hbm_bytes_per_launch": 1024.0 * (fk * ff + wk * wf),
+                         "hbm_bytes_per_evaluation": (1024.0 * (sum(fv) * ff + sum(wv) * wf) / evals
+                                                      if evals else None),
+                         "shapes": shapes}
+    return {"workload": workload, "command": command, "evaluations": evals,
             "calibration": {"copy_bytes": CALIBRATION_BYTES, "fetch_kib": f_kib, "write_kib": w_kib,
                             "fetch_factor": ff, "write_factor": wf},
             "sources_sha256": sources_sha256(), "kernels": kernels}
