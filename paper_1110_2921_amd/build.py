@@ -21,7 +21,7 @@ COMMON = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 SOURCES = ["kernels_tree.hip", "kernels_fmm.hip", "kernels_p2p.hip", "kernels_step.hip", "kernels_adjoint.hip",
-           "kernels_adaptive.hip",
+           "kernels_adaptive.hip", "kernels_m2l_sym.hip",
            "kernels_rbf.hip", "kernels_spectrum.hip",
            "operators.cpp",
            "vmfmm.cpp"]

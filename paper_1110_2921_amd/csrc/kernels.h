@@ -292,4 +292,89 @@ inline int tr_nks(int C) { return (pad4(C) + 31) / 32 * 8; }
 inline size_t tr_frag(int C) { return size_t(tr_nrb(C)) * tr_nks(C) * 64; }
 inline int tr_col(int ks, int h) { return 16 * (ks >> 2) + 4 * h + (ks & 3); }
 
+
+// --- reflection-symmetric M2L (kernels_m2l_sym.hip) ---------------------------
+// Reflecting the configuration in the plane x = 0 (y = 0, z = 0) multiplies each
+// real coefficient of the basis by a sign: (-1)^m for Re Rb_n^m and -(-1)^m for
+// Im (x), +1 for Re and -1 for Im (y), (-1)^(n+m) for both (z).  The three signs
+// give every coefficient a class c in 0..7 (bit a set: sign -1 under the
+// reflection of axis a), and the M2L operator of a reflected offset R d is
+// P_R T_d P_R with P_R = diag(chi_c(R)), chi_c(R) = (-1)^popcount(c & R).  The
+// M2L of the offsets of one reflection orbit therefore needs one operator: its
+// block (a, b) between classes a and b meets the sources of the orbit combined
+// with the character of a ^ b (a Walsh-Hadamard transform over the orbit).
+//
+// Class-major layout: class c holds its coefficients in ascending standard
+// index, in ceil(size / 16) blocks of 16; block k of the layout is of class
+// bcls[k], with bnv[k] valid elements starting at rank brank0[k] of its class,
+// which take the first bsteps[k] = ceil(bnv / 4) of the block's four k steps
+// (element e of a block sits at position 4 (e % 4) + e / 4).
+constexpr int kSymMaxBlk = 16;
+struct SymLayout {
+    int p = 0, C = 0, nblk = 0;
+    int csize[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int bcls[kSymMaxBlk] = {}, bnv[kSymMaxBlk] = {}, bsteps[kSymMaxBlk] = {}, brank0[kSymMaxBlk] = {};
+};
+
+// class of the coefficient at standard index i (n n for m = 0, n n + 2m - 1 for
+// Re, n n + 2m for Im)
+constexpr int sym_class(int i) {
+    int n = 0;
+    while ((n + 1) * (n + 1) <= i) ++n;
+    const int r = i - n * n;
+    const int m = (r + 1) / 2, im = (r > 0 && r % 2 == 0) ? 1 : 0;
+    return ((m & 1) ^ im) | (im << 1) | (((n + m) & 1) << 2);
+}
+
+// nblk = 0 when a class needs more than kSymMaxBlk blocks in total
+constexpr SymLayout sym_layout(int p) {
+    SymLayout L;
+    L.p = p;
+    L.C = (p + 1) * (p + 1);
+    for (int i = 0; i < L.C; ++i) ++L.csize[sym_class(i)];
+    int k = 0;
+    for (int c = 0; c < 8; ++c)
+        for (int r = 0; r < L.csize[c]; r += 16) {
+            if (k == kSymMaxBlk) {
+                L.nblk = 0;
+                return L;
+            }
+            L.bcls[k] = c;
+            L.brank0[k] = r;
+            L.bnv[k] = L.csize[c] - r < 16 ? L.csize[c] - r : 16;
+            L.bsteps[k] = (L.bnv[k] + 3) / 4;
+            ++k;
+        }
+    L.nblk = k;
+    return L;
+}
+
+// The 56 orbits of the octant-0 interaction list under the reflections that
+// keep it (axes with |d_a| = 1 or 2): representative r (components 0..3,
+// source - target, largest >= 2), packed rx | ry << 2 | rz << 4 | G << 6 | Z << 9
+// with G the axes of the orbit's reflections and Z the axes where r_a = 0.
+constexpr int kSymOrbits = 56;
+
+// Mc[cell][3][16 nblk] (FP32) from the standard-layout multipoles of `ncells`
+// cells (M[cell][3][kp]): mc_src[16 k + q] is the standard index held at
+// position q of block k (-1: zero).  Cell `ncells` of Mc is written as zeros.
+hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const float *M, const int16_t *mc_src,
+                           float *Mc);
+// Offset-range splits of an M2L launch of `level` with `ttn` targets per
+// workgroup (enough workgroups to fill the chip, within part_elems), and the
+// fixed-order sum of the splits' partials into dst (rows < C).
+int translate_splits(int level, int ttn, int kp, size_t part_elems);
+hipError_t launch_split_reduce(hipStream_t s, int level, int kp, int C, int nsplit, const float *part, float *dst,
+                               int accumulate);
+// True if the symmetric M2L kernel is built for degree p.
+bool m2l_sym_supported(int p);
+// M2L at `level` (FP32): dst[cell] (+)= sum over the interaction list, from the
+// class-major multipoles mc of the level (zero_cell: index of a zero cell,
+// relative to mc), operators ops (per octant, orbit-compact, offsets op_off
+// [8][57] in floats), orbit table `orbits`, output map row_std[16 nblk].
+// Splits over orbit ranges with partial sums in `part` as launch_translate.
+hipError_t launch_m2l_sym(hipStream_t s, int level, int periodic, int p, int kp, const float *mc, int64_t zero_cell,
+                          const float *ops, const int32_t *op_off, const int32_t *orbits, const int16_t *row_std,
+                          float *dst, int accumulate, float *part, size_t part_elems);
+
 }  // namespace vmfmm

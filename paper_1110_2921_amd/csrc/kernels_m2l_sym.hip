@@ -1,0 +1,289 @@
+// M2L in FP32 by reflection orbits (paper Sec. 3.1, eq. 11: the multipole-to-
+// local translation of the interaction list).
+//
+// The 189 offsets of an octant's interaction list fall into 56 orbits under
+// the reflections of the axes along which the list is symmetric; all offsets
+// of an orbit share one operator up to the sign matrices P_R (kernels.h).  A
+// target's local expansion is then
+//   L_a += sum_orbits sum_b T_ab Y_{a^b, b},  Y_{x, b} = sum_R chi_x(R) M_{R d, b},
+// where a, b run over the coefficient classes, d is the orbit's representative
+// and R its reflections: one operator application per orbit instead of one per
+// offset, and blocks T_ab with a ^ b along an axis where d is zero vanish.  The
+// octant's own reflection is folded into per-octant operator copies.
+//
+// Work split: a workgroup of 12 waves takes 64 same-octant target cells; wave
+// w serves targets 16 (w / 3) .. +15 and component w % 3, so no source is
+// loaded twice.  Per orbit the operator's nonzero blocks sit in LDS (two
+// buffers: the next orbit's copy is spread over the current orbit's k blocks,
+// one barrier per orbit).  Per k block a lane loads its target's sources of
+// the orbit's members (one 16-byte quad each), transforms them in registers
+// and feeds the class blocks of the block's column to the MFMAs; the next k
+// block's sources are loaded before the MFMAs of the current one.
+#include "kernels.h"
+
+#include <type_traits>
+
+namespace vmfmm {
+namespace {
+
+constexpr int kSymWaves = 12;
+constexpr int kSymThreads = 64 * kSymWaves;
+constexpr int kSymTargets = 64;
+
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
+// bits of v (< 2^10) spread to every third bit
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x3ffu;
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_sym_pack(int64_t nelem, int kp, int kc, const float *__restrict__ M,
+                                                  const int16_t *__restrict__ mc_src, float *__restrict__ Mc) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= nelem) return;
+    const int q = int(e % kc);
+    const int64_t cc = e / kc;   // cell * 3 + component
+    const int src = mc_src[q];
+    // the cell past the last one is the zero cell
+    Mc[e] = (src >= 0 && cc < nelem / kc - 3) ? M[cc * kp + src] : 0.0f;
+}
+
+template <int P>
+__global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic, int kp,
+                                                         const float *__restrict__ mc, uint32_t zero_off,
+                                                         const float *__restrict__ ops,
+                                                         const int32_t *__restrict__ op_off,
+                                                         const int32_t *__restrict__ orbits,
+                                                         const int16_t *__restrict__ row_std,
+                                                         float *__restrict__ dst, int accumulate, int nsplit,
+                                                         float *__restrict__ part) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr SymLayout SL = sym_layout(P);
+    constexpr int NB = SL.nblk, KC = 16 * NB;
+    static_assert(NB > 0, "degree without a class layout");
+    constexpr int OPF = 16 * SL.C * NB;        // floats of a full orbit (every block)
+    constexpr int BUF = OPF + 64;              // + slack for the row over-reads of short blocks
+    constexpr int CELL = 3 * KC;               // floats per cell of mc
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *opl = reinterpret_cast<float *>(smem_raw);   // [2][BUF]
+    __shared__ int32_t sorb[kSymOrbits];
+    __shared__ int32_t soff[kSymOrbits + 1];
+    __shared__ int16_t srow[KC];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int comp = wave % 3, tg = wave / 3, h = lane >> 4, col = lane & 15;
+    const int octant = blockIdx.x & 7, tile = blockIdx.x >> 3;
+    const int o0 = int(blockIdx.y) * kSymOrbits / nsplit;
+    const int o1 = (int(blockIdx.y) + 1) * kSymOrbits / nsplit;
+    const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
+    const int side = 1 << level;
+
+    if (tid < kSymOrbits) sorb[tid] = orbits[tid];
+    if (tid <= kSymOrbits) soff[tid] = op_off[octant * (kSymOrbits + 1) + tid];
+    for (int i = tid; i < KC; i += kSymThreads) srow[i] = row_std[i];
+    if (tid < 64) {
+        opl[OPF + tid] = 0.0f;
+        opl[BUF + OPF + tid] = 0.0f;
+    }
+    {
+        const int b0 = op_off[octant * (kSymOrbits + 1) + o0];
+        const int n4 = (op_off[octant * (kSymOrbits + 1) + o0 + 1] - b0) / 4;
+        for (int q = tid; q < n4; q += kSymThreads)
+            *reinterpret_cast<f4 *>(opl + 4 * q) = *reinterpret_cast<const f4 *>(ops + b0 + 4 * q);
+    }
+    const int64_t slot = int64_t(tile) * kSymTargets + tg * 16 + col;
+    const bool tvalid = slot < ncell_t;
+    const uint32_t tkey = tvalid ? uint32_t((slot << 3) | octant) : 0u;
+    const int tc[3] = {int(compact3(tkey)), int(compact3(tkey >> 1)), int(compact3(tkey >> 2))};
+    __syncthreads();
+
+    // offsets (floats, relative to mc) of the member sources of orbit o; slot r
+    // is the reflection of the axes in r, present when r lies within G
+    uint32_t mo[8];
+    auto members = [&](int o) {
+        const int info = sorb[o];
+        const int G = (info >> 6) & 7;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (r & ~G) {
+                mo[r] = zero_off;
+                continue;
+            }
+            bool ok = tvalid;
+            uint32_t key = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int rep = (info >> (2 * a)) & 3;
+                int d = ((r >> a) & 1) ? -rep : rep;
+                if ((octant >> a) & 1) d = -d;
+                int c = tc[a] + d;
+                if (periodic) c &= side - 1;
+                else ok = ok && c >= 0 && c < side;
+                key |= spread3(uint32_t(c)) << a;
+            }
+            mo[r] = ok ? key * uint32_t(CELL) : zero_off;
+        }
+    };
+    // the lane's quad of k block b of every member; absent slots read the zero
+    // cell (loads issued unconditionally keep the wait counts static)
+    f4 val[8];
+    auto load_block = [&](int b) {
+        const uint32_t base = uint32_t(comp * KC + 16 * b + 4 * h);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) val[r] = *reinterpret_cast<const f4 *>(mc + (mo[r] + base));
+    };
+
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    v4 acc[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) acc[i] = v4{0.f, 0.f, 0.f, 0.f};
+
+    if (o0 < o1) {
+        members(o0);
+        load_block(0);
+    }
+    for (int o = o0; o < o1; ++o) {
+        const int cur = (o - o0) & 1;
+        const float *olc = opl + cur * BUF;
+        float *oln = opl + (cur ^ 1) * BUF;
+        const bool more = o + 1 < o1;
+        const int nn4 = more ? (soff[o + 2] - soff[o + 1]) / 4 : 0;
+        const float *ogn = ops + (more ? soff[o + 1] : 0);
+        const int info = sorb[o];
+        const int G = (info >> 6) & 7, Z = (info >> 9) & 7;
+        int off = 0;   // running LDS offset of the next block of this orbit (floats)
+        f4 stage;
+        static_for<NB>([&](auto bi) {
+            constexpr int B = decltype(bi)::value;
+            // the next orbit's operator: chunk B - 1 out to LDS, chunk B in
+            if constexpr (B > 0) {
+                const int q = (B - 1) * kSymThreads + tid;
+                if (q < nn4) *reinterpret_cast<f4 *>(oln + 4 * q) = stage;
+            }
+            {
+                const int q = B * kSymThreads + tid;
+                stage = *reinterpret_cast<const f4 *>(ogn + 4 * (q < nn4 ? q : 0));
+            }
+            // Walsh-Hadamard transform over the reflection slots: y[x] = sum_r chi_x(r) val[r]
+            f4 y[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) y[r] = val[r];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int bit = 1 << a;
+                if (G & bit) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r)
+                        if (!(r & bit)) {
+                            const f4 u = y[r], v = y[r | bit];
+                            y[r] = u + v;
+                            y[r | bit] = u - v;
+                        }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r)
+                        if (!(r & bit)) y[r | bit] = y[r];
+                }
+            }
+            // sources of the next k block (or of the next orbit's first)
+            if constexpr (B + 1 < NB) {
+                load_block(B + 1);
+            } else {
+                members(more ? o + 1 : o);
+                load_block(0);
+            }
+            // class blocks of column B
+            static_for<8>([&](auto xi) {
+                constexpr int X = decltype(xi)::value;
+                if (!(X & Z)) {
+                    static_for<NB>([&](auto ai) {
+                        constexpr int A = decltype(ai)::value;
+                        if constexpr (SL.bcls[A] == (SL.bcls[B] ^ X)) {
+                            const f4 aq = *reinterpret_cast<const f4 *>(olc + off + 4 * (h * SL.bnv[A] + col));
+                            off += 16 * SL.bnv[A];
+                            static_for<SL.bsteps[B]>([&](auto si) {
+                                constexpr int S = decltype(si)::value;
+                                acc[A] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[S], y[X][S], acc[A], 0, 0, 0);
+                            });
+                        }
+                    });
+                }
+            });
+        });
+        {
+            const int q = (NB - 1) * kSymThreads + tid;
+            if (q < nn4) *reinterpret_cast<f4 *>(oln + 4 * q) = stage;
+        }
+        __syncthreads();
+    }
+    if (!tvalid) return;
+    const bool split = part != nullptr;
+    float *out = (split ? part + (size_t(blockIdx.y) * (size_t(1) << (3 * level)) + tkey) * 3 * kp
+                        : dst + size_t(tkey) * 3 * kp) + comp * kp;
+    static_for<NB>([&](auto ai) {
+        constexpr int A = decltype(ai)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = 4 * h + r;
+            if (e < SL.bnv[A]) {
+                float *o = out + srow[16 * A + e];
+                *o = (accumulate && !split) ? *o + acc[A][r] : acc[A][r];
+            }
+        }
+    });
+}
+
+}  // namespace
+
+bool m2l_sym_supported(int p) { return p == 10; }
+
+hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const float *M, const int16_t *mc_src,
+                           float *Mc) {
+    const int64_t nelem = (ncells + 1) * 3 * kc;
+    hipLaunchKernelGGL(k_sym_pack, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, nelem, kp, kc, M, mc_src,
+                       Mc);
+    return hipGetLastError();
+}
+
+hipError_t launch_m2l_sym(hipStream_t s, int level, int periodic, int p, int kp, const float *mc, int64_t zero_cell,
+                          const float *ops, const int32_t *op_off, const int32_t *orbits, const int16_t *row_std,
+                          float *dst, int accumulate, float *part, size_t part_elems) {
+    if (!m2l_sym_supported(p) || level < 1) return hipErrorInvalidValue;
+    constexpr SymLayout SL = sym_layout(10);
+    constexpr int KC = 16 * SL.nblk;
+    if (uint64_t(zero_cell) * 3 * KC >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
+    const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
+    int nsplit = part ? translate_splits(level, kSymTargets, kp, part_elems) : 1;
+    if (nsplit > kSymOrbits) nsplit = kSymOrbits;
+    float *pbuf = nsplit > 1 ? part : nullptr;
+    const dim3 grid(unsigned((ncell_t + kSymTargets - 1) / kSymTargets * 8), unsigned(nsplit));
+    const size_t smem = 2 * sizeof(float) * size_t(16 * SL.C * SL.nblk + 64);
+    hipLaunchKernelGGL(k_m2l_sym<10>, grid, dim3(kSymThreads), smem, s, level, periodic, kp, mc,
+                       uint32_t(zero_cell * 3 * KC), ops, op_off, orbits, row_std, dst, accumulate, nsplit, pbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsplit == 1) return e;
+    return launch_split_reduce(s, level, kp, SL.C, nsplit, pbuf, dst, accumulate);
+}
+
+}  // namespace vmfmm

@@ -7,6 +7,7 @@
 #include <hipfft/hipfft.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -91,6 +92,9 @@ struct OpSet {
     // M2L operators truncated to n + n' <= p, and their transposes (built on first use)
     bool tri_ready = false, tri_adj_ready = false;
     DevBuf m2lt64, m2lt32, m2lTt64, m2lTt32;
+    // reflection-orbit M2L (FP32, square truncation; built on first use)
+    bool sym_ready = false;
+    DevBuf sym_ops, sym_off, sym_orb, sym_mcsrc, sym_row;
 };
 
 // Zeroes the entries of a C x C operator that pair target degree n (row) with
@@ -113,6 +117,7 @@ struct vm_ctx {
     DevBuf keys_a, keys_b, vals_a, vals_b, hist, start, p64, p32, far, flag, mbuf, lbuf;
     DevBuf trpart;   // partial sums of M2L launches split over the offsets (coarse levels)
     DevBuf zeros;    // a zero expansion cell read in place of missing M2L sources
+    DevBuf mcbuf;    // class-major FP32 multipoles of every level for the reflection-orbit M2L
     DevBuf rk_u, rk_s, rk_x, rk_a, diag;
     DevBuf adj_u, adj_J, adj_v, adj_Jv, adj_far, adj_p64, adj_p32;
     DevBuf rbf_b, rbf_x, rbf_V, rbf_part, rbf_dots;   // RBF solve: right side, iterate, Krylov basis, reductions
@@ -427,6 +432,80 @@ vm_status ensure_tri_ops(vm_ctx *ctx, OpSet *set, int adjoint) {
     return VM_OK;
 }
 
+// Tables of the reflection-orbit M2L for degree p: the class-major maps, the
+// 56 orbits of the octant-0 list and, per octant, the nonzero class blocks of
+// each orbit's operator with the octant's reflection folded in, in the order
+// the kernel consumes them (column block b, then class offset x, then the row
+// blocks of class bcls[b] ^ x), each block as 4 lane groups x its valid rows x
+// 4 k steps.
+vm_status ensure_sym_ops(vm_ctx *ctx, OpSet *set) {
+    if (set->sym_ready) return VM_OK;
+    const int p = set->p, C = ncoef(p);
+    const SymLayout SL = sym_layout(p);
+    if (SL.nblk == 0) return VM_EINVAL;
+    const int NB = SL.nblk, KC = 16 * NB;
+    std::vector<int> members[8];
+    for (int i = 0; i < C; ++i) members[sym_class(i)].push_back(i);
+    std::vector<int16_t> mc_src(KC, -1), row_std(KC, -1);
+    for (int k = 0; k < NB; ++k)
+        for (int e = 0; e < SL.bnv[k]; ++e) {
+            const int idx = members[SL.bcls[k]][SL.brank0[k] + e];
+            mc_src[16 * k + 4 * (e % 4) + e / 4] = int16_t(idx);   // element e at k step e / 4 of lane group e % 4
+            row_std[16 * k + e] = int16_t(idx);
+        }
+    std::vector<int32_t> orb;
+    std::vector<std::array<int, 3>> reps;
+    for (int z = 0; z < 4; ++z)
+        for (int y = 0; y < 4; ++y)
+            for (int x = 0; x < 4; ++x) {
+                if (std::max(x, std::max(y, z)) < 2) continue;
+                const int r[3] = {x, y, z};
+                int G = 0, Z = 0;
+                for (int a = 0; a < 3; ++a) {
+                    if (r[a] == 1 || r[a] == 2) G |= 1 << a;
+                    if (r[a] == 0) Z |= 1 << a;
+                }
+                orb.push_back(x | (y << 2) | (z << 4) | (G << 6) | (Z << 9));
+                reps.push_back({x, y, z});
+            }
+    if (int(orb.size()) != kSymOrbits) return VM_EINVAL;
+    auto chi = [](int c, int refl) { return (__builtin_popcount(unsigned(c & refl)) & 1) ? -1.0 : 1.0; };
+    std::vector<float> ops;
+    std::vector<int32_t> off(8 * (kSymOrbits + 1));
+    std::vector<double> T(size_t(C) * C);
+    for (int o = 0; o < 8; ++o)
+        for (int j = 0; j < kSymOrbits; ++j) {
+            off[o * (kSymOrbits + 1) + j] = int32_t(ops.size());
+            // operator of the representative offset d (source - target): D = target - source
+            const double D[3] = {-double(reps[j][0]), -double(reps[j][1]), -double(reps[j][2])};
+            m2l_matrix(p, D, 1.0, 1.0, T.data());
+            const int Z = (orb[j] >> 9) & 7;
+            for (int b = 0; b < NB; ++b)
+                for (int x = 0; x < 8; ++x) {
+                    if (x & Z) continue;
+                    for (int a = 0; a < NB; ++a) {
+                        if (SL.bcls[a] != (SL.bcls[b] ^ x)) continue;
+                        const double sg = chi(SL.bcls[a], o) * chi(SL.bcls[b], o);
+                        for (int h = 0; h < 4; ++h)
+                            for (int e = 0; e < SL.bnv[a]; ++e)
+                                for (int st = 0; st < 4; ++st) {
+                                    const int cidx = mc_src[16 * b + 4 * h + st];
+                                    const double v = cidx >= 0 ? sg * T[size_t(row_std[16 * a + e]) * C + cidx] : 0.0;
+                                    ops.push_back(float(v));
+                                }
+                    }
+                }
+        }
+    for (int o = 0; o < 8; ++o) off[o * (kSymOrbits + 1) + kSymOrbits] = int32_t(ops.size());
+    VM_HIP(upload(set->sym_ops, ops), "upload symmetric M2L");
+    VM_HIP(upload(set->sym_off, off), "upload symmetric M2L");
+    VM_HIP(upload(set->sym_orb, orb), "upload symmetric M2L");
+    VM_HIP(upload(set->sym_mcsrc, mc_src), "upload symmetric M2L");
+    VM_HIP(upload(set->sym_row, row_std), "upload symmetric M2L");
+    set->sym_ready = true;
+    return VM_OK;
+}
+
 vm_status ensure_lattice_t(vm_ctx *ctx, int p, int K, const double **out) {
     const auto key = std::make_pair(p, K);
     auto it = ctx->lattice_t.find(key);
@@ -731,6 +810,11 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     if (vm_status st = ensure_ops(ctx, p, &ops); st != VM_OK) return st;
     if (opts->truncation == VM_TRIANGULAR)
         if (vm_status st = ensure_tri_ops(ctx, ops, 0); st != VM_OK) return st;
+    // FP32 square-truncation M2L by reflection orbits where its kernel is built
+    // (its source offsets are 32-bit: levels up to 7)
+    const bool use_sym = mixed && opts->truncation != VM_TRIANGULAR && m2l_sym_supported(p) && level <= 7;
+    if (use_sym)
+        if (vm_status st = ensure_sym_ops(ctx, ops); st != VM_OK) return st;
     const double *tlat = nullptr;
     if (K >= 2)
         if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
@@ -755,6 +839,10 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
         ctx->layout_p = p;
         ctx->layout_prec = mixed;
     }
+
+    if (use_sym)
+        VM_HIP(ctx->mcbuf.reserve(sizeof(float) * size_t(ncells + 1) * 3 * (16 * sym_layout(p).nblk)),
+               "alloc class-major multipoles");
 
     // --- tree ------------------------------------------------------------
     TreeGeom g;
@@ -816,6 +904,15 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                 VM_HIP(launch_translate<T>(s, 2, l, periodic, p, kp, m2m, lists, offs, lev(M, l + 1), lev(M, l), 0),
                        "M2M");
             }
+            const bool sym = f32 && use_sym;
+            const int kc = 16 * sym_layout(p).nblk;
+            float *mc = ctx->mcbuf.as<float>();
+            if (sym) {
+                Timed tm(ctx, VM_PH_M2L);
+                VM_HIP(launch_sym_pack(s, ncells, kp, kc, reinterpret_cast<const float *>(M),
+                                       ops->sym_mcsrc.as<int16_t>(), mc),
+                       "M2L class-major multipoles");
+            }
             bool have_parent = false;   // L at level l-1 holds something
             if (periodic && K >= 2) {
                 Timed tm(ctx, VM_PH_LATTICE);
@@ -829,10 +926,20 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                            "L2L");
                 }
                 Timed tm(ctx, VM_PH_M2L);
-                VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
-                                           have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
-                                           ctx->zeros.as<T>(), tri),
-                       "M2L");
+                if (sym) {
+                    const int64_t base = ((int64_t(1) << (3 * l)) - 1) / 7;
+                    VM_HIP(launch_m2l_sym(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
+                                          ops->sym_ops.as<float>(), ops->sym_off.as<int32_t>(),
+                                          ops->sym_orb.as<int32_t>(), ops->sym_row.as<int16_t>(),
+                                          reinterpret_cast<float *>(lev(L, l)), have_parent ? 1 : 0,
+                                          ctx->trpart.as<float>(), ctx->trpart.bytes / sizeof(float)),
+                           "M2L");
+                } else {
+                    VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
+                                               have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
+                                               ctx->zeros.as<T>(), tri),
+                           "M2L");
+                }
                 have_parent = true;
             }
             Timed tm(ctx, VM_PH_L2P);

@@ -331,3 +331,26 @@ def test_degrees_inside_the_operator_stationary_shapes(ctx, p):
     um, _, Jm = _run(ctx, x, a, h, p, 2, 3, precision="mixed")
     close(um, u, MIXED_U, "um vs u")
     close(Jm, J, MIXED_J, "Jm vs J")
+
+
+@pytest.mark.parametrize("level,K", [(1, 2), (2, 0), (2, 3), (3, 0), (3, 1), (4, 3), (4, 0)])
+def test_reflection_orbit_m2l(ctx, level, K):
+    """p = 10 mixed runs the M2L by reflection orbits (one operator per orbit
+    of the interaction list applied to the Walsh-Hadamard-combined sources,
+    per-octant signs, class-blocked MFMAs).  Against FP64 (dense operators,
+    itself pinned to the oracle) at 1e-5 / 4e-5 (u) and 1e-4 / 4e-4 (J): free
+    space (missing sources beyond the domain), periodic with and without the
+    lattice, coarse levels split over orbit ranges and level 4 without; the
+    FP64 result is also held to the oracle at level 2."""
+    ng = {1: 4, 2: 8, 3: 16, 4: 24}[level]
+    x, a = W.random_field(ng, 4.0, 300 + 10 * level + K)
+    h = L / ng
+    print(f"[orbit-m2l] level={level} K={K} n={len(x)}", flush=True)
+    u, _, J = _run(ctx, x, a, h, 10, level, K)
+    um, _, Jm = _run(ctx, x, a, h, 10, level, K, precision="mixed")
+    close(um, u, MIXED_U, "um vs u")
+    close(Jm, J, MIXED_J, "Jm vs J")
+    if level == 2:
+        uo, Jo = OF.fmm(x, a, h, 10, level, periodic=K)
+        close(u, uo, FP64, "u vs uo")
+        close(J, Jo, FP64, "J vs Jo")
