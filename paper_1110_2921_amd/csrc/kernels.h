@@ -354,6 +354,9 @@ constexpr SymLayout sym_layout(int p) {
 // source - target, largest >= 2), packed rx | ry << 2 | rz << 4 | G << 6 | Z << 9
 // with G the axes of the orbit's reflections and Z the axes where r_a = 0.
 constexpr int kSymOrbits = 56;
+// coarsest level the orbit kernel runs (coarser levels have too few target cells
+// to fill the chip without splitting every workgroup down to one orbit)
+constexpr int kSymMinLevel = 4;
 
 // Mc[cell][3][16 nblk] (FP32) from the standard-layout multipoles of `ncells`
 // cells (M[cell][3][kp]): mc_src[16 k + q] is the standard index held at

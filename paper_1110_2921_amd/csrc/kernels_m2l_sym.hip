@@ -26,9 +26,6 @@
 namespace vmfmm {
 namespace {
 
-constexpr int kSymWaves = 12;
-constexpr int kSymThreads = 64 * kSymWaves;
-constexpr int kSymTargets = 64;
 
 template <int N, int I = 0, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -68,22 +65,28 @@ __global__ void __launch_bounds__(256) k_sym_pack(int64_t nelem, int kp, int kc,
     Mc[e] = (src >= 0 && cc < nelem / kc - 3) ? M[cc * kp + src] : 0.0f;
 }
 
+constexpr int kSymWaves = 12;
+constexpr int kSymThreads = 64 * kSymWaves;
+constexpr int kSymTargets = 64;
+
 template <int P>
 __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic, int kp,
-                                                         const float *__restrict__ mc, uint32_t zero_off,
-                                                         const float *__restrict__ ops,
-                                                         const int32_t *__restrict__ op_off,
-                                                         const int32_t *__restrict__ orbits,
-                                                         const int16_t *__restrict__ row_std,
-                                                         float *__restrict__ dst, int accumulate, int nsplit,
-                                                         float *__restrict__ part) {
+                                                                    const float *__restrict__ mc, uint32_t zero_off,
+                                                                    const float *__restrict__ ops,
+                                                                    const int32_t *__restrict__ op_off,
+                                                                    const int32_t *__restrict__ orbits,
+                                                                    const int16_t *__restrict__ row_std,
+                                                                    float *__restrict__ dst, int accumulate,
+                                                                    int nsplit, float *__restrict__ part) {
     typedef float f4 __attribute__((ext_vector_type(4)));
     constexpr SymLayout SL = sym_layout(P);
     constexpr int NB = SL.nblk, KC = 16 * NB;
     static_assert(NB > 0, "degree without a class layout");
+    constexpr int NT = kSymThreads, TT = kSymTargets;
     constexpr int OPF = 16 * SL.C * NB;        // floats of a full orbit (every block)
     constexpr int BUF = OPF + 64;              // + slack for the row over-reads of short blocks
     constexpr int CELL = 3 * KC;               // floats per cell of mc
+    static_assert(NB * NT * 4 >= OPF, "the operator copy must finish within one orbit");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float *opl = reinterpret_cast<float *>(smem_raw);   // [2][BUF]
     __shared__ int32_t sorb[kSymOrbits];
@@ -92,7 +95,8 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int comp = wave % 3, tg = wave / 3, h = lane >> 4, col = lane & 15;
+    const int comp = wave % 3, tg = wave / 3;
+    const int h = lane >> 4, col = lane & 15;
     const int octant = blockIdx.x & 7, tile = blockIdx.x >> 3;
     const int o0 = int(blockIdx.y) * kSymOrbits / nsplit;
     const int o1 = (int(blockIdx.y) + 1) * kSymOrbits / nsplit;
@@ -101,7 +105,7 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
 
     if (tid < kSymOrbits) sorb[tid] = orbits[tid];
     if (tid <= kSymOrbits) soff[tid] = op_off[octant * (kSymOrbits + 1) + tid];
-    for (int i = tid; i < KC; i += kSymThreads) srow[i] = row_std[i];
+    for (int i = tid; i < KC; i += NT) srow[i] = row_std[i];
     if (tid < 64) {
         opl[OPF + tid] = 0.0f;
         opl[BUF + OPF + tid] = 0.0f;
@@ -109,25 +113,27 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
     {
         const int b0 = op_off[octant * (kSymOrbits + 1) + o0];
         const int n4 = (op_off[octant * (kSymOrbits + 1) + o0 + 1] - b0) / 4;
-        for (int q = tid; q < n4; q += kSymThreads)
+        for (int q = tid; q < n4; q += NT)
             *reinterpret_cast<f4 *>(opl + 4 * q) = *reinterpret_cast<const f4 *>(ops + b0 + 4 * q);
     }
-    const int64_t slot = int64_t(tile) * kSymTargets + tg * 16 + col;
+    const int64_t slot = int64_t(tile) * TT + tg * 16 + col;
     const bool tvalid = slot < ncell_t;
     const uint32_t tkey = tvalid ? uint32_t((slot << 3) | octant) : 0u;
     const int tc[3] = {int(compact3(tkey)), int(compact3(tkey >> 1)), int(compact3(tkey >> 2))};
     __syncthreads();
 
-    // offsets (floats, relative to mc) of the member sources of orbit o; slot r
-    // is the reflection of the axes in r, present when r lies within G
+    // byte offsets (relative to mc, with the lane group's quad) of the member
+    // sources of orbit o; slot r is the reflection of the axes in r, present
+    // when r lies within G
     uint32_t mo[8];
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(mc), 0, -1, 0x00020000);
     auto members = [&](int o) {
         const int info = sorb[o];
         const int G = (info >> 6) & 7;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             if (r & ~G) {
-                mo[r] = zero_off;
+                mo[r] = zero_off * 4u + uint32_t(16 * h);
                 continue;
             }
             bool ok = tvalid;
@@ -142,16 +148,33 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
                 else ok = ok && c >= 0 && c < side;
                 key |= spread3(uint32_t(c)) << a;
             }
-            mo[r] = ok ? key * uint32_t(CELL) : zero_off;
+            mo[r] = (ok ? key * uint32_t(CELL) : zero_off) * 4u + uint32_t(16 * h);
         }
     };
     // the lane's quad of k block b of every member; absent slots read the zero
     // cell (loads issued unconditionally keep the wait counts static)
     f4 val[8];
     auto load_block = [&](int b) {
-        const uint32_t base = uint32_t(comp * KC + 16 * b + 4 * h);
+        const uint32_t cb = uint32_t((comp * KC + 16 * b) * 4);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) val[r] = *reinterpret_cast<const f4 *>(mc + (mo[r] + base));
+        for (int r = 0; r < 8; ++r)
+            val[r] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, int(mo[r] + cb), 0, 0));
+    };
+    // Walsh-Hadamard transform over the reflection slots: y[x] = sum_r chi_x(r) v[r].
+    // Absent slots hold zeros (the zero cell), so every stage is a plain
+    // butterfly: along an axis outside G it copies, (u + 0, u - 0).
+    auto wht = [&](f4 (&y)[8]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int bit = 1 << a;
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (!(r & bit)) {
+                    const f4 u = y[r], v = y[r | bit];
+                    y[r] = u + v;
+                    y[r | bit] = u - v;
+                }
+        }
     };
 
     typedef float v4 __attribute__((ext_vector_type(4)));
@@ -171,49 +194,30 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
         const int nn4 = more ? (soff[o + 2] - soff[o + 1]) / 4 : 0;
         const float *ogn = ops + (more ? soff[o + 1] : 0);
         const int info = sorb[o];
-        const int G = (info >> 6) & 7, Z = (info >> 9) & 7;
-        int off = 0;   // running LDS offset of the next block of this orbit (floats)
+        const int Z = (info >> 9) & 7;
+        int off = 0;   // LDS offset of column block B of this orbit (floats)
         f4 stage;
         static_for<NB>([&](auto bi) {
             constexpr int B = decltype(bi)::value;
             // the next orbit's operator: chunk B - 1 out to LDS, chunk B in
             if constexpr (B > 0) {
-                const int q = (B - 1) * kSymThreads + tid;
+                const int q = (B - 1) * NT + tid;
                 if (q < nn4) *reinterpret_cast<f4 *>(oln + 4 * q) = stage;
             }
             {
-                const int q = B * kSymThreads + tid;
+                const int q = B * NT + tid;
                 stage = *reinterpret_cast<const f4 *>(ogn + 4 * (q < nn4 ? q : 0));
             }
-            // Walsh-Hadamard transform over the reflection slots: y[x] = sum_r chi_x(r) val[r]
+            if constexpr (B + 1 == NB) members(more ? o + 1 : o);
+            // transform into y, load the next k block into val, then the class
+            // blocks of column B against y
             f4 y[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) y[r] = val[r];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int bit = 1 << a;
-                if (G & bit) {
-#pragma unroll
-                    for (int r = 0; r < 8; ++r)
-                        if (!(r & bit)) {
-                            const f4 u = y[r], v = y[r | bit];
-                            y[r] = u + v;
-                            y[r | bit] = u - v;
-                        }
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 8; ++r)
-                        if (!(r & bit)) y[r | bit] = y[r];
-                }
-            }
-            // sources of the next k block (or of the next orbit's first)
-            if constexpr (B + 1 < NB) {
-                load_block(B + 1);
-            } else {
-                members(more ? o + 1 : o);
-                load_block(0);
-            }
-            // class blocks of column B
+            wht(y);
+            __builtin_amdgcn_sched_barrier(0);
+            load_block(B + 1 < NB ? B + 1 : 0);
+            __builtin_amdgcn_sched_barrier(0);
             static_for<8>([&](auto xi) {
                 constexpr int X = decltype(xi)::value;
                 if (!(X & Z)) {
@@ -232,7 +236,7 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
             });
         });
         {
-            const int q = (NB - 1) * kSymThreads + tid;
+            const int q = (NB - 1) * NT + tid;
             if (q < nn4) *reinterpret_cast<f4 *>(oln + 4 * q) = stage;
         }
         __syncthreads();
@@ -274,11 +278,11 @@ hipError_t launch_m2l_sym(hipStream_t s, int level, int periodic, int p, int kp,
     constexpr int KC = 16 * SL.nblk;
     if (uint64_t(zero_cell) * 3 * KC >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
     const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
+    const size_t smem = 2 * sizeof(float) * size_t(16 * SL.C * SL.nblk + 64);
     int nsplit = part ? translate_splits(level, kSymTargets, kp, part_elems) : 1;
     if (nsplit > kSymOrbits) nsplit = kSymOrbits;
     float *pbuf = nsplit > 1 ? part : nullptr;
     const dim3 grid(unsigned((ncell_t + kSymTargets - 1) / kSymTargets * 8), unsigned(nsplit));
-    const size_t smem = 2 * sizeof(float) * size_t(16 * SL.C * SL.nblk + 64);
     hipLaunchKernelGGL(k_m2l_sym<10>, grid, dim3(kSymThreads), smem, s, level, periodic, kp, mc,
                        uint32_t(zero_cell * 3 * KC), ops, op_off, orbits, row_std, dst, accumulate, nsplit, pbuf);
     hipError_t e = hipGetLastError();

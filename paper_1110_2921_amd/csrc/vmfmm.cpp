@@ -926,7 +926,9 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                            "L2L");
                 }
                 Timed tm(ctx, VM_PH_M2L);
-                if (sym) {
+                // the orbit kernel from level 4 on; the few cells of the coarser
+                // levels run the dense operators
+                if (sym && l >= kSymMinLevel) {
                     const int64_t base = ((int64_t(1) << (3 * l)) - 1) / 7;
                     VM_HIP(launch_m2l_sym(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
                                           ops->sym_ops.as<float>(), ops->sym_off.as<int32_t>(),
