@@ -17,6 +17,7 @@ bounded sample.
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import math
 import os
@@ -43,6 +44,32 @@ GAUSS_FLOP_PER_PAIR = 16.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def _sym_class(i):
+    """Reflection class of the real coefficient at standard index i (bit a: sign
+    -1 under the reflection of axis a)."""
+    n = int(math.isqrt(i))
+    r = i - n * n
+    m, im = (r + 1) // 2, int(r > 0 and r % 2 == 0)
+    return ((m & 1) ^ im) | (im << 1) | (((n + m) & 1) << 2)
+
+
+def orbit_m2l_flop_per_target(p):
+    """Flops of the orbit-form M2L per target cell (3 components, FMA = 2): per
+    orbit of the octant-0 list, the class blocks (a, b) that survive its zero
+    axes, |a| x |b| products each (the Walsh-Hadamard adds not counted)."""
+    C = (p + 1) ** 2
+    size = [0] * 8
+    for i in range(C):
+        size[_sym_class(i)] += 1
+    macs = 0
+    for rep in itertools.product(range(4), repeat=3):
+        if max(rep) < 2:
+            continue
+        zmask = sum(1 << a for a in range(3) if rep[a] == 0)
+        macs += sum(size[a] * size[b] for a in range(8) for b in range(8) if not ((a ^ b) & zmask))
+    return 6.0 * macs
 
 
 def m2l_translations(level, periodic):
@@ -340,13 +367,22 @@ def main():
     p2p_flop = P2P_FLOP_PER_PAIR[args.precision] * pairs
     f32 = args.precision == "mixed"
     esz = 4 if f32 else 8
-    m2l_kernel = "k_m2l_os<4,8,false>" if (f32 and w.p in (9, 10)) else ("k_translate<double,1,1,0,24>"
-                                                                       if not f32 else "k_m2l_os")
-    m2l_traffic = measured_traffic(w.name, args.precision, m2l_kernel, m2l_launch)
+    # FP32 at p = 10: the orbit kernel from level 4 on (class-major pack of the
+    # multipoles first), dense operator-stationary MFMAs below
+    orbit = f32 and w.p == 10
+    lev0 = 1 if w.periodic else 2
+    if orbit:
+        m2l_kernel = "k_m2l_sym<10> (levels 4+) + k_m2l_os<4,8,false> (levels < 4) + k_sym_pack"
+        per_t = orbit_m2l_flop_per_target(w.p)
+        m2l_flop = sum(8 ** l * (per_t if l >= 4 else 6.0 * C * C * 189) for l in range(lev0, w.level + 1))
+    else:
+        m2l_kernel = "k_translate<double,1,1,0,24>" if not f32 else "k_m2l_os"
+    m2l_traffic = measured_traffic(w.name, args.precision, "k_m2l_sym<10>" if orbit else m2l_kernel, m2l_launch)
     # algorithmic bytes of the M2L phase: read M, read and write L at every level, the operators once
-    cells = sum(8 ** l for l in range(1 if w.periodic else 2, w.level + 1))
+    cells = sum(8 ** l for l in range(lev0, w.level + 1))
     m2l_alg_bytes = (cells * 3 * C * esz * 3 + 316 * C * C * esz) / m2l_launch
-    roof_m2l = {"bound": "mfma", "kernel": f"{m2l_kernel} (M2L, all levels)",
+    roof_m2l = {"bound": "mfma", "kernel": f"{m2l_kernel} (M2L phase, all levels)",
+                "flop_per_eval": m2l_flop,
                 "achieved": m2l_flop / m2l_launch / (m2l_ms / m2l_launch * 1e-3) / 1e12,
                 "peak": PEAKS["mfma_f32_tflops" if f32 else "mfma_f64_tflops"], "unit": "TFLOP/s",
                 "traffic": m2l_traffic, "traffic_unit": "bytes per launch",
@@ -672,29 +708,43 @@ def main():
         max_level = 8                 # leaves at least 4 sigma wide
         xa = torch.from_numpy(np.ascontiguousarray(xa_np.T)).to(dev)
         aa = torch.from_numpy(np.ascontiguousarray(aa_np.T)).to(dev)
-        # the uniform tree at its finest admissible level (leaves >= 4 sigma, no more
-        # leaves than particles); coarser levels put thousands of clustered particles
-        # in one leaf, whose near field one wave then runs alone for seconds
+        # the uniform tree at the finest level with no more leaves than particles
+        # (lv) and one finer (leaves still >= 4 sigma); coarser levels put thousands
+        # of clustered particles in one leaf, whose near field one wave then runs
+        # alone for seconds; the faster of the two is the uniform figure
         lv = 0
         while lv < 10 and w.box_len / 2 ** (lv + 1) >= 4 * sg and 8 ** (lv + 1) <= na:
             lv += 1
-        log(f"[bench] clustered {na}: uniform tree at level {lv}, tuning the adaptive leaf size")
+        levels = [lv] + ([lv + 1] if w.box_len / 2 ** (lv + 1) >= 4 * sg else [])
+        log(f"[bench] clustered {na}: uniform tree at levels {levels}, tuning the adaptive leaf size")
         nc, nms = ctx.tune_ncrit(xa, aa, sg, pa, max_level, periodic=0, box_len=w.box_len, reps=1)
         log(f"[bench] adaptive ncrit {nc}: " + ", ".join(f"{k}: {v:.1f} ms" for k, v in sorted(nms.items())))
         reps = 3
-        timings = {}
-        for name, fn in (("uniform", lambda: ctx.eval(xa, aa, sg, pa, lv, box_len=w.box_len, precision="fp64",
-                                                      want_grad=True)),
-                         ("adaptive", lambda: ctx.eval_adaptive(xa, aa, sg, pa, nc, max_level, box_len=w.box_len,
-                                                                want_grad=True))):
+
+        def timed(fn):
             out = fn()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
                 out = fn()
             torch.cuda.synchronize()
-            timings[name] = ((time.perf_counter() - t0) / reps, out)
-            log(f"[bench] clustered {name}: {1e3 * timings[name][0]:.1f} ms per evaluation")
+            return (time.perf_counter() - t0) / reps, out
+
+        uni = {}
+        for l in levels:
+            uni[l] = timed(lambda: ctx.eval(xa, aa, sg, pa, l, box_len=w.box_len, precision="fp64", want_grad=True))
+            log(f"[bench] clustered uniform level {l}: {1e3 * uni[l][0]:.1f} ms per evaluation")
+        lbest = min(uni, key=lambda l: uni[l][0])
+        timings = {"uniform": uni[lbest]}
+        timings["adaptive"] = timed(lambda: ctx.eval_adaptive(xa, aa, sg, pa, nc, max_level, box_len=w.box_len,
+                                                              want_grad=True))
+        log(f"[bench] clustered adaptive: {1e3 * timings['adaptive'][0]:.1f} ms per evaluation")
+        ctx.set_timing(True)
+        ctx.eval_adaptive(xa, aa, sg, pa, nc, max_level, box_len=w.box_len, want_grad=True)
+        torch.cuda.synchronize()
+        ad_phases = {k: v[0] for k, v in ctx.timing().items() if v[1]}
+        ctx.set_timing(False)
+        log("[bench] adaptive phases: " + ", ".join(f"{k} {v:.2f}" for k, v in ad_phases.items()) + " ms")
         cells = ctx.debug_adaptive("cells")
         lists = {k: int(len(ctx.debug_adaptive(k))) for k in ("p2p", "m2l", "m2p", "p2l")}
         tga = np.sort(np.random.default_rng(12).choice(na, 16, replace=False))
@@ -702,17 +752,20 @@ def main():
         result["adaptive"] = {
             "workload": f"{na} particles in 8 Gaussian clusters (std 1/64 .. 1/8 of the box) and a uniform tenth, "
                         f"free space, sigma = box/1024, p = {pa}, FP64, u + J + dalpha/dt",
-            "uniform": {"level": lv, "ms": 1e3 * timings["uniform"][0],
-                        "what": "finest level with leaves at least 4 sigma wide and no more leaves than particles"},
+            "uniform": {"level": lbest, "ms": 1e3 * timings["uniform"][0],
+                        "ms_per_level": {str(l): 1e3 * v[0] for l, v in uni.items()},
+                        "what": "the faster of the finest level with no more leaves than particles and one finer "
+                                "(leaves at least 4 sigma wide)"},
             "adaptive": {"ncrit": nc, "max_level": max_level, "ms": 1e3 * timings["adaptive"][0],
                          "tuning_ms_per_ncrit": {str(k): v for k, v in sorted(nms.items())},
                          "cells": int(len(cells)), "leaves": int(cells[:, 5].sum()),
-                         "deepest_leaf_level": int(cells[cells[:, 5] == 1, 1].max()), "lists": lists},
+                         "deepest_leaf_level": int(cells[cells[:, 5] == 1, 1].max()), "lists": lists,
+                         "phase_ms": ad_phases},
             "speedup_vs_uniform": timings["uniform"][0] / timings["adaptive"][0]}
-        log(f"[bench] clustered {na}: uniform level {lv} {1e3 * timings['uniform'][0]:.1f} ms, adaptive ncrit {nc} "
+        log(f"[bench] clustered {na}: uniform level {lbest} {1e3 * timings['uniform'][0]:.1f} ms, adaptive ncrit {nc} "
             f"{1e3 * timings['adaptive'][0]:.1f} ms ({len(cells)} cells)")
         pending_adaptive = (xa_np, aa_np, sg, tga, got_a)
-        del xa, aa, timings
+        del xa, aa, timings, uni
 
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

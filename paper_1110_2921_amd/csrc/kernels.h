@@ -361,14 +361,16 @@ constexpr int kSymMinLevel = 4;
 // Mc[cell][3][16 nblk] (FP32) from the standard-layout multipoles of `ncells`
 // cells (M[cell][3][kp]): mc_src[16 k + q] is the standard index held at
 // position q of block k (-1: zero).  Cell `ncells` of Mc is written as zeros.
-hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const float *M, const int16_t *mc_src,
-                           float *Mc);
+template <typename T>
+hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const T *M, const int16_t *mc_src, T *Mc);
 // Offset-range splits of an M2L launch of `level` with `ttn` targets per
 // workgroup (enough workgroups to fill the chip, within part_elems), and the
 // fixed-order sum of the splits' partials into dst (rows < C).
 int translate_splits(int level, int ttn, int kp, size_t part_elems);
 hipError_t launch_split_reduce(hipStream_t s, int level, int kp, int C, int nsplit, const float *part, float *dst,
                                int accumulate);
+hipError_t launch_split_reduce64(hipStream_t s, int level, int kp, int C, int nsplit, const double *part,
+                                 double *dst, int accumulate);
 // True if the symmetric M2L kernel is built for degree p.
 bool m2l_sym_supported(int p);
 // M2L at `level` (FP32): dst[cell] (+)= sum over the interaction list, from the
@@ -379,5 +381,12 @@ bool m2l_sym_supported(int p);
 hipError_t launch_m2l_sym(hipStream_t s, int level, int periodic, int p, int kp, const float *mc, int64_t zero_cell,
                           const float *ops, const int32_t *op_off, const int32_t *orbits, const int16_t *row_std,
                           float *dst, int accumulate, float *part, size_t part_elems);
+
+// FP64 form of launch_m2l_sym: class-major FP64 multipoles mc (zero_cell as
+// there), operators per octant stored per column slice, sl_off[8][56 nblk + 1]
+// the offsets (doubles) of the slices of orbit o, column b at o nblk + b.
+hipError_t launch_m2l_sym64(hipStream_t s, int level, int periodic, int p, int kp, const double *mc,
+                            int64_t zero_cell, const double *ops, const int32_t *sl_off, const int32_t *orbits,
+                            const int16_t *row_std, double *dst, int accumulate, double *part, size_t part_elems);
 
 }  // namespace vmfmm

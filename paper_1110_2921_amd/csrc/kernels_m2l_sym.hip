@@ -54,15 +54,16 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
     return v;
 }
 
-__global__ void __launch_bounds__(256) k_sym_pack(int64_t nelem, int kp, int kc, const float *__restrict__ M,
-                                                  const int16_t *__restrict__ mc_src, float *__restrict__ Mc) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_sym_pack(int64_t nelem, int kp, int kc, const T *__restrict__ M,
+                                                  const int16_t *__restrict__ mc_src, T *__restrict__ Mc) {
     const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (e >= nelem) return;
     const int q = int(e % kc);
     const int64_t cc = e / kc;   // cell * 3 + component
     const int src = mc_src[q];
     // the cell past the last one is the zero cell
-    Mc[e] = (src >= 0 && cc < nelem / kc - 3) ? M[cc * kp + src] : 0.0f;
+    Mc[e] = (src >= 0 && cc < nelem / kc - 3) ? M[cc * kp + src] : T(0);
 }
 
 constexpr int kSymWaves = 12;
@@ -160,20 +161,25 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
         for (int r = 0; r < 8; ++r)
             val[r] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, int(mo[r] + cb), 0, 0));
     };
-    // Walsh-Hadamard transform over the reflection slots: y[x] = sum_r chi_x(r) v[r].
-    // Absent slots hold zeros (the zero cell), so every stage is a plain
-    // butterfly: along an axis outside G it copies, (u + 0, u - 0).
-    auto wht = [&](f4 (&y)[8]) {
+    // Walsh-Hadamard transform over the reflection slots: y[x] = sum_r chi_x(r) v[r];
+    // along an axis outside G the partner slots are zero and the stage copies
+    auto wht = [&](f4 (&y)[8], int G) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int bit = 1 << a;
+            if (G & bit) {
 #pragma unroll
-            for (int r = 0; r < 8; ++r)
-                if (!(r & bit)) {
-                    const f4 u = y[r], v = y[r | bit];
-                    y[r] = u + v;
-                    y[r | bit] = u - v;
-                }
+                for (int r = 0; r < 8; ++r)
+                    if (!(r & bit)) {
+                        const f4 u = y[r], v = y[r | bit];
+                        y[r] = u + v;
+                        y[r | bit] = u - v;
+                    }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (!(r & bit)) y[r | bit] = y[r];
+            }
         }
     };
 
@@ -194,7 +200,7 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
         const int nn4 = more ? (soff[o + 2] - soff[o + 1]) / 4 : 0;
         const float *ogn = ops + (more ? soff[o + 1] : 0);
         const int info = sorb[o];
-        const int Z = (info >> 9) & 7;
+        const int G = (info >> 6) & 7, Z = (info >> 9) & 7;
         int off = 0;   // LDS offset of column block B of this orbit (floats)
         f4 stage;
         static_for<NB>([&](auto bi) {
@@ -214,10 +220,8 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
             f4 y[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) y[r] = val[r];
-            wht(y);
-            __builtin_amdgcn_sched_barrier(0);
+            wht(y, G);
             load_block(B + 1 < NB ? B + 1 : 0);
-            __builtin_amdgcn_sched_barrier(0);
             static_for<8>([&](auto xi) {
                 constexpr int X = decltype(xi)::value;
                 if (!(X & Z)) {
@@ -258,16 +262,235 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
     });
 }
 
+// FP64 form.  An orbit's operator (up to 139 KB) does not fit twice in LDS,
+// so it streams through a ring of kRing column slices (slice (o, B): the class
+// blocks of column B), one barrier per slice: while slice k is multiplied, the
+// workgroup copies slice k + kRing - 1 into the slot slice k - 1 left.  Each k
+// block runs as two halves of two k steps (a lane's 16-byte half quad per
+// member), transformed in place; a half's sources for the next step are loaded
+// right after its MFMAs.  Blocks are stored as [half][lane group][row][2].
+constexpr int kRing = 8;
+
+template <int P>
+__global__ void __launch_bounds__(kSymThreads) k_m2l_sym64(int level, int periodic, int kp,
+                                                           const double *__restrict__ mc, uint32_t zero_off,
+                                                           const double *__restrict__ ops,
+                                                           const int32_t *__restrict__ sl_off,
+                                                           const int32_t *__restrict__ orbits,
+                                                           const int16_t *__restrict__ row_std,
+                                                           double *__restrict__ dst, int accumulate, int nsplit,
+                                                           double *__restrict__ part) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr SymLayout SL = sym_layout(P);
+    constexpr int NB = SL.nblk, KC = 16 * NB, CELL = 3 * KC;
+    static_assert(NB > 0, "degree without a class layout");
+    constexpr int NT = kSymThreads, TT = kSymTargets;
+    constexpr int SLICE = 16 * SL.C;           // doubles of the largest slice (every class block)
+    constexpr int SLOT = SLICE + 32;           // + slack for the row over-reads of short blocks
+    constexpr int NSL = kSymOrbits * NB + 1;   // slice offsets per octant
+    static_assert(SLICE <= 4 * NT, "a slice is copied in two 16-byte chunks per thread");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *ring = reinterpret_cast<double *>(smem_raw);   // [kRing][SLOT]
+    __shared__ int32_t sorb[kSymOrbits];
+    __shared__ int32_t ssl[NSL];
+    __shared__ int16_t srow[KC];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int comp = wave % 3, tg = wave / 3;
+    const int h = lane >> 4, col = lane & 15;
+    const int octant = blockIdx.x & 7, tile = blockIdx.x >> 3;
+    const int o0 = int(blockIdx.y) * kSymOrbits / nsplit;
+    const int o1 = (int(blockIdx.y) + 1) * kSymOrbits / nsplit;
+    const int nk = (o1 - o0) * NB;
+    const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
+    const int side = 1 << level;
+
+    if (tid < kSymOrbits) sorb[tid] = orbits[tid];
+    for (int i = tid; i < NSL; i += NT) ssl[i] = sl_off[octant * NSL + i];
+    for (int i = tid; i < KC; i += NT) srow[i] = row_std[i];
+    for (int i = tid; i < kRing * 32; i += NT) ring[(i / 32) * SLOT + SLICE + i % 32] = 0.0;
+    __syncthreads();
+    // the first kRing - 1 slices
+    for (int k = 0; k < kRing - 1 && k < nk; ++k) {
+        const int g0 = ssl[o0 * NB + k], n2 = (ssl[o0 * NB + k + 1] - g0) / 2;
+        for (int q = tid; q < n2; q += NT)
+            *reinterpret_cast<d2 *>(ring + k * SLOT + 2 * q) = *reinterpret_cast<const d2 *>(ops + g0 + 2 * q);
+    }
+    const int64_t slot = int64_t(tile) * TT + tg * 16 + col;
+    const bool tvalid = slot < ncell_t;
+    const uint32_t tkey = tvalid ? uint32_t((slot << 3) | octant) : 0u;
+    const int tc[3] = {int(compact3(tkey)), int(compact3(tkey >> 1)), int(compact3(tkey >> 2))};
+    __syncthreads();
+
+    uint32_t mo[8];   // byte offsets of the member sources (+ the lane group's quad)
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(mc), 0, -1, 0x00020000);
+    auto members = [&](int o) {
+        const int info = sorb[o];
+        const int G = (info >> 6) & 7;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (r & ~G) {
+                mo[r] = zero_off * 8u + uint32_t(32 * h);
+                continue;
+            }
+            bool ok = tvalid;
+            uint32_t key = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int rep = (info >> (2 * a)) & 3;
+                int d = ((r >> a) & 1) ? -rep : rep;
+                if ((octant >> a) & 1) d = -d;
+                int c = tc[a] + d;
+                if (periodic) c &= side - 1;
+                else ok = ok && c >= 0 && c < side;
+                key |= spread3(uint32_t(c)) << a;
+            }
+            mo[r] = (ok ? key * uint32_t(CELL) : zero_off) * 8u + uint32_t(32 * h);
+        }
+    };
+    d2 val[8];   // the lane's half quad of every member for the current step
+    auto load_half = [&](int b, int half) {
+        const uint32_t cb = uint32_t((comp * KC + 16 * b + 2 * half) * 8);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            val[r] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rsrc, int(mo[r] + cb), 0, 0));
+    };
+    auto wht = [&](int G) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int bit = 1 << a;
+            if (G & bit) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (!(r & bit)) {
+                        const d2 u = val[r], v = val[r | bit];
+                        val[r] = u + v;
+                        val[r | bit] = u - v;
+                    }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (!(r & bit)) val[r | bit] = val[r];
+            }
+        }
+    };
+
+    d4 acc[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+
+    if (o0 < o1) {
+        members(o0);
+        load_half(0, 0);
+    }
+    for (int o = o0; o < o1; ++o) {
+        const bool more = o + 1 < o1;
+        const int info = sorb[o];
+        const int G = (info >> 6) & 7, Z = (info >> 9) & 7;
+        static_for<NB>([&](auto bi) {
+            constexpr int B = decltype(bi)::value;
+            constexpr int HALVES = SL.bsteps[B] > 2 ? 2 : 1;
+            const int k = (o - o0) * NB + B;
+            // slice k + kRing - 1 in (16-byte chunks q = tid, tid + NT)
+            const int kc = k + kRing - 1;
+            const bool has = kc < nk;
+            const int g0 = has ? ssl[o0 * NB + kc] : 0;
+            const int n2 = has ? (ssl[o0 * NB + kc + 1] - g0) / 2 : 0;
+            const d2 st0 = *reinterpret_cast<const d2 *>(ops + g0 + 2 * (tid < n2 ? tid : 0));
+            const d2 st1 = *reinterpret_cast<const d2 *>(ops + g0 + 2 * (tid + NT < n2 ? tid + NT : 0));
+            const double *sl = ring + (k % kRing) * SLOT;
+            static_for<HALVES>([&](auto hi) {
+                constexpr int HALF = decltype(hi)::value;
+                wht(G);
+                int boff = 0;
+                static_for<8>([&](auto xi) {
+                    constexpr int X = decltype(xi)::value;
+                    if (!(X & Z)) {
+                        static_for<NB>([&](auto ai) {
+                            constexpr int A = decltype(ai)::value;
+                            if constexpr (SL.bcls[A] == (SL.bcls[B] ^ X)) {
+                                const d2 aq = *reinterpret_cast<const d2 *>(
+                                    sl + boff + 2 * ((HALF * 4 + h) * SL.bnv[A] + col));
+                                boff += 16 * SL.bnv[A];
+                                static_for<2>([&](auto si) {
+                                    constexpr int S = decltype(si)::value;
+                                    if constexpr (2 * HALF + S < SL.bsteps[B])
+                                        acc[A] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq[S], val[X][S], acc[A], 0,
+                                                                                      0, 0);
+                                });
+                            }
+                        });
+                    }
+                });
+                // the sources of the next step: this block's second half, the next
+                // block's first, or the next orbit's first
+                if constexpr (HALF + 1 < HALVES) {
+                    load_half(B, HALF + 1);
+                } else if constexpr (B + 1 < NB) {
+                    load_half(B + 1, 0);
+                } else {
+                    members(more ? o + 1 : o);
+                    load_half(0, 0);
+                }
+            });
+            double *dsl = ring + (kc % kRing) * SLOT;
+            if (tid < n2) *reinterpret_cast<d2 *>(dsl + 2 * tid) = st0;
+            if (tid + NT < n2) *reinterpret_cast<d2 *>(dsl + 2 * (tid + NT)) = st1;
+            __syncthreads();
+        });
+    }
+    if (!tvalid) return;
+    const bool split = part != nullptr;
+    double *out = (split ? part + (size_t(blockIdx.y) * (size_t(1) << (3 * level)) + tkey) * 3 * kp
+                         : dst + size_t(tkey) * 3 * kp) + comp * kp;
+    static_for<NB>([&](auto ai) {
+        constexpr int A = decltype(ai)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = h + 4 * r;   // the FP64 MFMA's output row of lane group h, element r
+            if (e < SL.bnv[A]) {
+                double *o = out + srow[16 * A + e];
+                *o = (accumulate && !split) ? *o + acc[A][r] : acc[A][r];
+            }
+        }
+    });
+}
+
 }  // namespace
 
 bool m2l_sym_supported(int p) { return p == 10; }
 
-hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const float *M, const int16_t *mc_src,
-                           float *Mc) {
+template <typename T>
+hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const T *M, const int16_t *mc_src, T *Mc) {
     const int64_t nelem = (ncells + 1) * 3 * kc;
-    hipLaunchKernelGGL(k_sym_pack, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, nelem, kp, kc, M, mc_src,
-                       Mc);
+    hipLaunchKernelGGL(k_sym_pack<T>, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, nelem, kp, kc, M,
+                       mc_src, Mc);
     return hipGetLastError();
+}
+template hipError_t launch_sym_pack<float>(hipStream_t, int64_t, int, int, const float *, const int16_t *, float *);
+template hipError_t launch_sym_pack<double>(hipStream_t, int64_t, int, int, const double *, const int16_t *,
+                                            double *);
+
+hipError_t launch_m2l_sym64(hipStream_t s, int level, int periodic, int p, int kp, const double *mc,
+                            int64_t zero_cell, const double *ops, const int32_t *sl_off, const int32_t *orbits,
+                            const int16_t *row_std, double *dst, int accumulate, double *part, size_t part_elems) {
+    if (!m2l_sym_supported(p) || level < 1) return hipErrorInvalidValue;
+    constexpr SymLayout SL = sym_layout(10);
+    constexpr int KC = 16 * SL.nblk;
+    if (uint64_t(zero_cell) * 3 * KC * 8 >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
+    const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
+    const size_t smem = sizeof(double) * size_t(kRing) * size_t(16 * SL.C + 32);
+    int nsplit = part ? translate_splits(level, kSymTargets, kp, part_elems) : 1;
+    if (nsplit > kSymOrbits) nsplit = kSymOrbits;
+    double *pbuf = nsplit > 1 ? part : nullptr;
+    const dim3 grid(unsigned((ncell_t + kSymTargets - 1) / kSymTargets * 8), unsigned(nsplit));
+    hipLaunchKernelGGL(k_m2l_sym64<10>, grid, dim3(kSymThreads), smem, s, level, periodic, kp, mc,
+                       uint32_t(zero_cell * 3 * KC), ops, sl_off, orbits, row_std, dst, accumulate, nsplit, pbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsplit == 1) return e;
+    return launch_split_reduce64(s, level, kp, SL.C, nsplit, pbuf, dst, accumulate);
 }
 
 hipError_t launch_m2l_sym(hipStream_t s, int level, int periodic, int p, int kp, const float *mc, int64_t zero_cell,

@@ -94,7 +94,7 @@ struct OpSet {
     DevBuf m2lt64, m2lt32, m2lTt64, m2lTt32;
     // reflection-orbit M2L (FP32, square truncation; built on first use)
     bool sym_ready = false;
-    DevBuf sym_ops, sym_off, sym_orb, sym_mcsrc, sym_row;
+    DevBuf sym_ops, sym_off, sym_orb, sym_mcsrc, sym_row, sym_ops64, sym_sl64;
 };
 
 // Zeroes the entries of a C x C operator that pair target degree n (row) with
@@ -117,7 +117,7 @@ struct vm_ctx {
     DevBuf keys_a, keys_b, vals_a, vals_b, hist, start, p64, p32, far, flag, mbuf, lbuf;
     DevBuf trpart;   // partial sums of M2L launches split over the offsets (coarse levels)
     DevBuf zeros;    // a zero expansion cell read in place of missing M2L sources
-    DevBuf mcbuf;    // class-major FP32 multipoles of every level for the reflection-orbit M2L
+    DevBuf mcbuf;    // class-major multipoles of every level for the reflection-orbit M2L
     DevBuf rk_u, rk_s, rk_x, rk_a, diag;
     DevBuf adj_u, adj_J, adj_v, adj_Jv, adj_far, adj_p64, adj_p32;
     DevBuf rbf_b, rbf_x, rbf_V, rbf_part, rbf_dots;   // RBF solve: right side, iterate, Krylov basis, reductions
@@ -470,8 +470,11 @@ vm_status ensure_sym_ops(vm_ctx *ctx, OpSet *set) {
             }
     if (int(orb.size()) != kSymOrbits) return VM_EINVAL;
     auto chi = [](int c, int refl) { return (__builtin_popcount(unsigned(c & refl)) & 1) ? -1.0 : 1.0; };
+    // FP32: per block [lane group][row][k step]; FP64: [half][lane group][row][2 k steps],
+    // with the offsets of every column slice (orbit o, column b at o NB + b)
     std::vector<float> ops;
-    std::vector<int32_t> off(8 * (kSymOrbits + 1));
+    std::vector<double> ops64;
+    std::vector<int32_t> off(8 * (kSymOrbits + 1)), sl(8 * (kSymOrbits * NB + 1));
     std::vector<double> T(size_t(C) * C);
     for (int o = 0; o < 8; ++o)
         for (int j = 0; j < kSymOrbits; ++j) {
@@ -480,24 +483,35 @@ vm_status ensure_sym_ops(vm_ctx *ctx, OpSet *set) {
             const double D[3] = {-double(reps[j][0]), -double(reps[j][1]), -double(reps[j][2])};
             m2l_matrix(p, D, 1.0, 1.0, T.data());
             const int Z = (orb[j] >> 9) & 7;
-            for (int b = 0; b < NB; ++b)
+            for (int b = 0; b < NB; ++b) {
+                sl[o * (kSymOrbits * NB + 1) + j * NB + b] = int32_t(ops64.size());
                 for (int x = 0; x < 8; ++x) {
                     if (x & Z) continue;
                     for (int a = 0; a < NB; ++a) {
                         if (SL.bcls[a] != (SL.bcls[b] ^ x)) continue;
                         const double sg = chi(SL.bcls[a], o) * chi(SL.bcls[b], o);
+                        auto val = [&](int e, int h, int st) {
+                            const int cidx = mc_src[16 * b + 4 * h + st];
+                            return cidx >= 0 ? sg * T[size_t(row_std[16 * a + e]) * C + cidx] : 0.0;
+                        };
                         for (int h = 0; h < 4; ++h)
                             for (int e = 0; e < SL.bnv[a]; ++e)
-                                for (int st = 0; st < 4; ++st) {
-                                    const int cidx = mc_src[16 * b + 4 * h + st];
-                                    const double v = cidx >= 0 ? sg * T[size_t(row_std[16 * a + e]) * C + cidx] : 0.0;
-                                    ops.push_back(float(v));
-                                }
+                                for (int st = 0; st < 4; ++st) ops.push_back(float(val(e, h, st)));
+                        for (int half = 0; half < 2; ++half)
+                            for (int h = 0; h < 4; ++h)
+                                for (int e = 0; e < SL.bnv[a]; ++e)
+                                    for (int st = 0; st < 2; ++st) ops64.push_back(val(e, h, 2 * half + st));
                     }
                 }
+            }
         }
-    for (int o = 0; o < 8; ++o) off[o * (kSymOrbits + 1) + kSymOrbits] = int32_t(ops.size());
+    for (int o = 0; o < 8; ++o) {
+        off[o * (kSymOrbits + 1) + kSymOrbits] = int32_t(ops.size());
+        sl[o * (kSymOrbits * NB + 1) + kSymOrbits * NB] = int32_t(ops64.size());
+    }
     VM_HIP(upload(set->sym_ops, ops), "upload symmetric M2L");
+    VM_HIP(upload(set->sym_ops64, ops64), "upload symmetric M2L");
+    VM_HIP(upload(set->sym_sl64, sl), "upload symmetric M2L");
     VM_HIP(upload(set->sym_off, off), "upload symmetric M2L");
     VM_HIP(upload(set->sym_orb, orb), "upload symmetric M2L");
     VM_HIP(upload(set->sym_mcsrc, mc_src), "upload symmetric M2L");
@@ -810,9 +824,11 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     if (vm_status st = ensure_ops(ctx, p, &ops); st != VM_OK) return st;
     if (opts->truncation == VM_TRIANGULAR)
         if (vm_status st = ensure_tri_ops(ctx, ops, 0); st != VM_OK) return st;
-    // FP32 square-truncation M2L by reflection orbits where its kernel is built
-    // (its source offsets are 32-bit: levels up to 7)
-    const bool use_sym = mixed && opts->truncation != VM_TRIANGULAR && m2l_sym_supported(p) && level <= 7;
+    // square-truncation M2L by reflection orbits where its kernel is built (from
+    // level kSymMinLevel on; its source offsets are 32-bit byte offsets: levels
+    // up to 7 in FP32, 6 in FP64)
+    const bool use_sym = opts->truncation != VM_TRIANGULAR && m2l_sym_supported(p) && level >= kSymMinLevel &&
+                         level <= (mixed ? 7 : 6);
     if (use_sym)
         if (vm_status st = ensure_sym_ops(ctx, ops); st != VM_OK) return st;
     const double *tlat = nullptr;
@@ -841,7 +857,7 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     }
 
     if (use_sym)
-        VM_HIP(ctx->mcbuf.reserve(sizeof(float) * size_t(ncells + 1) * 3 * (16 * sym_layout(p).nblk)),
+        VM_HIP(ctx->mcbuf.reserve(esz * size_t(ncells + 1) * 3 * (16 * sym_layout(p).nblk)),
                "alloc class-major multipoles");
 
     // --- tree ------------------------------------------------------------
@@ -904,13 +920,12 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                 VM_HIP(launch_translate<T>(s, 2, l, periodic, p, kp, m2m, lists, offs, lev(M, l + 1), lev(M, l), 0),
                        "M2M");
             }
-            const bool sym = f32 && use_sym;
+            const bool sym = use_sym;
             const int kc = 16 * sym_layout(p).nblk;
-            float *mc = ctx->mcbuf.as<float>();
+            T *mc = ctx->mcbuf.as<T>();
             if (sym) {
                 Timed tm(ctx, VM_PH_M2L);
-                VM_HIP(launch_sym_pack(s, ncells, kp, kc, reinterpret_cast<const float *>(M),
-                                       ops->sym_mcsrc.as<int16_t>(), mc),
+                VM_HIP(launch_sym_pack<T>(s, ncells, kp, kc, M, ops->sym_mcsrc.as<int16_t>(), mc),
                        "M2L class-major multipoles");
             }
             bool have_parent = false;   // L at level l-1 holds something
@@ -930,12 +945,20 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                 // levels run the dense operators
                 if (sym && l >= kSymMinLevel) {
                     const int64_t base = ((int64_t(1) << (3 * l)) - 1) / 7;
-                    VM_HIP(launch_m2l_sym(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
-                                          ops->sym_ops.as<float>(), ops->sym_off.as<int32_t>(),
-                                          ops->sym_orb.as<int32_t>(), ops->sym_row.as<int16_t>(),
-                                          reinterpret_cast<float *>(lev(L, l)), have_parent ? 1 : 0,
-                                          ctx->trpart.as<float>(), ctx->trpart.bytes / sizeof(float)),
-                           "M2L");
+                    if constexpr (sizeof(T) == 4)
+                        VM_HIP(launch_m2l_sym(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
+                                              ops->sym_ops.as<float>(), ops->sym_off.as<int32_t>(),
+                                              ops->sym_orb.as<int32_t>(), ops->sym_row.as<int16_t>(), lev(L, l),
+                                              have_parent ? 1 : 0, ctx->trpart.as<float>(),
+                                              ctx->trpart.bytes / sizeof(float)),
+                               "M2L");
+                    else
+                        VM_HIP(launch_m2l_sym64(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
+                                                ops->sym_ops64.as<double>(), ops->sym_sl64.as<int32_t>(),
+                                                ops->sym_orb.as<int32_t>(), ops->sym_row.as<int16_t>(), lev(L, l),
+                                                have_parent ? 1 : 0, ctx->trpart.as<double>(),
+                                                ctx->trpart.bytes / sizeof(double)),
+                               "M2L");
                 } else {
                     VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2l, lists, offs, lev(M, l), lev(L, l),
                                                have_parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),

@@ -335,13 +335,15 @@ def test_degrees_inside_the_operator_stationary_shapes(ctx, p):
 
 @pytest.mark.parametrize("level,K", [(2, 3), (4, 3), (4, 0), (5, 1), (5, 0)])
 def test_reflection_orbit_m2l(ctx, level, K):
-    """p = 10 mixed runs the M2L of levels >= 4 by reflection orbits (one
-    operator per orbit of the interaction list applied to the Walsh-Hadamard-
-    combined sources, per-octant signs, class-blocked MFMAs; level 4 split
-    over orbit ranges, level 5 whole).  Against FP64 (dense operators, itself
-    pinned to the oracle) at 1e-5 / 4e-5 (u) and 1e-4 / 4e-4 (J): free space
-    (missing sources beyond the domain) and periodic with and without the
-    lattice; at level 2 (dense FP32 operators) FP64 is also held to the oracle."""
+    """p = 10 runs the M2L of levels >= 4 by reflection orbits (one operator
+    per orbit of the interaction list applied to the Walsh-Hadamard-combined
+    sources, per-octant signs, class-blocked MFMAs; FP32 with the whole orbit
+    operator double-buffered in LDS, FP64 through a ring of column slices;
+    level 4 split over orbit ranges, level 5 whole).  FP64 against the oracle
+    at 24 sampled particles (oracle.fmm.fmm_at) at 1e-10; mixed against FP64
+    at 1e-5 / 4e-5 (u) and 1e-4 / 4e-4 (J); free space (missing sources
+    beyond the domain) and periodic with and without the lattice.  Level 2
+    (dense operators) is held to the whole oracle FMM."""
     ng = {2: 8, 4: 24, 5: 40}[level]
     x, a = W.random_field(ng, 4.0, 300 + 10 * level + K)
     h = L / ng
@@ -354,3 +356,8 @@ def test_reflection_orbit_m2l(ctx, level, K):
         uo, Jo = OF.fmm(x, a, h, 10, level, periodic=K)
         close(u, uo, FP64, "u vs uo")
         close(J, Jo, FP64, "J vs Jo")
+    else:
+        t = np.sort(np.random.default_rng(level + K).choice(len(x), 24, replace=False))
+        uo, Jo = OF.fmm_at(x, a, h, 10, level, t, periodic=K)
+        close(u[t], uo, FP64, "u vs oracle (sampled)")
+        close(J[t], Jo, FP64, "J vs oracle (sampled)")
