@@ -456,7 +456,29 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const i
             for (int r = 0; r < kM2PMaxRow; ++r) {
                 if (r >= nrow) break;
                 double s0v = 0.0, s1v = 0.0, s2v = 0.0;
-                for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+                const int k1 = rowptr[r + 1];
+                int k = rowptr[r];
+                // eight terms at a time: their table entries (wave-uniform) and
+                // LDS reads are all issued before the first product
+                for (; k + 8 <= k1; k += 8) {
+                    int cc[8], hh[8];
+                    double ww[8], hv[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        cc[j] = col[k + j];
+                        hh[j] = harm[k + j];
+                        ww[j] = wt[k + j];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) hv[j] = ww[j] * hs[hh[j] * 64 + lane];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        s0v += hv[j] * mb[cc[j]];
+                        s1v += hv[j] * mb[kp + cc[j]];
+                        s2v += hv[j] * mb[2 * kp + cc[j]];
+                    }
+                }
+                for (; k < k1; ++k) {
                     const double hv = wt[k] * hs[harm[k] * 64 + lane];
                     const int c = col[k];
                     s0v += hv * mb[c];
