@@ -92,9 +92,15 @@ struct OpSet {
     // M2L operators truncated to n + n' <= p, and their transposes (built on first use)
     bool tri_ready = false, tri_adj_ready = false;
     DevBuf m2lt64, m2lt32, m2lTt64, m2lTt32;
-    // reflection-orbit M2L (FP32, square truncation; built on first use)
+    // reflection-orbit M2L (square truncation; built on first use): class maps and
+    // orbits, and the operators of the forward gather and of the adjoint one
+    struct SymOps {
+        bool ready = false;
+        DevBuf ops, off, ops64, sl64;
+    };
     bool sym_ready = false;
-    DevBuf sym_ops, sym_off, sym_orb, sym_mcsrc, sym_row, sym_ops64, sym_sl64;
+    DevBuf sym_orb, sym_mcsrc, sym_row;
+    SymOps sym[2];
 };
 
 // Zeroes the entries of a C x C operator that pair target degree n (row) with
@@ -438,8 +444,11 @@ vm_status ensure_tri_ops(vm_ctx *ctx, OpSet *set, int adjoint) {
 // the kernel consumes them (column block b, then class offset x, then the row
 // blocks of class bcls[b] ^ x), each block as 4 lane groups x its valid rows x
 // 4 k steps.
-vm_status ensure_sym_ops(vm_ctx *ctx, OpSet *set) {
-    if (set->sym_ready) return VM_OK;
+// adjoint 0: the forward gather, operator T_d for offset d (source - target);
+// adjoint 1: the adjoint gather, T_{-d}^T, which has the same reflection
+// structure (the transpose of P T P is P T^T P).
+vm_status ensure_sym_ops(vm_ctx *ctx, OpSet *set, int adjoint) {
+    if (set->sym[adjoint].ready) return VM_OK;
     const int p = set->p, C = ncoef(p);
     const SymLayout SL = sym_layout(p);
     if (SL.nblk == 0) return VM_EINVAL;
@@ -479,9 +488,14 @@ vm_status ensure_sym_ops(vm_ctx *ctx, OpSet *set) {
     for (int o = 0; o < 8; ++o)
         for (int j = 0; j < kSymOrbits; ++j) {
             off[o * (kSymOrbits + 1) + j] = int32_t(ops.size());
-            // operator of the representative offset d (source - target): D = target - source
-            const double D[3] = {-double(reps[j][0]), -double(reps[j][1]), -double(reps[j][2])};
+            // operator of the representative offset d (source - target): D = target - source;
+            // the adjoint gather takes the transpose of the operator of -d
+            const double sd = adjoint ? 1.0 : -1.0;
+            const double D[3] = {sd * reps[j][0], sd * reps[j][1], sd * reps[j][2]};
             m2l_matrix(p, D, 1.0, 1.0, T.data());
+            if (adjoint)
+                for (int r = 0; r < C; ++r)
+                    for (int c = r + 1; c < C; ++c) std::swap(T[size_t(r) * C + c], T[size_t(c) * C + r]);
             const int Z = (orb[j] >> 9) & 7;
             for (int b = 0; b < NB; ++b) {
                 sl[o * (kSymOrbits * NB + 1) + j * NB + b] = int32_t(ops64.size());
@@ -509,14 +523,18 @@ vm_status ensure_sym_ops(vm_ctx *ctx, OpSet *set) {
         off[o * (kSymOrbits + 1) + kSymOrbits] = int32_t(ops.size());
         sl[o * (kSymOrbits * NB + 1) + kSymOrbits * NB] = int32_t(ops64.size());
     }
-    VM_HIP(upload(set->sym_ops, ops), "upload symmetric M2L");
-    VM_HIP(upload(set->sym_ops64, ops64), "upload symmetric M2L");
-    VM_HIP(upload(set->sym_sl64, sl), "upload symmetric M2L");
-    VM_HIP(upload(set->sym_off, off), "upload symmetric M2L");
-    VM_HIP(upload(set->sym_orb, orb), "upload symmetric M2L");
-    VM_HIP(upload(set->sym_mcsrc, mc_src), "upload symmetric M2L");
-    VM_HIP(upload(set->sym_row, row_std), "upload symmetric M2L");
-    set->sym_ready = true;
+    OpSet::SymOps &so = set->sym[adjoint];
+    VM_HIP(upload(so.ops, ops), "upload symmetric M2L");
+    VM_HIP(upload(so.ops64, ops64), "upload symmetric M2L");
+    VM_HIP(upload(so.sl64, sl), "upload symmetric M2L");
+    VM_HIP(upload(so.off, off), "upload symmetric M2L");
+    if (!set->sym_ready) {
+        VM_HIP(upload(set->sym_orb, orb), "upload symmetric M2L");
+        VM_HIP(upload(set->sym_mcsrc, mc_src), "upload symmetric M2L");
+        VM_HIP(upload(set->sym_row, row_std), "upload symmetric M2L");
+        set->sym_ready = true;
+    }
+    so.ready = true;
     return VM_OK;
 }
 
@@ -830,7 +848,7 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     const bool use_sym = opts->truncation != VM_TRIANGULAR && m2l_sym_supported(p) && level >= kSymMinLevel &&
                          level <= (mixed ? 7 : 6);
     if (use_sym)
-        if (vm_status st = ensure_sym_ops(ctx, ops); st != VM_OK) return st;
+        if (vm_status st = ensure_sym_ops(ctx, ops, 0); st != VM_OK) return st;
     const double *tlat = nullptr;
     if (K >= 2)
         if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
@@ -947,14 +965,14 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                     const int64_t base = ((int64_t(1) << (3 * l)) - 1) / 7;
                     if constexpr (sizeof(T) == 4)
                         VM_HIP(launch_m2l_sym(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
-                                              ops->sym_ops.as<float>(), ops->sym_off.as<int32_t>(),
+                                              ops->sym[0].ops.as<float>(), ops->sym[0].off.as<int32_t>(),
                                               ops->sym_orb.as<int32_t>(), ops->sym_row.as<int16_t>(), lev(L, l),
                                               have_parent ? 1 : 0, ctx->trpart.as<float>(),
                                               ctx->trpart.bytes / sizeof(float)),
                                "M2L");
                     else
                         VM_HIP(launch_m2l_sym64(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
-                                                ops->sym_ops64.as<double>(), ops->sym_sl64.as<int32_t>(),
+                                                ops->sym[0].ops64.as<double>(), ops->sym[0].sl64.as<int32_t>(),
                                                 ops->sym_orb.as<int32_t>(), ops->sym_row.as<int16_t>(), lev(L, l),
                                                 have_parent ? 1 : 0, ctx->trpart.as<double>(),
                                                 ctx->trpart.bytes / sizeof(double)),
@@ -1497,6 +1515,16 @@ vm_status adjoint_impl(vm_ctx *ctx, int64_t n, const double *x, const double *al
     const double *tlat_t = nullptr;
     if (K >= 2)
         if (vm_status e = ensure_lattice_t(ctx, p, K, &tlat_t); e != VM_OK) return e;
+    // the adjoint M2L by reflection orbits where the forward one runs so
+    const bool use_sym = opts->truncation != VM_TRIANGULAR && m2l_sym_supported(p) && level >= kSymMinLevel &&
+                         level <= (mixed ? 7 : 6);
+    const int64_t ncells = ((int64_t(1) << (3 * (level + 1))) - 1) / 7;
+    if (use_sym) {
+        if (vm_status e = ensure_sym_ops(ctx, ops, 1); e != VM_OK) return e;
+        VM_HIP(ctx->mcbuf.reserve((mixed ? sizeof(float) : sizeof(double)) * size_t(ncells + 1) * 3 *
+                                  (16 * sym_layout(p).nblk)),
+               "alloc class-major multipoles");
+    }
     VM_HIP(ctx->adj_v.reserve(v3), "alloc adjoint");
     VM_HIP(ctx->adj_Jv.reserve(v9), "alloc adjoint");
     VM_HIP(ctx->adj_far.reserve(2 * v3), "alloc adjoint");
@@ -1545,15 +1573,39 @@ vm_status adjoint_impl(vm_ctx *ctx, int64_t n, const double *x, const double *al
                 VM_HIP(launch_lattice<T>(s, p, kp, tlat_t, lev(Lb, 0), lev(Mb, 0)), "lattice^T");
                 parent = true;
             }
+            // the local adjoints of every level are final here: class-major copy for the orbit kernel
+            const int kc = 16 * sym_layout(p).nblk;
+            T *mc = ctx->mcbuf.as<T>();
+            if (use_sym)
+                VM_HIP(launch_sym_pack<T>(s, ncells, kp, kc, Lb, ops->sym_mcsrc.as<int16_t>(), mc),
+                       "M2L^T class-major local adjoints");
             for (int l = periodic ? 1 : lmin; l <= level; ++l) {
                 if (parent)
                     VM_HIP(launch_translate<T>(s, 1, l, periodic, p, kp, m2mT, lists, offs, lev(Mb, l - 1),
                                                lev(Mb, l), 0),
                            "M2M^T");
-                VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2lT, lists, offs, lev(Lb, l), lev(Mb, l),
-                                           parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
-                                           ctx->zeros.as<T>(), tri),
-                       "M2L^T");
+                if (use_sym && l >= kSymMinLevel) {
+                    const int64_t base = ((int64_t(1) << (3 * l)) - 1) / 7;
+                    if constexpr (sizeof(T) == 4)
+                        VM_HIP(launch_m2l_sym(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
+                                              ops->sym[1].ops.as<float>(), ops->sym[1].off.as<int32_t>(),
+                                              ops->sym_orb.as<int32_t>(), ops->sym_row.as<int16_t>(), lev(Mb, l),
+                                              parent ? 1 : 0, ctx->trpart.as<float>(),
+                                              ctx->trpart.bytes / sizeof(float)),
+                               "M2L^T");
+                    else
+                        VM_HIP(launch_m2l_sym64(s, l, periodic, p, kp, mc + size_t(base) * 3 * kc, ncells - base,
+                                                ops->sym[1].ops64.as<double>(), ops->sym[1].sl64.as<int32_t>(),
+                                                ops->sym_orb.as<int32_t>(), ops->sym_row.as<int16_t>(), lev(Mb, l),
+                                                parent ? 1 : 0, ctx->trpart.as<double>(),
+                                                ctx->trpart.bytes / sizeof(double)),
+                               "M2L^T");
+                } else {
+                    VM_HIP(launch_translate<T>(s, 0, l, periodic, p, kp, m2lT, lists, offs, lev(Lb, l), lev(Mb, l),
+                                               parent ? 1 : 0, ctx->trpart.as<T>(), ctx->trpart.bytes / sizeof(T),
+                                               ctx->zeros.as<T>(), tri),
+                           "M2L^T");
+                }
                 parent = true;
             }
             VM_HIP(launch_p2m_adj<T>(s, int(nleaf), ni, parts, start, p, kp, inv_w, tab, ops->g_idx.as<int32_t>(), gw,

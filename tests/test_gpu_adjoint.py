@@ -319,3 +319,25 @@ def test_velocity_rejects_output_keywords(ctx):
     x, a, h = _case()
     with pytest.raises(TypeError):
         vm.velocity(_dev(x), _dev(a), ctx, h, CASE["p"], CASE["level"], want_grad=True)
+
+
+@pytest.mark.parametrize("precision,K", [("fp64", 3), ("fp64", 0), ("mixed", 3), ("mixed", 0)])
+def test_orbit_m2l_adjoint_is_the_transpose(ctx, precision, K):
+    """p = 10 at level 4: the forward and the adjoint M2L both run by reflection
+    orbits (the adjoint with the transposed operators of the negated offsets),
+    so the alpha-adjoint satisfies <u_bar, u(alpha)> = <alpha_bar(u_bar), alpha>
+    to round-off (FP64: 1e-12, mixed: 1e-5 of sum |u_bar u|), periodic and free."""
+    import torch
+    x, a = W.random_field(24, 4.0, 77 + K)
+    h = L / 24
+    rng = np.random.default_rng(5 + K)
+    ubar = rng.standard_normal(x.shape)
+    u, _, _ = ctx.eval(_dev(x), _dev(a), h, 10, 4, periodic=K, precision=precision, want_dalpha=False)
+    torch.cuda.synchronize()
+    u = _host(u)
+    _, ab = ctx.adjoint(_dev(x), _dev(a), _dev(ubar), h, 10, 4, periodic=K, precision=precision, want_x=False)
+    lhs = np.sum(ubar * u)
+    rhs = np.sum(_host(ab) * a)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    print(f"[orbit-adjoint] {precision} K={K}: {abs(lhs - rhs) / np.sum(np.abs(ubar * u)):.2e}", flush=True)
+    assert abs(lhs - rhs) < tol * np.sum(np.abs(ubar * u))
