@@ -97,5 +97,44 @@ __device__ __forceinline__ void irregular_packed(T X, T Y, T Z, int deg, const T
     }
 }
 
+// The orders m = m0, m0 + mstep, ... of irregular_packed only (the diagonal
+// chain runs through every order; the n-chains of the other orders are skipped):
+// lanes that share a point can split its harmonics between them.
+template <typename T>
+__device__ __forceinline__ void irregular_packed_orders(T X, T Y, T Z, int deg, const T *__restrict__ c1,
+                                                        const T *__restrict__ c2, const T *__restrict__ dg, T sgn,
+                                                        int m0, int mstep, T *__restrict__ out, int stride) {
+    const T r2 = X * X + Y * Y + Z * Z;
+    const T ir2 = T(1) / r2;
+    T dre = sqrt(ir2), dim = T(0);
+    for (int m = 0; m <= deg; ++m) {
+        if (m > 0) {
+            const T s = -dg[m] * ir2;
+            const T nre = s * (X * dre - Y * dim);
+            const T nim = s * (X * dim + Y * dre);
+            dre = nre;
+            dim = nim;
+        }
+        if (m < m0 || (m - m0) % mstep != 0) continue;
+        T are = dre, aim = dim, bre = T(0), bim = T(0);
+        for (int n = m; n <= deg; ++n) {
+            if (n > m) {
+                const int e = n * (n + 1) / 2 + m;
+                const T k1 = c1[e] * Z, k2 = c2[e];
+                const T cre = (k1 * are - k2 * bre) * ir2;
+                const T cim = (k1 * aim - k2 * bim) * ir2;
+                bre = are; bim = aim;
+                are = cre; aim = cim;
+            }
+            if (m == 0) {
+                out[(n * n) * stride] = are;
+            } else {
+                out[(n * n + 2 * m - 1) * stride] = are;
+                out[(n * n + 2 * m) * stride] = sgn * aim;
+            }
+        }
+    }
+}
+
 }  // namespace dev
 }  // namespace vmfmm

@@ -30,6 +30,7 @@ namespace vmfmm {
 namespace {
 
 using dev::irregular_packed;
+using dev::irregular_packed_orders;
 
 __device__ __forceinline__ int ad_coord(uint32_t k, int d, int level) {
     int c = 0;
@@ -418,91 +419,105 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const i
                                                const double *__restrict__ wt, const double *__restrict__ G,
                                                const Part64 *__restrict__ parts, const double *__restrict__ M,
                                                double *__restrict__ far) {
+    // The item's 64 targets in four rounds of 16 particles; particle pi of a
+    // round has lanes 4 pi .. 4 pi + 3: lane j computes the harmonic orders
+    // m = j (mod 4) and sums every fourth term of each local row, and the
+    // lanes' partial rows are added by two butterflies.  LDS holds a round's
+    // harmonics (16 particles) and the source cell's multipole.
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 it = items[blockIdx.x];
     const int a = lcell[it.x];
     const uint32_t e0 = ls.off[size_t(1) * ncell + a];
     const uint32_t e1 = e0 + ls.cnt[size_t(1) * ncell + a];
     if (e1 == e0) return;
-    const int lane = threadIdx.x;
-    double *hs = reinterpret_cast<double *>(smem_raw);     // [nharm][64]
-    double *mb = hs + size_t(nharm) * 64;                   // [3][kp]
+    const int lane = threadIdx.x, pi = lane >> 2, j = lane & 3;
+    double *hs = reinterpret_cast<double *>(smem_raw);     // [nharm][16]
+    double *mb = hs + size_t(nharm) * 16;                   // [3][kp]
     double ca[3];
     centre(t, a, ca);
     const int s0 = lstart[it.x], cnt = lstart[it.x + 1] - s0;
-    {
-        const int base = it.y;
-        const bool valid = base + lane < cnt;
-        const Part64 me = parts[s0 + base + (valid ? lane : 0)];
-        double out[12];
-        for (int o = 0; o < 12; ++o) out[o] = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        const int base = it.y + 16 * q;
+        if (base >= cnt) break;                            // uniform
+        const bool valid = base + pi < cnt;
+        const Part64 me = parts[s0 + base + (valid ? pi : 0)];
+        double out[3] = {0.0, 0.0, 0.0};                    // outputs j, j + 4, j + 8
         for (uint32_t e = e0; e < e1; ++e) {
             const int b = ls.src[1][e], code = ls.code[1][e];
             double cb[3];
             centre(t, b, cb);
             const int lb = t.level[b];
-            const double inv_w = ldexp(t.inv_len, lb), w = ldexp(t.box_len, -lb);
+            const double inv_w = ldexp(t.inv_len, lb);
             __syncthreads();
             for (int k = lane; k < 3 * kp; k += 64) mb[k] = M[size_t(b) * 3 * kp + k];
             // particle relative to the source centre: delta_i + (c_a - c_b - s L)
             const double X = (me.dx + (ca[0] - cb[0] - shift_of(code, 0) * t.box_len)) * inv_w;
             const double Y = (me.dy + (ca[1] - cb[1] - shift_of(code, 1) * t.box_len)) * inv_w;
             const double Z = (me.dz + (ca[2] - cb[2] - shift_of(code, 2) * t.box_len)) * inv_w;
-            irregular_packed<double>(X, Y, Z, p + 2, tab.c1_64, tab.c2_64, tab.diag_64, 1.0, hs + lane, 64);
+            irregular_packed_orders<double>(X, Y, Z, p + 2, tab.c1_64, tab.c2_64, tab.diag_64, 1.0, j, 4, hs + pi,
+                                            16);
             __syncthreads();
             double loc[3][kM2PMaxRow];
-            for (int r = 0; r < kM2PMaxRow; ++r) loc[0][r] = loc[1][r] = loc[2][r] = 0.0;
 #pragma unroll
             for (int r = 0; r < kM2PMaxRow; ++r) {
-                if (r >= nrow) break;
                 double s0v = 0.0, s1v = 0.0, s2v = 0.0;
-                const int k1 = rowptr[r + 1];
-                int k = rowptr[r];
-                // eight terms at a time: their table entries (wave-uniform) and
-                // LDS reads are all issued before the first product
-                for (; k + 8 <= k1; k += 8) {
-                    int cc[8], hh[8];
-                    double ww[8], hv[8];
+                if (r < nrow) {
+                    const int k1 = rowptr[r + 1];
+                    int k = rowptr[r] + j;
+                    // this lane's terms four apart, eight at a time
+                    for (; k + 28 < k1; k += 32) {
+                        int cc[8], hh[8];
+                        double ww[8], hv[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        cc[j] = col[k + j];
-                        hh[j] = harm[k + j];
-                        ww[j] = wt[k + j];
+                        for (int i = 0; i < 8; ++i) {
+                            cc[i] = col[k + 4 * i];
+                            hh[i] = harm[k + 4 * i];
+                            ww[i] = wt[k + 4 * i];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) hv[i] = ww[i] * hs[hh[i] * 16 + pi];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            s0v += hv[i] * mb[cc[i]];
+                            s1v += hv[i] * mb[kp + cc[i]];
+                            s2v += hv[i] * mb[2 * kp + cc[i]];
+                        }
                     }
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) hv[j] = ww[j] * hs[hh[j] * 64 + lane];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        s0v += hv[j] * mb[cc[j]];
-                        s1v += hv[j] * mb[kp + cc[j]];
-                        s2v += hv[j] * mb[2 * kp + cc[j]];
+                    for (; k < k1; k += 4) {
+                        const double hv = wt[k] * hs[harm[k] * 16 + pi];
+                        const int c = col[k];
+                        s0v += hv * mb[c];
+                        s1v += hv * mb[kp + c];
+                        s2v += hv * mb[2 * kp + c];
                     }
                 }
-                for (; k < k1; ++k) {
-                    const double hv = wt[k] * hs[harm[k] * 64 + lane];
-                    const int c = col[k];
-                    s0v += hv * mb[c];
-                    s1v += hv * mb[kp + c];
-                    s2v += hv * mb[2 * kp + c];
-                }
+                // the four lanes' partial sums, fixed order
+                s0v += __shfl_xor(s0v, 1);
+                s1v += __shfl_xor(s1v, 1);
+                s2v += __shfl_xor(s2v, 1);
+                s0v += __shfl_xor(s0v, 2);
+                s1v += __shfl_xor(s1v, 2);
+                s2v += __shfl_xor(s2v, 2);
                 loc[0][r] = s0v;
                 loc[1][r] = s1v;
                 loc[2][r] = s2v;
             }
             const double su = 0.079577471545947667884 * inv_w * inv_w, sj = su * inv_w;
-            (void)w;
-            for (int o = 0; o < 12; ++o) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int o = j + 4 * i;
                 double v = 0.0;
                 for (int k = 0; k < 3; ++k)
 #pragma unroll
                     for (int r = 0; r < kM2PMaxRow; ++r)
                         if (r < nrow) v += G[size_t(o) * 3 * nrow + k * nrow + r] * loc[k][r];
-                out[o] += v * (o < 3 ? su : sj);
+                out[i] += v * (o < 3 ? su : sj);
             }
         }
         if (valid) {
-            const size_t gi = size_t(s0) + base + lane;
-            for (int o = 0; o < 12; ++o) far[size_t(o) * n + gi] += out[o];
+            const size_t gi = size_t(s0) + base + pi;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) far[size_t(j + 4 * i) * n + gi] += out[i];
         }
     }
 }
@@ -604,7 +619,7 @@ hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, 
                          const int32_t *harm, const double *w, const double *G, const Part64 *parts, const double *M,
                          double *far) {
     if (nitem == 0) return hipSuccess;
-    const size_t smem = sizeof(double) * (size_t(nharm) * 64 + size_t(3) * kp);
+    const size_t smem = sizeof(double) * (size_t(nharm) * 16 + size_t(3) * kp);
     hipLaunchKernelGGL(k_ad_m2p, dim3(nitem), dim3(64), smem, s, t, ls, items, lcell, lstart, n, ncell, p, kp, nrow,
                        nharm, tab, rowptr, col, harm, w, G, parts, M, far);
     return hipGetLastError();
