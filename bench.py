@@ -173,6 +173,29 @@ def measured_traffic(workload, precision, kernel, launches_per_eval=None):
     return k["hbm_bytes_per_launch"]
 
 
+def measured_phase_bytes(workload, precision, kernels):
+    """HBM bytes per evaluation of all dispatches of `kernels` (names or name
+    prefixes) in the committed summary of an evaluations-only run, or None."""
+    d = _traffic_summary(workload, precision)
+    if d is None:
+        return None
+    ks = d.get("kernels", {})
+    hit = [v for k, v in ks.items() if any(k.startswith(x) for x in kernels)]
+    if not hit or any(v.get("hbm_bytes_per_evaluation") is None for v in hit):
+        return None
+    return sum(v["hbm_bytes_per_evaluation"] for v in hit)
+
+
+def measured_finest_launch(workload, precision, kernel):
+    """(grid size, HBM bytes) of the largest launch shape of `kernel`, or None."""
+    d = _traffic_summary(workload, precision)
+    k = None if d is None else d.get("kernels", {}).get(kernel)
+    if not k or not k.get("shapes"):
+        return None
+    sh = max(k["shapes"], key=lambda x: x["grid_size"])
+    return sh["grid_size"], sh["hbm_bytes_per_dispatch"]
+
+
 def measured_tree_bytes(workload, precision):
     """HBM bytes of the tree build per evaluation (sum over its kernels), or None."""
     d = _traffic_summary(workload, precision)
@@ -377,16 +400,22 @@ def main():
         m2l_flop = sum(8 ** l * (per_t if l >= 4 else 6.0 * C * C * 189) for l in range(lev0, w.level + 1))
     else:
         m2l_kernel = "k_translate<double,1,1,0,24>" if not f32 else "k_m2l_os"
-    m2l_traffic = measured_traffic(w.name, args.precision, "k_m2l_sym<10>" if orbit else m2l_kernel, m2l_launch)
+    # HBM bytes of the whole M2L phase per evaluation (every launch of its kernels)
+    m2l_traffic = measured_phase_bytes(w.name, args.precision,
+                                       ("k_m2l_sym", "k_m2l_os", "k_sym_pack", "k_split_reduce", "k_translate"))
     # algorithmic bytes of the M2L phase: read M, read and write L at every level, the operators once
     cells = sum(8 ** l for l in range(lev0, w.level + 1))
-    m2l_alg_bytes = (cells * 3 * C * esz * 3 + 316 * C * C * esz) / m2l_launch
+    m2l_alg_bytes = cells * 3 * C * esz * 3 + 316 * C * C * esz
     roof_m2l = {"bound": "mfma", "kernel": f"{m2l_kernel} (M2L phase, all levels)",
                 "flop_per_eval": m2l_flop,
-                "achieved": m2l_flop / m2l_launch / (m2l_ms / m2l_launch * 1e-3) / 1e12,
+                "achieved": m2l_flop / (m2l_ms * 1e-3) / 1e12,
                 "peak": PEAKS["mfma_f32_tflops" if f32 else "mfma_f64_tflops"], "unit": "TFLOP/s",
-                "traffic": m2l_traffic, "traffic_unit": "bytes per launch",
-                "algorithmic_bytes_per_launch": m2l_alg_bytes, "launches_per_eval": m2l_launch}
+                "traffic": m2l_traffic, "traffic_unit": "bytes per evaluation",
+                "algorithmic_bytes_per_eval": m2l_alg_bytes, "launches_per_eval": m2l_launch}
+    fin = measured_finest_launch(w.name, args.precision, "k_m2l_sym<10>") if orbit else None
+    if fin:
+        roof_m2l["finest_level_launch"] = {"kernel": "k_m2l_sym<10>", "grid_size": fin[0], "hbm_bytes": fin[1],
+                                           "algorithmic_bytes": 8 ** w.level * 3 * C * esz * 2}
     roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
     p2p_kernel = "k_p2p32" if f32 else "k_p2p64"
     roof_p2p = {"bound": "alu", "kernel": p2p_kernel,

@@ -34,10 +34,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CALIBRATION_BYTES = 1 << 30
 
 
-# the sources the measured kernels (tree, expansions, translations, near field,
-# Gaussian sums) and their launch configurations are built from
+# the sources the profiled kernels (tree, expansions, translations, near field)
+# and their launch configurations are built from
 MEASURED_SOURCES = ("kernels.h", "device_harmonics.h", "kernels_tree.hip", "kernels_fmm.hip", "kernels_p2p.hip",
-                    "kernels_rbf.hip", "kernels_adaptive.hip", "operators.h", "operators.cpp", "vmfmm.cpp")
+                    "kernels_m2l_sym.hip", "operators.h", "operators.cpp", "vmfmm.cpp")
 
 
 def sources_sha256() -> str:
@@ -77,7 +77,7 @@ def trace_summary(d: str, command: str | None) -> str:
     shapes = collections.defaultdict(list)
     for r in trace:
         n = short_name(r["Kernel_Name"])
-        if n.startswith(("k_m2l_os", "k_translate", "k_p2p", "k_split_reduce", "k_gauss")):
+        if n.startswith(("k_m2l_os", "k_m2l_sym", "k_translate", "k_p2p", "k_split_reduce", "k_gauss")):
             key = (n, int(r["Grid_Size_X"]), int(r.get("Grid_Size_Y", 1) or 1))
             shapes[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
     out.append("")
@@ -126,7 +126,8 @@ def traffic_summary(fetch_dir: str, write_dir: str, workload: str, command: str 
     kernels = {}
     evals = len(fetch.get("k_keys", []))
     for name in sorted(set(fetch) | set(write)):
-        if not name.startswith(("k_m2l_os", "k_translate", "k_p2p", "k_split_reduce", "k_permute",
+        if not name.startswith(("k_m2l_os", "k_m2l_sym", "k_sym_pack", "k_translate", "k_p2p", "k_split_reduce",
+                                "k_permute",
                                 "k_radix", "k_keys", "k_iota", "k_scan", "k_ranges", "k_p2m", "k_l2p",
                                 "k_gauss", "k_pack", "k_multidot", "k_multiaxpy", "k_gather3", "k_scatter3")):
             continue
