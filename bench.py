@@ -392,17 +392,20 @@ def main():
     esz = 4 if f32 else 8
     # FP32 at p = 10: the orbit kernel from level 4 on (class-major pack of the
     # multipoles first), dense operator-stationary MFMAs below
-    orbit = f32 and w.p == 10
+    orbit = w.p == 10 and w.level >= 4
     lev0 = 1 if w.periodic else 2
     if orbit:
-        m2l_kernel = "k_m2l_sym<10> (levels 4+) + k_m2l_os<4,8,false> (levels < 4) + k_sym_pack"
+        m2l_kernel = ("k_m2l_sym<10> (levels 4+) + k_m2l_os<4,8,false> (levels < 4) + k_sym_pack" if f32 else
+                      "k_m2l_sym64<10> (levels 4+) + k_translate<double,1,1,0,24> (levels < 4) + k_sym_pack")
         per_t = orbit_m2l_flop_per_target(w.p)
         m2l_flop = sum(8 ** l * (per_t if l >= 4 else 6.0 * C * C * 189) for l in range(lev0, w.level + 1))
     else:
         m2l_kernel = "k_translate<double,1,1,0,24>" if not f32 else "k_m2l_os"
     # HBM bytes of the whole M2L phase per evaluation (every launch of its kernels)
     m2l_traffic = measured_phase_bytes(w.name, args.precision,
-                                       ("k_m2l_sym", "k_m2l_os", "k_sym_pack", "k_split_reduce", "k_translate"))
+                                       ("k_m2l_sym<", "k_m2l_os", "k_sym_pack<float>", "k_split_reduce<float>")
+                                       if f32 else ("k_m2l_sym64", "k_translate<double,1,1,0,", "k_sym_pack<double>",
+                                                    "k_split_reduce<double>"))
     # algorithmic bytes of the M2L phase: read M, read and write L at every level, the operators once
     cells = sum(8 ** l for l in range(lev0, w.level + 1))
     m2l_alg_bytes = cells * 3 * C * esz * 3 + 316 * C * C * esz
@@ -412,9 +415,10 @@ def main():
                 "peak": PEAKS["mfma_f32_tflops" if f32 else "mfma_f64_tflops"], "unit": "TFLOP/s",
                 "traffic": m2l_traffic, "traffic_unit": "bytes per evaluation",
                 "algorithmic_bytes_per_eval": m2l_alg_bytes, "launches_per_eval": m2l_launch}
-    fin = measured_finest_launch(w.name, args.precision, "k_m2l_sym<10>") if orbit else None
+    sym_name = "k_m2l_sym<10>" if f32 else "k_m2l_sym64<10>"
+    fin = measured_finest_launch(w.name, args.precision, sym_name) if orbit else None
     if fin:
-        roof_m2l["finest_level_launch"] = {"kernel": "k_m2l_sym<10>", "grid_size": fin[0], "hbm_bytes": fin[1],
+        roof_m2l["finest_level_launch"] = {"kernel": sym_name, "grid_size": fin[0], "hbm_bytes": fin[1],
                                            "algorithmic_bytes": 8 ** w.level * 3 * C * esz * 2}
     roof_m2l["frac"] = roof_m2l["achieved"] / roof_m2l["peak"]
     p2p_kernel = "k_p2p32" if f32 else "k_p2p64"
