@@ -479,7 +479,7 @@ hipError_t launch_m2l_sym64(hipStream_t s, int level, int periodic, int p, int k
     if (!m2l_sym_supported(p) || level < 1) return hipErrorInvalidValue;
     constexpr SymLayout SL = sym_layout(10);
     constexpr int KC = 16 * SL.nblk;
-    if (uint64_t(zero_cell) * 3 * KC * 8 >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
+    if ((uint64_t(zero_cell) + 1) * 3 * KC * sizeof(double) > (uint64_t(1) << 32)) return hipErrorInvalidValue;
     const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
     const size_t smem = sizeof(double) * size_t(kRing) * size_t(16 * SL.C + 32);
     int nsplit = part ? translate_splits(level, kSymTargets, kp, part_elems) : 1;
@@ -499,7 +499,8 @@ hipError_t launch_m2l_sym(hipStream_t s, int level, int periodic, int p, int kp,
     if (!m2l_sym_supported(p) || level < 1) return hipErrorInvalidValue;
     constexpr SymLayout SL = sym_layout(10);
     constexpr int KC = 16 * SL.nblk;
-    if (uint64_t(zero_cell) * 3 * KC >= (uint64_t(1) << 32)) return hipErrorInvalidValue;
+    // byte offsets into mc (the zero cell included) must fit 32 bits
+    if ((uint64_t(zero_cell) + 1) * 3 * KC * sizeof(float) > (uint64_t(1) << 32)) return hipErrorInvalidValue;
     const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
     const size_t smem = 2 * sizeof(float) * size_t(16 * SL.C * SL.nblk + 64);
     int nsplit = part ? translate_splits(level, kSymTargets, kp, part_elems) : 1;

@@ -361,3 +361,22 @@ def test_reflection_orbit_m2l(ctx, level, K):
         uo, Jo = OF.fmm_at(x, a, h, 10, level, t, periodic=K)
         close(u[t], uo, FP64, "u vs oracle (sampled)")
         close(J[t], Jo, FP64, "J vs oracle (sampled)")
+
+
+def test_reflection_orbit_m2l_at_level_7(ctx):
+    """The finest level the FP32 orbit kernel takes (level 7: 2^21 target cells,
+    byte offsets into the class-major multipoles near 2^32), random particles
+    in free space: mixed against FP64 (whose M2L at level 7 runs the dense
+    operators) at 64 sampled particles, 1e-5 / 4e-5 (u) and 1e-4 / 4e-4 (J)."""
+    import torch
+    x, a = W.random_particles(1 << 17, 71)
+    sigma = L / 512
+    t = torch.from_numpy(np.sort(np.random.default_rng(3).choice(len(x), 64, replace=False))).cuda()
+    out = {}
+    for prec in ("fp64", "mixed"):
+        u, _, J = ctx.eval(_dev(x), _dev(a), sigma, 10, 7, periodic=0, precision=prec, want_grad=True)
+        out[prec] = (u[:, t].cpu().numpy().T, J[:, t].cpu().numpy().T)
+        del u, J
+    torch.cuda.empty_cache()
+    close(out["mixed"][0], out["fp64"][0], MIXED_U, "u mixed vs fp64, level 7")
+    close(out["mixed"][1], out["fp64"][1], MIXED_J, "J mixed vs fp64, level 7")
