@@ -138,11 +138,14 @@ vm_status vm_fmm_eval_at(vm_ctx *ctx, int64_t n, const double *x, const double *
  *            periodic, its 26 images) pairs cells: two cells whose closed cubes
  *            (the source shifted by its image) do not touch interact through
  *            expansions -- M2L between cells of one level (cell-cell), M2P from
- *            a finer source cell to the particles of a leaf and P2L from the
- *            particles of a coarser leaf to a cell (cell-particle) -- touching
- *            leaves exchange the exact regularised kernel (P2P), any other
- *            touching pair is refined.  Every (target, source, image) triple is
- *            covered once; on a uniform tree the lists are vm_fmm_eval's.
+ *            a finer split source cell to the particles of a leaf and P2L from
+ *            the particles of a coarser leaf to a split cell (cell-particle) --
+ *            touching leaves, and leaves of different levels that do not touch,
+ *            exchange the exact regularised kernel (P2P: for a cell side of at
+ *            most ncrit particles the direct sum is the cheaper interaction),
+ *            any other touching pair is refined.  Every (target, source,
+ *            image) triple is covered once; on a uniform tree the lists are
+ *            vm_fmm_eval's.
  *   far field  the cutoff is dropped in all expansion interactions (the cells
  *            are at least one width of the smaller one apart, so at leaves of
  *            width >= 4 sigma as in vm_fmm_eval);

@@ -27,6 +27,16 @@ must reproduce the tree and the lists bit for bit):
   Otherwise the pair is refined: both cells when both are split and of one
   level, else the one that is split.  Every (target particle, source
   particle, image) triple is then covered by exactly one interaction.
+* cost choice: the hybrid takes the cheaper of the interactions that are
+  valid for a pair (Sec. 3.2 argues from the rule that a well-built FMM
+  always does).  A cell-particle interaction replaces |cell| particles by
+  one expansion of (p+1)^2 terms per component and costs thousands of
+  operations per particle of the other side, while the exact kernel costs
+  tens per pair, so the break-even cell holds some hundreds of particles.
+  The reading: a cell-particle interaction needs a split cell (more than
+  ncrit particles, ncrit being tuned) on its cell side; two leaves of
+  different levels that do not touch are P2P as well.  Between cells of one
+  level (M2L) nothing changes, so the uniform-tree reduction holds.
 * the cutoff is dropped in all expansion interactions (text after
   eqs. 12-13); the separation of the cells, at least one width of the
   smaller cell, is what makes g = 1 there.
@@ -145,7 +155,7 @@ def lists(tree):
     while stack:
         a, b, s = stack.pop()
         la, lb = lev[a], lev[b]
-        if not touching(tree, a, b, s):
+        if not touching(tree, a, b, s) and (la == lb or not leaf[b if la < lb else a]):
             name = "m2l" if la == lb else ("m2p" if la < lb else "p2l")
             out[name].append((a, b, shift_code(s)))
             continue

@@ -234,7 +234,10 @@ __global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, in
 
     auto classify = [&](int b, int code) {
         const int lb = t.level[b];
-        if (!touching(t, a, b, code)) {
+        // apart: cell-cell between cells of one level; particle-cell from a
+        // coarser leaf b only into a split cell a -- a leaf a takes b's
+        // particles directly, the cheaper of the two for cells of <= ncrit
+        if (!touching(t, a, b, code) && (lb == l || !leaf_a)) {
             if (lb == l) {
                 if (pass == 1) {
                     int idx = 0, mul = 1;
@@ -257,7 +260,8 @@ __global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, in
         if (leaf_a && leaf_b) {
             put(ls, pass, ncell, 0, a, cnt[0], b, code);
         } else if (leaf_a) {
-            // walk b's subtree: cells apart from a are M2P sources
+            // walk b's subtree: split cells apart from a are M2P sources,
+            // its leaves (apart or touching) P2P sources
             int sp = 0;
             for (int o = 0; o < 8; ++o) {
                 const int e = t.child[8 * b + o];
@@ -268,9 +272,10 @@ __global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, in
             }
             while (sp > 0) {
                 const int e = stack[--sp];
-                if (!touching(t, a, e, code)) {
-                    put(ls, pass, ncell, 1, a, cnt[1], e, code);
-                } else if (ad_leaf(t, e)) {
+                const bool leaf_e = ad_leaf(t, e);
+                if (!leaf_e && !touching(t, a, e, code)) {
+                    put(ls, pass, ncell, 1, a, cnt[1], e, code);   // M2P from a split cell only
+                } else if (leaf_e) {
                     put(ls, pass, ncell, 0, a, cnt[0], e, code);
                 } else {
                     for (int o = 0; o < 8; ++o) {

@@ -6,9 +6,10 @@
   key; children tile their parent's particle range.
 * Lists: every (target particle, source particle, image of S_1) triple is
   covered by exactly one interaction (brute force over all triples); each
-  interaction has the geometry its kind requires (P2P: touching leaves; M2L:
-  one level, apart, parents touching; M2P: target leaf, finer source apart
-  whose parent touches it; P2L: the mirror image).
+  interaction has the geometry its kind requires (P2P: leaves that touch, or
+  of different levels with the finer one's parent touching the other; M2L:
+  one level, apart, parents touching; M2P: target leaf, finer split source
+  apart whose parent touches it; P2L: the mirror image).
 * On a tree that happens to be uniform the lists are the uniform FMM's (the
   189-offset interaction lists and the 27 neighbours, no cell-particle
   interactions) and the evaluation equals the uniform oracle FMM to
@@ -95,15 +96,24 @@ def test_interaction_geometry(periodic):
     ls = A.lists(tr)
     lev, leaf, par = tr["level"], tr["leaf"], tr["parent"]
     touch = lambda a, b, c: A.touching(tr, a, b, A.code_shift(c))
+    apart = 0
     for t, s, c in ls["p2p"]:
-        assert leaf[t] and leaf[s] and touch(t, s, c)
+        assert leaf[t] and leaf[s]
+        if not touch(t, s, c):
+            # separated leaves are direct only across levels, with the finer
+            # one's parent touching the coarser leaf
+            assert lev[t] != lev[s]
+            f, g = (t, s) if lev[t] > lev[s] else (s, t)
+            assert touch(par[f], g, c) if f == t else touch(g, par[f], c)
+            apart += 1
+    assert apart > 0
     for t, s, c in ls["m2l"]:
         assert lev[t] == lev[s] and not touch(t, s, c)
         assert par[t] < 0 or touch(par[t], par[s], c)
     for t, s, c in ls["m2p"]:
-        assert leaf[t] and lev[s] > lev[t] and not touch(t, s, c) and touch(t, par[s], c)
+        assert leaf[t] and not leaf[s] and lev[s] > lev[t] and not touch(t, s, c) and touch(t, par[s], c)
     for t, s, c in ls["p2l"]:
-        assert leaf[s] and lev[t] > lev[s] and not touch(t, s, c) and touch(par[t], s, c)
+        assert leaf[s] and not leaf[t] and lev[t] > lev[s] and not touch(t, s, c) and touch(par[t], s, c)
 
 
 @pytest.mark.parametrize("periodic", [0, 3])
