@@ -243,10 +243,13 @@ hipError_t launch_ad_no_children(hipStream_t s, const AdTreeView &t, int off, in
 // leaves in particle order: lcell, lstart (nleaf + 1), llev; *nleaf_out
 hipError_t launch_ad_leaves(hipStream_t s, const AdTreeView &t, int ncell, int n, int32_t *leaf_at, uint32_t *rank,
                             uint32_t *tile_sums, int32_t *lcell, int32_t *lstart, int32_t *llev, int *nleaf_out);
-// target blocks of 64 of the leaves (particle order): items (leaf, first
-// target), their number in *nitem_out; rank / tile_sums scratch of nleaf words
-hipError_t launch_ad_blocks(hipStream_t s, int nleaf, const int32_t *lstart, uint32_t *rank, uint32_t *tile_sums,
-                            int2 *items, int *nitem_out);
+// target blocks of bs of the leaves (particle order): items (leaf, first
+// target), their number in *nitem_out; with a gate (per cell, indexed through
+// lcell) only the leaves whose gate count is non-zero; rank / tile_sums
+// scratch of nleaf words
+hipError_t launch_ad_blocks(hipStream_t s, int nleaf, const int32_t *lstart, const int32_t *lcell,
+                            const uint32_t *gate, int bs, uint32_t *rank, uint32_t *tile_sums, int2 *items,
+                            int *nitem_out);
 // sorted FP64 records relative to each leaf's centre
 hipError_t launch_ad_permute(hipStream_t s, const AdTreeView &t, int n, const double *x, const double *alpha,
                              const int32_t *perm, int nleaf, const int32_t *lcell, Part64 *parts);

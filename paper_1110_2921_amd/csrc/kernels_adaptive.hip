@@ -408,7 +408,7 @@ __global__ void __launch_bounds__(64) k_ad_p2l(AdTreeView t, AdLists ls, int off
     }
 }
 
-// M2P: one workgroup per target leaf with an M2P list, one particle per lane.
+// M2P: one workgroup per block of 16 targets of a leaf with an M2P list.
 // For each source cell the lane writes the balanced irregular harmonics of its
 // particle's offset from the source centre (degree p + 2) into its LDS column,
 // forms the degree <= 2 local expansion about the particle from the table
@@ -424,11 +424,12 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const i
                                                const double *__restrict__ wt, const double *__restrict__ G,
                                                const Part64 *__restrict__ parts, const double *__restrict__ M,
                                                double *__restrict__ far) {
-    // The item's 64 targets in four rounds of 16 particles; particle pi of a
-    // round has lanes 4 pi .. 4 pi + 3: lane j computes the harmonic orders
-    // m = j (mod 4) and sums every fourth term of each local row, and the
-    // lanes' partial rows are added by two butterflies.  LDS holds a round's
-    // harmonics (16 particles) and the source cell's multipole.
+    // Particle pi of the item's 16 has lanes 4 pi .. 4 pi + 3: lane j computes
+    // the harmonic orders m = j (mod 4) and sums every fourth term of each
+    // local row, and the lanes' partial rows are added by two butterflies.
+    // LDS holds the 16 particles' harmonics and the source cell's multipole.
+    // Blocks of 16 rather than 64 targets give a leaf with a long list four
+    // times as many waves; the list is walked once per block either way.
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 it = items[blockIdx.x];
     const int a = lcell[it.x];
@@ -441,9 +442,8 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const i
     double ca[3];
     centre(t, a, ca);
     const int s0 = lstart[it.x], cnt = lstart[it.x + 1] - s0;
-    for (int q = 0; q < 4; ++q) {
-        const int base = it.y + 16 * q;
-        if (base >= cnt) break;                            // uniform
+    {
+        const int base = it.y;
         const bool valid = base + pi < cnt;
         const Part64 me = parts[s0 + base + (valid ? pi : 0)];
         double out[3] = {0.0, 0.0, 0.0};                    // outputs j, j + 4, j + 8
@@ -527,21 +527,33 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const i
     }
 }
 
-// target blocks of 64 per leaf, then the (leaf, first target) items
+// target blocks of bs per leaf (none for a leaf whose gate count is zero,
+// when a gate is given), then the (leaf, first target) items
+__device__ __forceinline__ int leaf_blocks(int i, const int32_t *__restrict__ lstart,
+                                           const int32_t *__restrict__ lcell, const uint32_t *__restrict__ gate,
+                                           int bs) {
+    if (gate != nullptr && gate[lcell[i]] == 0u) return 0;
+    return (lstart[i + 1] - lstart[i] + bs - 1) / bs;
+}
+
 __global__ void __launch_bounds__(256) k_ad_block_count(int nleaf, const int32_t *__restrict__ lstart,
+                                                        const int32_t *__restrict__ lcell,
+                                                        const uint32_t *__restrict__ gate, int bs,
                                                         uint32_t *__restrict__ nb) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nleaf) nb[i] = uint32_t((lstart[i + 1] - lstart[i] + 63) / 64);
+    if (i < nleaf) nb[i] = uint32_t(leaf_blocks(i, lstart, lcell, gate, bs));
 }
 
 __global__ void __launch_bounds__(256) k_ad_block_fill(int nleaf, const int32_t *__restrict__ lstart,
+                                                       const int32_t *__restrict__ lcell,
+                                                       const uint32_t *__restrict__ gate, int bs,
                                                        const uint32_t *__restrict__ boff, int2 *__restrict__ items,
                                                        int *__restrict__ nitem) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nleaf) return;
-    const int nb = (lstart[i + 1] - lstart[i] + 63) / 64;
+    const int nb = leaf_blocks(i, lstart, lcell, gate, bs);
     if (i == nleaf - 1) *nitem = int(boff[i]) + nb;
-    for (int b = 0; b < nb; ++b) items[boff[i] + b] = make_int2(i, 64 * b);
+    for (int b = 0; b < nb; ++b) items[boff[i] + b] = make_int2(i, bs * b);
 }
 
 inline int blocks(int n, int t) { return (n + t - 1) / t; }
@@ -630,12 +642,14 @@ hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, 
     return hipGetLastError();
 }
 
-hipError_t launch_ad_blocks(hipStream_t s, int nleaf, const int32_t *lstart, uint32_t *rank, uint32_t *tile_sums,
-                            int2 *items, int *nitem_out) {
-    hipLaunchKernelGGL(k_ad_block_count, dim3(blocks(nleaf, 256)), dim3(256), 0, s, nleaf, lstart, rank);
+hipError_t launch_ad_blocks(hipStream_t s, int nleaf, const int32_t *lstart, const int32_t *lcell,
+                            const uint32_t *gate, int bs, uint32_t *rank, uint32_t *tile_sums, int2 *items,
+                            int *nitem_out) {
+    hipLaunchKernelGGL(k_ad_block_count, dim3(blocks(nleaf, 256)), dim3(256), 0, s, nleaf, lstart, lcell, gate, bs,
+                       rank);
     hipError_t e = launch_exclusive_scan(s, nleaf, rank, tile_sums);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ad_block_fill, dim3(blocks(nleaf, 256)), dim3(256), 0, s, nleaf, lstart,
+    hipLaunchKernelGGL(k_ad_block_fill, dim3(blocks(nleaf, 256)), dim3(256), 0, s, nleaf, lstart, lcell, gate, bs,
                        (const uint32_t *)rank, items, nitem_out);
     return hipGetLastError();
 }
