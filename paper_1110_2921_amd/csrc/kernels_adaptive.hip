@@ -208,57 +208,76 @@ __global__ void __launch_bounds__(64) k_ad_permute(AdTreeView t, int n, const do
 constexpr int kAdStack = 128;
 constexpr int kM2LSlots = 189;
 
-__device__ __forceinline__ void put(const AdLists &ls, int pass, int ncell, int k, int a, uint32_t &cnt, int b,
-                                    int code) {
-    if (pass == 1) {
-        const size_t pos = size_t(ls.off[size_t(k) * ncell + a]) + cnt;
-        ls.src[k][pos] = b;
-        ls.code[k][pos] = int8_t(code);
+// exclusive prefix over the wave's lanes (lane order) and the wave's total
+__device__ __forceinline__ uint32_t wave_scan(uint32_t v, uint32_t &total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
     }
-    ++cnt;
+    total = __shfl(x, 63, 64);
+    return x - v;
 }
 
+// One wave per cell a of level l.  Candidate c of a's list is (parent partner
+// c / 8, child c % 8); a leaf partner stands for itself at c % 8 == 0 (the
+// root: itself under each of its images).  The lanes classify the candidates
+// 64 at a time; each lane walks its own candidate's subtree when that is
+// needed.  List entries go to the cell's lists in candidate order: in the
+// filling pass every lane first counts its entries, the wave's prefix sums
+// place them, and the lane classifies again, writing.
 __global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, int l, int off, int ncl, int pass,
                                                     int vcell0, int ncell) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncl) return;
-    const int a = off + i;
+    const int a = off + int(blockIdx.x);
+    const int lane = threadIdx.x;
     const bool leaf_a = ad_leaf(t, a);
     const int oct = int(t.key[a] & 7u);
     int ca[3];
     for (int d = 0; d < 3; ++d) ca[d] = ad_coord(t.key[a], d, l);
-    uint32_t cnt[3] = {0u, 0u, 0u};
-    int np = 0;
-    int stack[kAdStack];
     bool bad = false;
+    int stack[kAdStack];
 
-    auto classify = [&](int b, int code) {
+    // classify candidate b: with write == false count the list entries into
+    // cnt, with write == true store them from pos on (and the M2L slot)
+    auto classify = [&](int b, int code, bool write, uint32_t (&pos)[3], uint32_t (&cnt)[3], bool &partner) {
+        auto put = [&](int k, int src) {
+            if (write) {
+                ls.src[k][pos[k]] = src;
+                ls.code[k][pos[k]] = int8_t(code);
+                ++pos[k];
+            } else {
+                ++cnt[k];
+            }
+        };
         const int lb = t.level[b];
         // apart: cell-cell between cells of one level; particle-cell from a
         // coarser leaf b only into a split cell a -- a leaf a takes b's
         // particles directly, the cheaper of the two for cells of <= ncrit
         if (!touching(t, a, b, code) && (lb == l || !leaf_a)) {
             if (lb == l) {
-                if (pass == 1) {
+                if (write) {
                     int idx = 0, mul = 1;
+                    bool out = false;
                     for (int d = 0; d < 3; ++d) {
                         const int dd = ad_coord(t.key[b], d, l) + shift_of(code, d) * (1 << l) - ca[d];
-                        if (dd < -3 || dd > 3) bad = true;
+                        if (dd < -3 || dd > 3) out = true;
                         idx += (dd + 3) * mul;
                         mul *= 7;
                     }
-                    const int slot = bad ? -1 : ls.vslot[oct * 343 + idx];
+                    const int slot = out ? -1 : ls.vslot[oct * 343 + idx];
                     if (slot < 0) bad = true;
                     else ls.vtab[size_t(a - vcell0) * kM2LSlots + slot] = b;
                 }
             } else {
-                put(ls, pass, ncell, 2, a, cnt[2], b, code);      // P2L: b is a coarser leaf
+                put(2, b);      // P2L: b is a coarser leaf
             }
             return;
         }
         const bool leaf_b = ad_leaf(t, b);
         if (leaf_a && leaf_b) {
-            put(ls, pass, ncell, 0, a, cnt[0], b, code);
+            put(0, b);
         } else if (leaf_a) {
             // walk b's subtree: split cells apart from a are M2P sources,
             // its leaves (apart or touching) P2P sources
@@ -274,9 +293,9 @@ __global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, in
                 const int e = stack[--sp];
                 const bool leaf_e = ad_leaf(t, e);
                 if (!leaf_e && !touching(t, a, e, code)) {
-                    put(ls, pass, ncell, 1, a, cnt[1], e, code);   // M2P from a split cell only
+                    put(1, e);   // M2P from a split cell only
                 } else if (leaf_e) {
-                    put(ls, pass, ncell, 0, a, cnt[0], e, code);
+                    put(0, e);
                 } else {
                     for (int o = 0; o < 8; ++o) {
                         const int f = t.child[8 * e + o];
@@ -288,43 +307,62 @@ __global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, in
                 }
             }
         } else {
-            // a is split: the pair goes to a's children
-            if (pass == 0) {
-                if (np < 27) {
-                    ls.part[size_t(a) * 27 + np] = b;
-                    ls.pcode[size_t(a) * 27 + np] = int8_t(code);
-                } else {
-                    bad = true;
-                }
-            }
-            ++np;
+            partner = true;     // a is split: the pair goes to a's children
         }
     };
 
+    int P = -1, ncand;
     if (l == 0) {
-        if (t.periodic) {
-            for (int code = 0; code < 27; ++code) classify(0, code);
-        } else {
-            classify(0, 13);
-        }
+        ncand = t.periodic ? 27 : 1;
     } else {
-        const int P = t.parent[a];
-        const int npp = ls.npart[P];
-        for (int k = 0; k < npp; ++k) {
-            const int B = ls.part[size_t(P) * 27 + k], code = ls.pcode[size_t(P) * 27 + k];
-            if (ad_leaf(t, B)) {
-                classify(B, code);
+        P = t.parent[a];
+        ncand = 8 * ls.npart[P];
+    }
+    uint32_t base[3] = {0u, 0u, 0u};
+    if (pass == 1)
+        for (int k = 0; k < 3; ++k) base[k] = ls.off[size_t(k) * ncell + a];
+    uint32_t nent[3] = {0u, 0u, 0u};
+    int np = 0;
+    for (int c0 = 0; c0 < ncand; c0 += 64) {
+        const int c = c0 + lane;
+        int b = -1, code = 13;
+        if (c < ncand) {
+            if (l == 0) {
+                b = 0;
+                code = t.periodic ? c : 13;
             } else {
-                for (int o = 0; o < 8; ++o) {
-                    const int b = t.child[8 * B + o];
-                    if (b >= 0) classify(b, code);
-                }
+                const int B = ls.part[size_t(P) * 27 + (c >> 3)];
+                code = ls.pcode[size_t(P) * 27 + (c >> 3)];
+                b = ad_leaf(t, B) ? ((c & 7) == 0 ? B : -1) : t.child[8 * B + (c & 7)];
             }
         }
+        uint32_t cnt[3] = {0u, 0u, 0u}, pos[3];
+        bool partner = false;
+        if (b >= 0) classify(b, code, false, pos, cnt, partner);
+        uint32_t tot[3], ptot;
+        uint32_t pre[3];
+        for (int k = 0; k < 3; ++k) pre[k] = wave_scan(cnt[k], tot[k]);
+        const uint32_t pp = wave_scan(partner ? 1u : 0u, ptot);
+        if (pass == 0 && partner) {
+            const int slot = np + int(pp);
+            if (slot < 27) {
+                ls.part[size_t(a) * 27 + slot] = b;
+                ls.pcode[size_t(a) * 27 + slot] = int8_t(code);
+            } else {
+                bad = true;
+            }
+        }
+        if (pass == 1 && b >= 0) {
+            for (int k = 0; k < 3; ++k) pos[k] = base[k] + nent[k] + pre[k];
+            bool unused = false;
+            classify(b, code, true, pos, cnt, unused);
+        }
+        for (int k = 0; k < 3; ++k) nent[k] += tot[k];
+        np += int(ptot);
     }
-    if (pass == 0) {
+    if (pass == 0 && lane == 0) {
         ls.npart[a] = np < 27 ? np : 27;
-        for (int k = 0; k < 3; ++k) ls.cnt[size_t(k) * ncell + a] = cnt[k];
+        for (int k = 0; k < 3; ++k) ls.cnt[size_t(k) * ncell + a] = nent[k];
     }
     if (bad) atomicExch(ls.err, 1);
 }
@@ -603,7 +641,8 @@ hipError_t launch_ad_permute(hipStream_t s, const AdTreeView &t, int n, const do
 
 hipError_t launch_ad_traverse(hipStream_t s, const AdTreeView &t, const AdLists &ls, int l, int off, int ncl,
                               int pass, int vcell0, int ncell) {
-    hipLaunchKernelGGL(k_ad_traverse, dim3(blocks(ncl, 64)), dim3(64), 0, s, t, ls, l, off, ncl, pass, vcell0, ncell);
+    if (ncl == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ad_traverse, dim3(ncl), dim3(64), 0, s, t, ls, l, off, ncl, pass, vcell0, ncell);
     return hipGetLastError();
 }
 
