@@ -107,10 +107,15 @@ struct AdaptTr {
     int ntarget = 0;                                   // M2M: tcell[0 .. ntarget)
     int cell0 = 0;                                     // M2L: first cell of the stab rows
     const int32_t *stab = nullptr, *parent = nullptr, *child = nullptr;
+    int part_cell0 = 0, part_cells = 0;                // M2L splits: the level's cells [part_cell0, + part_cells)
 };
+// M2L (mode 0) with a partial-sum buffer `part` of part_elems elements: the 189
+// offsets are split over up to 189 workgroups per target tile when a level has
+// too few tiles to fill the chip, and the partial sums are added in fixed order
 template <typename T>
 hipError_t launch_translate_adaptive(hipStream_t s, int mode, int p, int kp, const T *ops, const int16_t *oct_lists,
-                                     const T *src, T *dst, int accumulate, const AdaptTr &ad);
+                                     const T *src, T *dst, int accumulate, const AdaptTr &ad, T *part = nullptr,
+                                     size_t part_elems = 0);
 
 // --- near field (kernels_p2p.hip) ---------------------------------------------
 struct P2PArgs {

@@ -406,7 +406,10 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
         while (octant < 7 && int(blockIdx.x) >= ad.tile_start[octant + 1]) ++octant;
         tile = int(blockIdx.x) - ad.tile_start[octant];
         ncell_t = ad.oct_n[octant];
-        if (mode == 0) npair = 189;
+        if (mode == 0) {
+            pr0 = int(blockIdx.y) * 189 / nsplit;
+            npair = (int(blockIdx.y) + 1) * 189 / nsplit - pr0;
+        }
     } else {                          // M2L / L2L: targets at `level`, grouped by octant
         octant = blockIdx.x & 7;
         tile = blockIdx.x >> 3;
@@ -575,8 +578,9 @@ __global__ void __launch_bounds__(kTrThreads) k_translate(int level, int periodi
     for (int g = 0; g < NT; ++g) {
         const int32_t t = tkey[g * 16 + (lane & 15)];
         if (t < 0) continue;
-        T *out = split ? part + (size_t(blockIdx.y) * (size_t(1) << (3 * level)) + t) * per_cell
-                       : dst + size_t(t) * per_cell;
+        T *out = !split ? dst + size_t(t) * per_cell
+                 : adaptive ? part + (size_t(blockIdx.y) * size_t(ad.part_cells) + size_t(t - ad.part_cell0)) * per_cell
+                            : part + (size_t(blockIdx.y) * (size_t(1) << (3 * level)) + t) * per_cell;
 #pragma unroll
         for (int i = 0; i < NRBW; ++i) {
             const int rb = wave + kTrWaves * i;
@@ -1046,7 +1050,8 @@ hipError_t launch_translate(hipStream_t s, int mode, int level, int periodic, in
 
 template <typename T>
 hipError_t launch_translate_adaptive(hipStream_t s, int mode, int p, int kp, const T *ops, const int16_t *oct_lists,
-                                     const T *src, T *dst, int accumulate, const AdaptTr &ad) {
+                                     const T *src, T *dst, int accumulate, const AdaptTr &ad, T *part,
+                                     size_t part_elems) {
     const int C = (p + 1) * (p + 1);
     const int nrb = tr_nrb(C);
     const int nrbw = nrb / kTrWaves;
@@ -1062,14 +1067,29 @@ hipError_t launch_translate_adaptive(hipStream_t s, int mode, int p, int kp, con
         grid = a.tile_start[8];
     }
     if (grid == 0) return hipSuccess;
+    int nsplit = 1;
+    if (mode == 0 && part != nullptr && a.part_cells > 0 && grid < kTrFillWorkgroups) {
+        nsplit = (kTrFillWorkgroups + grid - 1) / grid;
+        if (nsplit > 189) nsplit = 189;
+        const size_t per_split = size_t(a.part_cells) * 3 * kp;
+        while (nsplit > 1 && size_t(nsplit) * per_split > part_elems) --nsplit;
+    }
+    T *pbuf = nsplit > 1 ? part : nullptr;
     const size_t smem = sizeof(T) * size_t(ttn) * 3 * tr_row_stride<T>(tr_nks(C)) * (sh.pf > 0 ? 2 : 1);
     constexpr int NTP = sizeof(T) == 4 ? 2 : 1;
-    const dim3 g3(grid, 1);
+    const dim3 g3(grid, nsplit);
+    hipError_t e;
     if (sh.pf > 0)
-        return launch_translate_rows<T, NTP, 24>(s, mode, nrbw, g3, smem, 0, 0, C, kp, nrb, ops, oct_lists, nullptr,
-                                                 src, dst, accumulate, 1, nullptr, a);
-    return launch_translate_rows<T, 1, 0>(s, mode, nrbw, g3, smem, 0, 0, C, kp, nrb, ops, oct_lists, nullptr, src,
-                                          dst, accumulate, 1, nullptr, a);
+        e = launch_translate_rows<T, NTP, 24>(s, mode, nrbw, g3, smem, 0, 0, C, kp, nrb, ops, oct_lists, nullptr,
+                                              src, dst, accumulate, nsplit, pbuf, a);
+    else
+        e = launch_translate_rows<T, 1, 0>(s, mode, nrbw, g3, smem, 0, 0, C, kp, nrb, ops, oct_lists, nullptr, src,
+                                           dst, accumulate, nsplit, pbuf, a);
+    if (e != hipSuccess || nsplit == 1) return e;
+    const int64_t nelem = int64_t(a.part_cells) * 3 * kp;
+    hipLaunchKernelGGL(k_split_reduce<T>, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, nelem, kp, C, nsplit,
+                       (const T *)pbuf, dst + size_t(a.part_cell0) * 3 * kp, accumulate);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -1090,7 +1110,7 @@ hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, cons
                                             size_t, const T *, int);                                        \
     template hipError_t launch_lattice<T>(hipStream_t, int, int, const double *, const T *, T *);          \
     template hipError_t launch_translate_adaptive<T>(hipStream_t, int, int, int, const T *, const int16_t *,  \
-                                                     const T *, T *, int, const AdaptTr &);
+                                                     const T *, T *, int, const AdaptTr &, T *, size_t);
 VM_INST(double)
 VM_INST(float)
 #undef VM_INST

@@ -25,6 +25,7 @@ using namespace vmfmm;
 namespace {
 
 constexpr size_t kTrPartBytes = size_t(64) << 20;   // scratch of split M2L launches
+constexpr size_t kAdSplitElems = size_t(8) << 20;  // doubles of the adaptive M2L partial sums (64 MiB)
 
 struct DevBuf {
     void *ptr = nullptr;
@@ -168,6 +169,7 @@ struct vm_ctx {
         DevBuf sstart, scount, rank, tsum, ints;                // construction scratch, device counters
         DevBuf leaf_at, lcell, lstart, llev, iota, items;       // leaves in particle order, target blocks
         DevBuf items16;                                         // M2P target blocks
+        DevBuf tpart;                                           // M2L partial sums of the offset splits
         DevBuf part, pcode, npart, vtab, cnt, off, src, code;   // traversal
         DevBuf tcell, M, L, parts;
         DevBuf rec_c1, rec_c2, rec_dg;                          // recurrence of degree p + 2
@@ -1280,6 +1282,7 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     VM_HIP(ctx->far.reserve(sizeof(double) * 12 * size_t(n)), "alloc far field");
     VM_HIP(A.iota.reserve(sizeof(int32_t) * size_t(ncell)), "alloc cell list");
     VM_HIP(A.tcell.reserve(sizeof(int32_t) * 8 * size_t(ncell)), "alloc octant groups");
+    VM_HIP(A.tpart.reserve(sizeof(double) * kAdSplitElems), "alloc M2L partial sums");
     VM_HIP(launch_iota(s, ncell, A.iota.as<int32_t>(), A.rank.as<uint32_t>()), "cell list");
     double *M = A.M.as<double>(), *L = A.L.as<double>();
     DevTables tab;
@@ -1334,6 +1337,8 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
         ad.parent = t.parent;
         ad.stab = A.vtab.as<int32_t>();
         ad.cell0 = 0;
+        ad.part_cell0 = lo[l];
+        ad.part_cells = nl;
         {
             Timed tm(ctx, VM_PH_L2L);
             VM_HIP(launch_translate_adaptive<double>(s, 1, p, kp, ops->l2l64.as<double>(), lists, L, L, 1, ad),
@@ -1341,7 +1346,8 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
         }
         {
             Timed tm(ctx, VM_PH_M2L);
-            VM_HIP(launch_translate_adaptive<double>(s, 0, p, kp, ops->m2l64.as<double>(), lists, M, L, 1, ad),
+            VM_HIP(launch_translate_adaptive<double>(s, 0, p, kp, ops->m2l64.as<double>(), lists, M, L, 1, ad,
+                                                     A.tpart.as<double>(), kAdSplitElems),
                    "adaptive M2L");
         }
         Timed tm(ctx, VM_PH_P2L);
