@@ -252,15 +252,26 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
         lcell = size_t(lm.cell[leaf]);
     }
     const T *src = lleaf + lcell * 3 * kp;
-    for (int i = lane; i < 3 * C; i += 64) lam[i] = src[(i / C) * kp + (i % C)];
+    // the expansion in 64-element rounds of loads issued together (clamped
+    // indices, unconditional loads), then stored
+    for (int i0 = 0; i0 < 3 * C; i0 += 256) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 64 * u + lane, ic = i < 3 * C ? i : 0;
+            v[u] = src[(ic / C) * kp + (ic % C)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 64 * u + lane;
+            if (i < 3 * C) lam[i] = v[u];
+        }
+    }
+    for (int r = lane; r < 12 * nu; r += 64) coef[r] = T(0);
     __syncthreads();
     const T *tw = Tab<T>::w(tab);
     const int rows = 3 * nu + 9 * ng;
-    for (int r = lane; r < 12 * nu; r += 64) coef[r] = T(0);
-    __syncthreads();
-    for (int r = lane; r < rows; r += 64) {
-        T s = T(0);
-        for (int e = 0; e < width; ++e) s += tw[size_t(e) * rows + r] * lam[tab.l2p_idx[size_t(e) * rows + r]];
+    auto put = [&](int r, T v) {
         int slot, comp;
         if (r < 3 * nu) {
             comp = r / nu;
@@ -269,7 +280,20 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
             comp = 3 + (r - 3 * nu) / ng;
             slot = (r - 3 * nu) % ng;
         }
-        coef[slot * 12 + comp] = s;
+        coef[slot * 12 + comp] = v;
+    };
+    // two rows per lane at a time (r, r + 64): twice the table loads in flight
+    for (int r = lane; r < rows; r += 128) {
+        const int r2 = r + 64;
+        const int rc = r2 < rows ? r2 : r;
+        T s = T(0), s2 = T(0);
+        for (int e = 0; e < width; ++e) {
+            const size_t e0 = size_t(e) * rows;
+            s += tw[e0 + r] * lam[tab.l2p_idx[e0 + r]];
+            s2 += tw[e0 + rc] * lam[tab.l2p_idx[e0 + rc]];
+        }
+        put(r, s);
+        if (r2 < rows) put(r2, s2);
     }
     __syncthreads();
     const T *c1 = Tab<T>::c1(tab), *c2 = Tab<T>::c2(tab), *dg = Tab<T>::dg(tab);
