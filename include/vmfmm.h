@@ -478,8 +478,10 @@ vm_status vm_debug_tree(vm_ctx *ctx, uint32_t *keys, int32_t *perm, int32_t *lea
  *   kp = (p+1)^2 rounded up to a multiple of 32, element type double (FP64
  *   form) or float (mixed form); *bytes receives the size.  `out` is a device
  *   buffer of at least that size, or NULL to query the size only.
- * vm_debug_far: far-field velocity and gradient per particle in sorted order,
- *   device double [12][n] (u_x, u_y, u_z, then J[3a+b]).
+ * vm_debug_far: far-field velocity and gradient per target in sorted order,
+ *   device double [12][n] (u_x, u_y, u_z, then J[3a+b]): the last
+ *   vm_fmm_eval / vm_fmm_eval_at evaluates it again from its local expansions
+ *   (its L2P adds the far field straight into the outputs).
  */
 vm_status vm_debug_expansions(vm_ctx *ctx, int which, int level, void *out, int64_t *bytes);
 vm_status vm_debug_far(vm_ctx *ctx, double *out);

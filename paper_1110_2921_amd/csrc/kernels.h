@@ -67,10 +67,23 @@ hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t
                       int p, int kp, double inv_w, const DevTables &tab, T *m_out,
                       const LeafMap &lm = LeafMap());
 
+// With `near` set, L2P adds the far field it evaluates to the near field a P2P
+// launch stored there (P2PArgs::near, sorted order) and writes u, grad and
+// dalpha in caller order, exactly as the P2P epilogue combines them; `far` is
+// then not written.
+struct NearCombine {
+    const double *near = nullptr;
+    const int32_t *perm = nullptr;   // caller index of each sorted target
+    const double *alpha = nullptr;   // caller order [3][n] (stretching)
+    double *u = nullptr, *dalpha = nullptr, *grad = nullptr;
+    int scheme = 0;
+};
+
 template <typename T>
 hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start,
                       int p, int kp, double inv_w, double w, const DevTables &tab,
-                      const T *l_leaf, double *far, const LeafMap &lm = LeafMap());
+                      const T *l_leaf, double *far, const LeafMap &lm = LeafMap(),
+                      const NearCombine &nc = NearCombine());
 
 // Generic translation GEMM on MFMA: mode 0 = M2L, 1 = L2L, 2 = M2M.
 // `part` (part_elems elements of T, may be null) is scratch for M2L launches
@@ -128,6 +141,10 @@ struct P2PArgs {
     const double *alpha;  // caller order [3][n] (stretching contraction in FP64)
     const double *far;    // sorted order: u[3][n], then J[9][n]
     double *u, *dalpha, *grad;   // caller order
+    // non-null: the near field only, in sorted order, to near[15][n] (u, the
+    // raw gradient sums, the strength sums q alpha; rows 3.. only with grad or
+    // dalpha), combined with the far field afterwards by L2P (NearCombine)
+    double *near = nullptr;
 };
 hipError_t launch_p2p64(hipStream_t s, const P2PArgs &a, const Part64 *parts);
 hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts);

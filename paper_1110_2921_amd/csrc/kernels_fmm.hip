@@ -230,11 +230,45 @@ __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__re
 // Per leaf: velocity / gradient expansions from the sparse table, then per
 // particle u_b = sU sum U_b c(X), J_ab = sJ sum G_ab c(X), written in sorted
 // order as far[0..2][n] (u) and far[3..11][n] (J, index 3a+b).
+constexpr double kInv4PiL2P = 0.079577471545947667884441881686257181;
+
+// u, grad, dalpha of sorted target gi from the near field of a P2P launch and
+// the far field uf, Jf: the P2P epilogue's operations in its order.
+__device__ __forceinline__ void combine_store(const NearCombine &c, size_t n, size_t gi, const double uf[3],
+                                              const double Jf[9]) {
+    const double *nr = c.near;
+    const int oi = c.perm[gi];
+    for (int b = 0; b < 3; ++b) c.u[b * n + oi] = nr[b * n + gi] * kInv4PiL2P + uf[b];
+    if (!c.grad && !c.dalpha) return;
+    double Sd[3];
+    for (int k = 0; k < 3; ++k) Sd[k] = nr[(12 + k) * n + gi];
+    double al[3] = {0.0, 0.0, 0.0};
+    if (c.dalpha)
+        for (int k = 0; k < 3; ++k) al[k] = c.alpha[k * n + oi];
+    double da[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            // antisymmetric part eps_rkm S_m of the near gradient J[r][k]
+            const int m = 3 - r - k;
+            const double anti = r == k ? 0.0 : ((k == (r + 1) % 3) ? Sd[m] : -Sd[m]);
+            const double J = (nr[(3 + 3 * r + k) * n + gi] + anti) * kInv4PiL2P + Jf[3 * r + k];
+            if (c.grad) c.grad[(3 * r + k) * n + oi] = J;
+            if (c.scheme == 0) da[k] += al[r] * J;      // classic: sum_a alpha_a J[a][b]
+            else da[r] += J * al[k];                     // transpose: sum_c J[b][c] alpha_c
+        }
+    }
+    if (c.dalpha)
+        for (int b = 0; b < 3; ++b) c.dalpha[b * n + oi] = da[b];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__restrict__ parts,
                                             const int32_t *__restrict__ start, int n, int p, int kp,
                                             T inv_w, double su, double sj, DevTables tab,
-                                            const T *__restrict__ lleaf, double *__restrict__ far, LeafMap lm) {
+                                            const T *__restrict__ lleaf, double *__restrict__ far, LeafMap lm,
+                                            NearCombine nc) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int C = (p + 1) * (p + 1);
     const int nu = tab.nu, ng = tab.ng, width = tab.l2p_width;
@@ -325,8 +359,15 @@ __global__ void __launch_bounds__(64) k_l2p(const typename PartOf<T>::type *__re
                                  }
                              });
         const size_t gi = size_t(s0) + i;
-        for (int b = 0; b < 3; ++b) far[size_t(b) * n + gi] = double(u[b]) * su;
-        for (int kk = 0; kk < 9; ++kk) far[size_t(3 + kk) * n + gi] = double(J[kk]) * sj;
+        double uf[3], Jf[9];
+        for (int b = 0; b < 3; ++b) uf[b] = double(u[b]) * su;
+        for (int kk = 0; kk < 9; ++kk) Jf[kk] = double(J[kk]) * sj;
+        if (nc.near) {
+            combine_store(nc, size_t(n), gi, uf, Jf);
+        } else {
+            for (int b = 0; b < 3; ++b) far[size_t(b) * n + gi] = uf[b];
+            for (int kk = 0; kk < 9; ++kk) far[size_t(3 + kk) * n + gi] = Jf[kk];
+        }
     }
 }
 
@@ -884,13 +925,13 @@ hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t
 template <typename T>
 hipError_t launch_l2p(hipStream_t s, int nleaf, int n, const void *parts, const int32_t *start, int p,
                       int kp, double inv_w, double w, const DevTables &tab, const T *l_leaf, double *far,
-                      const LeafMap &lm) {
+                      const LeafMap &lm, const NearCombine &nc) {
     const int C = (p + 1) * (p + 1);
     const size_t smem = sizeof(T) * (3 * size_t(C) + 12 * size_t(tab.nu) + 12);
     const double four_pi = 12.566370614359172953850573533118;
     hipLaunchKernelGGL(k_l2p<T>, dim3(nleaf), dim3(64), smem, s, (const typename PartOf<T>::type *)parts,
                        start, n, p, kp, T(inv_w), 1.0 / (four_pi * w * w), 1.0 / (four_pi * w * w * w), tab,
-                       l_leaf, far, lm);
+                       l_leaf, far, lm, nc);
     return hipGetLastError();
 }
 
@@ -1128,7 +1169,7 @@ hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, cons
                                       const DevTables &, T *, const LeafMap &);                             \
     template hipError_t launch_l2p<T>(hipStream_t, int, int, const void *, const int32_t *, int, int,       \
                                       double, double, const DevTables &, const T *, double *,               \
-                                      const LeafMap &);                                                     \
+                                      const LeafMap &, const NearCombine &);                                \
     template hipError_t launch_translate<T>(hipStream_t, int, int, int, int, int, const T *,                \
                                             const int16_t *, const int8_t *, const T *, T *, int, T *,      \
                                             size_t, const T *, int);                                        \

@@ -118,10 +118,15 @@ void triangular(std::vector<double> &m, int C, int p) {
 struct vm_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // the near field runs on `side` while the far field runs on `stream`:
+    // fork and join by events (default priority, non-blocking)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::string err;
 
     // workspace
     DevBuf keys_a, keys_b, vals_a, vals_b, hist, start, p64, p32, far, flag, mbuf, lbuf;
+    DevBuf nearf;    // near field [15][n] of a P2P launch overlapped with the far field
     DevBuf trpart;   // partial sums of M2L launches split over the offsets (coarse levels)
     DevBuf zeros;    // a zero expansion cell read in place of missing M2L sources
     DevBuf mcbuf;    // class-major multipoles of every level for the reflection-orbit M2L
@@ -155,6 +160,16 @@ struct vm_ctx {
     int64_t last_n = 0;
     int last_level = -1;
     int last_p = -1, last_mixed = 0, last_far = 0;
+    // the L2P launch of the last evaluation, re-run by vm_debug_far (the far
+    // field goes straight into the outputs otherwise)
+    struct {
+        bool valid = false;
+        int nleaf = 0, n = 0, p = 0, kp = 0, mixed = 0;
+        double inv_w = 0.0, w = 0.0;
+        const void *tparts = nullptr, *lptr = nullptr;
+        const int32_t *tstart = nullptr;
+        DevTables tab{};
+    } last_l2p;
 
     // device-time accounting
     bool timing = false;
@@ -209,8 +224,10 @@ vm_status hip_fail(vm_ctx *c, hipError_t e, const char *what) {
 // Brackets one launch with a pair of events when timing is enabled.
 struct Timed {
     vm_ctx *ctx;
+    hipStream_t st;
     int ev = -1;
-    Timed(vm_ctx *c, int phase) : ctx(c) {
+    Timed(vm_ctx *c, int phase) : Timed(c, phase, c->stream) {}
+    Timed(vm_ctx *c, int phase, hipStream_t stream) : ctx(c), st(stream) {
         if (!ctx->timing || ctx->timed.size() >= 65536) return;
         const size_t need = 2 * (ctx->timed.size() + 1);
         while (ctx->events.size() < need) {
@@ -220,10 +237,10 @@ struct Timed {
         }
         ev = int(2 * ctx->timed.size());
         ctx->timed.push_back({phase, ev});
-        (void)hipEventRecord(ctx->events[ev], ctx->stream);
+        (void)hipEventRecord(ctx->events[ev], st);
     }
     void stop() {
-        if (ev >= 0) (void)hipEventRecord(ctx->events[ev + 1], ctx->stream);
+        if (ev >= 0) (void)hipEventRecord(ctx->events[ev + 1], st);
         ev = -1;
     }
     ~Timed() { stop(); }
@@ -681,6 +698,7 @@ vm_status build_tree(vm_ctx *ctx, const TreeBufs &b, int ni, const double *x, co
         ctx->last_level = level;
         ctx->last_p = -1;
         ctx->last_far = 0;
+        ctx->last_l2p.valid = false;
     }
     perm = vin;
     parts = mixed ? b.p32->ptr : b.p64->ptr;
@@ -861,6 +879,7 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
     const int64_t ncells = ((int64_t(1) << (3 * (level + 1))) - 1) / 7;
     VM_HIP(ctx->far.reserve(sizeof(double) * 12 * size_t(mi)), "alloc far field");
+    VM_HIP(ctx->nearf.reserve(sizeof(double) * 15 * size_t(mi)), "alloc near field");
     VM_HIP(ctx->trpart.reserve(kTrPartBytes), "alloc split partials");
     if (ctx->zeros.bytes == 0) VM_HIP(ctx->zeros.reserve(tr_zero_elems(coef_stride(ncoef(VM_MAX_P))) * sizeof(double), true),
                                       "alloc zero cell");
@@ -906,10 +925,45 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
         tstart = ctx->t_start.as<int32_t>();
     }
 
-    // --- far field --------------------------------------------------------
+    // --- near field (side stream) and far field (stream), then combine -------
     const int lmin = periodic ? 0 : 2;
     const bool far = level >= lmin && !(periodic && K < 2 && level == 0);
     ctx->last_far = far;
+    P2PArgs a;
+    a.n = mi;
+    a.nleaf = int(nleaf);
+    a.level = level;
+    a.periodic = periodic;
+    a.scheme = opts->scheme;
+    a.have_far = far ? 1 : 0;
+    a.w = g.w;
+    a.sigma = sigma;
+    a.start = start;
+    a.tstart = tstart;
+    a.tparts = tparts;
+    a.perm = tperm;
+    a.alpha = alpha;
+    a.far = ctx->far.as<double>();
+    a.u = u;
+    a.dalpha = y ? nullptr : dalpha_dt;
+    a.grad = grad;
+    auto near_field = [&](hipStream_t st, const P2PArgs &args) -> vm_status {
+        Timed tm(ctx, VM_PH_P2P, st);
+        if (mixed) VM_HIP(launch_p2p32(st, args, ctx->p32.as<Part32>()), "P2P");
+        else VM_HIP(launch_p2p64(st, args, ctx->p64.as<Part64>()), "P2P");
+        return VM_OK;
+    };
+    if (far) {
+        // the near field (VALU) alongside the far field's launches (MFMA,
+        // latency-bound small levels), into the near buffer; L2P joins
+        P2PArgs an = a;
+        an.have_far = 0;
+        an.near = ctx->nearf.as<double>();
+        VM_HIP(hipEventRecord(ctx->ev_fork, s), "fork");
+        VM_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0), "fork");
+        if (vm_status st = near_field(ctx->side, an); st != VM_OK) return st;
+        VM_HIP(hipEventRecord(ctx->ev_join, ctx->side), "join");
+    }
     if (far) {
         DevTables tab;
         tab.c1_64 = ops->c1_64.as<double>(); tab.c2_64 = ops->c2_64.as<double>(); tab.diag_64 = ops->dg_64.as<double>();
@@ -988,9 +1042,22 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                 }
                 have_parent = true;
             }
+            // the near field first (side stream), then L2P adds the far field
+            // and writes the outputs
+            VM_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0), "join");
+            NearCombine nc;
+            nc.near = ctx->nearf.as<double>();
+            nc.perm = tperm;
+            nc.alpha = alpha;
+            nc.u = u;
+            nc.dalpha = y ? nullptr : dalpha_dt;
+            nc.grad = grad;
+            nc.scheme = opts->scheme;
+            auto &ll = ctx->last_l2p;
+            ll = {true, int(nleaf), mi, p, kp, int(f32), g.inv_w, g.w, tparts, lev(L, level), tstart, tab};
             Timed tm(ctx, VM_PH_L2P);
             VM_HIP(launch_l2p<T>(s, int(nleaf), mi, tparts, tstart, p, kp, g.inv_w, g.w, tab, lev(L, level),
-                                 ctx->far.as<double>()),
+                                 ctx->far.as<double>(), LeafMap(), nc),
                    "L2P");
             return VM_OK;
         };
@@ -998,30 +1065,8 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
         if (st != VM_OK) return st;
     }
 
-    // --- near field + combine -----------------------------------------------
-    P2PArgs a;
-    a.n = mi;
-    a.nleaf = int(nleaf);
-    a.level = level;
-    a.periodic = periodic;
-    a.scheme = opts->scheme;
-    a.have_far = far ? 1 : 0;
-    a.w = g.w;
-    a.sigma = sigma;
-    a.start = start;
-    a.tstart = tstart;
-    a.tparts = tparts;
-    a.perm = tperm;
-    a.alpha = alpha;
-    a.far = ctx->far.as<double>();
-    a.u = u;
-    a.dalpha = y ? nullptr : dalpha_dt;
-    a.grad = grad;
-    {
-        Timed tm(ctx, VM_PH_P2P);
-        if (mixed) VM_HIP(launch_p2p32(s, a, ctx->p32.as<Part32>()), "P2P");
-        else VM_HIP(launch_p2p64(s, a, ctx->p64.as<Part64>()), "P2P");
-    }
+    if (!far)
+        if (vm_status st = near_field(s, a); st != VM_OK) return st;
 
     if (!y) {
         auto &le = ctx->last_eval;
@@ -1421,6 +1466,17 @@ vm_status vm_create(vm_ctx **out, int device, void *hip_stream) {
     if (!c) return VM_ENOMEM;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    bool ok = hipSetDevice(device) == hipSuccess &&
+              hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
+    (void)hipSetDevice(prev);
+    if (!ok) {
+        vm_destroy(c);
+        return VM_EDEVICE;
+    }
     *out = c;
     return VM_OK;
 }
@@ -1429,6 +1485,12 @@ void vm_destroy(vm_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->fft_ng > 0) (void)hipfftDestroy(ctx->fft_plan);
     delete ctx;
@@ -2336,9 +2398,18 @@ vm_status vm_debug_expansions(vm_ctx *ctx, int which, int level, void *out, int6
 
 vm_status vm_debug_far(vm_ctx *ctx, double *out) {
     if (!ctx || !out) return VM_EINVAL;
-    if (ctx->last_level < 0 || !ctx->last_far) return fail(ctx, VM_EINVAL, "no far field in the last evaluation");
-    VM_HIP(hipMemcpyAsync(out, ctx->far.ptr, sizeof(double) * 12 * size_t(ctx->last_n), hipMemcpyDeviceToDevice,
-                          ctx->stream), "copy far field");
+    const auto &ll = ctx->last_l2p;
+    if (ctx->last_level < 0 || !ctx->last_far || !ll.valid)
+        return fail(ctx, VM_EINVAL, "no far field in the last evaluation");
+    VM_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    if (ll.mixed)
+        VM_HIP(launch_l2p<float>(ctx->stream, ll.nleaf, ll.n, ll.tparts, ll.tstart, ll.p, ll.kp, ll.inv_w, ll.w,
+                                 ll.tab, static_cast<const float *>(ll.lptr), out),
+               "far field");
+    else
+        VM_HIP(launch_l2p<double>(ctx->stream, ll.nleaf, ll.n, ll.tparts, ll.tstart, ll.p, ll.kp, ll.inv_w, ll.w,
+                                  ll.tab, static_cast<const double *>(ll.lptr), out),
+               "far field");
     return VM_OK;
 }
 

@@ -380,3 +380,40 @@ def test_reflection_orbit_m2l_at_level_7(ctx):
     torch.cuda.empty_cache()
     close(out["mixed"][0], out["fp64"][0], MIXED_U, "u mixed vs fp64, level 7")
     close(out["mixed"][1], out["fp64"][1], MIXED_J, "J mixed vs fp64, level 7")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_far_field_view_adds_up_with_the_near_field(ctx, precision):
+    """vm_debug_far evaluates the last evaluation's far field again (the
+    evaluation itself adds it straight into its outputs): with the near field,
+    the exact kernel over the 27 neighbour leaves and their images summed by
+    the oracle's direct sum, it gives the velocity and gradient returned."""
+    import itertools
+    level, s = 2, 4
+    x, a = W.particles_with_leaf_counts([8] * 64, level, 13)
+    sigma, p, n = 0.12, 6, 512
+    print(f"[fmm] far-field view {precision}", flush=True)
+    u, _, J = _run(ctx, x, a, sigma, p, level, periodic=1, precision=precision)
+    far = ctx.debug_far(n)
+    _, perm, _ = ctx.debug_tree(n, level)
+    c = np.floor(x / (L / s)).astype(np.int64)
+    leaf = c[:, 0] + s * (c[:, 1] + s * c[:, 2])
+    un, Jn = np.zeros((n, 3)), np.zeros((n, 3, 3))
+    for t in range(s ** 3):
+        ti = np.nonzero(leaf == t)[0]
+        tc = np.array([t % s, (t // s) % s, t // (s * s)])
+        xs, as_ = [], []
+        for d in itertools.product((-1, 0, 1), repeat=3):
+            nc = tc + np.array(d)
+            js = np.nonzero(leaf == (nc % s)[0] + s * ((nc % s)[1] + s * (nc % s)[2]))[0]
+            xs.append(x[js] + (nc // s) * L)
+            as_.append(a[js])
+        ud, Jd = D.direct(x[ti], np.concatenate(xs), np.concatenate(as_), sigma, L, K=0)
+        un[ti], Jn[ti] = ud, Jd.reshape(-1, 3, 3)
+    want_u = (u - un)[perm]
+    want_J = (J - Jn).reshape(n, 9)[perm]
+    # mixed: the outputs carry the FP32 near field's rounding (near field
+    # larger than the far one), so the gate is the mixed one on the totals
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    assert np.max(np.abs(far[:3].T - want_u)) < tol * np.max(np.abs(u))
+    assert np.max(np.abs(far[3:].T - want_J)) < 10 * tol * np.max(np.abs(J))
