@@ -678,7 +678,8 @@ vm_status build_tree(vm_ctx *ctx, const TreeBufs &b, int ni, const double *x, co
     VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * (size_t(nblk) * 256 + size_t(nblk) * 256 / 4096 + 256)),
            "alloc histogram");
     VM_HIP(b.start->reserve(sizeof(int32_t) * size_t(nleaf + 1)), "alloc leaf ranges");
-    if (mixed) VM_HIP(b.p32->reserve(sizeof(Part32) * n), "alloc particles");
+    // one record to spare: the FP32 P2P prefetches one record past a block's end
+    if (mixed) VM_HIP(b.p32->reserve(sizeof(Part32) * (size_t(n) + 1)), "alloc particles");
     else VM_HIP(b.p64->reserve(sizeof(Part64) * n), "alloc particles");
 
     int32_t *start = b.start->as<int32_t>();
@@ -1603,7 +1604,7 @@ vm_status adjoint_impl(vm_ctx *ctx, int64_t n, const double *x, const double *al
     VM_HIP(ctx->adj_v.reserve(v3), "alloc adjoint");
     VM_HIP(ctx->adj_Jv.reserve(v9), "alloc adjoint");
     VM_HIP(ctx->adj_far.reserve(2 * v3), "alloc adjoint");
-    if (mixed) VM_HIP(ctx->adj_p32.reserve(sizeof(Part32) * n), "alloc adjoint");
+    if (mixed) VM_HIP(ctx->adj_p32.reserve(sizeof(Part32) * (size_t(n) + 1)), "alloc adjoint");
     else VM_HIP(ctx->adj_p64.reserve(sizeof(Part64) * n), "alloc adjoint");
     const int32_t *start = ctx->start.as<int32_t>();
     const int32_t *perm = ctx->last_perm;
