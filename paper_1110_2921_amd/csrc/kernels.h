@@ -396,6 +396,9 @@ hipError_t launch_split_reduce(hipStream_t s, int level, int kp, int C, int nspl
                                int accumulate);
 hipError_t launch_split_reduce64(hipStream_t s, int level, int kp, int C, int nsplit, const double *part,
                                  double *dst, int accumulate);
+// the same over nelem = cells * 3 * kp elements of dst (the cells of a split launch)
+hipError_t launch_split_reduce64_n(hipStream_t s, int64_t nelem, int kp, int C, int nsplit, const double *part,
+                                   double *dst, int accumulate);
 // True if the symmetric M2L kernel is built for degree p.
 bool m2l_sym_supported(int p);
 // M2L at `level` (FP32): dst[cell] (+)= sum over the interaction list, from the
@@ -407,11 +410,34 @@ hipError_t launch_m2l_sym(hipStream_t s, int level, int periodic, int p, int kp,
                           const float *ops, const int32_t *op_off, const int32_t *orbits, const int16_t *row_std,
                           float *dst, int accumulate, float *part, size_t part_elems);
 
+// Targets and sources of one level of an adaptive tree for the FP64 orbit
+// M2L: the level's cells grouped by octant, tcell[oct_base[o] ..] of oct_n[o]
+// cells (global cell indices); vtab[cell - cell0][189] the source cell of each
+// slot of the cell's octant list (-1: none), vslot[8][343] the slot of offset
+// d = source - target (index (dx+3) + 7 (dy+3) + 49 (dz+3)) in octant o's list;
+// split partials indexed by cell - part_cell0 over part_cells cells.
+struct SymAdapt {
+    const int32_t *tcell = nullptr, *vtab = nullptr;
+    const int16_t *vslot = nullptr;
+    int tile_start[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // set by the launcher
+    int oct_base[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int oct_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int cell0 = 0, part_cell0 = 0, part_cells = 0;
+};
+
 // FP64 form of launch_m2l_sym: class-major FP64 multipoles mc (zero_cell as
 // there), operators per octant stored per column slice, sl_off[8][56 nblk + 1]
 // the offsets (doubles) of the slices of orbit o, column b at o nblk + b.
 hipError_t launch_m2l_sym64(hipStream_t s, int level, int periodic, int p, int kp, const double *mc,
                             int64_t zero_cell, const double *ops, const int32_t *sl_off, const int32_t *orbits,
                             const int16_t *row_std, double *dst, int accumulate, double *part, size_t part_elems);
+// The same for one level of an adaptive tree: mc the class-major multipoles of
+// every cell (zero_cell: their count), dst the locals of every cell; the
+// level's orbit ranges split over workgroups (partials in `part`) when its
+// tiles do not fill the chip.
+hipError_t launch_m2l_sym64_adaptive(hipStream_t s, int p, int kp, const double *mc, int64_t zero_cell,
+                                     const double *ops, const int32_t *sl_off, const int32_t *orbits,
+                                     const int16_t *row_std, double *dst, int accumulate, const SymAdapt &ad,
+                                     double *part, size_t part_elems);
 
 }  // namespace vmfmm

@@ -1010,6 +1010,13 @@ hipError_t launch_split_reduce64(hipStream_t s, int level, int kp, int C, int ns
     return hipGetLastError();
 }
 
+hipError_t launch_split_reduce64_n(hipStream_t s, int64_t nelem, int kp, int C, int nsplit, const double *part,
+                                   double *dst, int accumulate) {
+    hipLaunchKernelGGL(k_split_reduce<double>, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, nelem, kp, C,
+                       nsplit, part, dst, accumulate);
+    return hipGetLastError();
+}
+
 hipError_t launch_split_reduce(hipStream_t s, int level, int kp, int C, int nsplit, const float *part, float *dst,
                                int accumulate) {
     const int64_t nelem = (int64_t(1) << (3 * level)) * 3 * kp;

@@ -271,7 +271,9 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym(int level, int periodic
 // right after its MFMAs.  Blocks are stored as [half][lane group][row][2].
 constexpr int kRing = 8;
 
-template <int P>
+// AD: the targets and sources of an adaptive tree's level (SymAdapt) instead
+// of a uniform level's cells.
+template <int P, bool AD>
 __global__ void __launch_bounds__(kSymThreads) k_m2l_sym64(int level, int periodic, int kp,
                                                            const double *__restrict__ mc, uint32_t zero_off,
                                                            const double *__restrict__ ops,
@@ -279,7 +281,7 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym64(int level, int period
                                                            const int32_t *__restrict__ orbits,
                                                            const int16_t *__restrict__ row_std,
                                                            double *__restrict__ dst, int accumulate, int nsplit,
-                                                           double *__restrict__ part) {
+                                                           double *__restrict__ part, SymAdapt ad) {
     typedef double d2 __attribute__((ext_vector_type(2)));
     typedef double d4 __attribute__((ext_vector_type(4)));
     constexpr SymLayout SL = sym_layout(P);
@@ -295,18 +297,32 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym64(int level, int period
     __shared__ int32_t sorb[kSymOrbits];
     __shared__ int32_t ssl[NSL];
     __shared__ int16_t srow[KC];
+    __shared__ int16_t svs[AD ? 343 : 1];   // adaptive: slot of offset d in the octant's list
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int comp = wave % 3, tg = wave / 3;
     const int h = lane >> 4, col = lane & 15;
-    const int octant = blockIdx.x & 7, tile = blockIdx.x >> 3;
+    int octant, tile;
+    int64_t ncell_t;
+    if constexpr (AD) {
+        // octant groups of the level: tile_start[o] .. tile_start[o + 1] - 1
+        octant = 0;
+        while (octant < 7 && int(blockIdx.x) >= ad.tile_start[octant + 1]) ++octant;
+        tile = int(blockIdx.x) - ad.tile_start[octant];
+        ncell_t = ad.oct_n[octant];
+    } else {
+        octant = blockIdx.x & 7;
+        tile = blockIdx.x >> 3;
+        ncell_t = int64_t(1) << (3 * (level - 1));
+    }
     const int o0 = int(blockIdx.y) * kSymOrbits / nsplit;
     const int o1 = (int(blockIdx.y) + 1) * kSymOrbits / nsplit;
     const int nk = (o1 - o0) * NB;
-    const int64_t ncell_t = int64_t(1) << (3 * (level - 1));
     const int side = 1 << level;
 
+    if constexpr (AD)
+        for (int i = tid; i < 343; i += NT) svs[i] = ad.vslot[octant * 343 + i];
     if (tid < kSymOrbits) sorb[tid] = orbits[tid];
     for (int i = tid; i < NSL; i += NT) ssl[i] = sl_off[octant * NSL + i];
     for (int i = tid; i < KC; i += NT) srow[i] = row_std[i];
@@ -320,7 +336,9 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym64(int level, int period
     }
     const int64_t slot = int64_t(tile) * TT + tg * 16 + col;
     const bool tvalid = slot < ncell_t;
-    const uint32_t tkey = tvalid ? uint32_t((slot << 3) | octant) : 0u;
+    // uniform: the target's key at the level; adaptive: its cell index
+    const uint32_t tkey = !tvalid ? 0u : AD ? uint32_t(ad.tcell[ad.oct_base[octant] + slot])
+                                          : uint32_t((slot << 3) | octant);
     const int tc[3] = {int(compact3(tkey)), int(compact3(tkey >> 1)), int(compact3(tkey >> 2))};
     __syncthreads();
 
@@ -328,6 +346,29 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym64(int level, int period
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(mc), 0, -1, 0x00020000);
     auto members = [&](int o) {
         const int info = sorb[o];
+        if constexpr (AD) {
+            // the source of each member offset from the target's table row
+            const int32_t *row = ad.vtab + size_t(tvalid ? int(tkey) - ad.cell0 : 0) * 189;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                int src = -1;
+                if (!(r & ~((info >> 6) & 7)) && tvalid) {
+                    int idx = 0, mul = 1;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const int rep = (info >> (2 * a)) & 3;
+                        int d = ((r >> a) & 1) ? -rep : rep;
+                        if ((octant >> a) & 1) d = -d;
+                        idx += (d + 3) * mul;
+                        mul *= 7;
+                    }
+                    const int sl = svs[idx];   // every member offset is in the octant's list
+                    src = sl >= 0 ? row[sl] : -1;
+                }
+                mo[r] = (src >= 0 ? uint32_t(src) * uint32_t(CELL) : zero_off) * 8u + uint32_t(32 * h);
+            }
+            return;
+        }
         const int G = (info >> 6) & 7;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
@@ -443,7 +484,9 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym64(int level, int period
     }
     if (!tvalid) return;
     const bool split = part != nullptr;
-    double *out = (split ? part + (size_t(blockIdx.y) * (size_t(1) << (3 * level)) + tkey) * 3 * kp
+    const size_t tslot = AD ? size_t(tkey) - size_t(ad.part_cell0) : size_t(tkey);
+    const size_t pstride = AD ? size_t(ad.part_cells) : (size_t(1) << (3 * level));
+    double *out = (split ? part + (size_t(blockIdx.y) * pstride + tslot) * 3 * kp
                          : dst + size_t(tkey) * 3 * kp) + comp * kp;
     static_for<NB>([&](auto ai) {
         constexpr int A = decltype(ai)::value;
@@ -486,11 +529,45 @@ hipError_t launch_m2l_sym64(hipStream_t s, int level, int periodic, int p, int k
     if (nsplit > kSymOrbits) nsplit = kSymOrbits;
     double *pbuf = nsplit > 1 ? part : nullptr;
     const dim3 grid(unsigned((ncell_t + kSymTargets - 1) / kSymTargets * 8), unsigned(nsplit));
-    hipLaunchKernelGGL(k_m2l_sym64<10>, grid, dim3(kSymThreads), smem, s, level, periodic, kp, mc,
-                       uint32_t(zero_cell * 3 * KC), ops, sl_off, orbits, row_std, dst, accumulate, nsplit, pbuf);
+    hipLaunchKernelGGL((k_m2l_sym64<10, false>), grid, dim3(kSymThreads), smem, s, level, periodic, kp, mc,
+                       uint32_t(zero_cell * 3 * KC), ops, sl_off, orbits, row_std, dst, accumulate, nsplit, pbuf,
+                       SymAdapt());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nsplit == 1) return e;
     return launch_split_reduce64(s, level, kp, SL.C, nsplit, pbuf, dst, accumulate);
+}
+
+hipError_t launch_m2l_sym64_adaptive(hipStream_t s, int p, int kp, const double *mc, int64_t zero_cell,
+                                     const double *ops, const int32_t *sl_off, const int32_t *orbits,
+                                     const int16_t *row_std, double *dst, int accumulate, const SymAdapt &ad_in,
+                                     double *part, size_t part_elems) {
+    if (!m2l_sym_supported(p)) return hipErrorInvalidValue;
+    constexpr SymLayout SL = sym_layout(10);
+    constexpr int KC = 16 * SL.nblk;
+    if ((uint64_t(zero_cell) + 1) * 3 * KC * sizeof(double) > (uint64_t(1) << 32)) return hipErrorInvalidValue;
+    SymAdapt ad = ad_in;
+    ad.tile_start[0] = 0;
+    for (int o = 0; o < 8; ++o) ad.tile_start[o + 1] = ad.tile_start[o] + (ad.oct_n[o] + kSymTargets - 1) / kSymTargets;
+    const int grid = ad.tile_start[8];
+    if (grid == 0) return hipSuccess;
+    // orbit-range splits while the level's tiles do not fill the chip
+    int nsplit = 1;
+    if (part != nullptr && ad.part_cells > 0 && grid < 1024) {
+        nsplit = (1024 + grid - 1) / grid;
+        if (nsplit > kSymOrbits) nsplit = kSymOrbits;
+        const size_t per_split = size_t(ad.part_cells) * 3 * kp;
+        while (nsplit > 1 && size_t(nsplit) * per_split > part_elems) --nsplit;
+    }
+    double *pbuf = nsplit > 1 ? part : nullptr;
+    const size_t smem = sizeof(double) * size_t(kRing) * size_t(16 * SL.C + 32);
+    hipLaunchKernelGGL((k_m2l_sym64<10, true>), dim3(unsigned(grid), unsigned(nsplit)), dim3(kSymThreads), smem, s,
+                       0, 0, kp, mc, uint32_t(zero_cell * 3 * KC), ops, sl_off, orbits, row_std, dst, accumulate,
+                       nsplit, pbuf, ad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsplit == 1) return e;
+    const int64_t nelem = int64_t(ad.part_cells) * 3 * kp;
+    return launch_split_reduce64_n(s, nelem, kp, SL.C, nsplit, pbuf, dst + size_t(ad.part_cell0) * 3 * kp,
+                                   accumulate);
 }
 
 hipError_t launch_m2l_sym(hipStream_t s, int level, int periodic, int p, int kp, const float *mc, int64_t zero_cell,

@@ -26,6 +26,7 @@ namespace {
 
 constexpr size_t kTrPartBytes = size_t(64) << 20;   // scratch of split M2L launches
 constexpr size_t kAdSplitElems = size_t(8) << 20;  // doubles of the adaptive M2L partial sums (64 MiB)
+constexpr int kAdSymMinCells = 256;   // adaptive levels with fewer cells keep the dense M2L
 
 struct DevBuf {
     void *ptr = nullptr;
@@ -185,6 +186,7 @@ struct vm_ctx {
         DevBuf leaf_at, lcell, lstart, llev, iota, items;       // leaves in particle order, target blocks
         DevBuf items16;                                         // M2P target blocks
         DevBuf tpart;                                           // M2L partial sums of the offset splits
+        DevBuf mc;                                              // class-major multipoles (orbit M2L)
         DevBuf part, pcode, npart, vtab, cnt, off, src, code;   // traversal
         DevBuf tcell, M, L, parts;
         DevBuf rec_c1, rec_c2, rec_dg;                          // recurrence of degree p + 2
@@ -1189,6 +1191,10 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     if (K >= 2)
         if (vm_status st = ensure_lattice(ctx, p, K, &tlat); st != VM_OK) return st;
     if (vm_status st = ensure_ad_tables(ctx, p); st != VM_OK) return st;
+    // M2L by reflection orbits at the levels with enough cells (p = 10)
+    const bool ad_sym = m2l_sym_supported(p);
+    if (ad_sym)
+        if (vm_status st = ensure_sym_ops(ctx, ops, 0); st != VM_OK) return st;
     const int C = ncoef(p), kp = coef_stride(C);
     A.valid = false;
     ++ctx->tree_gen;
@@ -1329,6 +1335,8 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     VM_HIP(A.iota.reserve(sizeof(int32_t) * size_t(ncell)), "alloc cell list");
     VM_HIP(A.tcell.reserve(sizeof(int32_t) * 8 * size_t(ncell)), "alloc octant groups");
     VM_HIP(A.tpart.reserve(sizeof(double) * kAdSplitElems), "alloc M2L partial sums");
+    const int ad_kc = 16 * sym_layout(p).nblk;
+    if (ad_sym) VM_HIP(A.mc.reserve(sizeof(double) * (size_t(ncell) + 1) * 3 * ad_kc), "alloc class-major multipoles");
     VM_HIP(launch_iota(s, ncell, A.iota.as<int32_t>(), A.rank.as<uint32_t>()), "cell list");
     double *M = A.M.as<double>(), *L = A.L.as<double>();
     DevTables tab;
@@ -1364,6 +1372,11 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
         VM_HIP(launch_translate_adaptive<double>(s, 2, p, kp, ops->m2m64.as<double>(), lists, M, M, 0, ad),
                "adaptive M2M");
     }
+    if (ad_sym) {
+        Timed tm(ctx, VM_PH_M2L);
+        VM_HIP(launch_sym_pack<double>(s, ncell, kp, ad_kc, M, ops->sym_mcsrc.as<int16_t>(), A.mc.as<double>()),
+               "M2L class-major multipoles");
+    }
     if (K >= 2) {
         Timed tm(ctx, VM_PH_LATTICE);
         VM_HIP(launch_lattice<double>(s, p, kp, tlat, M, L), "lattice");
@@ -1392,9 +1405,28 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
         }
         {
             Timed tm(ctx, VM_PH_M2L);
-            VM_HIP(launch_translate_adaptive<double>(s, 0, p, kp, ops->m2l64.as<double>(), lists, M, L, 1, ad,
-                                                     A.tpart.as<double>(), kAdSplitElems),
-                   "adaptive M2L");
+            if (ad_sym && nl >= kAdSymMinCells) {
+                SymAdapt sa;
+                sa.tcell = A.tcell.as<int32_t>();
+                sa.vtab = A.vtab.as<int32_t>();
+                sa.vslot = A.vslot.as<int16_t>();
+                for (int o = 0; o < 8; ++o) {
+                    sa.oct_base[o] = o * nl;
+                    sa.oct_n[o] = oc[o];
+                }
+                sa.cell0 = 0;
+                sa.part_cell0 = lo[l];
+                sa.part_cells = nl;
+                VM_HIP(launch_m2l_sym64_adaptive(s, p, kp, A.mc.as<double>(), ncell, ops->sym[0].ops64.as<double>(),
+                                                 ops->sym[0].sl64.as<int32_t>(), ops->sym_orb.as<int32_t>(),
+                                                 ops->sym_row.as<int16_t>(), L, 1, sa, A.tpart.as<double>(),
+                                                 kAdSplitElems),
+                       "adaptive M2L");
+            } else {
+                VM_HIP(launch_translate_adaptive<double>(s, 0, p, kp, ops->m2l64.as<double>(), lists, M, L, 1, ad,
+                                                         A.tpart.as<double>(), kAdSplitElems),
+                       "adaptive M2L");
+            }
         }
         Timed tm(ctx, VM_PH_P2L);
         VM_HIP(launch_ad_p2l(s, t, ls, lo[l], nl, ncell, p, kp, tabI, parts, L), "adaptive P2L");

@@ -106,6 +106,25 @@ def test_uniform_tree_equals_uniform_fmm(ctx):
         assert rel(u, uu) < 1e-12 and rel(J, Ju) < 1e-12 and rel(da, dau) < 1e-12, periodic
 
 
+@pytest.mark.parametrize("ml,periodic", [(3, 0), (3, 3), (4, 0), (4, 1)])
+def test_orbit_m2l_on_a_uniform_tree(ctx, ml, periodic):
+    """p = 10 runs the reflection-orbit M2L on the adaptive levels of at least
+    256 cells, its sources looked up in the cells' M2L tables; on a tree that
+    happens to be uniform the adaptive evaluation equals the uniform one (which
+    runs the dense M2L at level 3 and its own coordinate-gathering orbit kernel
+    at level 4), free space (missing sources) and periodic."""
+    x, a = W.particles_with_leaf_counts([8] * (8 ** ml), ml, 31 + ml)
+    sigma, p = L / (4 << ml), 10
+    print(f"[adaptive] orbit M2L on a uniform tree: level {ml} K={periodic}", flush=True)
+    u, da, J = _run(ctx, x, a, sigma, p, 7, ml, periodic)
+    uu, dau, Ju = ctx.eval(_dev(x), _dev(a), sigma, p, ml, periodic=periodic, want_grad=True)
+    torch.cuda.synchronize()
+    uu, dau, Ju = _host(uu), _host(dau), _host(Ju).reshape(-1, 3, 3)
+    cells = ctx.debug_adaptive("cells")
+    assert np.all(cells[cells[:, 5] == 1, 1] == ml)
+    assert rel(u, uu) < 1e-12 and rel(J, Ju) < 1e-12 and rel(da, dau) < 1e-12
+
+
 @pytest.mark.parametrize("periodic", [0, 1])
 def test_one_leaf_is_the_direct_sum(ctx, periodic):
     x, a = W.clustered_particles(200, 4)
