@@ -239,6 +239,7 @@ struct AdTreeView {
     const int32_t *level, *start, *count, *parent, *child;   // child: [cell][8], -1 absent
     int ncrit, max_level, periodic;
     double lo[3], box_len, inv_len;
+    const double *ctr = nullptr;   // [cell][4] centres (x, y, z, 0) once launch_ad_centres has run
 };
 // Interaction lists: partners (unresolved touching pairs a cell hands to its
 // children), the M2L table, and P2P / M2P / P2L lists in CSR form.
@@ -255,6 +256,9 @@ struct AdLists {
     int *err;                 // set on a partner overflow or an M2L offset outside the list
 };
 hipError_t launch_ad_root(hipStream_t s, const AdTreeView &t, int n);
+// the centres of the ncell cells into ctr[cell][4] (the cell-particle and near
+// field kernels read them instead of decoding keys)
+hipError_t launch_ad_centres(hipStream_t s, const AdTreeView &t, int ncell, double *ctr);
 // children of the cells [off, off + ncl) of one level; writes the next level's
 // cells from off + ncl on, and their number to *nnext
 hipError_t launch_ad_level(hipStream_t s, const AdTreeView &t, int off, int ncl, const uint32_t *fine_keys,

@@ -60,9 +60,23 @@ __device__ __forceinline__ bool touching(const AdTreeView &t, int a, int b, int 
 }
 
 __device__ __forceinline__ void centre(const AdTreeView &t, int c, double out[3]) {
+    if (t.ctr) {
+        for (int d = 0; d < 3; ++d) out[d] = t.ctr[4 * size_t(c) + d];
+        return;
+    }
     const int l = t.level[c];
     const double w = ldexp(t.box_len, -l);
     for (int d = 0; d < 3; ++d) out[d] = t.lo[d] + (double(ad_coord(t.key[c], d, l)) + 0.5) * w;
+}
+
+__global__ void __launch_bounds__(256) k_ad_centres(AdTreeView t, int ncell, double *__restrict__ ctr) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    t.ctr = nullptr;
+    double v[3];
+    centre(t, c, v);
+    for (int d = 0; d < 3; ++d) ctr[4 * size_t(c) + d] = v[d];
+    ctr[4 * size_t(c) + 3] = 0.0;
 }
 
 // ------------------------------------------------------------- construction ----
@@ -597,6 +611,12 @@ __global__ void __launch_bounds__(256) k_ad_block_fill(int nleaf, const int32_t 
 inline int blocks(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
+
+hipError_t launch_ad_centres(hipStream_t s, const AdTreeView &t, int ncell, double *ctr) {
+    if (ncell == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ad_centres, dim3(blocks(ncell, 256)), dim3(256), 0, s, t, ncell, ctr);
+    return hipGetLastError();
+}
 
 hipError_t launch_ad_root(hipStream_t s, const AdTreeView &t, int n) {
     hipLaunchKernelGGL(k_ad_root, dim3(1), dim3(64), 0, s, t, n);

@@ -187,6 +187,7 @@ struct vm_ctx {
         DevBuf items16;                                         // M2P target blocks
         DevBuf tpart;                                           // M2L partial sums of the offset splits
         DevBuf mc;                                              // class-major multipoles (orbit M2L)
+        DevBuf ctr;                                             // cell centres
         DevBuf part, pcode, npart, vtab, cnt, off, src, code;   // traversal
         DevBuf tcell, M, L, parts;
         DevBuf rec_c1, rec_c2, rec_dg;                          // recurrence of degree p + 2
@@ -1274,6 +1275,9 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     if (vm_status st = read_ints(ctx, dints + 3, &nitem, 1); st != VM_OK) return st;
     VM_HIP(A.parts.reserve(sizeof(Part64) * size_t(n)), "alloc particles");
     Part64 *parts = A.parts.as<Part64>();
+    VM_HIP(A.ctr.reserve(sizeof(double) * 4 * size_t(ncell)), "alloc cell centres");
+    VM_HIP(launch_ad_centres(s, t, ncell, A.ctr.as<double>()), "cell centres");
+    t.ctr = A.ctr.as<double>();
     VM_HIP(launch_ad_permute(s, t, n, x, alpha, vin, nleaf, A.lcell.as<int32_t>(), parts), "adaptive permute");
 
     // --- dual traversal: counting pass (partners), offsets, filling pass --------
