@@ -62,10 +62,13 @@ struct LeafMap {
     double box_len = 0.0, inv_len = 0.0;
 };
 
+// With mc_out, the multipoles go also to the class-major copy of the orbit M2L
+// (mc_out[leaf][3][kc], position mc_pos[standard index]).
 template <typename T>
 hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t *start,
                       int p, int kp, double inv_w, const DevTables &tab, T *m_out,
-                      const LeafMap &lm = LeafMap());
+                      const LeafMap &lm = LeafMap(), T *mc_out = nullptr, const int16_t *mc_pos = nullptr,
+                      int kc = 0);
 
 // With `near` set, L2P adds the far field it evaluates to the near field a P2P
 // launch stored there (P2PArgs::near, sorted order) and writes u, grad and
@@ -392,6 +395,10 @@ constexpr int kSymMinLevel = 4;
 // position q of block k (-1: zero).  Cell `ncells` of Mc is written as zeros.
 template <typename T>
 hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const T *M, const int16_t *mc_src, T *Mc);
+// The same for the first npack cells only, the zero cell at index zero_cell.
+template <typename T>
+hipError_t launch_sym_pack_range(hipStream_t s, int64_t npack, int64_t zero_cell, int kp, int kc, const T *M,
+                                 const int16_t *mc_src, T *Mc);
 // Offset-range splits of an M2L launch of `level` with `ttn` targets per
 // workgroup (enough workgroups to fill the chip, within part_elems), and the
 // fixed-order sum of the splits' partials into dst (rows < C).

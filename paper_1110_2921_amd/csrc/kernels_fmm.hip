@@ -157,7 +157,8 @@ template <typename T, int PT>
 __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__restrict__ parts,
                                             const int32_t *__restrict__ start, int nleaf, int p, int kp,
                                             T inv_w, DevTables tab, MGroups grp, T *__restrict__ mout,
-                                            LeafMap lm) {
+                                            LeafMap lm, T *__restrict__ mcout, const int16_t *__restrict__ mc_pos,
+                                            int kc) {
     static_assert(PT == 0 || p2m_groups(PT).ng > 0, "no partition of the orders for this degree");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = threadIdx.x;
@@ -224,6 +225,11 @@ __global__ void __launch_bounds__(64) k_p2m(const typename PartOf<T>::type *__re
     const int sidx = m == 0 ? n * n : n * n + 2 * m - 1 + part;
     T *dst = mout + mcell * 3 * kp;
     for (int c = 0; c < 3; ++c) dst[c * kp + sidx] = acc[c];
+    if (mcout) {
+        // the class-major copy the reflection-orbit M2L reads (padding stays zero)
+        T *mc = mcout + mcell * 3 * kc + mc_pos[sidx];
+        for (int c = 0; c < 3; ++c) mc[c * kc] = acc[c];
+    }
 }
 
 // ---------------------------------------------------------------- L2P ----
@@ -906,7 +912,8 @@ __global__ void __launch_bounds__(256) k_lattice(int C, int kp, const double *__
 
 template <typename T>
 hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t *start, int p, int kp,
-                      double inv_w, const DevTables &tab, T *m_out, const LeafMap &lm) {
+                      double inv_w, const DevTables &tab, T *m_out, const LeafMap &lm, T *mc_out,
+                      const int16_t *mc_pos, int kc) {
     const MGroups grp = p2m_groups(p);
     if (grp.ng == 0) return hipErrorInvalidValue;
     const size_t smem = sizeof(T) * (size_t(64) * (grp.maxn + 1) + 64 * 3);
@@ -914,10 +921,10 @@ hipError_t launch_p2m(hipStream_t s, int nleaf, const void *parts, const int32_t
     const dim3 grid(unsigned(nleaf) * grp.ng);
     // the degrees of the workloads at compile time, any other at run time
     switch (p) {
-    case 6: hipLaunchKernelGGL((k_p2m<T, 6>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm); break;
-    case 8: hipLaunchKernelGGL((k_p2m<T, 8>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm); break;
-    case 10: hipLaunchKernelGGL((k_p2m<T, 10>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm); break;
-    default: hipLaunchKernelGGL((k_p2m<T, 0>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm);
+    case 6: hipLaunchKernelGGL((k_p2m<T, 6>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm, mc_out, mc_pos, kc); break;
+    case 8: hipLaunchKernelGGL((k_p2m<T, 8>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm, mc_out, mc_pos, kc); break;
+    case 10: hipLaunchKernelGGL((k_p2m<T, 10>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm, mc_out, mc_pos, kc); break;
+    default: hipLaunchKernelGGL((k_p2m<T, 0>), grid, dim3(64), smem, s, pp, start, nleaf, p, kp, T(inv_w), tab, grp, m_out, lm, mc_out, mc_pos, kc);
     }
     return hipGetLastError();
 }
@@ -1173,7 +1180,7 @@ hipError_t launch_lattice(hipStream_t s, int p, int kp, const double *tlat, cons
 
 #define VM_INST(T)                                                                                          \
     template hipError_t launch_p2m<T>(hipStream_t, int, const void *, const int32_t *, int, int, double,    \
-                                      const DevTables &, T *, const LeafMap &);                             \
+                                      const DevTables &, T *, const LeafMap &, T *, const int16_t *, int);  \
     template hipError_t launch_l2p<T>(hipStream_t, int, int, const void *, const int32_t *, int, int,       \
                                       double, double, const DevTables &, const T *, double *,               \
                                       const LeafMap &, const NearCombine &);                                \

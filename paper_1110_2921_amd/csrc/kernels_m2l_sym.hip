@@ -54,16 +54,22 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
     return v;
 }
 
+// Elements [0, npack) from M (cell-major, 3 components of kc), then the 3 kc
+// elements of the zero cell at element zero_off.
 template <typename T>
-__global__ void __launch_bounds__(256) k_sym_pack(int64_t nelem, int kp, int kc, const T *__restrict__ M,
-                                                  const int16_t *__restrict__ mc_src, T *__restrict__ Mc) {
+__global__ void __launch_bounds__(256) k_sym_pack(int64_t npack, int64_t zero_off, int kp, int kc,
+                                                  const T *__restrict__ M, const int16_t *__restrict__ mc_src,
+                                                  T *__restrict__ Mc) {
     const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= nelem) return;
+    if (e >= npack + 3 * kc) return;
+    if (e >= npack) {
+        Mc[zero_off + (e - npack)] = T(0);
+        return;
+    }
     const int q = int(e % kc);
     const int64_t cc = e / kc;   // cell * 3 + component
     const int src = mc_src[q];
-    // the cell past the last one is the zero cell
-    Mc[e] = (src >= 0 && cc < nelem / kc - 3) ? M[cc * kp + src] : T(0);
+    Mc[e] = src >= 0 ? M[cc * kp + src] : T(0);
 }
 
 constexpr int kSymWaves = 12;
@@ -506,15 +512,25 @@ __global__ void __launch_bounds__(kSymThreads) k_m2l_sym64(int level, int period
 bool m2l_sym_supported(int p) { return p == 10; }
 
 template <typename T>
-hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const T *M, const int16_t *mc_src, T *Mc) {
-    const int64_t nelem = (ncells + 1) * 3 * kc;
-    hipLaunchKernelGGL(k_sym_pack<T>, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, nelem, kp, kc, M,
-                       mc_src, Mc);
+hipError_t launch_sym_pack_range(hipStream_t s, int64_t npack, int64_t zero_cell, int kp, int kc, const T *M,
+                                 const int16_t *mc_src, T *Mc) {
+    const int64_t nelem = (npack + 1) * 3 * kc;
+    hipLaunchKernelGGL(k_sym_pack<T>, dim3(unsigned((nelem + 255) / 256)), dim3(256), 0, s, npack * 3 * kc,
+                       zero_cell * 3 * kc, kp, kc, M, mc_src, Mc);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sym_pack(hipStream_t s, int64_t ncells, int kp, int kc, const T *M, const int16_t *mc_src, T *Mc) {
+    return launch_sym_pack_range<T>(s, ncells, ncells, kp, kc, M, mc_src, Mc);
 }
 template hipError_t launch_sym_pack<float>(hipStream_t, int64_t, int, int, const float *, const int16_t *, float *);
 template hipError_t launch_sym_pack<double>(hipStream_t, int64_t, int, int, const double *, const int16_t *,
                                             double *);
+template hipError_t launch_sym_pack_range<float>(hipStream_t, int64_t, int64_t, int, int, const float *,
+                                                 const int16_t *, float *);
+template hipError_t launch_sym_pack_range<double>(hipStream_t, int64_t, int64_t, int, int, const double *,
+                                                  const int16_t *, double *);
 
 hipError_t launch_m2l_sym64(hipStream_t s, int level, int periodic, int p, int kp, const double *mc,
                             int64_t zero_cell, const double *ops, const int32_t *sl_off, const int32_t *orbits,

@@ -101,7 +101,7 @@ struct OpSet {
         DevBuf ops, off, ops64, sl64;
     };
     bool sym_ready = false;
-    DevBuf sym_orb, sym_mcsrc, sym_row;
+    DevBuf sym_orb, sym_mcsrc, sym_row, sym_mcpos;   // sym_mcpos[standard index] = class-major position
     SymOps sym[2];
 };
 
@@ -555,6 +555,10 @@ vm_status ensure_sym_ops(vm_ctx *ctx, OpSet *set, int adjoint) {
         VM_HIP(upload(set->sym_orb, orb), "upload symmetric M2L");
         VM_HIP(upload(set->sym_mcsrc, mc_src), "upload symmetric M2L");
         VM_HIP(upload(set->sym_row, row_std), "upload symmetric M2L");
+        std::vector<int16_t> mc_pos(coef_stride(C), -1);
+        for (int q = 0; q < KC; ++q)
+            if (mc_src[q] >= 0) mc_pos[mc_src[q]] = int16_t(q);
+        VM_HIP(upload(set->sym_mcpos, mc_pos), "upload symmetric M2L");
         set->sym_ready = true;
     }
     so.ready = true;
@@ -892,8 +896,10 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     const bool relayout = ctx->layout_p != p || ctx->layout_prec != mixed;
     if (relayout || ctx->mbuf.bytes < cbytes) {
         // coefficient padding (rows C..kp-1) must stay zero: clear on any change of layout
+        // (the class-major copy's padding too: P2M writes only its valid positions)
         ctx->mbuf.release();
         ctx->lbuf.release();
+        ctx->mcbuf.release();
         VM_HIP(ctx->mbuf.reserve(cbytes, true), "alloc multipoles");
         VM_HIP(ctx->lbuf.reserve(cbytes, true), "alloc locals");
         ctx->layout_p = p;
@@ -901,7 +907,7 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
     }
 
     if (use_sym)
-        VM_HIP(ctx->mcbuf.reserve(esz * size_t(ncells + 1) * 3 * (16 * sym_layout(p).nblk)),
+        VM_HIP(ctx->mcbuf.reserve(esz * size_t(ncells + 1) * 3 * (16 * sym_layout(p).nblk), true),
                "alloc class-major multipoles");
 
     // --- tree ------------------------------------------------------------
@@ -990,9 +996,16 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
             const T *l2l = f32 ? (const T *)ops->l2l32.ptr : (const T *)ops->l2l64.ptr;
             const int16_t *lists = ctx->octlists.as<int16_t>();
             const int8_t *offs = ctx->offsets.as<int8_t>();
+            // with the orbit M2L, P2M also writes the finest level's class-major copy
+            const int kc = use_sym ? 16 * sym_layout(p).nblk : 0;
+            T *mc = use_sym ? ctx->mcbuf.as<T>() : nullptr;
+            const int64_t base_fine = ((int64_t(1) << (3 * level)) - 1) / 7;
             {
                 Timed tm(ctx, VM_PH_P2M);
-                VM_HIP(launch_p2m<T>(s, int(nleaf), parts, start, p, kp, g.inv_w, tab, lev(M, level)), "P2M");
+                VM_HIP(launch_p2m<T>(s, int(nleaf), parts, start, p, kp, g.inv_w, tab, lev(M, level), LeafMap(),
+                                     use_sym ? mc + size_t(base_fine) * 3 * kc : nullptr,
+                                     ops->sym_mcpos.as<int16_t>(), kc),
+                       "P2M");
             }
             for (int l = level - 1; l >= lmin; --l) {
                 Timed tm(ctx, VM_PH_M2M);
@@ -1000,11 +1013,10 @@ vm_status fmm_impl(vm_ctx *ctx, int64_t n, const double *x, const double *alpha,
                        "M2M");
             }
             const bool sym = use_sym;
-            const int kc = 16 * sym_layout(p).nblk;
-            T *mc = ctx->mcbuf.as<T>();
             if (sym) {
+                // the coarser levels' class-major copy (the finest came from P2M)
                 Timed tm(ctx, VM_PH_M2L);
-                VM_HIP(launch_sym_pack<T>(s, ncells, kp, kc, M, ops->sym_mcsrc.as<int16_t>(), mc),
+                VM_HIP(launch_sym_pack_range<T>(s, base_fine, ncells, kp, kc, M, ops->sym_mcsrc.as<int16_t>(), mc),
                        "M2L class-major multipoles");
             }
             bool have_parent = false;   // L at level l-1 holds something
