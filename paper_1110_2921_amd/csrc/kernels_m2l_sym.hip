@@ -566,13 +566,29 @@ hipError_t launch_m2l_sym64_adaptive(hipStream_t s, int p, int kp, const double 
     for (int o = 0; o < 8; ++o) ad.tile_start[o + 1] = ad.tile_start[o] + (ad.oct_n[o] + kSymTargets - 1) / kSymTargets;
     const int grid = ad.tile_start[8];
     if (grid == 0) return hipSuccess;
-    // orbit-range splits while the level's tiles do not fill the chip
+    // orbit-range splits: a workgroup holds a compute unit (its LDS), so the
+    // level takes ceil(grid nsplit / CUs) rounds of ceil(56 / nsplit) orbits;
+    // the smallest nsplit with the fewest orbit-rounds that the partial-sum
+    // buffer holds
     int nsplit = 1;
-    if (part != nullptr && ad.part_cells > 0 && grid < 1024) {
-        nsplit = (1024 + grid - 1) / grid;
-        if (nsplit > kSymOrbits) nsplit = kSymOrbits;
+    if (part != nullptr && ad.part_cells > 0) {
+        static int ncu = 0;
+        if (ncu == 0) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+                ncu = 256;
+        }
         const size_t per_split = size_t(ad.part_cells) * 3 * kp;
-        while (nsplit > 1 && size_t(nsplit) * per_split > part_elems) --nsplit;
+        int64_t best = -1;
+        for (int ns = 1; ns <= kSymOrbits && size_t(ns) * per_split <= part_elems; ++ns) {
+            const int64_t rounds = (int64_t(grid) * ns + ncu - 1) / ncu;
+            const int64_t cost = rounds * ((kSymOrbits + ns - 1) / ns);
+            if (best < 0 || cost < best) {
+                best = cost;
+                nsplit = ns;
+            }
+        }
     }
     double *pbuf = nsplit > 1 ? part : nullptr;
     const size_t smem = sizeof(double) * size_t(kRing) * size_t(16 * SL.C + 32);

@@ -25,7 +25,7 @@ using namespace vmfmm;
 namespace {
 
 constexpr size_t kTrPartBytes = size_t(64) << 20;   // scratch of split M2L launches
-constexpr size_t kAdSplitElems = size_t(8) << 20;  // doubles of the adaptive M2L partial sums (64 MiB)
+constexpr size_t kAdSplitElems = size_t(32) << 20;  // doubles of the adaptive M2L partial sums (256 MiB)
 constexpr int kAdSymMinCells = 256;   // adaptive levels with fewer cells keep the dense M2L
 
 struct DevBuf {
