@@ -298,10 +298,20 @@ hipError_t launch_ad_p2l(hipStream_t s, const AdTreeView &t, const AdLists &ls, 
 // M2P: far[12][n] of the particles of the target blocks `items` += the
 // derivatives of the source cells' multipoles (m2p_table layout; tab's
 // recurrence of degree >= p + 2)
-hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nitem, const int2 *items,
+hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nitem, const int4 *items,
                          const int32_t *lcell, const int32_t *lstart, int n, int ncell, int p, int kp, int nrow, int nharm,
                          const DevTables &tab, const int32_t *rowptr, const int32_t *col, const int32_t *harm,
-                         const double *w, const double *G, const Part64 *parts, const double *M, double *far);
+                         const double *w, const double *G, const Part64 *parts, const double *M, double *far,
+                         double *part);
+// M2P work items (leaf, first target, chunk, chunks): blocks of 16 targets of
+// the leaves with an M2P list times chunks of its entries.  count: per-leaf
+// item counts scanned into ioff (nleaf words; tile_sums scratch) and the total
+// in *nitem_out; fill: the items (needs the total's room: nitem int4).  M2P
+// takes part (nitem x 12 x 16 doubles) for the chunks' shares.
+hipError_t launch_ad_m2p_count(hipStream_t s, int nleaf, const int32_t *lstart, const int32_t *lcell,
+                               const uint32_t *cnt1, uint32_t *ioff, uint32_t *tile_sums, int *nitem_out);
+hipError_t launch_ad_m2p_fill(hipStream_t s, int nleaf, const int32_t *lstart, const int32_t *lcell,
+                              const uint32_t *cnt1, const uint32_t *ioff, int4 *items);
 
 // rows of the translation-operator GEMM tile
 inline int pad16(int c) { return (c + 15) / 16 * 16; }

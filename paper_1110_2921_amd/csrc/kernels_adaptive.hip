@@ -467,27 +467,32 @@ __global__ void __launch_bounds__(64) k_ad_p2l(AdTreeView t, AdLists ls, int off
 // (rows x (col, harm, weight)), and the table's evaluation matrix G turns
 // those coefficients into u and J at the particle, added to far[12][n].
 constexpr int kM2PMaxRow = 9;
+constexpr int kM2PChunk = 2;   // list entries per M2P work item
 
-__global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const int2 *__restrict__ items,
+__global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const int4 *__restrict__ items,
                                                const int32_t *__restrict__ lcell,
                                                const int32_t *__restrict__ lstart, int n, int ncell, int p, int kp,
                                                int nrow, int nharm, DevTables tab, const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col, const int32_t *__restrict__ harm,
                                                const double *__restrict__ wt, const double *__restrict__ G,
                                                const Part64 *__restrict__ parts, const double *__restrict__ M,
-                                               double *__restrict__ far) {
+                                               double *__restrict__ far, double *__restrict__ part) {
     // Particle pi of the item's 16 has lanes 4 pi .. 4 pi + 3: lane j computes
     // the harmonic orders m = j (mod 4) and sums every fourth term of each
     // local row, and the lanes' partial rows are added by two butterflies.
     // LDS holds the 16 particles' harmonics and the source cell's multipole.
-    // Blocks of 16 rather than 64 targets give a leaf with a long list four
-    // times as many waves; the list is walked once per block either way.
+    // Item (leaf, first target, chunk c, chunks): 16 targets against entries
+    // c kM2PChunk .. of the leaf's list, so that the few leaves with M2P lists
+    // still give the chip many short waves; with several chunks the outputs go
+    // to part[item][12][16] and k_ad_m2p_reduce adds them in chunk order.
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int2 it = items[blockIdx.x];
+    const int4 it = items[blockIdx.x];
     const int a = lcell[it.x];
-    const uint32_t e0 = ls.off[size_t(1) * ncell + a];
-    const uint32_t e1 = e0 + ls.cnt[size_t(1) * ncell + a];
-    if (e1 == e0) return;
+    const uint32_t l0 = ls.off[size_t(1) * ncell + a];
+    const uint32_t l1 = l0 + ls.cnt[size_t(1) * ncell + a];
+    const uint32_t e0 = l0 + uint32_t(it.z) * kM2PChunk;
+    const uint32_t e1 = e0 + kM2PChunk < l1 ? e0 + kM2PChunk : l1;
+    if (e1 <= e0) return;
     const int lane = threadIdx.x, pi = lane >> 2, j = lane & 3;
     double *hs = reinterpret_cast<double *>(smem_raw);     // [nharm][16]
     double *mb = hs + size_t(nharm) * 16;                   // [3][kp]
@@ -571,11 +576,70 @@ __global__ void __launch_bounds__(64) k_ad_m2p(AdTreeView t, AdLists ls, const i
                 out[i] += v * (o < 3 ? su : sj);
             }
         }
-        if (valid) {
+        if (it.w > 1) {
+            // this chunk's share, summed over the chunks by k_ad_m2p_reduce
+#pragma unroll
+            for (int i = 0; i < 3; ++i) part[(size_t(blockIdx.x) * 12 + j + 4 * i) * 16 + pi] = out[i];
+        } else if (valid) {
             const size_t gi = size_t(s0) + base + pi;
 #pragma unroll
             for (int i = 0; i < 3; ++i) far[size_t(j + 4 * i) * n + gi] += out[i];
         }
+    }
+}
+
+// M2P work items of leaf i: blocks of 16 targets times chunks of kM2PChunk
+// entries of its M2P list
+__device__ __forceinline__ int m2p_items_of(int i, const int32_t *__restrict__ lstart,
+                                            const int32_t *__restrict__ lcell, const uint32_t *__restrict__ cnt1,
+                                            int &nb, int &nch) {
+    const uint32_t len = cnt1[lcell[i]];
+    nb = (lstart[i + 1] - lstart[i] + 15) / 16;
+    nch = int((len + kM2PChunk - 1) / kM2PChunk);
+    return nb * nch;
+}
+
+__global__ void __launch_bounds__(256) k_ad_m2p_count(int nleaf, const int32_t *__restrict__ lstart,
+                                                      const int32_t *__restrict__ lcell,
+                                                      const uint32_t *__restrict__ cnt1, uint32_t *__restrict__ ni) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int nb, nch;
+    if (i < nleaf) ni[i] = uint32_t(m2p_items_of(i, lstart, lcell, cnt1, nb, nch));
+}
+
+// after the exclusive scan: the item count (last leaf's offset + its items)
+__global__ void k_ad_m2p_total(int nleaf, const int32_t *__restrict__ lstart, const int32_t *__restrict__ lcell,
+                               const uint32_t *__restrict__ cnt1, const uint32_t *__restrict__ ioff,
+                               int *__restrict__ nitem) {
+    int nb, nch;
+    *nitem = nleaf == 0 ? 0 : int(ioff[nleaf - 1]) + m2p_items_of(nleaf - 1, lstart, lcell, cnt1, nb, nch);
+}
+
+__global__ void __launch_bounds__(256) k_ad_m2p_fill(int nleaf, const int32_t *__restrict__ lstart,
+                                                     const int32_t *__restrict__ lcell,
+                                                     const uint32_t *__restrict__ cnt1,
+                                                     const uint32_t *__restrict__ ioff, int4 *__restrict__ items) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaf) return;
+    int nb, nch;
+    if (m2p_items_of(i, lstart, lcell, cnt1, nb, nch) == 0) return;
+    for (int b = 0; b < nb; ++b)
+        for (int c = 0; c < nch; ++c) items[ioff[i] + b * nch + c] = make_int4(i, 16 * b, c, nch);
+}
+
+// the chunks of a target block (consecutive items) summed in chunk order
+__global__ void __launch_bounds__(64) k_ad_m2p_reduce(const int4 *__restrict__ items,
+                                                      const int32_t *__restrict__ lstart, int n,
+                                                      const double *__restrict__ part, double *__restrict__ far) {
+    const int4 it = items[blockIdx.x];
+    if (it.z != 0 || it.w <= 1) return;
+    const int s0 = lstart[it.x], cnt = lstart[it.x + 1] - s0;
+    for (int v = threadIdx.x; v < 12 * 16; v += 64) {
+        const int o = v / 16, pi = v % 16;
+        if (it.y + pi >= cnt) continue;
+        double sum = 0.0;
+        for (int c = 0; c < it.w; ++c) sum += part[(size_t(blockIdx.x + c) * 12 + o) * 16 + pi];
+        far[size_t(o) * n + s0 + it.y + pi] += sum;
     }
 }
 
@@ -689,15 +753,35 @@ hipError_t launch_ad_p2l(hipStream_t s, const AdTreeView &t, const AdLists &ls, 
     return hipGetLastError();
 }
 
-hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nitem, const int2 *items,
+hipError_t launch_ad_m2p(hipStream_t s, const AdTreeView &t, const AdLists &ls, int nitem, const int4 *items,
                          const int32_t *lcell, const int32_t *lstart, int n, int ncell, int p, int kp, int nrow,
                          int nharm, const DevTables &tab, const int32_t *rowptr, const int32_t *col,
                          const int32_t *harm, const double *w, const double *G, const Part64 *parts, const double *M,
-                         double *far) {
+                         double *far, double *part) {
     if (nitem == 0) return hipSuccess;
     const size_t smem = sizeof(double) * (size_t(nharm) * 16 + size_t(3) * kp);
     hipLaunchKernelGGL(k_ad_m2p, dim3(nitem), dim3(64), smem, s, t, ls, items, lcell, lstart, n, ncell, p, kp, nrow,
-                       nharm, tab, rowptr, col, harm, w, G, parts, M, far);
+                       nharm, tab, rowptr, col, harm, w, G, parts, M, far, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ad_m2p_reduce, dim3(nitem), dim3(64), 0, s, items, lstart, n, (const double *)part, far);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_m2p_count(hipStream_t s, int nleaf, const int32_t *lstart, const int32_t *lcell,
+                               const uint32_t *cnt1, uint32_t *ioff, uint32_t *tile_sums, int *nitem_out) {
+    hipLaunchKernelGGL(k_ad_m2p_count, dim3(blocks(nleaf, 256)), dim3(256), 0, s, nleaf, lstart, lcell, cnt1, ioff);
+    hipError_t e = launch_exclusive_scan(s, nleaf, ioff, tile_sums);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ad_m2p_total, dim3(1), dim3(1), 0, s, nleaf, lstart, lcell, cnt1, (const uint32_t *)ioff,
+                       nitem_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ad_m2p_fill(hipStream_t s, int nleaf, const int32_t *lstart, const int32_t *lcell,
+                              const uint32_t *cnt1, const uint32_t *ioff, int4 *items) {
+    hipLaunchKernelGGL(k_ad_m2p_fill, dim3(blocks(nleaf, 256)), dim3(256), 0, s, nleaf, lstart, lcell, cnt1, ioff,
+                       items);
     return hipGetLastError();
 }
 

@@ -184,7 +184,7 @@ struct vm_ctx {
         DevBuf key, level, start, count, parent, child;        // cells
         DevBuf sstart, scount, rank, tsum, ints;                // construction scratch, device counters
         DevBuf leaf_at, lcell, lstart, llev, iota, items;       // leaves in particle order, target blocks
-        DevBuf items16;                                         // M2P target blocks
+        DevBuf items16, m2p_off, m2p_part;                      // M2P work items, their offsets, partial sums
         DevBuf tpart;                                           // M2L partial sums of the offset splits
         DevBuf mc;                                              // class-major multipoles (orbit M2L)
         DevBuf ctr;                                             // cell centres
@@ -1330,15 +1330,21 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     VM_HIP(hipMemsetAsync(A.vtab.ptr, 0xff, sizeof(int32_t) * 189 * size_t(ncell), s), "clear M2L table");
     for (int l = 0; l < nlev; ++l)
         VM_HIP(launch_ad_traverse(s, t, ls, l, lo[l], lo[l + 1] - lo[l], 1, 0, ncell), "adaptive traversal");
-    // M2P work items: blocks of 16 targets of the leaves with an M2P list
-    VM_HIP(A.items16.reserve(sizeof(int2) * (size_t(nleaf) + size_t(n) / 16 + 1)), "alloc work items");
-    VM_HIP(launch_ad_blocks(s, nleaf, A.lstart.as<int32_t>(), A.lcell.as<int32_t>(), A.cnt.as<uint32_t>() + ncell, 16,
-                            A.rank.as<uint32_t>(), A.tsum.as<uint32_t>(), A.items16.as<int2>(), dints + 4),
+    // M2P work items: blocks of 16 targets of the leaves with an M2P list, times
+    // chunks of their entries (counted here, written once their number is known)
+    VM_HIP(A.m2p_off.reserve(sizeof(uint32_t) * (size_t(nleaf) + 1)), "alloc work items");
+    VM_HIP(launch_ad_m2p_count(s, nleaf, A.lstart.as<int32_t>(), A.lcell.as<int32_t>(), A.cnt.as<uint32_t>() + ncell,
+                               A.m2p_off.as<uint32_t>(), A.tsum.as<uint32_t>(), dints + 4),
            "M2P work items");
     int err_m2p[3] = {0, 0, 0};   // error flag, (target blocks of 64), M2P items
     if (vm_status st = read_ints(ctx, dints + 2, err_m2p, 3); st != VM_OK) return st;
     const int err = err_m2p[0], nitem16 = err_m2p[2];
     if (err) return fail(ctx, VM_EDEVICE, "adaptive traversal: partner or stack overflow, or an M2L offset outside its list");
+    VM_HIP(A.items16.reserve(sizeof(int4) * (size_t(nitem16) + 1)), "alloc work items");
+    VM_HIP(A.m2p_part.reserve(sizeof(double) * 12 * 16 * (size_t(nitem16) + 1)), "alloc M2P partial sums");
+    VM_HIP(launch_ad_m2p_fill(s, nleaf, A.lstart.as<int32_t>(), A.lcell.as<int32_t>(), A.cnt.as<uint32_t>() + ncell,
+                              A.m2p_off.as<uint32_t>(), A.items16.as<int4>()),
+           "M2P work items");
     tm_lists.stop();
 
     // --- expansions -------------------------------------------------------------
@@ -1454,10 +1460,11 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     }
     {
         Timed tm(ctx, VM_PH_M2P);
-        VM_HIP(launch_ad_m2p(s, t, ls, nitem16, A.items16.as<int2>(), lcell, lstart, n, ncell, p, kp, A.m2p_nrow,
+        VM_HIP(launch_ad_m2p(s, t, ls, nitem16, A.items16.as<int4>(), lcell, lstart, n, ncell, p, kp, A.m2p_nrow,
                              A.m2p_nharm, tabI,
                              A.m2p_rowptr.as<int32_t>(), A.m2p_col.as<int32_t>(), A.m2p_harm.as<int32_t>(),
-                             A.m2p_w.as<double>(), A.m2p_G.as<double>(), parts, M, ctx->far.as<double>()),
+                             A.m2p_w.as<double>(), A.m2p_G.as<double>(), parts, M, ctx->far.as<double>(),
+                             A.m2p_part.as<double>()),
                "adaptive M2P");
     }
     P2PArgs a{};
