@@ -161,9 +161,16 @@ hipError_t launch_p2p32(hipStream_t s, const P2PArgs &a, const Part32 *parts);
 // a.perm, a.alpha, a.far, a.u, a.dalpha, a.grad, a.scheme, a.have_far,
 // a.sigma are used).
 struct AdTreeView;
+// One P2P list entry of an adaptive target leaf: the source leaf's sorted
+// particle range and D = centre_b + s L - centre_a, which takes the source
+// records (relative to their leaf's centre) into the target leaf's frame.
+struct __align__(32) P2PMeta {
+    double dx, dy, dz;
+    int js, je;
+};
 hipError_t launch_p2p64_list(hipStream_t s, const P2PArgs &a, int nitem, const int2 *items, const int32_t *lcell,
-                             const int32_t *lstart, const AdTreeView &t, const uint32_t *off, const uint32_t *cnt,
-                             const int32_t *src, const int8_t *code, const Part64 *parts);
+                             const int32_t *lstart, const uint32_t *off, const uint32_t *cnt, const P2PMeta *meta,
+                             const Part64 *parts);
 
 // --- RBF interpolation (kernels_rbf.hip) --------------------------------------------
 struct GaussArgs {
@@ -259,6 +266,9 @@ struct AdLists {
     int *err;                 // set on a partner overflow or an M2L offset outside the list
 };
 hipError_t launch_ad_root(hipStream_t s, const AdTreeView &t, int n);
+// meta[e] of every P2P list entry e of the ncell cells (list 0 of off / cnt)
+hipError_t launch_ad_p2p_meta(hipStream_t s, const AdTreeView &t, int ncell, const uint32_t *off,
+                              const uint32_t *cnt, const int32_t *src, const int8_t *code, P2PMeta *meta);
 // the centres of the ncell cells into ctr[cell][4] (the cell-particle and near
 // field kernels read them instead of decoding keys)
 hipError_t launch_ad_centres(hipStream_t s, const AdTreeView &t, int ncell, double *ctr);

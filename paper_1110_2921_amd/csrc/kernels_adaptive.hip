@@ -69,6 +69,31 @@ __device__ __forceinline__ void centre(const AdTreeView &t, int c, double out[3]
     for (int d = 0; d < 3; ++d) out[d] = t.lo[d] + (double(ad_coord(t.key[c], d, l)) + 0.5) * w;
 }
 
+// per cell: its P2P entries' source ranges and frame shifts
+__global__ void __launch_bounds__(64) k_ad_p2p_meta(AdTreeView t, int ncell, const uint32_t *__restrict__ off,
+                                                    const uint32_t *__restrict__ cnt,
+                                                    const int32_t *__restrict__ src, const int8_t *__restrict__ code,
+                                                    P2PMeta *__restrict__ meta) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= ncell) return;
+    const uint32_t e0 = off[a], e1 = e0 + cnt[a];
+    if (e1 == e0) return;
+    double ca[3];
+    centre(t, a, ca);
+    for (uint32_t e = e0; e < e1; ++e) {
+        const int b = src[e], cd = code[e];
+        double cb[3];
+        centre(t, b, cb);
+        P2PMeta m;
+        m.dx = cb[0] + shift_of(cd, 0) * t.box_len - ca[0];
+        m.dy = cb[1] + shift_of(cd, 1) * t.box_len - ca[1];
+        m.dz = cb[2] + shift_of(cd, 2) * t.box_len - ca[2];
+        m.js = t.start[b];
+        m.je = m.js + t.count[b];
+        meta[e] = m;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_ad_centres(AdTreeView t, int ncell, double *__restrict__ ctr) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -675,6 +700,13 @@ __global__ void __launch_bounds__(256) k_ad_block_fill(int nleaf, const int32_t 
 inline int blocks(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
+
+hipError_t launch_ad_p2p_meta(hipStream_t s, const AdTreeView &t, int ncell, const uint32_t *off,
+                              const uint32_t *cnt, const int32_t *src, const int8_t *code, P2PMeta *meta) {
+    if (ncell == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ad_p2p_meta, dim3(blocks(ncell, 64)), dim3(64), 0, s, t, ncell, off, cnt, src, code, meta);
+    return hipGetLastError();
+}
 
 hipError_t launch_ad_centres(hipStream_t s, const AdTreeView &t, int ncell, double *ctr) {
     if (ncell == 0) return hipSuccess;

@@ -188,6 +188,7 @@ struct vm_ctx {
         DevBuf tpart;                                           // M2L partial sums of the offset splits
         DevBuf mc;                                              // class-major multipoles (orbit M2L)
         DevBuf ctr;                                             // cell centres
+        DevBuf p2p_meta;                                        // P2P entries' source ranges and frame shifts
         DevBuf part, pcode, npart, vtab, cnt, off, src, code;   // traversal
         DevBuf tcell, M, L, parts;
         DevBuf rec_c1, rec_c2, rec_dg;                          // recurrence of degree p + 2
@@ -1322,6 +1323,7 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     VM_HIP(hipStreamSynchronize(s), "synchronize");
     const size_t nentry = size_t(tail[0]) + tail[1];
     VM_HIP(A.src.reserve(sizeof(int32_t) * std::max<size_t>(nentry, 1)), "alloc lists");
+    VM_HIP(A.p2p_meta.reserve(sizeof(P2PMeta) * std::max<size_t>(nentry, 1)), "alloc lists");
     VM_HIP(A.code.reserve(std::max<size_t>(nentry, 1)), "alloc lists");
     for (int k = 0; k < 3; ++k) {
         ls.src[k] = A.src.as<int32_t>();
@@ -1480,8 +1482,11 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     a.grad = grad;
     {
         Timed tm(ctx, VM_PH_P2P);
-        VM_HIP(launch_p2p64_list(s, a, nitem, A.items.as<int2>(), lcell, lstart, t, A.off.as<uint32_t>(),
-                                 A.cnt.as<uint32_t>(), A.src.as<int32_t>(), A.code.as<int8_t>(), parts),
+        VM_HIP(launch_ad_p2p_meta(s, t, ncell, A.off.as<uint32_t>(), A.cnt.as<uint32_t>(), A.src.as<int32_t>(),
+                                  A.code.as<int8_t>(), A.p2p_meta.as<P2PMeta>()),
+               "adaptive P2P entries");
+        VM_HIP(launch_p2p64_list(s, a, nitem, A.items.as<int2>(), lcell, lstart, A.off.as<uint32_t>(),
+                                 A.cnt.as<uint32_t>(), A.p2p_meta.as<P2PMeta>(), parts),
                "adaptive P2P");
     }
     A.valid = true;
