@@ -266,6 +266,12 @@ struct AdLists {
     int *err;                 // set on a partner overflow or an M2L offset outside the list
 };
 hipError_t launch_ad_root(hipStream_t s, const AdTreeView &t, int n);
+// Octant groups of every level at once: the cells sorted stably by
+// (level, octant) into vb (ka, va, kb scratch of ncell words; hist the radix
+// histogram, as for a pass over ncell keys), starts[level * 8 + octant] the
+// first position of each group and starts[8 nlev] = ncell (device ints).
+hipError_t launch_ad_groups(hipStream_t s, const AdTreeView &t, int ncell, int nlev, uint32_t *ka, int32_t *va,
+                            uint32_t *kb, int32_t *vb, uint32_t *hist, int *starts);
 // meta[e] of every P2P list entry e of the ncell cells (list 0 of off / cnt)
 hipError_t launch_ad_p2p_meta(hipStream_t s, const AdTreeView &t, int ncell, const uint32_t *off,
                               const uint32_t *cnt, const int32_t *src, const int8_t *code, P2PMeta *meta);
@@ -297,10 +303,6 @@ hipError_t launch_ad_permute(hipStream_t s, const AdTreeView &t, int n, const do
 // list k of cell c at off[k ncell + c] ..) and the M2L table (row c - vcell0)
 hipError_t launch_ad_traverse(hipStream_t s, const AdTreeView &t, const AdLists &ls, int l, int off, int ncl,
                               int pass, int vcell0, int ncell);
-// octant groups of the cells [off, off + ncl): group o (key order) in
-// tcell[o ncl ..], its size in oct_count[o] (device)
-hipError_t launch_ad_octants(hipStream_t s, const AdTreeView &t, int off, int ncl, int32_t *tcell, uint32_t *rank,
-                             uint32_t *tile_sums, int *oct_count);
 // P2L: local expansions of the cells [off, off + ncl) (holding L2L and M2L)
 // += the particles of the source leaves of their P2L lists
 hipError_t launch_ad_p2l(hipStream_t s, const AdTreeView &t, const AdLists &ls, int off, int ncl, int ncell, int p,

@@ -69,6 +69,25 @@ __device__ __forceinline__ void centre(const AdTreeView &t, int c, double out[3]
     for (int d = 0; d < 3; ++d) out[d] = t.lo[d] + (double(ad_coord(t.key[c], d, l)) + 0.5) * w;
 }
 
+// sort key of each cell for the octant groups of all levels at once:
+// level * 8 + octant (a stable sort keeps the key order inside a group)
+__global__ void __launch_bounds__(256) k_ad_group_keys(AdTreeView t, int ncell, uint32_t *__restrict__ keys,
+                                                       int32_t *__restrict__ idx) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    keys[c] = uint32_t(t.level[c]) * 8u + (t.key[c] & 7u);
+    idx[c] = c;
+}
+
+// the first position of each (level, octant) group, from the sort pass's
+// scanned histogram (digit-major, block 0 first), and the cell count
+__global__ void k_ad_group_starts(int ngroup, int nblk, int ncell, const uint32_t *__restrict__ offs,
+                                  int *__restrict__ starts) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ngroup) starts[g] = int(offs[size_t(g) * nblk]);
+    if (g == 0) starts[ngroup] = ncell;
+}
+
 // per cell: its P2P entries' source ranges and frame shifts
 __global__ void __launch_bounds__(64) k_ad_p2p_meta(AdTreeView t, int ncell, const uint32_t *__restrict__ off,
                                                     const uint32_t *__restrict__ cnt,
@@ -406,22 +425,6 @@ __global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, in
     if (bad) atomicExch(ls.err, 1);
 }
 
-// octant groups of one level: counts, then stable placement by prefix within each octant
-__global__ void __launch_bounds__(256) k_ad_oct_flags(AdTreeView t, int off, int ncl, int o, uint32_t *__restrict__ f) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ncl) f[i] = int(t.key[off + i] & 7u) == o ? 1u : 0u;
-}
-
-__global__ void __launch_bounds__(256) k_ad_oct_place(AdTreeView t, int off, int ncl, int o,
-                                                      const uint32_t *__restrict__ rank, int32_t *__restrict__ out,
-                                                      int *__restrict__ count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncl) return;
-    const bool mine = int(t.key[off + i] & 7u) == o;
-    if (i == ncl - 1) *count = int(rank[i]) + (mine ? 1 : 0);
-    if (mine) out[rank[i]] = off + i;
-}
-
 // ------------------------------------------------------------ cell-particle ----
 // P2L: one workgroup per target cell with a P2L list.  Lane j takes the
 // conjugated irregular harmonics of source particle j (relative to the target
@@ -701,6 +704,20 @@ inline int blocks(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
 
+hipError_t launch_ad_groups(hipStream_t s, const AdTreeView &t, int ncell, int nlev, uint32_t *ka, int32_t *va,
+                            uint32_t *kb, int32_t *vb, uint32_t *hist, int *starts) {
+    if (ncell == 0 || nlev * 8 > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ad_group_keys, dim3(blocks(ncell, 256)), dim3(256), 0, s, t, ncell, ka, va);
+    int bits = 0;
+    while ((1 << bits) < nlev * 8) ++bits;
+    hipError_t e = launch_radix_pass(s, ncell, 0, bits, ka, va, kb, vb, hist);
+    if (e != hipSuccess) return e;
+    const int nblk = (ncell + kRadixTile - 1) / kRadixTile;
+    hipLaunchKernelGGL(k_ad_group_starts, dim3(blocks(nlev * 8, 256)), dim3(256), 0, s, nlev * 8, nblk, ncell,
+                       (const uint32_t *)hist, starts);
+    return hipGetLastError();
+}
+
 hipError_t launch_ad_p2p_meta(hipStream_t s, const AdTreeView &t, int ncell, const uint32_t *off,
                               const uint32_t *cnt, const int32_t *src, const int8_t *code, P2PMeta *meta) {
     if (ncell == 0) return hipSuccess;
@@ -759,21 +776,6 @@ hipError_t launch_ad_traverse(hipStream_t s, const AdTreeView &t, const AdLists 
                               int pass, int vcell0, int ncell) {
     if (ncl == 0) return hipSuccess;
     hipLaunchKernelGGL(k_ad_traverse, dim3(ncl), dim3(64), 0, s, t, ls, l, off, ncl, pass, vcell0, ncell);
-    return hipGetLastError();
-}
-
-hipError_t launch_ad_octants(hipStream_t s, const AdTreeView &t, int off, int ncl, int32_t *tcell, uint32_t *rank,
-                             uint32_t *tile_sums, int *oct_count) {
-    // octant o's cells land after those of octants < o; their offsets are
-    // prefix sums of oct_count, known only on the host, so each group is
-    // written into its own stretch of ncl entries: tcell[o ncl ...]
-    for (int o = 0; o < 8; ++o) {
-        hipLaunchKernelGGL(k_ad_oct_flags, dim3(blocks(ncl, 256)), dim3(256), 0, s, t, off, ncl, o, rank);
-        hipError_t e = launch_exclusive_scan(s, ncl, rank, tile_sums);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_ad_oct_place, dim3(blocks(ncl, 256)), dim3(256), 0, s, t, off, ncl, o,
-                           (const uint32_t *)rank, tcell + size_t(o) * ncl, oct_count + o);
-    }
     return hipGetLastError();
 }
 

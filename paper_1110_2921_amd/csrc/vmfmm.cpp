@@ -188,6 +188,7 @@ struct vm_ctx {
         DevBuf tpart;                                           // M2L partial sums of the offset splits
         DevBuf mc;                                              // class-major multipoles (orbit M2L)
         DevBuf ctr;                                             // cell centres
+        DevBuf gk, gv;                                          // octant-group sort scratch
         DevBuf p2p_meta;                                        // P2P entries' source ranges and frame shifts
         DevBuf part, pcode, npart, vtab, cnt, off, src, code;   // traversal
         DevBuf tcell, M, L, parts;
@@ -1225,7 +1226,7 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     VM_HIP(b.vals_b->reserve(sizeof(int32_t) * size_t(n)), "alloc perm");
     VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * (size_t(nblk) * 256 + size_t(nblk) * 256 / 4096 + 256)),
            "alloc histogram");
-    VM_HIP(A.ints.reserve(sizeof(int) * 32), "alloc counters");
+    VM_HIP(A.ints.reserve(sizeof(int) * 320), "alloc counters");
     int *dints = A.ints.as<int>();
     if (vm_status st = clear_flag(ctx, opts); st != VM_OK) return st;
     TreeGeom g;
@@ -1357,7 +1358,7 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
     VM_HIP(hipMemsetAsync(A.L.ptr, 0, cbytes, s), "clear locals");
     VM_HIP(ctx->far.reserve(sizeof(double) * 12 * size_t(n)), "alloc far field");
     VM_HIP(A.iota.reserve(sizeof(int32_t) * size_t(ncell)), "alloc cell list");
-    VM_HIP(A.tcell.reserve(sizeof(int32_t) * 8 * size_t(ncell)), "alloc octant groups");
+    VM_HIP(A.tcell.reserve(sizeof(int32_t) * size_t(ncell)), "alloc octant groups");
     VM_HIP(A.tpart.reserve(sizeof(double) * kAdSplitElems), "alloc M2L partial sums");
     const int ad_kc = 16 * sym_layout(p).nblk;
     if (ad_sym) VM_HIP(A.mc.reserve(sizeof(double) * (size_t(ncell) + 1) * 3 * ad_kc), "alloc class-major multipoles");
@@ -1405,17 +1406,28 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
         Timed tm(ctx, VM_PH_LATTICE);
         VM_HIP(launch_lattice<double>(s, p, kp, tlat, M, L), "lattice");
     }
+    // octant groups of every level: one stable sort of the cells by (level,
+    // octant), the groups' starts read once
+    std::vector<int> gstart(size_t(8) * nlev + 1, 0);
+    {
+        const size_t gblk = (std::max<size_t>(size_t(n), size_t(ncell)) + kRadixTile - 1) / kRadixTile;
+        VM_HIP(ctx->hist.reserve(sizeof(uint32_t) * (gblk * 256 + gblk * 256 / 4096 + 256)), "alloc histogram");
+        VM_HIP(A.gk.reserve(sizeof(uint32_t) * 2 * size_t(ncell)), "alloc octant groups");
+        VM_HIP(A.gv.reserve(sizeof(int32_t) * size_t(ncell)), "alloc octant groups");
+        uint32_t *gk = A.gk.as<uint32_t>();
+        VM_HIP(launch_ad_groups(s, t, ncell, nlev, gk, A.gv.as<int32_t>(), gk + ncell, A.tcell.as<int32_t>(),
+                                ctx->hist.as<uint32_t>(), dints + 16),
+               "octant groups");
+        if (vm_status st = read_ints(ctx, dints + 16, gstart.data(), int(gstart.size())); st != VM_OK) return st;
+    }
     for (int l = 1; l < nlev; ++l) {
         const int nl = lo[l + 1] - lo[l];
-        VM_HIP(launch_ad_octants(s, t, lo[l], nl, A.tcell.as<int32_t>(), A.rank.as<uint32_t>(), A.tsum.as<uint32_t>(),
-                                 dints + 8), "octant groups");
         int oc[8];
-        if (vm_status st = read_ints(ctx, dints + 8, oc, 8); st != VM_OK) return st;
         AdaptTr ad;
         ad.tcell = A.tcell.as<int32_t>();
         for (int o = 0; o < 8; ++o) {
-            ad.oct_base[o] = o * nl;
-            ad.oct_n[o] = oc[o];
+            ad.oct_base[o] = gstart[8 * l + o];
+            ad.oct_n[o] = oc[o] = gstart[8 * l + o + 1] - gstart[8 * l + o];
         }
         ad.parent = t.parent;
         ad.stab = A.vtab.as<int32_t>();
@@ -1435,7 +1447,7 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
                 sa.vtab = A.vtab.as<int32_t>();
                 sa.vslot = A.vslot.as<int16_t>();
                 for (int o = 0; o < 8; ++o) {
-                    sa.oct_base[o] = o * nl;
+                    sa.oct_base[o] = ad.oct_base[o];
                     sa.oct_n[o] = oc[o];
                 }
                 sa.cell0 = 0;
