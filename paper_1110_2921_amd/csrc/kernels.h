@@ -298,7 +298,8 @@ hipError_t launch_ad_blocks(hipStream_t s, int nleaf, const int32_t *lstart, con
 // sorted FP64 records relative to each leaf's centre
 hipError_t launch_ad_permute(hipStream_t s, const AdTreeView &t, int n, const double *x, const double *alpha,
                              const int32_t *perm, int nleaf, const int32_t *lcell, Part64 *parts);
-// dual traversal of the cells [off, off + ncl) of level l: pass 0 counts the
+// dual traversal of the cells [off, off + ncl) of level l (l < 0: each cell at
+// its own level, for pass 1 over cells of several levels): pass 0 counts the
 // list entries and records the partners, pass 1 fills the lists (entries of
 // list k of cell c at off[k ncell + c] ..) and the M2L table (row c - vcell0)
 hipError_t launch_ad_traverse(hipStream_t s, const AdTreeView &t, const AdLists &ls, int l, int off, int ncl,

@@ -286,9 +286,12 @@ __device__ __forceinline__ uint32_t wave_scan(uint32_t v, uint32_t &total) {
 // needed.  List entries go to the cell's lists in candidate order: in the
 // filling pass every lane first counts its entries, the wave's prefix sums
 // place them, and the lane classifies again, writing.
-__global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, int l, int off, int ncl, int pass,
+__global__ void __launch_bounds__(64) k_ad_traverse(AdTreeView t, AdLists ls, int lvl, int off, int ncl, int pass,
                                                     int vcell0, int ncell) {
     const int a = off + int(blockIdx.x);
+    // lvl < 0: cells of every level in one launch (the filling pass, whose
+    // partners are all known), each at its own level
+    const int l = lvl >= 0 ? lvl : t.level[a];
     const int lane = threadIdx.x;
     const bool leaf_a = ad_leaf(t, a);
     const int oct = int(t.key[a] & 7u);

@@ -1331,8 +1331,8 @@ vm_status adaptive_impl(vm_ctx *ctx, int64_t n64, const double *x, const double 
         ls.code[k] = A.code.as<int8_t>();
     }
     VM_HIP(hipMemsetAsync(A.vtab.ptr, 0xff, sizeof(int32_t) * 189 * size_t(ncell), s), "clear M2L table");
-    for (int l = 0; l < nlev; ++l)
-        VM_HIP(launch_ad_traverse(s, t, ls, l, lo[l], lo[l + 1] - lo[l], 1, 0, ncell), "adaptive traversal");
+    // the filling pass over every cell in one launch (the partners are final)
+    VM_HIP(launch_ad_traverse(s, t, ls, -1, 0, ncell, 1, 0, ncell), "adaptive traversal");
     // M2P work items: blocks of 16 targets of the leaves with an M2P list, times
     // chunks of their entries (counted here, written once their number is known)
     VM_HIP(A.m2p_off.reserve(sizeof(uint32_t) * (size_t(nleaf) + 1)), "alloc work items");
