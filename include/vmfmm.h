@@ -81,7 +81,11 @@ typedef struct {
 
 /* Creates a context bound to HIP device `device` and stream `hip_stream`
  * (a hipStream_t, or NULL for the default stream).  The context owns its
- * workspace (grown on demand, reused across calls) and its operator cache. */
+ * workspace (grown on demand, reused across calls), its operator cache and
+ * a second non-blocking stream (default priority) with two events, which
+ * vm_fmm_eval forks from and joins back into the bound stream, so callers
+ * still see every call ordered on their stream (graph capture included).
+ * VM_EDEVICE when the device, the stream or the events cannot be set up. */
 vm_status vm_create(vm_ctx **ctx, int device, void *hip_stream);
 void vm_destroy(vm_ctx *ctx);
 vm_status vm_set_stream(vm_ctx *ctx, void *hip_stream);
@@ -432,8 +436,12 @@ vm_status vm_tune_level(vm_ctx *ctx, int64_t n, const double *x, const double *a
                         const vm_opts *opts, double min_leaf_sigmas, int reps, int *level, double *ms);
 
 /*
- * Device-time accounting (HIP events on the context's stream around every
- * launch).  vm_set_timing(ctx, 1) starts a fresh account (and 0 stops it);
+ * Device-time accounting (HIP events around every launch, on the stream the
+ * launch goes to: vm_fmm_eval runs its near field (VM_PH_P2P) on a second,
+ * non-blocking stream of the context, forked after the tree build by an event
+ * and joined by L2P, so the P2P phase overlaps P2M and what of the far field
+ * the hardware schedules beside it, and the combine of near and far field is
+ * part of VM_PH_L2P).  vm_set_timing(ctx, 1) starts a fresh account (and 0 stops it);
  * vm_get_timing reports, summed over every vm_fmm_eval since then, the
  * milliseconds and the number of launches of each phase (at most 32768
  * launches are recorded); it synchronises the stream.  vm_gauss_sum and
@@ -448,7 +456,7 @@ enum {
     VM_PH_L2L,
     VM_PH_M2L,
     VM_PH_L2P,
-    VM_PH_P2P,        /* near field + combine + scatter to caller order */
+    VM_PH_P2P,        /* near field (+ combine and scatter to caller order without a far field) */
     VM_PH_GAUSS,      /* Gaussian sums of vm_gauss_sum / vm_rbf_solve (with the strength packing) */
     VM_PH_KRYLOV,     /* vector work of vm_rbf_solve: dots, updates, gathers and scatters */
     VM_PH_LISTS,      /* adaptive tree: cells, leaves and the dual traversal's lists */
