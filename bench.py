@@ -40,6 +40,11 @@ PEAKS = {  # MI355X published peaks
 P2P_FLOP_PER_PAIR = {"mixed": 79.0, "fp64": 69.0}   # counted from the pair kernels
 # Gaussian sum: r = t - s (3), |r|^2 (5), scale (1), exp2 (1), three strength FMAs (6)
 GAUSS_FLOP_PER_PAIR = 16.0
+# The paper's base run (Sec. 4.1): time step (forward Euler in its loop),
+# reinitialisation every 10 steps, Krylov drop tolerance
+PAPER_DT = 0.005
+PAPER_REINIT_EVERY = 10
+PAPER_TOL = 1e-3
 
 
 def log(*a):
@@ -325,7 +330,7 @@ def main():
     J = torch.empty((9, n), dtype=torch.float64, device=dev)
     ctx = vm.FMM(0)
     kw = dict(periodic=w.periodic, box_len=w.box_len, scheme="classic")
-    dt = 0.005                               # the paper's time step (Sec. 4.1)
+    dt = PAPER_DT
     h3 = w.h ** 3
 
     def step(prec, xs, as_):
@@ -602,13 +607,13 @@ def main():
         om = a0 / h3
         gam = torch.empty_like(a0)
         rkw = dict(periodic=w.periodic, box_len=w.box_len, precision=args.precision, out=gam)
-        ctx.rbf_solve(x0, om, w.sigma, h3, w.level, tol=1e-3, max_iter=100, **rkw)
+        ctx.rbf_solve(x0, om, w.sigma, h3, w.level, tol=PAPER_TOL, max_iter=100, **rkw)
         torch.cuda.synchronize()
         ctx.set_timing(True)
         reps = 3
         t0 = time.perf_counter()
         for _ in range(reps):
-            _, iters, resid = ctx.rbf_solve(x0, om, w.sigma, h3, w.level, tol=1e-3, max_iter=100, **rkw)
+            _, iters, resid = ctx.rbf_solve(x0, om, w.sigma, h3, w.level, tol=PAPER_TOL, max_iter=100, **rkw)
         torch.cuda.synchronize()
         tr = (time.perf_counter() - t0) / reps
         ph = ctx.timing()
@@ -623,7 +628,7 @@ def main():
                       "traffic_unit": "bytes per launch"}
         roof_gauss["frac"] = roof_gauss["achieved"] / roof_gauss["peak"]
         result["rbf"] = {"ms": 1e3 * tr, "iterations": iters, "products": products, "resid": resid,
-                         "tol": 1e-3, "precision": args.precision, "gauss_ms_per_product": gauss_ms,
+                         "tol": PAPER_TOL, "precision": args.precision, "gauss_ms_per_product": gauss_ms,
                          "gauss_gpairs_per_s": pairs / (gauss_ms * 1e-3) / 1e9,
                          "krylov_ms": ph["krylov"][0] / reps, "tree_ms": ph["tree"][0] / reps,
                          "vs_rk2_step": 1e3 * tr / ms_per_step, "roofline": roof_gauss,
@@ -672,14 +677,16 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sg, diag, prods, resid = ctx.run(x, a, w.sigma, w.p, w.level, dt, args.loop_steps, nu=nu,
-                                         integrator="euler", reinit_every=10, ng=w.ng, tol=1e-3, max_iter=100,
+                                         integrator="euler", reinit_every=PAPER_REINIT_EVERY, ng=w.ng,
+                                         tol=PAPER_TOL, max_iter=100,
                                          periodic=w.periodic, box_len=w.box_len, precision=args.precision,
                                          want_diag=True)
         torch.cuda.synchronize()
         tl = time.perf_counter() - t0
         dg = diag.cpu().numpy()
         result["time_loop"] = {"steps": args.loop_steps, "ms_per_step": 1e3 * tl / args.loop_steps,
-                               "integrator": "euler", "dt": dt, "nu": nu, "reinit_every": 10, "tol": 1e-3,
+                               "integrator": "euler", "dt": dt, "nu": nu, "reinit_every": PAPER_REINIT_EVERY,
+                               "tol": PAPER_TOL,
                                "gmres_products": prods, "gmres_resid": resid, "sigma_end": sg,
                                "energy_drift": float((dg[-1, 0] - dg[0, 0]) / dg[0, 0]),
                                "what": "Euler steps with core spreading and lattice reinitialisation (RBF), "
