@@ -245,6 +245,30 @@ def test_invalid_arguments_are_rejected(ctx):
     assert e.value.status == vm._lib.VM_EDOMAIN
 
 
+def test_one_particle_and_the_empty_set(ctx):
+    """No particles: VM_EINVAL.  One particle: in free space no velocity at
+    all (the self pair has r = 0) and the gradient is the self term; with the
+    images of S_1, the oracle FMM's velocity and gradient."""
+    import paper_1110_2921_amd as vm
+    x = np.array([[1.1, 2.3, 4.0]])
+    a = np.array([[0.3, -0.2, 0.5]])
+    with pytest.raises(vm._lib.VmError) as e:
+        ctx.eval(_dev(x[:0]), _dev(a[:0]), 0.2, 6, 2)
+    assert e.value.status == vm._lib.VM_EINVAL
+    for K in (0, 1):
+        uo, Jo = OF.fmm(x, a, 0.2, 6, 2, periodic=K)
+        print(f"[fmm] one particle, periodic {K}", flush=True)
+        u, _, J = ctx.eval(_dev(x), _dev(a), 0.2, 6, 2, periodic=K, want_grad=True)
+        um, _, Jm = ctx.eval(_dev(x), _dev(a), 0.2, 6, 2, periodic=K, want_grad=True, precision="mixed")
+        u, J, um, Jm = _host(u), _host(J).reshape(-1, 3, 3), _host(um), _host(Jm).reshape(-1, 3, 3)
+        close(J, Jo, FP64, "J vs oracle")
+        close(Jm, J, MIXED_J, "J mixed vs fp64")
+        if K == 0:
+            assert np.all(u == 0.0) and np.all(um == 0.0)
+        else:
+            assert np.abs(u - uo).max() < 1e-13 * np.abs(Jo).max()
+
+
 @pytest.mark.parametrize("p", [6, 8, 10])
 def test_triangular_truncation_matches_oracle(ctx, p):
     """M2L truncated to n + n' <= p: FP64 against the oracle with the same
