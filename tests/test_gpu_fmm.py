@@ -269,6 +269,25 @@ def test_one_particle_and_the_empty_set(ctx):
             assert np.abs(u - uo).max() < 1e-13 * np.abs(Jo).max()
 
 
+@pytest.mark.parametrize("periodic", [0, 2])
+def test_coincident_particles(ctx, periodic):
+    """Particles at the same position (40 pairs, different strengths): each
+    such pair is a pair at r = 0, summed like the self term (the small-r
+    series); FP64 against the oracle FMM, mixed against FP64."""
+    x, a = W.random_particles(300, 77)
+    x = np.concatenate([x, x[:40]])
+    a = np.concatenate([a, a[40:80]])
+    uo, Jo = OF.fmm(x, a, 0.2, 8, 2, periodic=periodic)
+    print(f"[fmm] coincident particles, periodic {periodic}", flush=True)
+    u, _, J = ctx.eval(_dev(x), _dev(a), 0.2, 8, 2, periodic=periodic, want_grad=True)
+    um, _, Jm = ctx.eval(_dev(x), _dev(a), 0.2, 8, 2, periodic=periodic, want_grad=True, precision="mixed")
+    u, J = _host(u), _host(J).reshape(-1, 3, 3)
+    close(u, uo, FP64, "u vs oracle")
+    close(J, Jo, FP64, "J vs oracle")
+    close(_host(um), u, MIXED_U, "u mixed vs fp64")
+    close(_host(Jm).reshape(-1, 3, 3), J, MIXED_J, "J mixed vs fp64")
+
+
 @pytest.mark.parametrize("p", [6, 8, 10])
 def test_triangular_truncation_matches_oracle(ctx, p):
     """M2L truncated to n + n' <= p: FP64 against the oracle with the same
