@@ -174,3 +174,40 @@ def test_multipole_basis_gradient_table(p):
         fd = (_cvec(Y + e, p) @ f - _cvec(Y - e, p) @ f) / (2 * h)
         an = _cvec(Y, p)[:, :nu] @ (G[a * nu:(a + 1) * nu] @ f)
         assert np.abs(fd - an).max() < 1e-8 * np.abs(fd).max()
+
+
+@pytest.mark.parametrize("p", [4, 10])
+def test_m2l_operators_are_reflection_symmetric(p):
+    """The reflection-orbit M2L rests on the operators' symmetry: reflecting
+    axis a maps the real coefficient i to s_i times itself (s_i = -1 when bit a
+    of its class is set: x by (m + [Im]) odd, y by [Im], z by n + m odd), so
+    T(R_a d) = P_a T(d) P_a, and where d_a = 0 the entries between
+    coefficients of opposite sign vanish.  The 189 offsets of a list fall into
+    56 orbits, and the product count per target of the orbit form is the sum
+    over the orbits' representatives of the entries that survive."""
+    import bench
+    offs = [tuple(map(int, d)) for d in lib.debug_offsets()]
+    idx = {d: i for i, d in enumerate(offs)}
+    C = (p + 1) ** 2
+    cls = np.array([bench._sym_class(i) for i in range(C)])
+    ops = {d: lib.debug_operator(0, p, i) for d, i in idx.items()}
+    for d, T in ops.items():
+        sc = np.abs(T).max()
+        for a in range(3):
+            s = np.where((cls >> a) & 1, -1.0, 1.0)
+            dr = tuple(-v if b == a else v for b, v in enumerate(d))
+            assert np.abs(ops[dr] - s[:, None] * T * s[None, :]).max() <= 1e-14 * sc
+            if d[a] == 0:
+                assert np.abs(T[s[:, None] != s[None, :]]).max() <= 1e-14 * sc
+    # octant 0's list: offsets with components in [-2, 3], outside the neighbours
+    lst = [d for d in offs if all(-2 <= v <= 3 for v in d)]
+    assert len(lst) == 189
+    reps = {tuple(abs(v) for v in d) for d in lst}
+    assert len(reps) == 56
+    entries = 0
+    for rep in reps:
+        zmask = sum(1 << a for a in range(3) if rep[a] == 0)
+        entries += int(np.sum(((cls[:, None] ^ cls[None, :]) & zmask) == 0))
+    assert bench.orbit_m2l_flop_per_target(p) == 6.0 * entries
+    if p == 10:
+        assert bench.orbit_m2l_flop_per_target(p) == 3480816.0
