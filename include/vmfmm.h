@@ -167,8 +167,8 @@ vm_status vm_fmm_eval_adaptive(vm_ctx *ctx, int64_t n, const double *x, const do
                                double *grad);
 
 /*
- * Auto-tuned leaf size of the adaptive tree (Sec. 3.2: the number of particles
- * per box at the deepest levels is chosen without user input): candidates
+ * Auto-tuned leaf size of the adaptive tree (Sec. 3.2: the library picks how
+ * many particles a leaf may hold, the user does not): candidates
  * ncrit = 8, 16, ..., 1024 in increasing order, each run once untimed and
  * `reps` times timed (HIP events on the context's stream) with
  * vm_fmm_eval_adaptive, until the time has risen twice in a row.
