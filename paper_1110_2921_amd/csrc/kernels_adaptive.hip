@@ -14,12 +14,16 @@
 // neighbour positions of the cell.  A cell's candidates are its parent's
 // partners, split ones replaced by their children (the root: itself and, when
 // periodic, its 26 images).  A candidate that does not touch the cell is an
-// M2L source (same level) or a P2L source (a coarser leaf); a touching one is
-// a P2P source when both are leaves, a partner when the cell is split, and
-// when only the candidate is split its subtree is walked with an explicit
-// stack: cells that do not touch the leaf are M2P sources, touching leaves
-// P2P sources, touching split cells are opened.  Each (target particle,
-// source particle, image) triple is then covered by exactly one interaction.
+// M2L source when it has the cell's level, and a P2L source when it is a
+// coarser leaf and the cell is split.  Cell-particle interactions need a split
+// cell on the cell side (a cell of at most ncrit particles is cheaper taken
+// particle by particle), so any other candidate -- touching, or a coarser leaf
+// apart from a leaf cell -- is a P2P source when both are leaves, a partner
+// when the cell is split, and when only the candidate is split its subtree is
+// walked with an explicit stack: split cells that do not touch the leaf are
+// M2P sources, its leaves (touching or not) P2P sources, touching split cells
+// are opened.  Each (target particle, source particle, image) triple is then
+// covered by exactly one interaction.
 #include <cstdio>
 
 #include "device_harmonics.h"
