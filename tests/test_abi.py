@@ -63,3 +63,16 @@ def test_operator_generation_is_finite(p):
         m = vm.debug_operator(kind, p, idx)
         assert np.all(np.isfinite(m))
         assert np.abs(m).max() > 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library there is no fallback: loading it, and so
+    creating a context, raises."""
+    import paper_1110_2921_amd as vm
+    from paper_1110_2921_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libvmfmm.so"))
+    monkeypatch.setattr(_lib, "_LIB", None)
+    with pytest.raises(ImportError):
+        _lib.load()
+    with pytest.raises(ImportError):
+        vm.FMM(0)
