@@ -88,7 +88,13 @@ typedef struct {
  * VM_EDEVICE when the device, the stream or the events cannot be set up. */
 vm_status vm_create(vm_ctx **ctx, int device, void *hip_stream);
 void vm_destroy(vm_ctx *ctx);
+/* Binds the context to another stream for the calls that follow.  Nothing is
+ * enqueued: work a previous call left on the old stream is not waited for, and
+ * since every call reuses the context's workspace, the caller orders the two
+ * streams (an event or a synchronisation) before the next call when they
+ * differ.  VM_EINVAL for a NULL context. */
 vm_status vm_set_stream(vm_ctx *ctx, void *hip_stream);
+/* The message of the context's last failed call (a static string for NULL). */
 const char *vm_last_error(const vm_ctx *ctx);
 
 /*
