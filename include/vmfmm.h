@@ -87,6 +87,8 @@ typedef struct {
  * still see every call ordered on their stream (graph capture included).
  * VM_EDEVICE when the device, the stream or the events cannot be set up. */
 vm_status vm_create(vm_ctx **ctx, int device, void *hip_stream);
+/* Waits for the context's work on its bound and second streams, then frees
+ * its workspace, operator cache, second stream and events (NULL: no-op). */
 void vm_destroy(vm_ctx *ctx);
 /* Binds the context to another stream for the calls that follow.  Nothing is
  * enqueued: work a previous call left on the old stream is not waited for, and
